@@ -1,0 +1,104 @@
+"""The oracle pins must catch plausible mistakes.
+
+Each case plants one mistake in a copy of the C oracle (a dropped factor, a
+flipped sign, a shifted index, a transposed operand), builds it into a
+temporary library on the CPU, and runs the pin functions of
+test_oracle_pins.py against it: at least one pin has to fail.  The committed
+oracle itself is never modified.
+"""
+import ctypes
+import os
+import subprocess
+
+import pytest
+
+import oracle
+from tests import test_oracle_pins as pins
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "tadmm_oracle.c")
+
+MUTANTS = {
+    "hessian_factor_2_dropped": ("q->Hd[k] = 2.0 * wq +", "q->Hd[k] = 1.0 * wq +"),
+    "consensus_term_sign": ("- (r < q->dp && ysum ? ysum[t * q->dp + r] : 0.0);",
+                            "+ (r < q->dp && ysum ? ysum[t * q->dp + r] : 0.0);"),
+    "terminal_weight_index": ("(t == T ? prm->qT_scale : 1.0)", "(t == T - 1 ? prm->qT_scale : 1.0)"),
+    "projection_half_step": ("a[c] += 0.5 * v * n[c]; b[c] -= 0.5 * v * n[c];",
+                             "a[c] += v * n[c]; b[c] -= v * n[c];"),
+    "dual_update_sign": ("lam[ZI(i, j, t) + c] += rho * (pi[c] - a[c]);",
+                         "lam[ZI(i, j, t) + c] -= rho * (pi[c] - a[c]);"),
+    "multiplier_sign": ("m = (W[k] == 1) ? -y : y;", "m = (W[k] == 1) ? y : -y;"),
+    "normal_orientation": ("n[c] = (pi[c] - pj[c]) / dd;", "n[c] = (pj[c] - pi[c]) / dd;"),
+    "dynamics_A_transposed": ("const double a = prm->A[r * nx + c];", "const double a = prm->A[c * nx + r];"),
+    "dual_residual_no_previous": ("rho * (zs[c] - zsum_old[((size_t)i * T + (t - 1)) * dp + c]);", "rho * zs[c];"),
+    "primal_residual_term": ("r2 += (pi[c] - zc) * (pi[c] - zc);", "r2 += zc * zc;"),
+    "consensus_init_zero": ("z[ZI(i, j, t) + k] = sc->xref[((size_t)i * (T + 1) + t) * nx + k];",
+                            "z[ZI(i, j, t) + k] = 0.0;"),
+    "never_drops_negative_multiplier": ("if (drop >= 0 && mu_min < -prm->mu_tol) {", "if (0) {"),
+}
+
+# The fast pins (each well under a second on the committed oracle).  Mistakes
+# that the active-set method corrects by itself on the way to the unique
+# optimum (a wrong side recorded for a clipped start, a wrong bound in the
+# ratio test) leave every output unchanged and are not listed above.
+PIN_FUNCS = [pins.test_agent_qp_unconstrained_matches_condensed_least_squares,
+             pins.test_agent_qp_long_horizon_first_gain_is_dare,
+             pins.test_agent_qp_bounded_matches_bvls,
+             pins.test_agent_qp_tiny_horizon_brute_force,
+             pins.test_agent_qp_dynamics_and_box_feasible,
+             pins.test_admm_point_symmetry,
+             pins.test_admm_duals_antisymmetric_and_along_normal,
+             pins.test_admm_consensus_copies_satisfy_half_planes,
+             pins.test_admm_residual_history_consistent_with_iterates,
+             pins.test_admm_translation_invariance,
+             pins.test_admm_single_agent_converges_first_iteration,
+             pins.test_admm_frozen_limit_is_centralized_qp_kkt_certificate]
+
+
+def _call_pin(fn):
+    """Run one pin with default parametrisation; returns True if it passed."""
+    import inspect
+    params = inspect.signature(fn).parameters
+    kw = {}
+    for name in params:
+        if name == "dp":
+            kw[name] = 2
+        elif name == "seed":
+            kw[name] = 0
+        elif name == "T":
+            kw[name] = 3
+        elif name == "start":
+            kw[name] = oracle.START_COLD
+    try:
+        fn(**kw)
+        return True
+    except (AssertionError, RuntimeError, ValueError, FloatingPointError, ZeroDivisionError, IndexError):
+        return False
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) >= 1, f"mutation anchor for {name} not found"
+    mut = tmp_path / "oracle_mut.c"
+    mut.write_text(src.replace(old, new))
+    hdr = os.path.join(os.path.dirname(SRC), "tadmm_oracle.h")
+    (tmp_path / "tadmm_oracle.h").write_text(open(hdr).read())
+    so = tmp_path / "liboracle_mut.so"
+    subprocess.run(["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-fopenmp", str(mut), "-o", str(so), "-lm"],
+                   check=True, capture_output=True)
+    saved = oracle._lib
+    try:
+        oracle._lib = None
+        orig_build = oracle.build
+        oracle.build = lambda force=False: str(so)
+        try:
+            oracle.lib()
+            results = {fn.__name__: _call_pin(fn) for fn in PIN_FUNCS}
+        finally:
+            oracle.build = orig_build
+    finally:
+        oracle._lib = saved
+    failed = [k for k, ok in results.items() if not ok]
+    assert failed, f"no pin caught mutant {name}"

@@ -1,0 +1,438 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test names what fixes the expected value: a printed table of the paper,
+a closed form, a library routine solving the same problem by another method,
+brute force on a tiny instance, a KKT certificate, or an invariance of the
+problem.  None of them re-types the oracle's own formulas.
+"""
+import copy
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.optimize
+
+import oracle
+import synth
+from tests import condensed
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------------------
+# Table I (Sec. V-A): problem dimensions of the centralized QP
+# ---------------------------------------------------------------------------
+
+def test_table1_problem_dimensions():
+    rows = [list(map(int, l.split())) for l in open(os.path.join(GOLDEN, "table1_problem_dimensions.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 5
+    for N, nvar, ndyn, ncol in rows:
+        v, d, c = synth.problem_dimensions(N, 20)
+        assert v == nvar and d == ndyn
+        # the table prints the collision count with "~"; 2 agents: 1 pair x 21 knots printed as ~20
+        assert abs(c - ncol) <= 1
+
+
+# ---------------------------------------------------------------------------
+# One agent's local QP (Eq. 3)
+# ---------------------------------------------------------------------------
+
+def _wide(dp=2):
+    return synth.ProblemParams(dp=dp, u_max=1e6)
+
+
+@pytest.mark.parametrize("dp", [2, 3])
+def test_agent_qp_unconstrained_matches_condensed_least_squares(dp):
+    """Pins the KKT assembly (factors of 2, terminal weight at T, the sign of
+    the consensus term) against the state-eliminated least-squares form."""
+    rng = np.random.default_rng(11)
+    p = _wide(dp)
+    T, n_nbr, rho = 12, 3, 1.7
+    x0 = rng.normal(size=p.nx)
+    xref = rng.normal(size=(T + 1, p.nx))
+    z = rng.normal(size=(n_nbr, T + 1, dp))
+    lam = rng.normal(size=(n_nbr, T + 1, dp))
+    ysum = (rho * z - lam).sum(axis=0)
+    q = rng.uniform(0.2, 2.0, size=p.nx)
+    r = rng.uniform(0.01, 0.5, size=p.nu)
+    res = oracle.agent_qp(p, T, n_nbr, x0, xref, q, r, ysum, opts=oracle.OracleOptions(rho=rho))
+    J, b = condensed.agent_ls(p.A, p.B, T, x0, xref, q, r, p.qT_scale, rho, z, lam)
+    u_ls = np.linalg.lstsq(J, b, rcond=None)[0].reshape(T, p.nu)
+    np.testing.assert_allclose(res["u"], u_ls, rtol=1e-9, atol=1e-10)
+    np.testing.assert_allclose(res["x"], condensed.rollout(p.A, p.B, x0, u_ls), rtol=1e-9, atol=1e-10)
+    assert not res["w"].any()
+
+
+def test_agent_qp_long_horizon_first_gain_is_dare():
+    """Infinite-horizon limit: with zero reference and no coupling the first
+    input tends to -K x0, K from the discrete algebraic Riccati equation."""
+    p = _wide(2)
+    T = 200
+    Q, R = np.diag(p.q_diag), np.diag(p.r_diag)
+    P = scipy.linalg.solve_discrete_are(p.A, p.B, Q, R)
+    K = np.linalg.solve(R + p.B.T @ P @ p.B, p.B.T @ P @ p.A)
+    x0 = np.array([1.0, -2.0, 0.3, 0.5])
+    res = oracle.agent_qp(p, T, 0, x0, np.zeros((T + 1, 4)), p.q_diag, p.r_diag)
+    np.testing.assert_allclose(res["u"][0], -K @ x0, rtol=1e-8, atol=1e-10)
+
+
+def _bounded_case(seed, T, u_max=0.6, dp=2):
+    rng = np.random.default_rng(seed)
+    p = synth.ProblemParams(dp=dp, u_max=u_max)
+    n_nbr, rho = 2, 1.0
+    x0 = np.concatenate([rng.normal(size=dp), rng.normal(scale=0.3, size=dp)])
+    sc = synth.Scenario(starts=x0[None, :dp], goals=x0[None, :dp] + rng.uniform(2, 4, size=(1, dp)), T=T)
+    xref = sc.xref()[0]
+    z = xref[None, :, :dp] + rng.normal(scale=0.3, size=(n_nbr, T + 1, dp))
+    lam = rng.normal(scale=0.5, size=(n_nbr, T + 1, dp))
+    ysum = (rho * z - lam).sum(axis=0)
+    return p, n_nbr, rho, x0, xref, z, lam, ysum
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_agent_qp_bounded_matches_bvls(seed):
+    """Input-box QP against scipy's bounded-variable least squares (an exact
+    active-set method on the condensed form): same inputs, same binding set,
+    and multipliers equal to the signed gradient of the condensed objective."""
+    T = 15
+    p, n_nbr, rho, x0, xref, z, lam, ysum = _bounded_case(seed, T)
+    res = oracle.agent_qp(p, T, n_nbr, x0, xref, p.q_diag, p.r_diag, ysum)
+    J, b = condensed.agent_ls(p.A, p.B, T, x0, xref, p.q_diag, p.r_diag, p.qT_scale, rho, z, lam)
+    lo, hi = np.full(T * p.nu, -p.u_max), np.full(T * p.nu, p.u_max)
+    ls = scipy.optimize.lsq_linear(J, b, bounds=(lo, hi), method="bvls", tol=1e-14)
+    np.testing.assert_allclose(res["u"].ravel(), ls.x, atol=1e-8)
+    g = 2.0 * J.T @ (J @ res["u"].ravel() - b)
+    Wf = res["w"].ravel()
+    assert Wf.any(), "case should have binding bounds"
+    np.testing.assert_array_equal(Wf == 1, np.isclose(ls.x, lo, atol=1e-9) & (g > 1e-7))
+    np.testing.assert_array_equal(Wf == 2, np.isclose(ls.x, hi, atol=1e-9) & (g < -1e-7))
+    mu = res["mu"].ravel()
+    np.testing.assert_allclose(mu[Wf == 1], g[Wf == 1], rtol=1e-7, atol=1e-9)
+    np.testing.assert_allclose(mu[Wf == 2], -g[Wf == 2], rtol=1e-7, atol=1e-9)
+    assert np.all(mu >= -1e-9)
+    np.testing.assert_allclose(g[Wf == 0], 0.0, atol=1e-8)
+
+
+@pytest.mark.parametrize("seed,T", [(5, 2), (6, 3), (7, 3)])
+def test_agent_qp_tiny_horizon_brute_force(seed, T):
+    """T <= 3: every free/lower/upper pattern of the T*nu inputs is tried;
+    exactly one is a KKT point and it is the oracle's solution."""
+    p, n_nbr, rho, x0, xref, z, lam, ysum = _bounded_case(seed, T, u_max=0.8)
+    J, b = condensed.agent_ls(p.A, p.B, T, x0, xref, p.q_diag, p.r_diag, p.qT_scale, rho, z, lam)
+    lo, hi = np.full(T * p.nu, -p.u_max), np.full(T * p.nu, p.u_max)
+    kkt = condensed.enumerate_active_sets(J, b, lo, hi)
+    assert len(kkt) == 1
+    pat, u = kkt[0]
+    res = oracle.agent_qp(p, T, n_nbr, x0, xref, p.q_diag, p.r_diag, ysum)
+    np.testing.assert_allclose(res["u"].ravel(), u, atol=1e-10)
+    np.testing.assert_array_equal(res["w"].ravel(), pat)
+
+
+@pytest.mark.parametrize("start", [oracle.START_WARM, oracle.START_COLD])
+def test_agent_qp_start_does_not_change_the_optimum(start):
+    """Warm (unconstrained solve + clip) and cold (u = 0) starts reach the
+    same unique optimum; the warm start needs no more equality solves."""
+    T = 20
+    p, n_nbr, rho, x0, xref, z, lam, ysum = _bounded_case(9, T, u_max=0.5)
+    ref = oracle.agent_qp(p, T, n_nbr, x0, xref, p.q_diag, p.r_diag, ysum, start=oracle.START_WARM)
+    res = oracle.agent_qp(p, T, n_nbr, x0, xref, p.q_diag, p.r_diag, ysum, start=start)
+    np.testing.assert_allclose(res["u"], ref["u"], atol=1e-10)
+    np.testing.assert_array_equal(res["w"], ref["w"])
+    cold = oracle.agent_qp(p, T, n_nbr, x0, xref, p.q_diag, p.r_diag, ysum, start=oracle.START_COLD)
+    assert ref["passes"] <= cold["passes"]
+
+
+def test_agent_qp_dynamics_and_box_feasible():
+    T = 25
+    p, n_nbr, rho, x0, xref, z, lam, ysum = _bounded_case(4, T, u_max=0.4)
+    res = oracle.agent_qp(p, T, n_nbr, x0, xref, p.q_diag, p.r_diag, ysum)
+    x, u = res["x"], res["u"]
+    np.testing.assert_allclose(x[0], x0, atol=0)
+    dyn = x[1:] - (x[:-1] @ p.A.T + u @ p.B.T)
+    assert np.abs(dyn).max() < 1e-12
+    assert np.all(u >= -p.u_max - 1e-15) and np.all(u <= p.u_max + 1e-15)
+    np.testing.assert_array_equal(u[res["w"] == 1], -p.u_max)
+    np.testing.assert_array_equal(u[res["w"] == 2], p.u_max)
+
+
+def test_agent_qp_hotstart_from_previous_solution():
+    """Starting from the optimum of a nearby QP with its working set gives the
+    new optimum (the parametric hotstart of Sec. IV-C)."""
+    T = 20
+    p, n_nbr, rho, x0, xref, z, lam, ysum = _bounded_case(12, T, u_max=0.5)
+    a = oracle.agent_qp(p, T, n_nbr, x0, xref, p.q_diag, p.r_diag, ysum)
+    ysum2 = ysum + 0.05 * np.random.default_rng(1).normal(size=ysum.shape)
+    cold = oracle.agent_qp(p, T, n_nbr, x0, xref, p.q_diag, p.r_diag, ysum2)
+    hot = oracle.agent_qp(p, T, n_nbr, x0, xref, p.q_diag, p.r_diag, ysum2, start=oracle.START_PREV,
+                          x=a["x"], u=a["u"], w=a["w"])
+    np.testing.assert_allclose(hot["u"], cold["u"], atol=1e-10)
+    np.testing.assert_array_equal(hot["w"], cold["w"])
+
+
+def test_agent_qp_active_set_cap():
+    T = 20
+    p, n_nbr, rho, x0, xref, z, lam, ysum = _bounded_case(3, T, u_max=0.2)
+    res = oracle.agent_qp(p, T, n_nbr, x0, xref, p.q_diag, p.r_diag, ysum,
+                          start=oracle.START_COLD, opts=oracle.OracleOptions(max_as_iter=1))
+    assert res["capped"]
+
+
+# ---------------------------------------------------------------------------
+# ADMM (Eqs. 3-5): the limit with frozen normals is the centralized QP
+# ---------------------------------------------------------------------------
+
+def _side_pass(T=20):
+    """Two agents passing side by side; point-symmetric about the origin."""
+    sc = synth.Scenario(starts=np.array([[-3.0, 0.6], [3.0, -0.6]]),
+                        goals=np.array([[3.0, 0.1], [-3.0, -0.1]]), T=T)
+    nrm = np.zeros((1, T, 2))
+    nrm[..., 1] = 1.0
+    return sc, nrm
+
+
+def _monolithic_pieces(p, sc, normals):
+    """Condensed centralized QP of Eq. (1) with the half-planes of Sec. III-A:
+    f(U) = sum_i ||J_i u_i - b_i||^2, G U >= h, lo <= U <= hi."""
+    N, T, nu, dp = sc.N, sc.T, p.nu, p.dp
+    Phi, Gam = condensed.state_maps(p.A, p.B, T)
+    Js, bs = [], []
+    x0 = sc.x0()
+    xref = sc.xref()
+    for i in range(N):
+        J, b = condensed.agent_ls(p.A, p.B, T, x0[i], xref[i], p.q_diag, p.r_diag, p.qT_scale)
+        Js.append(J)
+        bs.append(b)
+    J = scipy.linalg.block_diag(*Js)
+    b = np.concatenate(bs)
+    n = T * nu
+    G, h = [], []
+    pidx = 0
+    for i in range(N):
+        for j in range(i + 1, N):
+            for t in range(1, T + 1):
+                nv = normals[pidx, t - 1]
+                row = np.zeros(N * n)
+                row[i * n:(i + 1) * n] = nv @ Gam[t][:dp]
+                row[j * n:(j + 1) * n] = -nv @ Gam[t][:dp]
+                G.append(row)
+                h.append(p.d_min - nv @ ((Phi[t] @ x0[i])[:dp] - (Phi[t] @ x0[j])[:dp]))
+            pidx += 1
+    return J, b, np.array(G), np.array(h)
+
+
+def test_admm_frozen_limit_is_centralized_qp_kkt_certificate():
+    """C.1: with fixed normals the ADMM fixed point solves the strictly convex
+    centralized QP.  Certificate: primal feasibility plus nonnegative
+    multipliers on the binding bounds and half-planes that make the gradient of
+    the centralized objective vanish (solved here by least squares)."""
+    p = synth.ProblemParams(dp=2, u_max=2.0)
+    sc, nrm = _side_pass()
+    res = oracle.solve(p, sc, oracle.OracleOptions(normal_mode=oracle.NORMAL_FROZEN, rho=10.0, max_iter=5000,
+                                                   eps_abs=1e-11, eps_rel=1e-11), normals=nrm)
+    assert res["status"] == oracle.CONVERGED
+    J, b, G, h = _monolithic_pieces(p, sc, nrm)
+    U = res["u"].reshape(-1)
+    assert np.all(G @ U - h >= -1e-7)
+    grad = 2.0 * J.T @ (J @ U - b)
+    W = res["w"].reshape(-1)
+    cols, signs = [], []
+    for k in np.nonzero(W)[0]:
+        e = np.zeros(U.size)
+        e[k] = 1.0 if W[k] == 1 else -1.0     # gradient of the binding constraint (>= form)
+        cols.append(e)
+    act = np.nonzero(np.abs(G @ U - h) < 1e-6)[0]
+    assert act.size >= 1, "the half-plane should bind in this case"
+    for k in act:
+        cols.append(G[k])
+    M = np.array(cols).T
+    m, *_ = np.linalg.lstsq(M, grad, rcond=None)
+    assert np.linalg.norm(M @ m - grad) < 1e-6 * (1 + np.linalg.norm(grad))
+    assert np.all(m >= -1e-7)
+
+
+def test_admm_frozen_limit_matches_slsqp():
+    p = synth.ProblemParams(dp=2, u_max=2.0)
+    sc, nrm = _side_pass()
+    res = oracle.solve(p, sc, oracle.OracleOptions(normal_mode=oracle.NORMAL_FROZEN, rho=10.0, max_iter=5000,
+                                                   eps_abs=1e-11, eps_rel=1e-11), normals=nrm)
+    J, b, G, h = _monolithic_pieces(p, sc, nrm)
+    n = J.shape[1]
+    fun = lambda U: float(np.sum((J @ U - b) ** 2))
+    jac = lambda U: 2.0 * J.T @ (J @ U - b)
+    sol = scipy.optimize.minimize(fun, np.zeros(n), jac=jac, method="SLSQP",
+                                  bounds=[(-p.u_max, p.u_max)] * n,
+                                  constraints=[dict(type="ineq", fun=lambda U: G @ U - h, jac=lambda U: G)],
+                                  options=dict(ftol=1e-12, maxiter=2000))
+    # SLSQP may end on its own line-search precision limit; its point must
+    # still be feasible and agree with the ADMM limit, which must be no worse.
+    assert sol.status in (0, 8)
+    assert np.all(G @ sol.x - h >= -1e-8)
+    np.testing.assert_allclose(res["u"].reshape(-1), sol.x, atol=1e-4)
+    assert fun(res["u"].reshape(-1)) <= fun(sol.x) * (1 + 1e-9)
+
+
+def test_admm_point_symmetry():
+    """Point-symmetric data and normal e_y: the solution is point symmetric,
+    p_1(t) = -p_0(t), which checks the pair indexing and the signs of the
+    consensus and dual updates."""
+    p = synth.ProblemParams(dp=2, u_max=2.0)
+    sc, nrm = _side_pass()
+    res = oracle.solve(p, sc, oracle.OracleOptions(normal_mode=oracle.NORMAL_FROZEN, fixed_iters=60), normals=nrm)
+    np.testing.assert_allclose(res["x"][1], -res["x"][0], atol=1e-12)
+    np.testing.assert_allclose(res["u"][1], -res["u"][0], atol=1e-12)
+
+
+def test_admm_duals_antisymmetric_and_along_normal():
+    """Derived from Eqs. (4)-(5) under the projection reading:
+    lambda_ij = -lambda_ji = -(rho/2) max(0, v) n after every update."""
+    p, scs = synth.config2(S=1)
+    sc = scs[0]
+    res = oracle.solve(p, sc, oracle.OracleOptions(fixed_iters=30), keep_zl=True)
+    lam, x = res["lam"], res["x"]
+    N = sc.N
+    np.testing.assert_allclose(lam + lam.transpose(1, 0, 2, 3), 0.0, atol=1e-12)
+    for i in range(N):
+        for j in range(i + 1, N):
+            d = x[i, 1:, :2] - x[j, 1:, :2]
+            n = d / np.linalg.norm(d, axis=1, keepdims=True)
+            l = lam[i, j]
+            cross = l[:, 0] * n[:, 1] - l[:, 1] * n[:, 0]
+            np.testing.assert_allclose(cross, 0.0, atol=1e-9)
+            assert np.all(np.sum(l * n, axis=1) <= 1e-12)
+
+
+def test_admm_consensus_copies_satisfy_half_planes():
+    """Every consensus pair (z_ij, z_ji) lies in its half-plane."""
+    p, scs = synth.config2(S=2)
+    sc = scs[1]
+    res = oracle.solve(p, sc, oracle.OracleOptions(fixed_iters=25), keep_zl=True)
+    z, x = res["z"], res["x"]
+    for i in range(sc.N):
+        for j in range(i + 1, sc.N):
+            d = x[i, 1:, :2] - x[j, 1:, :2]
+            n = d / np.linalg.norm(d, axis=1, keepdims=True)
+            assert np.all(np.sum(n * (z[i, j] - z[j, i]), axis=1) >= p.d_min - 1e-12)
+
+
+def test_admm_residual_history_consistent_with_iterates():
+    """The residual recorded at iteration K+1 equals ||A x - z|| and
+    rho ||A'(z^(K+1) - z^K)|| computed from two separate runs (lockstep)."""
+    p, scs = synth.config2(S=1)
+    sc = scs[0]
+    K = 12
+    a = oracle.solve(p, sc, oracle.OracleOptions(fixed_iters=K), keep_zl=True)
+    b = oracle.solve(p, sc, oracle.OracleOptions(fixed_iters=K + 1), keep_zl=True)
+    N, T = sc.N, sc.T
+    r2 = s2 = 0.0
+    for i in range(N):
+        zs = np.zeros((T, 2))
+        for j in range(N):
+            if j == i:
+                continue
+            r2 += np.sum((b["x"][i, 1:, :2] - b["z"][i, j]) ** 2)
+            zs += b["z"][i, j] - a["z"][i, j]
+        s2 += np.sum((p.rho * zs) ** 2)
+    np.testing.assert_allclose(b["hist"][K, 0], math.sqrt(r2), rtol=1e-10)
+    np.testing.assert_allclose(b["hist"][K, 1], math.sqrt(s2), rtol=1e-10)
+    np.testing.assert_allclose(b["hist"][:K], a["hist"][:K], rtol=0, atol=0)
+
+
+def test_admm_single_agent_converges_first_iteration():
+    p = synth.ProblemParams(dp=2)
+    sc = synth.Scenario(starts=np.array([[0.0, 0.0]]), goals=np.array([[3.0, 1.0]]), T=20)
+    res = oracle.solve(p, sc)
+    assert res["status"] == oracle.CONVERGED and res["iters"] == 1
+    direct = oracle.agent_qp(p, 20, 0, sc.x0()[0], sc.xref()[0], p.q_diag, p.r_diag)
+    np.testing.assert_allclose(res["u"][0], direct["u"], atol=1e-12)
+
+
+def test_admm_far_apart_agents_decouple():
+    """No half-plane ever binds: the ADMM limit is each agent's own QP."""
+    p = synth.ProblemParams(dp=2)
+    sc = synth.Scenario(starts=np.array([[0.0, 0.0], [0.0, 20.0]]), goals=np.array([[3.0, 1.0], [-2.0, 21.0]]), T=20)
+    res = oracle.solve(p, sc, oracle.OracleOptions(eps_abs=1e-11, eps_rel=1e-11, max_iter=3000))
+    assert res["status"] == oracle.CONVERGED and not res["pair_active"].any()
+    for i in range(2):
+        direct = oracle.agent_qp(p, 20, 0, sc.x0()[i], sc.xref()[i], p.q_diag, p.r_diag)
+        np.testing.assert_allclose(res["u"][i], direct["u"], atol=1e-8)
+
+
+def _run_fixed(p, sc, K=40):
+    return oracle.solve(p, sc, oracle.OracleOptions(fixed_iters=K))
+
+
+def test_admm_translation_invariance():
+    p, scs = synth.config2(S=1)
+    sc = scs[0]
+    c = np.array([1.7, -2.3])
+    sh = copy.deepcopy(sc)
+    sh.starts = sc.starts + c
+    sh.goals = sc.goals + c
+    a, b = _run_fixed(p, sc), _run_fixed(p, sh)
+    np.testing.assert_allclose(b["x"][..., :2], a["x"][..., :2] + c, atol=1e-8)
+    np.testing.assert_allclose(b["u"], a["u"], atol=1e-8)
+    np.testing.assert_array_equal(b["w"], a["w"])
+
+
+def test_admm_rotation_invariance():
+    """A 90-degree rotation maps the input box onto itself."""
+    p, scs = synth.config2(S=1)
+    sc = scs[0]
+    Rm = np.array([[0.0, -1.0], [1.0, 0.0]])
+    ro = copy.deepcopy(sc)
+    ro.starts = sc.starts @ Rm.T
+    ro.goals = sc.goals @ Rm.T
+    a, b = _run_fixed(p, sc), _run_fixed(p, ro)
+    np.testing.assert_allclose(b["x"][..., :2], a["x"][..., :2] @ Rm.T, atol=1e-8)
+    np.testing.assert_allclose(b["u"], a["u"] @ Rm.T, atol=1e-8)
+
+
+def test_admm_permutation_invariance():
+    p, scs = synth.config2(S=1)
+    sc = scs[0]
+    perm = np.random.default_rng(3).permutation(sc.N)
+    pe = copy.deepcopy(sc)
+    pe.starts = sc.starts[perm]
+    pe.goals = sc.goals[perm]
+    a, b = _run_fixed(p, sc), _run_fixed(p, pe)
+    np.testing.assert_allclose(b["x"], a["x"][perm], atol=1e-8)
+    np.testing.assert_array_equal(b["w"], a["w"][perm])
+
+
+def test_admm_converged_solution_keeps_minimum_separation():
+    """Fig. 3 property: a converged solve keeps every pair at least d_min
+    apart (the half-planes are an inner approximation of the distance
+    constraint), up to the primal tolerance."""
+    p, scs = synth.config2(S=16)
+    res = oracle.solve_batch(p, scs, threads=4)
+    n_conv = 0
+    for sc, r in zip(scs, res):
+        if r["status"] != oracle.CONVERGED or sc.N < 2:
+            continue
+        n_conv += 1
+        x = r["x"][:, 1:, :2]
+        d = np.linalg.norm(x[:, None] - x[None], axis=-1)
+        iu = np.triu_indices(sc.N, 1)
+        assert d[iu].min() >= p.d_min - 2 * r["eps_pri"]
+    assert n_conv >= 2
+
+
+def test_admm_max_iter_and_cap_statuses():
+    p, scs = synth.config1()
+    r = oracle.solve(p, scs[0], oracle.OracleOptions(max_iter=1))
+    assert r["status"] == oracle.MAX_ITER and r["iters"] == 1
+    r = oracle.solve(p, scs[0], oracle.OracleOptions(max_as_iter=1))
+    assert r["status"] == oracle.ACTIVE_SET_CAP and r["iters"] == 1
+
+
+def test_admm_lu_reuse_changes_nothing():
+    """The factor reuse keyed by the working set (the CPU mirror of the
+    hotstart) is an optimisation only."""
+    p, scs = synth.config2(S=1)
+    a = oracle.solve(p, scs[0], oracle.OracleOptions(fixed_iters=20, lu_reuse=True))
+    b = oracle.solve(p, scs[0], oracle.OracleOptions(fixed_iters=20, lu_reuse=False))
+    np.testing.assert_allclose(a["x"], b["x"], atol=1e-9)
+    assert a["lu_factorizations"] < b["lu_factorizations"]
