@@ -1,0 +1,174 @@
+#!/usr/bin/env python3
+"""Throughput of the ADMM hot path on one MI355X.
+
+Workload: 4096 independent scenarios (agents N ~ U{2..32}, horizon
+T ~ U{10..40}, 2-D double integrator, random starts/goals in [-5,5]^2 with
+1.0 separation), solved to the 1e-4 residual test (at most 200 iterations).
+A step = one batched solve of the whole batch (persistent kernel launched
+through a cached hipGraph), inputs already resident in HBM.
+
+Prints one JSON line: scenario solves/s (value), agent-QP solves/s, the plain
+per-scenario path on a sample, the roofline of the persistent kernel and the
+FP64 oracle timed on the host cores on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic work per unit (FP32 flops, 2-D double integrator; 3-D in
+# parentheses), counted from the operations the method must perform:
+#   affine agent-stage pass (backward affine sweep + forward rollout + ratio
+#   test + costate/multiplier on fixed inputs):   190 (380)
+#   refactored agent-stage (Riccati factor with a working set): 520 (1400)
+#   pair-step (consensus projection + dual update + residual pieces): 40 (55)
+FLOPS_PER_UNIT = {2: dict(affine=190.0, refactor=520.0, pair=40.0), 3: dict(affine=380.0, refactor=1400.0, pair=55.0)}
+PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector (packed) peak
+PEAK_FP32_UNPACKED_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--scenarios", type=int, default=4096)
+    ap.add_argument("--plain-sample", type=int, default=32)
+    ap.add_argument("--cpu-sample", type=int, default=128)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--block-threads", type=int, default=0)
+    ap.add_argument("--profile-steps", action="store_true", help="print one line per step (for profiler runs)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    import paper_2602_15838_amd as tadmm
+    import synth
+
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    problem, scs = synth.config2(S=args.scenarios)
+    pk = synth.pack(problem, scs)
+    Ns, Ts = pk.n_agents.astype(np.int64), pk.horizon.astype(np.int64)
+    print(f"# generated {len(scs)} scenarios in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+
+    solver = tadmm.Solver(tadmm.make_params(problem, block_threads=args.block_threads))
+    prep = solver.prepare(pk.n_agents, pk.horizon, pk.x0, pk.xref, pk.q_diag, pk.r_diag)
+    tuned = None
+    if args.autotune:
+        tuned = prep.autotune()
+        print(f"# autotuned workgroup size {tuned}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        prep.run(tadmm.MODE_BATCHED)
+    torch.cuda.synchronize()
+    kms = []
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        kms.append(prep.run(tadmm.MODE_BATCHED))
+        if args.profile_steps:
+            print(f"# step {k} kernel {kms[-1]:.3f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms_step = 1e3 * wall / args.steps
+    res = prep.result()
+    status = res["status"].cpu().numpy()
+    iters = res["iters"].cpu().numpy().astype(np.int64)
+    cnt = res["counters"].cpu().numpy().astype(np.float64)
+    S = len(scs)
+    scen_per_s = S / (ms_step / 1e3)
+    agent_qp = float((Ns * iters).sum())
+    agent_qp_per_s = agent_qp / (ms_step / 1e3)
+
+    # roofline of the persistent kernel (events around its graph launch)
+    kernel_ms = float(np.mean(kms))
+    fu = FLOPS_PER_UNIT[problem.dp]
+    units = dict(affine=float(cnt[:, 2].sum()), refactor=float(cnt[:, 1].sum()), pair=float(cnt[:, 3].sum()))
+    flops = fu["affine"] * units["affine"] + fu["refactor"] * units["refactor"] + fu["pair"] * units["pair"]
+    achieved = flops / (kernel_ms / 1e3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 6),
+                "frac_of_unpacked_fp32": round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 6),
+                "traffic": None, "kernel": "k_admm_persistent<4,2>", "kernel_ms": round(kernel_ms, 4),
+                "algorithmic_gflop_per_launch": round(flops / 1e9, 4),
+                "units_per_launch": {k: int(v) for k, v in units.items()}}
+
+    out = {"metric": "ADMM scenario solves/s at 1e-4 residual (batched)", "value": round(scen_per_s, 2),
+           "unit": "scenario solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"ragged batch of {S} scenarios, N~U{{2..32}}, T~U{{10..40}}, 2-D double "
+                                  f"integrator, rho=1, d_min=0.5, eps_abs=eps_rel=1e-4, max_iter=200",
+                      "scenarios": S, "agents": int(Ns.sum()), "agent_stages": int((Ns * Ts).sum()),
+                      "pair_steps": int((Ns * (Ns - 1) // 2 * Ts).sum()), "mode": "batched persistent + hipGraph",
+                      "workgroup_threads": int(tuned or args.block_threads or 256)},
+           "agent_qp_solves_per_s": round(agent_qp_per_s, 1),
+           "converged_fraction": round(float((status == 0).mean()), 4),
+           "status_counts": {str(k): int((status == k).sum()) for k in range(4)},
+           "mean_iters": round(float(iters.mean()), 2),
+           "active_set_passes_per_agent_qp": round(float(cnt[:, 0].sum()) / max(agent_qp, 1.0), 4),
+           "roofline": roofline}
+
+    if not args.no_plain and args.plain_sample > 0:
+        ids = list(range(min(args.plain_sample, S)))
+        sub = [scs[i] for i in ids]
+        ps = synth.pack(problem, sub)
+        pprep = solver.prepare(ps.n_agents, ps.horizon, ps.x0, ps.xref, ps.q_diag, ps.r_diag)
+        pprep.run(tadmm.MODE_PLAIN)
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        pprep.run(tadmm.MODE_PLAIN)
+        torch.cuda.synchronize()
+        dtp = time.perf_counter() - tp
+        pit = pprep.o["iters"].cpu().numpy().astype(np.int64)
+        bprep = solver.prepare(ps.n_agents, ps.horizon, ps.x0, ps.xref, ps.q_diag, ps.r_diag)
+        bprep.run(tadmm.MODE_BATCHED)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        bprep.run(tadmm.MODE_BATCHED)
+        torch.cuda.synchronize()
+        dtb = time.perf_counter() - tb
+        out["plain"] = {"sample": f"scenarios 0..{len(ids) - 1} of the batch, solved one by one (host loop, "
+                                  f"3 launches + 1 sync per iteration)",
+                        "scenario_solves_per_s": round(len(ids) / dtp, 2),
+                        "agent_qp_solves_per_s": round(float((ps.n_agents * pit).sum()) / dtp, 1),
+                        "batched_same_sample_scenario_solves_per_s": round(len(ids) / dtb, 2),
+                        "batched_full_over_plain": round(scen_per_s / (len(ids) / dtp), 1)}
+        print(f"# plain sample {len(ids)} scenarios in {dtp:.2f}s", file=sys.stderr, flush=True)
+
+    if not args.no_cpu and args.cpu_sample > 0:
+        import oracle
+        ids = list(range(min(args.cpu_sample, S)))
+        sub = [scs[i] for i in ids]
+        th = oracle.max_threads()
+        tc = time.perf_counter()
+        ro = oracle.solve_batch(problem, sub, threads=th)
+        dtc = time.perf_counter() - tc
+        oit = np.array([r["iters"] for r in ro], dtype=np.int64)
+        out["cpu_baseline"] = {"value": round(len(ids) / dtc, 3), "unit": "scenario solves/s", "cores": int(th),
+                               "kind": "oracle",
+                               "sample": f"scenarios 0..{len(ids) - 1} of the batch, FP64 dense-KKT oracle, OpenMP "
+                                         f"over scenarios, {dtc:.1f}s",
+                               "agent_qp_solves_per_s": round(float((np.array([s.N for s in sub]) * oit).sum()) / dtc, 1)}
+        print(f"# cpu oracle sample {len(ids)} scenarios in {dtc:.1f}s on {th} threads", file=sys.stderr, flush=True)
+
+    print(json.dumps(out))
+    solver.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,210 @@
+/*
+ * turboadmm.h -- C ABI of the MI355X (gfx950) ADMM multi-agent trajectory solver.
+ *
+ * Method: the ADMM decomposition of the centralized multi-agent QP of
+ * Sec. III-A, Eq. (1).  Every iteration solves one local QP per agent
+ * (Sec. IV-A, Eq. 3: linear dynamics, quadratic tracking and effort cost,
+ * augmented-Lagrangian penalty toward the consensus positions, input box),
+ * then performs the consensus update (Eq. 4) and the dual update (Eq. 5) for
+ * every pair of agents and time step, then evaluates the primal and dual
+ * residuals (stopping rule of Sec. V-A).  Each local QP is solved by a
+ * Riccati backward sweep (Eq. 7), a forward rollout (Eq. 8) and costates
+ * (Eq. 9) inside a primal active-set loop on the input bounds; the Riccati
+ * factors are cached across ADMM iterations while the active set is unchanged
+ * (the factorization hotstart of Sec. IV-C) and iteration 1 starts from the
+ * unconstrained Riccati solution (the warm start of Sec. IV-B).
+ *
+ * Conventions shared by every entry point:
+ *  - Pointers marked DEVICE are device (HBM) addresses on the context's
+ *    device; pointers marked HOST are ordinary host memory.  The library never
+ *    frees caller memory and never keeps a caller pointer beyond the call,
+ *    except that tadmm_adjoint() reads the workspace left by the matching
+ *    tadmm_solve().
+ *  - All device work is ordered on the stream given to tadmm_create().
+ *    tadmm_solve() and tadmm_adjoint() return after the work has completed
+ *    (they synchronize the stream once at the end).
+ *  - A context is not thread-safe; use one context per host thread.
+ *  - Return codes report argument and runtime errors only.  Per-scenario
+ *    outcomes (converged, iteration cap, ...) are data in tadmm_out::status.
+ *  - Floating point is FP32 on the device.
+ *
+ * Problem layout (homogeneous agents; C selects the first dp = nu entries of
+ * the state as the position):
+ *   x_{t+1} = A x_t + B u_t,  t = 0..T-1,  x_0 given
+ *   cost  sum_{t=0}^{T-1} (x_t - r_t)' Q (x_t - r_t) + u_t' R u_t
+ *         + (x_T - r_T)' (qT_scale Q) (x_T - r_T)          (Eq. 1, no 1/2)
+ *   u_lo <= u_t <= u_hi componentwise
+ *   for every pair i < j and t = 1..T:  n_ij,t' (C x_i,t - C x_j,t) >= d_min,
+ *   the half-plane linearisation of ||p_i - p_j|| >= d_min (Sec. III-A).
+ */
+#ifndef TURBOADMM_H
+#define TURBOADMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TADMM_OK = 0,
+  TADMM_ERR_INVALID_ARG = 1,     /* a parameter outside its documented range        */
+  TADMM_ERR_SHAPE = 2,           /* inconsistent sizes / offsets                     */
+  TADMM_ERR_NONFINITE = 3,       /* NaN/Inf (or a non-positive weight) in the inputs */
+  TADMM_ERR_INFEASIBLE_START = 4,/* two agents start closer than d_min               */
+  TADMM_ERR_HIP = 5,             /* a HIP runtime call failed                        */
+  TADMM_ERR_WORKSPACE = 6,       /* workspace missing or too small                   */
+  TADMM_ERR_STATE = 7            /* call out of order (adjoint without its solve)   */
+} tadmm_status;
+
+/* Per-scenario outcome, written to tadmm_out::status. */
+typedef enum {
+  TADMM_SCEN_CONVERGED = 0,      /* primal and dual residual tests passed            */
+  TADMM_SCEN_MAX_ITER = 1,       /* max_iter iterations without passing the test     */
+  TADMM_SCEN_ACTIVE_SET_CAP = 2, /* a local QP hit max_as_iter passes (solve stopped) */
+  TADMM_SCEN_NONFINITE = 3       /* a residual became NaN/Inf (solve stopped)        */
+} tadmm_scen_status;
+
+/* Which half-planes the consensus step projects onto. */
+typedef enum {
+  /* Linearised about the latest primal iterate: n = (C x_i - C x_j)/||.||
+   * from the x just computed, with a fallback to the reference geometry when
+   * the two positions coincide (< 1e-6). */
+  TADMM_NORMAL_PER_ITER = 0,
+  /* Fixed for the whole solve: tadmm_batch::normals, or the reference
+   * normals when that pointer is NULL. */
+  TADMM_NORMAL_FROZEN = 1
+} tadmm_normal_mode;
+
+typedef enum {
+  /* Scenarios one after another; every ADMM iteration is three kernel
+   * launches plus a device-to-host copy and a stream synchronisation. */
+  TADMM_MODE_PLAIN = 0,
+  /* All scenarios in one persistent kernel: workgroups take scenarios from an
+   * atomic queue (largest first) and iterate ADMM on the device until each
+   * scenario's own stopping test passes; launched through a cached hipGraph. */
+  TADMM_MODE_BATCHED = 1
+} tadmm_mode;
+
+/* Problem constants and solver options (host struct, passed by pointer and
+ * copied by tadmm_create). */
+typedef struct {
+  int32_t nx, nu;            /* (4,2): 2-D double integrator; (6,3): 3-D. dp = nu */
+  float A[36];               /* row-major nx*nx (first nx*nx entries used)        */
+  float B[18];               /* row-major nx*nu                                    */
+  float u_lo[3], u_hi[3];    /* input box, u_lo[c] < u_hi[c]                       */
+  float qT_scale;            /* terminal weight Q_T = qT_scale * Q, > 0            */
+  float d_min;               /* minimum separation, >= 0                           */
+  float rho;                 /* ADMM penalty, > 0                                  */
+  float eps_abs, eps_rel;    /* stopping tolerances, >= 0                          */
+  float mu_tol;              /* a bound multiplier below -mu_tol is released, >= 0 */
+  int32_t max_iter;          /* >= 1                                               */
+  int32_t max_as_iter;       /* active-set passes per local QP; <= 0: 10*T*nu      */
+  int32_t normal_mode;       /* tadmm_normal_mode                                  */
+  int32_t cache_factors;     /* 1: keep Riccati factors while the active set is
+                                unchanged (default); 0: refactor on every pass     */
+  int32_t riccati_warmstart; /* 1: iteration 1 starts from the unconstrained
+                                Riccati solution, clipped (default); 0: u = 0      */
+  int32_t hotstart;          /* 1: iterations >= 2 start from the previous (x,u,W)
+                                (default); 0: every iteration starts afresh        */
+  int32_t check_inputs;      /* 1: reject non-finite inputs / close starts with an
+                                error code (default); 0: skip the checks, a bad
+                                scenario ends with status NONFINITE                 */
+  int32_t block_threads;     /* batched mode workgroup size (64..1024, multiple of
+                                64); 0: use the context's tuned value              */
+} tadmm_params;
+
+/* A ragged batch of S independent scenarios.  Scenario s has N_s agents and
+ * horizon T_s.  Orderings (row-major, scenarios back to back):
+ *   x0      DEVICE float [sum_s N_s][nx]            (s, agent)
+ *   xref    DEVICE float [sum_s N_s (T_s+1)][nx]    (s, agent, t = 0..T_s)
+ *   q_diag  DEVICE float [S][nx]   diagonal of Q, > 0
+ *   r_diag  DEVICE float [S][nu]   diagonal of R, > 0
+ *   normals DEVICE float [sum_s P_s T_s][nu] or NULL; FROZEN mode only;
+ *           (s, pair i<j in lexicographic order, t = 1..T_s), unit vectors.
+ * P_s = N_s (N_s - 1) / 2. */
+typedef struct {
+  int32_t n_scen;
+  const int32_t *n_agents;   /* HOST [S], N_s >= 1 */
+  const int32_t *horizon;    /* HOST [S], T_s >= 1 */
+  const float *x0;
+  const float *xref;
+  const float *q_diag;
+  const float *r_diag;
+  const float *normals;
+} tadmm_batch;
+
+/* Outputs, caller-allocated DEVICE buffers (any may be NULL except status
+ * and iters). */
+typedef struct {
+  float *x;                  /* [sum N_s (T_s+1)][nx]   (s, agent, t)           */
+  float *u;                  /* [sum N_s T_s][nu]       (s, agent, t)           */
+  int8_t *w;                 /* [sum N_s T_s][nu]  0 free, 1 at lower, 2 upper  */
+  uint8_t *pair_active;      /* [sum P_s T_s]  1 if the half-plane was violated
+                                at the last consensus update (s, pair, t=1..T)  */
+  int32_t *status;           /* [S] tadmm_scen_status                           */
+  int32_t *iters;            /* [S] ADMM iterations performed                   */
+  float *r_norm, *s_norm;    /* [S] final primal / dual residual norms          */
+  float *eps_pri, *eps_dual; /* [S] final tolerances of the stopping test       */
+  int64_t *counters;         /* [S][4]: active-set passes, refactored
+                                agent-stages, affine agent-stages, pair-updates */
+} tadmm_out;
+
+typedef struct tadmm_ctx tadmm_ctx;
+
+/* Bytes of device workspace needed by tadmm_solve() for this batch shape
+ * (HOST n_agents / horizon as in tadmm_batch).  The workspace holds the
+ * factor cache, trajectories, working sets and the pair duals; it must stay
+ * untouched between a solve and its adjoint. */
+tadmm_status tadmm_workspace_size(const tadmm_params *params, int32_t n_scen, const int32_t *n_agents,
+                                  const int32_t *horizon, size_t *bytes);
+
+/* Create a context on the current HIP device.  `stream` is a hipStream_t
+ * (NULL = the default stream).  Validates params (TADMM_ERR_INVALID_ARG). */
+tadmm_status tadmm_create(tadmm_ctx **ctx, const tadmm_params *params, void *stream);
+
+/* Solve every scenario of the batch (Eqs. 3-5 iterated to the stopping test
+ * of Sec. V-A).  `workspace` is a DEVICE buffer of at least
+ * tadmm_workspace_size() bytes, 256-byte aligned.  mode: tadmm_mode. */
+tadmm_status tadmm_solve(tadmm_ctx *ctx, const tadmm_batch *batch, const tadmm_out *out, void *workspace,
+                         size_t workspace_bytes, int32_t mode);
+
+/* Reverse-mode derivative of a trajectory loss through the converged solve.
+ * The solution of the last tadmm_solve() on this context is treated as the
+ * solution of the centralized QP with its final active sets (input bounds
+ * and binding half-planes) held as equalities and the normals held constant;
+ * the KKT system of that equality QP is solved by an adjoint ADMM that reuses
+ * the cached Riccati factors.  Upstream gradients (DEVICE, layouts of
+ * tadmm_out::x / u; dL_du may be NULL):
+ *   dL_dx [sum N_s (T_s+1)][nx],  dL_du [sum N_s T_s][nu]
+ * Outputs (DEVICE, any may be NULL):
+ *   dL_dx0    [sum N_s][nx]          dL_dxref [sum N_s (T_s+1)][nx]
+ *   dL_dlogq  [S][nx]  (w.r.t. log of q_diag)   dL_dlogr [S][nu]
+ * Returns TADMM_ERR_STATE without a preceding successful solve with the
+ * same batch and workspace. */
+tadmm_status tadmm_adjoint(tadmm_ctx *ctx, const tadmm_batch *batch, const tadmm_out *out, void *workspace,
+                           size_t workspace_bytes, const float *dL_dx, const float *dL_du, float *dL_dx0,
+                           float *dL_dxref, float *dL_dlogq, float *dL_dlogr);
+
+/* Measure candidate workgroup sizes of the batched kernel on this batch and
+ * keep the fastest in the context (used when params.block_threads == 0).
+ * Writes the chosen size to *best_threads (HOST, may be NULL). */
+tadmm_status tadmm_autotune(tadmm_ctx *ctx, const tadmm_batch *batch, const tadmm_out *out, void *workspace,
+                            size_t workspace_bytes, int32_t *best_threads);
+
+/* Average duration in milliseconds of the last batched kernel launch (HIP
+ * events recorded around it on the context's stream), or -1 if none. */
+float tadmm_last_kernel_ms(const tadmm_ctx *ctx);
+
+tadmm_status tadmm_destroy(tadmm_ctx *ctx);
+const char *tadmm_status_string(tadmm_status s);
+/* Message of the last error on this context ("" if none); owned by ctx. */
+const char *tadmm_last_error(const tadmm_ctx *ctx);
+/* Library version string. */
+const char *tadmm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,1130 @@
+// turboadmm.hip -- HIP kernels and C-ABI host library of the ADMM hot path.
+//
+// Method (see include/turboadmm.h): per ADMM iteration, one input-bounded
+// linear-quadratic local QP per agent (Sec. IV-A, Eq. 3) solved by a Riccati
+// factor (Eq. 7), an affine backward sweep, a forward rollout (Eq. 8) and
+// costates (Eq. 9) inside a primal active-set loop; then the consensus
+// projection (Eq. 4), the dual update (Eq. 5) and the residual test (Sec. V-A).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/turboadmm.h"
+#include "tadmm_device.h"
+
+namespace tadmm {
+
+// ===========================================================================
+// Local QP of one agent (x-update)
+// ===========================================================================
+template <int NX, int NU>
+struct AgentMem {
+  float *R;
+  int8_t *Wb;
+  int GS, N, i;
+  __device__ __forceinline__ float &f(int field, int t) const { return R[field * GS + t * N + i]; }
+  __device__ __forceinline__ int8_t &w(int c, int t) const { return Wb[c * GS + t * N + i]; }
+};
+
+// Refactor stages thi..0 for the current working set (Eq. 7 with fixed inputs).
+template <int NX, int NU>
+__device__ __forceinline__ void refactor(const Prob &pb, const AgentMem<NX, NU> &m, const float *qd, const float hu[NU],
+                                         int T, int n_nbr, int thi) {
+  using F = Fld<NX, NU>;
+  float Pn[NX][NX];
+#pragma unroll
+  for (int r = 0; r < NX; ++r)
+#pragma unroll
+    for (int c = 0; c < NX; ++c) Pn[r][c] = m.f(F::P + r * NX + c, thi + 1);
+  for (int t = thi; t >= 0; --t) {
+    float hx[NX];
+    stage_hx<NX, NU>(pb, qd, t, T, n_nbr, hx);
+    int8_t wt[NU];
+#pragma unroll
+    for (int a = 0; a < NU; ++a) wt[a] = m.w(a, t);
+    float Pt[NX][NX], K[NU][NX], Phi[NX][NX], Gm[NU][NX], kc[NU], cc[NX];
+    factor_stage<NX, NU>(pb, hx, hu, Pn, wt, t >= 1, Pt, K, Phi, Gm, kc, cc);
+#pragma unroll
+    for (int a = 0; a < NU; ++a) {
+#pragma unroll
+      for (int c = 0; c < NX; ++c) {
+        m.f(F::K + a * NX + c, t) = K[a][c];
+        m.f(F::GM + a * NX + c, t) = Gm[a][c];
+      }
+      m.f(F::KC + a, t) = kc[a];
+    }
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      m.f(F::CC + r, t) = cc[r];
+#pragma unroll
+      for (int c = 0; c < NX; ++c) m.f(F::PHI + r * NX + c, t) = Phi[r][c];
+    }
+    if (t >= 1) {
+#pragma unroll
+      for (int r = 0; r < NX; ++r)
+#pragma unroll
+        for (int c = 0; c < NX; ++c) {
+          m.f(F::P + r * NX + c, t) = Pt[r][c];
+          Pn[r][c] = Pt[r][c];
+        }
+    }
+  }
+}
+
+// Affine backward sweep with the cached factors:
+//   p_T = q_T;  k_t = GM_t p_{t+1} + kc_t;  p_t = Phi_t' p_{t+1} + q_t + c_t,
+// with q_t = -2 Q_t r_t - C' sum_j (rho z_ij,t - lambda_ij,t) (QP on positions).
+template <int NX, int NU>
+__device__ __forceinline__ void affine_sweep(const AgentMem<NX, NU> &m, int T) {
+  using F = Fld<NX, NU>;
+  float p[NX];
+#pragma unroll
+  for (int r = 0; r < NX; ++r) p[r] = (r < NU) ? m.f(F::QP + r, T) : m.f(F::GQ + r, T);
+  for (int t = T - 1; t >= 0; --t) {
+#pragma unroll
+    for (int r = 0; r < NX; ++r) m.f(F::PV + r, t + 1) = p[r];
+#pragma unroll
+    for (int a = 0; a < NU; ++a) {
+      float v = m.f(F::KC + a, t);
+#pragma unroll
+      for (int c = 0; c < NX; ++c) v = fmaf(m.f(F::GM + a * NX + c, t), p[c], v);
+      m.f(F::KV + a, t) = v;
+    }
+    if (t >= 1) {
+      float np[NX];
+#pragma unroll
+      for (int c = 0; c < NX; ++c) {
+        float v = ((c < NU) ? m.f(F::QP + c, t) : m.f(F::GQ + c, t)) + m.f(F::CC + c, t);
+#pragma unroll
+        for (int r = 0; r < NX; ++r) v = fmaf(m.f(F::PHI + r * NX + c, t), p[r], v);
+        np[c] = v;
+      }
+#pragma unroll
+      for (int r = 0; r < NX; ++r) p[r] = np[r];
+    }
+  }
+}
+
+struct StepInfo {
+  float alpha;   // largest feasible fraction of the step toward the EQP solution
+  int blk;       // flat index t*nu+c of the blocking bound (-1: none)
+  int side;      // 1 lower, 2 upper
+  float mu_min;  // most negative multiplier of the working set (0 if none < 0)
+  int drop;      // its flat index (-1: none)
+};
+
+// Forward rollout u_t = K_t x_t + k_t, x_{t+1} = A x_t + B u_t (Eq. 8) into
+// (UE, XE), with the ratio test against the current inputs and, on stages with
+// fixed inputs, the multipliers from the costates nu_{t+1} = P x + p (Eq. 9):
+// g = H_u u_t + B' nu_{t+1}; mu = g at a lower bound, -g at an upper bound.
+template <int NX, int NU>
+__device__ __forceinline__ StepInfo forward_rollout(const Prob &pb, const AgentMem<NX, NU> &m, int T, const float hu[NU]) {
+  using F = Fld<NX, NU>;
+  StepInfo si{1.0f, -1, 0, 0.0f, -1};
+  float x[NX];
+#pragma unroll
+  for (int r = 0; r < NX; ++r) x[r] = m.f(F::X + r, 0);
+  for (int t = 0; t < T; ++t) {
+    float ue[NU];
+#pragma unroll
+    for (int a = 0; a < NU; ++a) {
+      float v = m.f(F::KV + a, t);
+#pragma unroll
+      for (int c = 0; c < NX; ++c) v = fmaf(m.f(F::K + a * NX + c, t), x[c], v);
+      ue[a] = v;
+      m.f(F::UE + a, t) = v;
+    }
+    float xn[NX];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      float v = 0.f;
+#pragma unroll
+      for (int c = 0; c < NX; ++c) v = fmaf(pb.A[r * NX + c], x[c], v);
+#pragma unroll
+      for (int a = 0; a < NU; ++a) v = fmaf(pb.B[r * NU + a], ue[a], v);
+      xn[r] = v;
+      m.f(F::XE + r, t + 1) = v;
+    }
+    int8_t wt[NU];
+    bool any = false;
+#pragma unroll
+    for (int a = 0; a < NU; ++a) {
+      wt[a] = m.w(a, t);
+      any |= (wt[a] != 0);
+    }
+#pragma unroll
+    for (int a = 0; a < NU; ++a) {
+      if (wt[a] != 0) continue;
+      const float uc = m.f(F::U + a, t);
+      if (ue[a] < pb.ulo[a]) {
+        const float r = (pb.ulo[a] - uc) / (ue[a] - uc);
+        if (r < si.alpha) { si.alpha = r; si.blk = t * NU + a; si.side = 1; }
+      } else if (ue[a] > pb.uhi[a]) {
+        const float r = (pb.uhi[a] - uc) / (ue[a] - uc);
+        if (r < si.alpha) { si.alpha = r; si.blk = t * NU + a; si.side = 2; }
+      }
+    }
+    if (any) {
+      float nu[NX];
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        float v = m.f(F::PV + r, t + 1);
+#pragma unroll
+        for (int c = 0; c < NX; ++c) v = fmaf(m.f(F::P + r * NX + c, t + 1), xn[c], v);
+        nu[r] = v;
+      }
+#pragma unroll
+      for (int a = 0; a < NU; ++a) {
+        if (wt[a] == 0) continue;
+        float g = hu[a] * ue[a];
+#pragma unroll
+        for (int r = 0; r < NX; ++r) g = fmaf(pb.B[r * NU + a], nu[r], g);
+        const float mu = (wt[a] == 1) ? g : -g;
+        if (mu < si.mu_min) { si.mu_min = mu; si.drop = t * NU + a; }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NX; ++r) x[r] = xn[r];
+  }
+  return si;
+}
+
+// One agent's x-update at ADMM iteration k.  Returns 1 if the active-set
+// loop hit its cap.  cnt[] accumulates pass / stage counters.
+template <int NX, int NU>
+__device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i, int k, long long cnt[CT_NCOL]) {
+  using F = Fld<NX, NU>;
+  const int T = sc.T;
+  const AgentMem<NX, NU> m{ws.fr + sc.fo, ws.wr + sc.bo, sc.GS, sc.N, i};
+  const float *qd = ws.qd + (long long)sc.s * NX;
+  const float *rd = ws.rd + (long long)sc.s * NU;
+  float hu[NU];
+#pragma unroll
+  for (int a = 0; a < NU; ++a) hu[a] = 2.0f * rd[a];
+  const int n_nbr = sc.N - 1;
+  int td = ws.adirty[sc.ao + i];
+  const int cap = pb.max_as > 0 ? pb.max_as : 10 * T * NU;
+
+  if (k == 1 || !pb.hot) {
+    // fresh start: empty working set ...
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int a = 0; a < NU; ++a)
+        if (m.w(a, t) != 0) { m.w(a, t) = 0; td = max(td, t); }
+    float ust[NU];
+    if (pb.warm) {
+      // ... from the unconstrained affine LQ solution (Sec. IV-B), clipped
+      if (!pb.cache) td = T - 1;
+      if (td >= 0) { refactor<NX, NU>(pb, m, qd, hu, T, n_nbr, td); cnt[CT_REFACTOR] += td + 1; td = -1; }
+      affine_sweep<NX, NU>(m, T);
+      cnt[CT_AFFINE] += T;
+      (void)forward_rollout<NX, NU>(pb, m, T, hu);
+      cnt[CT_PASSES] += 1;
+    }
+    float x[NX];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) x[r] = m.f(F::X + r, 0);
+    for (int t = 0; t < T; ++t) {
+#pragma unroll
+      for (int a = 0; a < NU; ++a) {
+        float u = pb.warm ? m.f(F::UE + a, t) : 0.f;
+        int8_t s = 0;
+        if (u < pb.ulo[a]) { u = pb.ulo[a]; s = 1; }
+        else if (u > pb.uhi[a]) { u = pb.uhi[a]; s = 2; }
+        if (s) { m.w(a, t) = s; td = max(td, t); }
+        ust[a] = u;
+        m.f(F::U + a, t) = u;
+      }
+      float xn[NX];
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        float v = 0.f;
+#pragma unroll
+        for (int c = 0; c < NX; ++c) v = fmaf(pb.A[r * NX + c], x[c], v);
+#pragma unroll
+        for (int a = 0; a < NU; ++a) v = fmaf(pb.B[r * NU + a], ust[a], v);
+        xn[r] = v;
+      }
+#pragma unroll
+      for (int r = 0; r < NX; ++r) { x[r] = xn[r]; m.f(F::X + r, t + 1) = xn[r]; }
+    }
+  }
+
+  int done = 0;
+  for (int it = 0; it < cap; ++it) {
+    if (!pb.cache) td = T - 1;
+    if (td >= 0) { refactor<NX, NU>(pb, m, qd, hu, T, n_nbr, td); cnt[CT_REFACTOR] += td + 1; td = -1; }
+    affine_sweep<NX, NU>(m, T);
+    cnt[CT_AFFINE] += T;
+    const StepInfo si = forward_rollout<NX, NU>(pb, m, T, hu);
+    cnt[CT_PASSES] += 1;
+    if (si.blk >= 0) {
+      // blocked: move the fraction alpha toward the EQP solution, fix the bound
+      const float al = fmaxf(si.alpha, 0.f);
+      for (int t = 0; t < T; ++t) {
+#pragma unroll
+        for (int a = 0; a < NU; ++a) {
+          const float u = m.f(F::U + a, t);
+          m.f(F::U + a, t) = fmaf(al, m.f(F::UE + a, t) - u, u);
+        }
+#pragma unroll
+        for (int r = 0; r < NX; ++r) {
+          const float x = m.f(F::X + r, t + 1);
+          m.f(F::X + r, t + 1) = fmaf(al, m.f(F::XE + r, t + 1) - x, x);
+        }
+      }
+      const int bt = si.blk / NU, ba = si.blk % NU;
+      m.f(F::U + ba, bt) = (si.side == 1) ? pb.ulo[ba] : pb.uhi[ba];
+      m.w(ba, bt) = (int8_t)si.side;
+      td = max(td, bt);
+      continue;
+    }
+    // full step: the EQP solution becomes the iterate
+    for (int t = 0; t < T; ++t) {
+#pragma unroll
+      for (int a = 0; a < NU; ++a) m.f(F::U + a, t) = m.f(F::UE + a, t);
+#pragma unroll
+      for (int r = 0; r < NX; ++r) m.f(F::X + r, t + 1) = m.f(F::XE + r, t + 1);
+    }
+    if (si.drop >= 0 && si.mu_min < -pb.mu_tol) {
+      const int dt = si.drop / NU, da = si.drop % NU;
+      m.w(da, dt) = 0;
+      td = max(td, dt);
+      continue;
+    }
+    done = 1;
+    break;
+  }
+  ws.adirty[sc.ao + i] = td;
+  return done ? 0 : 1;
+}
+
+// ===========================================================================
+// Consensus (Eq. 4) + dual update (Eq. 5) for agent i at step t, all partners
+// ===========================================================================
+// Canonical pair (f < s) with positions pf, ps and lambda_fs (lambda_sf =
+// -lambda_fs): a = pf + lambda_fs/rho, b = ps - lambda_fs/rho,
+// v = d_min - n'(a - b); the projection onto {n'(a-b) >= d_min} moves a and b
+// by +-(v+/2) n, and Eq. 5 then gives lambda_fs <- -(rho/2) max(v, 0) n, which
+// is evaluated in this closed form (no cancellation); the copies follow from
+// Eq. 5 as z_f = pf + (lambda_fs - lambda_fs_new)/rho, z_s = ps - (same).
+template <int NX, int NU>
+__device__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, int i, int t) {
+  using F = Fld<NX, NU>;
+  const int N = sc.N, T = sc.T, GS = sc.GS;
+  float *R = ws.fr + sc.fo;
+  const int gi = t * N + i;
+  float pi[NU];
+  bool bad = false;
+#pragma unroll
+  for (int c = 0; c < NU; ++c) pi[c] = R[(F::X + c) * GS + gi];
+#pragma unroll
+  for (int c = 0; c < NX; ++c) bad |= !isfinite(R[(F::X + c) * GS + gi]);
+  float *lam = ws.lam + sc.lo;
+  uint8_t *pa = ws.pact + sc.lb;
+  const int LS = T * N * N;
+  const float rho = pb.rho, irho = 1.0f / pb.rho;
+  float es[NU], zd[NU], ls[NU];   // sum (lam_old - 2 lam_new), sum (z - C x), sum lam_new
+#pragma unroll
+  for (int c = 0; c < NU; ++c) { es[c] = 0.f; zd[c] = 0.f; ls[c] = 0.f; }
+  float r2 = 0.f, z2 = 0.f;
+  for (int j = 0; j < N; ++j) {
+    if (j == i) continue;
+    const bool first = i < j;
+    const int f = first ? i : j, s = first ? j : i;
+    float pj[NU], pf[NU], ps[NU];
+#pragma unroll
+    for (int c = 0; c < NU; ++c) {
+      pj[c] = R[(F::X + c) * GS + t * N + j];
+      pf[c] = first ? pi[c] : pj[c];
+      ps[c] = first ? pj[c] : pi[c];
+    }
+    float n[NU];
+    if (pb.normal_mode == NORMAL_FROZEN) {
+      if (ws.normals) {
+        const int pidx = f * N - f * (f + 1) / 2 + (s - f - 1);
+        const float *nv = ws.normals + (sc.po + (long long)pidx * T + (t - 1)) * NU;
+#pragma unroll
+        for (int c = 0; c < NU; ++c) n[c] = nv[c];
+      } else {
+        reference_normal<NX, NU>(ws, sc, f, s, t, n);
+      }
+    } else {
+      float d[NU], dd = 0.f;
+#pragma unroll
+      for (int c = 0; c < NU; ++c) { d[c] = pf[c] - ps[c]; dd = fmaf(d[c], d[c], dd); }
+      dd = sqrtf(dd);
+      if (dd >= 1e-6f) {
+#pragma unroll
+        for (int c = 0; c < NU; ++c) n[c] = d[c] / dd;
+      } else {
+        reference_normal<NX, NU>(ws, sc, f, s, t, n);
+      }
+    }
+    const int li = ((t - 1) * N + j) * N + i;  // this lane's ordered copy (i, j)
+    float lown[NU], lfs[NU];
+#pragma unroll
+    for (int c = 0; c < NU; ++c) {
+      lown[c] = lam[c * LS + li];
+      lfs[c] = first ? lown[c] : -lown[c];
+    }
+    float g = 0.f;
+#pragma unroll
+    for (int c = 0; c < NU; ++c) {
+      const float ab = (pf[c] - ps[c]) + 2.0f * irho * lfs[c];  // a - b
+      g = fmaf(n[c], ab, g);
+    }
+    const float v = pb.dmin - g;
+    const float gam = 0.5f * rho * fmaxf(v, 0.f);
+    float lnew_own[NU];
+#pragma unroll
+    for (int c = 0; c < NU; ++c) {
+      const float lnew = -gam * n[c];                 // lambda_fs after Eq. 5
+      const float dl = (lfs[c] - lnew) * irho;       // z_f - pf = -(z_s - ps)
+      const float sdl = first ? dl : -dl;            // z_own - C x_i
+      const float zo = pi[c] + sdl;
+      lnew_own[c] = first ? lnew : -lnew;
+      es[c] += lown[c] - 2.0f * lnew_own[c];         // rho z_own - lam_new - rho C x_i
+      zd[c] += sdl;
+      ls[c] += lnew_own[c];
+      r2 = fmaf(dl, dl, r2);
+      z2 = fmaf(zo, zo, z2);
+      lam[c * LS + li] = lnew_own[c];
+    }
+    if (first) pa[li] = (uint8_t)(v > 0.f);
+  }
+  float s2 = 0.f, ax2 = 0.f, aty2 = 0.f;
+  const float nn = (float)(N - 1);
+#pragma unroll
+  for (int c = 0; c < NU; ++c) {
+    // rho sum_j (z_ij^(k+1) - z_ij^k) = rho (n_nbr (C x^(k+1) - C x^k) + ZD^(k+1) - ZD^k)
+    const float ds = rho * fmaf(nn, pi[c] - R[(F::XP + c) * GS + gi], zd[c] - R[(F::ZD + c) * GS + gi]);
+    s2 = fmaf(ds, ds, s2);
+    ax2 = fmaf(pi[c], pi[c], ax2);
+    aty2 = fmaf(ls[c], ls[c], aty2);
+    R[(F::QP + c) * GS + gi] = fmaf(-rho * nn, pi[c], R[(F::GQ + c) * GS + gi]) - es[c];
+    R[(F::XP + c) * GS + gi] = pi[c];
+    R[(F::ZD + c) * GS + gi] = zd[c];
+  }
+  ax2 *= nn;
+  if (bad) r2 = NAN;
+  R[(F::RED + 0) * GS + gi] = r2;
+  R[(F::RED + 1) * GS + gi] = s2;
+  R[(F::RED + 2) * GS + gi] = ax2;
+  R[(F::RED + 3) * GS + gi] = z2;
+  R[(F::RED + 4) * GS + gi] = aty2;
+}
+
+// Residual norms and the stopping test of Sec. V-A (Boyd et al. 2011, Sec.
+// 3.3.1): p = 2 P T dp consensus rows, n = N T dp position variables.
+// Executed by one full wavefront; the sum over agent-stages has a fixed order
+// (lane l takes stages l, l+64, ...; then a fixed butterfly).
+template <int NX, int NU>
+__device__ int scenario_test(const Prob &pb, const WS &ws, const Scen &sc, int k, int lane, int cap_hit) {
+  using F = Fld<NX, NU>;
+  const float *R = ws.fr + sc.fo;
+  const int GS = sc.GS, NT = sc.N * sc.T;
+  float a[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int idx = lane; idx < NT; idx += 64) {
+    const int g = sc.N + idx;  // stages 1..T
+#pragma unroll
+    for (int q = 0; q < 5; ++q) a[q] += R[(F::RED + q) * GS + g];
+  }
+#pragma unroll
+  for (int q = 0; q < 5; ++q) a[q] = wave_sum(a[q]);
+  int done = 0;
+  if (lane == 0) {
+    const float P = 0.5f * (float)sc.N * (float)(sc.N - 1);
+    const float rn = sqrtf(a[0]), sn = sqrtf(a[1]);
+    const float epri = sqrtf(2.0f * P * (float)sc.T * (float)NU) * pb.eps_abs +
+                       pb.eps_rel * fmaxf(sqrtf(a[2]), sqrtf(a[3]));
+    const float edual = sqrtf((float)sc.N * (float)sc.T * (float)NU) * pb.eps_abs + pb.eps_rel * sqrtf(a[4]);
+    int *st = ws.sst + (long long)sc.s * ST_NCOL;
+    float *sn_out = ws.snorm + (long long)sc.s * SN_NCOL;
+    int status = SCEN_MAX_ITER;
+    if (cap_hit) { status = SCEN_CAP; done = 1; }
+    else if (!isfinite(rn) || !isfinite(sn)) { status = SCEN_NONFINITE; done = 1; }
+    else if (rn <= epri && sn <= edual) { status = SCEN_CONVERGED; done = 1; }
+    else if (k >= pb.max_iter) { done = 1; }
+    if (!cap_hit) {
+      sn_out[SN_R] = rn; sn_out[SN_S] = sn; sn_out[SN_EPRI] = epri; sn_out[SN_EDUAL] = edual;
+    }
+    st[ST_STATUS] = status;
+    st[ST_ITERS] = k;
+    st[ST_DONE] = done;
+  }
+  return __shfl(done, 0, 64);
+}
+
+// Per-scenario initial state: z^(0) = C r, lambda^(0) = 0 (the position
+// linear term starts at -2 Q r - rho n_nbr C r), P_T = H_T, empty working
+// sets, every factor stale.
+template <int NX, int NU>
+__device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int tid, int nthreads) {
+  using F = Fld<NX, NU>;
+  const int N = sc.N, T = sc.T, GS = sc.GS;
+  float *R = ws.fr + sc.fo;
+  int8_t *Wb = ws.wr + sc.bo;
+  const float *qd = ws.qd + (long long)sc.s * NX;
+  const int n_nbr = N - 1;
+  for (int idx = tid; idx < GS; idx += nthreads) {
+    const int t = idx / N, i = idx % N;
+    const float *r = ws.xref + (sc.xo + (long long)i * (T + 1) + t) * NX;
+    const float w = (t == T) ? pb.qT : 1.0f;
+    float gq[NX];
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      gq[c] = (t >= 1) ? -2.0f * w * qd[c] * r[c] : 0.f;
+      R[(F::GQ + c) * GS + idx] = gq[c];
+    }
+#pragma unroll
+    for (int c = 0; c < NU; ++c) {
+      // x^0 := r so that z^0 = C r, lambda^0 = 0
+      R[(F::QP + c) * GS + idx] = fmaf(-pb.rho * (float)n_nbr, r[c], gq[c]);
+      R[(F::XP + c) * GS + idx] = r[c];
+      R[(F::ZD + c) * GS + idx] = 0.f;
+      R[(F::U + c) * GS + idx] = 0.f;
+      Wb[c * GS + idx] = 0;
+    }
+    if (t == 0) {
+      const float *x0 = ws.x0 + (sc.ao + i) * NX;
+#pragma unroll
+      for (int c = 0; c < NX; ++c) { R[(F::X + c) * GS + idx] = x0[c]; R[(F::XE + c) * GS + idx] = x0[c]; }
+      ws.adirty[sc.ao + i] = T - 1;
+    }
+    if (t == T) {
+      float hx[NX];
+      stage_hx<NX, NU>(pb, qd, T, T, n_nbr, hx);
+#pragma unroll
+      for (int r2 = 0; r2 < NX; ++r2)
+#pragma unroll
+        for (int c = 0; c < NX; ++c) R[(F::P + r2 * NX + c) * GS + idx] = (r2 == c) ? hx[r2] : 0.f;
+    }
+  }
+  const int LS = T * N * N;
+  float *lam = ws.lam + sc.lo;
+  uint8_t *pa = ws.pact + sc.lb;
+  for (int idx = tid; idx < LS; idx += nthreads) {
+#pragma unroll
+    for (int c = 0; c < NU; ++c) lam[c * LS + idx] = 0.f;
+    pa[idx] = 0;
+  }
+  if (tid == 0) {
+    int *st = ws.sst + (long long)sc.s * ST_NCOL;
+    st[ST_STATUS] = SCEN_MAX_ITER;
+    st[ST_ITERS] = 0;
+    st[ST_CAP] = 0;
+    st[ST_DONE] = 0;
+    float *sn = ws.snorm + (long long)sc.s * SN_NCOL;
+    sn[SN_R] = sn[SN_S] = sn[SN_EPRI] = sn[SN_EDUAL] = 0.f;
+  }
+}
+
+__device__ __forceinline__ void add_counters(const WS &ws, int s, const long long c[CT_NCOL]) {
+#pragma unroll
+  for (int q = 0; q < CT_NCOL; ++q)
+    if (c[q]) atomicAdd(ws.cnt + (long long)s * CT_NCOL + q, (unsigned long long)c[q]);
+}
+
+// ===========================================================================
+// Kernels: plain path (one scenario, host loop)
+// ===========================================================================
+template <int NX, int NU>
+__global__ __launch_bounds__(256) void k_setup(Prob pb, WS ws, int s) {
+  const Scen sc = load_scen(ws, s);
+  scenario_setup<NX, NU>(pb, ws, sc, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+  if (blockIdx.x == 0 && threadIdx.x < CT_NCOL) ws.cnt[(long long)s * CT_NCOL + threadIdx.x] = 0ull;
+}
+
+template <int NX, int NU>
+__global__ __launch_bounds__(64) void k_xupdate(Prob pb, WS ws, int s, int k) {
+  const Scen sc = load_scen(ws, s);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= sc.N) return;
+  long long cnt[CT_NCOL] = {0, 0, 0, 0};
+  const int capped = agent_xupdate<NX, NU>(pb, ws, sc, i, k, cnt);
+  if (capped) atomicOr(ws.sst + (long long)s * ST_NCOL + ST_CAP, 1);
+  add_counters(ws, s, cnt);
+}
+
+template <int NX, int NU>
+__global__ __launch_bounds__(256) void k_pair(Prob pb, WS ws, int s) {
+  const Scen sc = load_scen(ws, s);
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= sc.N * sc.T) return;
+  pair_agent_stage<NX, NU>(pb, ws, sc, idx % sc.N, idx / sc.N + 1);
+  if (idx == 0) {
+    long long c[CT_NCOL] = {0, 0, 0, (long long)sc.N * (sc.N - 1) / 2 * sc.T};
+    add_counters(ws, s, c);
+  }
+}
+
+template <int NX, int NU>
+__global__ __launch_bounds__(64) void k_resid(Prob pb, WS ws, int s, int k, int *done_out) {
+  const Scen sc = load_scen(ws, s);
+  const int cap = ws.sst[(long long)s * ST_NCOL + ST_CAP];
+  const int done = scenario_test<NX, NU>(pb, ws, sc, k, threadIdx.x, cap);
+  if (threadIdx.x == 0) *done_out = done;
+}
+
+// ===========================================================================
+// Kernel: batched persistent solve
+// ===========================================================================
+// Workgroups take scenarios from an atomic counter in the host-given order
+// (largest estimated work first) and iterate ADMM on chip until the
+// scenario's own stopping test passes; the three phases are separated by
+// workgroup barriers.  Every wave reaches the queue read, so the grid drains
+// once the counter passes S.
+template <int NX, int NU>
+__global__ __launch_bounds__(1024) void k_admm_persistent(Prob pb, WS ws, int S) {
+  __shared__ int s_item;
+  __shared__ int s_cap;
+  __shared__ int s_done;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (;;) {
+    if (tid == 0) s_item = atomicAdd(ws.queue, 1);
+    __syncthreads();
+    const int item = s_item;
+    __syncthreads();
+    if (item >= S) return;
+    const int s = ws.order[item];
+    const Scen sc = load_scen(ws, s);
+    scenario_setup<NX, NU>(pb, ws, sc, tid, nt);
+    if (tid == 0) { s_cap = 0; s_done = 0; }
+    long long cnt[CT_NCOL] = {0, 0, 0, 0};
+    __syncthreads();
+    for (int k = 1; k <= pb.max_iter; ++k) {
+      for (int i = tid; i < sc.N; i += nt)
+        if (agent_xupdate<NX, NU>(pb, ws, sc, i, k, cnt)) atomicOr(&s_cap, 1);
+      __syncthreads();
+      const int cap = s_cap;
+      if (!cap) {
+        for (int idx = tid; idx < sc.N * sc.T; idx += nt) pair_agent_stage<NX, NU>(pb, ws, sc, idx % sc.N, idx / sc.N + 1);
+        if (tid == 0) cnt[CT_PAIRS] += (long long)sc.N * (sc.N - 1) / 2 * sc.T;
+      }
+      __syncthreads();
+      if (tid < 64) {
+        const int d = scenario_test<NX, NU>(pb, ws, sc, k, tid, cap);
+        if (tid == 0) s_done = d;
+      }
+      __syncthreads();
+      if (s_done) break;
+    }
+    add_counters(ws, s, cnt);
+    __syncthreads();
+  }
+}
+
+__global__ void k_fill_i32(int *p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_u64(unsigned long long *p, long long n) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+// ===========================================================================
+// Input checks and output write-back
+// ===========================================================================
+template <int NX, int NU>
+__global__ void k_check(Prob pb, WS ws, int S, int *flags) {
+  for (int s = blockIdx.x; s < S; s += gridDim.x) {
+    const Scen sc = load_scen(ws, s);
+    const int N = sc.N, T = sc.T;
+    int bad = 0, close = 0;
+    for (int e = threadIdx.x; e < N * NX; e += blockDim.x) bad |= !isfinite(ws.x0[sc.ao * NX + e]);
+    for (long long e = threadIdx.x; e < (long long)N * (T + 1) * NX; e += blockDim.x) bad |= !isfinite(ws.xref[sc.xo * NX + e]);
+    if (threadIdx.x < NX) { const float q = ws.qd[(long long)s * NX + threadIdx.x]; bad |= !(isfinite(q) && q > 0.f); }
+    if (threadIdx.x < NU) { const float r = ws.rd[(long long)s * NU + threadIdx.x]; bad |= !(isfinite(r) && r > 0.f); }
+    if (ws.normals && pb.normal_mode == NORMAL_FROZEN)
+      for (long long e = threadIdx.x; e < (long long)N * (N - 1) / 2 * T * NU; e += blockDim.x)
+        bad |= !isfinite(ws.normals[sc.po * NU + e]);
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+      const int i = e / N, j = e % N;
+      if (j <= i) continue;
+      float d2 = 0.f;
+#pragma unroll
+      for (int c = 0; c < NU; ++c) {
+        const float d = ws.x0[(sc.ao + i) * NX + c] - ws.x0[(sc.ao + j) * NX + c];
+        d2 = fmaf(d, d, d2);
+      }
+      close |= (sqrtf(d2) < pb.dmin);
+    }
+    if (bad) atomicOr(flags + 0, 1);
+    if (close) atomicOr(flags + 1, 1);
+  }
+}
+
+template <int NX, int NU>
+__global__ void k_writeback(WS ws, int S, tadmm_out out) {
+  using F = Fld<NX, NU>;
+  for (int s = blockIdx.x; s < S; s += gridDim.x) {
+    const Scen sc = load_scen(ws, s);
+    const int N = sc.N, T = sc.T, GS = sc.GS;
+    const float *R = ws.fr + sc.fo;
+    const int8_t *Wb = ws.wr + sc.bo;
+    if (out.x)
+      for (int e = threadIdx.x; e < N * (T + 1) * NX; e += blockDim.x) {
+        const int c = e % NX, it = e / NX, t = it % (T + 1), i = it / (T + 1);
+        out.x[sc.xo * NX + e] = R[(F::X + c) * GS + t * N + i];
+      }
+    if (out.u || out.w)
+      for (int e = threadIdx.x; e < N * T * NU; e += blockDim.x) {
+        const int c = e % NU, it = e / NU, t = it % T, i = it / T;
+        if (out.u) out.u[sc.uo * NU + e] = R[(F::U + c) * GS + t * N + i];
+        if (out.w) out.w[sc.uo * NU + e] = Wb[c * GS + t * N + i];
+      }
+    if (out.pair_active)
+      for (int e = threadIdx.x; e < N * N * T; e += blockDim.x) {
+        const int i = e % N, j = (e / N) % N, t = e / (N * N) + 1;
+        if (j <= i) continue;
+        const int p = i * N - i * (i + 1) / 2 + (j - i - 1);
+        out.pair_active[sc.po + (long long)p * T + (t - 1)] = ws.pact[sc.lb + e];
+      }
+    if (threadIdx.x == 0) {
+      const int *st = ws.sst + (long long)s * ST_NCOL;
+      const float *sn = ws.snorm + (long long)s * SN_NCOL;
+      if (out.status) out.status[s] = st[ST_STATUS];
+      if (out.iters) out.iters[s] = st[ST_ITERS];
+      if (out.r_norm) out.r_norm[s] = sn[SN_R];
+      if (out.s_norm) out.s_norm[s] = sn[SN_S];
+      if (out.eps_pri) out.eps_pri[s] = sn[SN_EPRI];
+      if (out.eps_dual) out.eps_dual[s] = sn[SN_EDUAL];
+    }
+    if (out.counters && threadIdx.x < CT_NCOL)
+      out.counters[(long long)s * CT_NCOL + threadIdx.x] = (int64_t)ws.cnt[(long long)s * CT_NCOL + threadIdx.x];
+  }
+}
+
+}  // namespace tadmm
+
+// ===========================================================================
+// Host library
+// ===========================================================================
+namespace {
+
+using namespace tadmm;
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  int S = 0, nx = 0, nu = 0, NF = 0;
+  long long A = 0, sumGS = 0, sumL = 0;
+  size_t o_N = 0, o_T = 0, o_tab = 0, o_order = 0, o_queue = 0, o_sst = 0, o_snorm = 0, o_cnt = 0, o_flags = 0;
+  size_t o_adirty = 0, o_fr = 0, o_wr = 0, o_lam = 0, o_pact = 0, bytes = 0;
+  std::vector<long long> tab;
+  std::vector<int> order;
+};
+
+int fields_per_stage(int nx, int nu) {
+  return (nx == 4) ? Fld<4, 2>::NF : Fld<6, 3>::NF;
+  (void)nu;
+}
+
+const char *kStatusStr[] = {"ok", "invalid argument", "shape error", "non-finite input", "infeasible start",
+                            "HIP runtime error", "workspace error", "state error"};
+
+bool params_ok(const tadmm_params *p, std::string &err) {
+  if (!p) { err = "params is NULL"; return false; }
+  if (!((p->nx == 4 && p->nu == 2) || (p->nx == 6 && p->nu == 3))) { err = "nx/nu must be 4/2 or 6/3"; return false; }
+  for (int k = 0; k < p->nx * p->nx; ++k) if (!std::isfinite(p->A[k])) { err = "A not finite"; return false; }
+  for (int k = 0; k < p->nx * p->nu; ++k) if (!std::isfinite(p->B[k])) { err = "B not finite"; return false; }
+  for (int c = 0; c < p->nu; ++c)
+    if (!(std::isfinite(p->u_lo[c]) && std::isfinite(p->u_hi[c]) && p->u_lo[c] < p->u_hi[c])) {
+      err = "need finite u_lo < u_hi"; return false;
+    }
+  if (!(std::isfinite(p->rho) && p->rho > 0.f)) { err = "rho must be > 0"; return false; }
+  if (!(std::isfinite(p->qT_scale) && p->qT_scale > 0.f)) { err = "qT_scale must be > 0"; return false; }
+  if (!(std::isfinite(p->d_min) && p->d_min >= 0.f)) { err = "d_min must be >= 0"; return false; }
+  if (!(std::isfinite(p->eps_abs) && p->eps_abs >= 0.f && std::isfinite(p->eps_rel) && p->eps_rel >= 0.f)) {
+    err = "eps_abs/eps_rel must be >= 0"; return false;
+  }
+  if (!(std::isfinite(p->mu_tol) && p->mu_tol >= 0.f)) { err = "mu_tol must be >= 0"; return false; }
+  if (p->max_iter < 1) { err = "max_iter must be >= 1"; return false; }
+  if (p->normal_mode != TADMM_NORMAL_PER_ITER && p->normal_mode != TADMM_NORMAL_FROZEN) {
+    err = "unknown normal_mode"; return false;
+  }
+  if (p->block_threads != 0 && (p->block_threads < 64 || p->block_threads > 1024 || p->block_threads % 64 != 0)) {
+    err = "block_threads must be 0 or a multiple of 64 in [64, 1024]"; return false;
+  }
+  return true;
+}
+
+bool make_layout(const tadmm_params *p, int S, const int32_t *N, const int32_t *T, Layout &L, std::string &err) {
+  if (S < 0) { err = "n_scen < 0"; return false; }
+  if (S > 0 && (!N || !T)) { err = "n_agents / horizon are NULL"; return false; }
+  L = Layout();
+  L.S = S; L.nx = p->nx; L.nu = p->nu; L.NF = fields_per_stage(p->nx, p->nu);
+  L.tab.assign((size_t)S * TB_NCOL, 0);
+  long long fo = 0, bo = 0, lo = 0, ao = 0, xo = 0, uo = 0, po = 0, lb = 0;
+  for (int s = 0; s < S; ++s) {
+    const long long n = N[s], t = T[s];
+    if (n < 1 || t < 1) { err = "every scenario needs N >= 1 and T >= 1"; return false; }
+    if (n > 4096 || t > 65536) { err = "scenario too large (N <= 4096, T <= 65536)"; return false; }
+    const long long GS = n * (t + 1);
+    if ((long long)L.NF * GS >= (1ll << 31) || (long long)p->nu * t * n * n >= (1ll << 31)) {
+      err = "scenario too large for 32-bit in-scenario offsets"; return false;
+    }
+    long long *tb = &L.tab[(size_t)s * TB_NCOL];
+    tb[TB_F] = fo; tb[TB_B] = bo; tb[TB_L] = lo; tb[TB_A] = ao; tb[TB_XO] = xo; tb[TB_UO] = uo; tb[TB_PO] = po; tb[TB_LB] = lb;
+    fo += (long long)L.NF * GS;
+    bo += (long long)p->nu * GS;
+    lo += (long long)p->nu * t * n * n;
+    lb += t * n * n;
+    ao += n;
+    xo += GS;
+    uo += n * t;
+    po += n * (n - 1) / 2 * t;
+  }
+  L.A = ao; L.sumGS = xo; L.sumL = lb;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { const size_t o = off; off = align_up(off + std::max<size_t>(bytes, 1)); return o; };
+  L.o_N = take(sizeof(int) * S);
+  L.o_T = take(sizeof(int) * S);
+  L.o_tab = take(sizeof(long long) * S * TB_NCOL);
+  L.o_order = take(sizeof(int) * S);
+  L.o_queue = take(sizeof(int) * 64);
+  L.o_sst = take(sizeof(int) * S * ST_NCOL);
+  L.o_snorm = take(sizeof(float) * S * SN_NCOL);
+  L.o_cnt = take(sizeof(unsigned long long) * S * CT_NCOL);
+  L.o_flags = take(sizeof(int) * 64);
+  L.o_adirty = take(sizeof(int) * (size_t)ao);
+  L.o_fr = take(sizeof(float) * (size_t)fo);
+  L.o_wr = take((size_t)bo);
+  L.o_lam = take(sizeof(float) * (size_t)lo);
+  L.o_pact = take((size_t)lb);
+  L.bytes = off;
+  // launch order for the persistent queue: largest N^2 T first (LPT)
+  L.order.resize(S);
+  std::iota(L.order.begin(), L.order.end(), 0);
+  std::stable_sort(L.order.begin(), L.order.end(), [&](int a, int b) {
+    return (long long)N[a] * N[a] * T[a] > (long long)N[b] * N[b] * T[b];
+  });
+  return true;
+}
+
+Prob to_prob(const tadmm_params &p) {
+  Prob pb;
+  std::memset(&pb, 0, sizeof(pb));
+  std::memcpy(pb.A, p.A, sizeof(pb.A));
+  std::memcpy(pb.B, p.B, sizeof(pb.B));
+  for (int c = 0; c < 3; ++c) { pb.ulo[c] = p.u_lo[c]; pb.uhi[c] = p.u_hi[c]; }
+  pb.qT = p.qT_scale; pb.dmin = p.d_min; pb.rho = p.rho; pb.eps_abs = p.eps_abs; pb.eps_rel = p.eps_rel;
+  pb.mu_tol = p.mu_tol; pb.max_iter = p.max_iter; pb.max_as = p.max_as_iter; pb.normal_mode = p.normal_mode;
+  pb.cache = p.cache_factors ? 1 : 0; pb.warm = p.riccati_warmstart ? 1 : 0; pb.hot = p.hotstart ? 1 : 0;
+  return pb;
+}
+
+struct GraphKey {
+  const void *ws = nullptr;
+  tadmm_out out{};
+  const float *x0 = nullptr, *xref = nullptr, *qd = nullptr, *rd = nullptr, *normals = nullptr;
+  int S = 0, threads = 0, grid = 0;
+  size_t bytes = 0;
+  tadmm_params prm{};
+  bool operator==(const GraphKey &o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
+};
+
+}  // namespace
+
+struct tadmm_ctx {
+  tadmm_params prm{};
+  hipStream_t stream = nullptr;      // caller's stream: every launch is ordered on it
+  hipStream_t cap_stream = nullptr;  // private stream used only to capture the graph
+  int device = 0, n_cu = 256;
+  std::string err;
+  int tuned_threads = 256;
+  void *h_stage = nullptr;
+  size_t h_stage_bytes = 0;
+  int *h_flags = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  GraphKey key{};
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  float last_ms = -1.f;
+  // adjoint bookkeeping: the last successful solve
+  bool solved = false;
+  const void *solved_ws = nullptr;
+  std::vector<int> solved_N, solved_T;
+};
+
+#define HIPCHK(expr)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      ctx->err = std::string(#expr) + " failed: " + hipGetErrorString(e_);      \
+      return TADMM_ERR_HIP;                                                       \
+    }                                                                             \
+  } while (0)
+
+namespace {
+
+tadmm_status fail(tadmm_ctx *ctx, tadmm_status s, const std::string &msg) {
+  if (ctx) ctx->err = msg;
+  return s;
+}
+
+tadmm_status stage_tables(tadmm_ctx *ctx, const Layout &L, const int32_t *N, const int32_t *T, char *ws) {
+  const size_t need = L.o_order + sizeof(int) * std::max(L.S, 1);
+  if (ctx->h_stage_bytes < need) {
+    if (ctx->h_stage) HIPCHK(hipHostFree(ctx->h_stage));
+    ctx->h_stage = nullptr;
+    HIPCHK(hipHostMalloc(&ctx->h_stage, need, hipHostMallocDefault));
+    ctx->h_stage_bytes = need;
+  }
+  char *h = (char *)ctx->h_stage;
+  std::memcpy(h + L.o_N, N, sizeof(int) * L.S);
+  std::memcpy(h + L.o_T, T, sizeof(int) * L.S);
+  std::memcpy(h + L.o_tab, L.tab.data(), sizeof(long long) * L.S * TB_NCOL);
+  std::memcpy(h + L.o_order, L.order.data(), sizeof(int) * L.S);
+  HIPCHK(hipMemcpyAsync(ws, h, need, hipMemcpyHostToDevice, ctx->stream));
+  return TADMM_OK;
+}
+
+WS make_ws(const Layout &L, char *ws, const tadmm_batch *b) {
+  WS w;
+  w.N = (const int *)(ws + L.o_N);
+  w.T = (const int *)(ws + L.o_T);
+  w.tab = (const long long *)(ws + L.o_tab);
+  w.order = (const int *)(ws + L.o_order);
+  w.queue = (int *)(ws + L.o_queue);
+  w.fr = (float *)(ws + L.o_fr);
+  w.wr = (int8_t *)(ws + L.o_wr);
+  w.adirty = (int *)(ws + L.o_adirty);
+  w.lam = (float *)(ws + L.o_lam);
+  w.pact = (uint8_t *)(ws + L.o_pact);
+  w.sst = (int *)(ws + L.o_sst);
+  w.snorm = (float *)(ws + L.o_snorm);
+  w.cnt = (unsigned long long *)(ws + L.o_cnt);
+  w.x0 = b->x0; w.xref = b->xref; w.qd = b->q_diag; w.rd = b->r_diag;
+  w.normals = (b->normals && true) ? b->normals : nullptr;
+  return w;
+}
+
+template <int NX, int NU>
+tadmm_status run_checks(tadmm_ctx *ctx, const Prob &pb, const WS &w, int S, int *d_flags) {
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, ctx->stream, d_flags, 64, 0);
+  hipLaunchKernelGGL((k_check<NX, NU>), dim3(std::min(S, 4096)), dim3(256), 0, ctx->stream, pb, w, S, d_flags);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(ctx->h_flags, d_flags, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (ctx->h_flags[0]) return fail(ctx, TADMM_ERR_NONFINITE, "non-finite input or non-positive weight");
+  if (ctx->h_flags[1]) return fail(ctx, TADMM_ERR_INFEASIBLE_START, "two agents start closer than d_min");
+  return TADMM_OK;
+}
+
+template <int NX, int NU>
+tadmm_status run_plain(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layout &L, const int32_t *N,
+                       const int32_t *T, int *d_flags, const tadmm_out &out) {
+  HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
+  for (int s = 0; s < L.S; ++s) {
+    const int n = N[s], t = T[s];
+    const long long work = std::max<long long>((long long)n * (t + 1), (long long)t * n * n);
+    const int gsetup = (int)std::min<long long>((work + 255) / 256, 4096);
+    hipLaunchKernelGGL((k_setup<NX, NU>), dim3(gsetup), dim3(256), 0, ctx->stream, pb, w, s);
+    for (int k = 1; k <= pb.max_iter; ++k) {
+      hipLaunchKernelGGL((k_xupdate<NX, NU>), dim3((n + 63) / 64), dim3(64), 0, ctx->stream, pb, w, s, k);
+      hipLaunchKernelGGL((k_pair<NX, NU>), dim3((n * t + 255) / 256), dim3(256), 0, ctx->stream, pb, w, s);
+      hipLaunchKernelGGL((k_resid<NX, NU>), dim3(1), dim3(64), 0, ctx->stream, pb, w, s, k, d_flags + 2);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(ctx->h_flags + 2, d_flags + 2, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      if (ctx->h_flags[2]) break;
+    }
+  }
+  hipLaunchKernelGGL((k_writeback<NX, NU>), dim3(std::min(L.S, 4096)), dim3(256), 0, ctx->stream, w, L.S, out);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventRecord(ctx->ev1, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  HIPCHK(hipEventElapsedTime(&ctx->last_ms, ctx->ev0, ctx->ev1));
+  return TADMM_OK;
+}
+
+template <int NX, int NU>
+tadmm_status run_batched(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layout &L, const tadmm_batch *b,
+                         const tadmm_out &out, void *ws, size_t bytes) {
+  const int threads = ctx->prm.block_threads ? ctx->prm.block_threads : ctx->tuned_threads;
+  int per_cu = 0;
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_admm_persistent<NX, NU>, threads, 0));
+  if (per_cu < 1) return fail(ctx, TADMM_ERR_HIP, "persistent kernel does not fit on a compute unit");
+  const int grid = std::max(1, std::min(L.S, per_cu * ctx->n_cu));
+  GraphKey key;
+  std::memset(&key, 0, sizeof(key));
+  key.ws = ws; key.out = out; key.x0 = b->x0; key.xref = b->xref; key.qd = b->q_diag; key.rd = b->r_diag;
+  key.normals = b->normals; key.S = L.S; key.threads = threads; key.grid = grid; key.bytes = bytes; key.prm = ctx->prm;
+  if (!(ctx->gexec && key == ctx->key)) {
+    if (ctx->gexec) { (void)hipGraphExecDestroy(ctx->gexec); ctx->gexec = nullptr; }
+    if (ctx->graph) { (void)hipGraphDestroy(ctx->graph); ctx->graph = nullptr; }
+    // Captured on the context's private stream (the caller's stream may be the
+    // legacy default stream, which cannot be captured); launched on the
+    // caller's stream below.
+    hipStream_t cs = ctx->cap_stream;
+    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    // counters and the queue are cleared by fill kernels (no memset nodes)
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, cs, w.queue, 1, 0);
+    const long long nc = (long long)L.S * CT_NCOL;
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, cs, w.cnt, nc);
+    hipLaunchKernelGGL((k_admm_persistent<NX, NU>), dim3(grid), dim3(threads), 0, cs, pb, w, L.S);
+    hipLaunchKernelGGL((k_writeback<NX, NU>), dim3(std::min(L.S, 4096)), dim3(256), 0, cs, w, L.S, out);
+    hipError_t le = hipGetLastError();
+    hipError_t ce = hipStreamEndCapture(cs, &ctx->graph);
+    if (le != hipSuccess || ce != hipSuccess) {
+      ctx->err = std::string("graph capture failed: ") + hipGetErrorString(le != hipSuccess ? le : ce);
+      return TADMM_ERR_HIP;
+    }
+    HIPCHK(hipGraphInstantiate(&ctx->gexec, ctx->graph, nullptr, nullptr, 0));
+    ctx->key = key;
+  }
+  HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
+  HIPCHK(hipGraphLaunch(ctx->gexec, ctx->stream));
+  HIPCHK(hipEventRecord(ctx->ev1, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  HIPCHK(hipEventElapsedTime(&ctx->last_ms, ctx->ev0, ctx->ev1));
+  return TADMM_OK;
+}
+
+template <int NX, int NU>
+tadmm_status solve_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *out, void *ws, size_t bytes, int mode) {
+  Layout L;
+  if (!make_layout(&ctx->prm, b->n_scen, b->n_agents, b->horizon, L, ctx->err)) return TADMM_ERR_SHAPE;
+  if (!ws || bytes < L.bytes) return fail(ctx, TADMM_ERR_WORKSPACE, "workspace missing or smaller than tadmm_workspace_size()");
+  if (((uintptr_t)ws) % kAlign) return fail(ctx, TADMM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  ctx->solved = false;
+  if (L.S == 0) return TADMM_OK;
+  if (!b->x0 || !b->xref || !b->q_diag || !b->r_diag) return fail(ctx, TADMM_ERR_INVALID_ARG, "batch input pointer is NULL");
+  if (!out->status || !out->iters) return fail(ctx, TADMM_ERR_INVALID_ARG, "out.status and out.iters are required");
+  char *w8 = (char *)ws;
+  tadmm_status st = stage_tables(ctx, L, b->n_agents, b->horizon, w8);
+  if (st != TADMM_OK) return st;
+  const Prob pb = to_prob(ctx->prm);
+  const WS w = make_ws(L, w8, b);
+  int *d_flags = (int *)(w8 + L.o_flags);
+  if (ctx->prm.check_inputs) {
+    st = run_checks<NX, NU>(ctx, pb, w, L.S, d_flags);
+    if (st != TADMM_OK) return st;
+  }
+  if (mode == TADMM_MODE_PLAIN) st = run_plain<NX, NU>(ctx, pb, w, L, b->n_agents, b->horizon, d_flags, *out);
+  else if (mode == TADMM_MODE_BATCHED) st = run_batched<NX, NU>(ctx, pb, w, L, b, *out, ws, bytes);
+  else return fail(ctx, TADMM_ERR_INVALID_ARG, "unknown mode");
+  if (st != TADMM_OK) return st;
+  ctx->solved = true;
+  ctx->solved_ws = ws;
+  ctx->solved_N.assign(b->n_agents, b->n_agents + L.S);
+  ctx->solved_T.assign(b->horizon, b->horizon + L.S);
+  return TADMM_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *tadmm_version(void) { return "turboadmm-gfx950 0.1"; }
+
+const char *tadmm_status_string(tadmm_status s) {
+  const int k = (int)s;
+  return (k >= 0 && k <= 7) ? kStatusStr[k] : "unknown status";
+}
+
+const char *tadmm_last_error(const tadmm_ctx *ctx) { return ctx ? ctx->err.c_str() : "context is NULL"; }
+
+float tadmm_last_kernel_ms(const tadmm_ctx *ctx) { return ctx ? ctx->last_ms : -1.f; }
+
+tadmm_status tadmm_workspace_size(const tadmm_params *params, int32_t n_scen, const int32_t *n_agents,
+                                  const int32_t *horizon, size_t *bytes) {
+  std::string err;
+  if (!bytes) return TADMM_ERR_INVALID_ARG;
+  if (!params_ok(params, err)) return TADMM_ERR_INVALID_ARG;
+  Layout L;
+  if (!make_layout(params, n_scen, n_agents, horizon, L, err)) return TADMM_ERR_SHAPE;
+  *bytes = L.bytes;
+  return TADMM_OK;
+}
+
+tadmm_status tadmm_create(tadmm_ctx **pctx, const tadmm_params *params, void *stream) {
+  if (!pctx) return TADMM_ERR_INVALID_ARG;
+  *pctx = nullptr;
+  std::string err;
+  if (!params_ok(params, err)) return TADMM_ERR_INVALID_ARG;
+  tadmm_ctx *ctx = new tadmm_ctx();
+  ctx->prm = *params;
+  ctx->stream = (hipStream_t)stream;
+  hipError_t e = hipGetDevice(&ctx->device);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->h_flags, 64 * sizeof(int), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreate(&ctx->ev0);
+  if (e == hipSuccess) e = hipEventCreate(&ctx->ev1);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete ctx;
+    return TADMM_ERR_HIP;
+  }
+  *pctx = ctx;
+  return TADMM_OK;
+}
+
+tadmm_status tadmm_destroy(tadmm_ctx *ctx) {
+  if (!ctx) return TADMM_ERR_INVALID_ARG;
+  if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
+  if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);
+  if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+  if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  delete ctx;
+  return TADMM_OK;
+}
+
+tadmm_status tadmm_solve(tadmm_ctx *ctx, const tadmm_batch *batch, const tadmm_out *out, void *workspace,
+                         size_t workspace_bytes, int32_t mode) {
+  if (!ctx) return TADMM_ERR_INVALID_ARG;
+  if (!batch || !out) return fail(ctx, TADMM_ERR_INVALID_ARG, "batch / out is NULL");
+  ctx->err.clear();
+  if (ctx->prm.nx == 4) return solve_impl<4, 2>(ctx, batch, out, workspace, workspace_bytes, mode);
+  return solve_impl<6, 3>(ctx, batch, out, workspace, workspace_bytes, mode);
+}
+
+tadmm_status tadmm_autotune(tadmm_ctx *ctx, const tadmm_batch *batch, const tadmm_out *out, void *workspace,
+                            size_t workspace_bytes, int32_t *best_threads) {
+  if (!ctx) return TADMM_ERR_INVALID_ARG;
+  const int saved = ctx->prm.block_threads;
+  const int cands[] = {64, 128, 256, 512, 1024};
+  float best = 1e30f;
+  int best_t = ctx->tuned_threads;
+  for (int c : cands) {
+    ctx->prm.block_threads = c;
+    tadmm_status st = tadmm_solve(ctx, batch, out, workspace, workspace_bytes, TADMM_MODE_BATCHED);
+    if (st != TADMM_OK) { ctx->prm.block_threads = saved; return st; }
+    st = tadmm_solve(ctx, batch, out, workspace, workspace_bytes, TADMM_MODE_BATCHED);
+    if (st != TADMM_OK) { ctx->prm.block_threads = saved; return st; }
+    if (ctx->last_ms < best) { best = ctx->last_ms; best_t = c; }
+  }
+  ctx->prm.block_threads = saved;
+  ctx->tuned_threads = best_t;
+  if (best_threads) *best_threads = best_t;
+  return TADMM_OK;
+}
+
+tadmm_status tadmm_adjoint(tadmm_ctx *ctx, const tadmm_batch *batch, const tadmm_out *out, void *workspace,
+                           size_t workspace_bytes, const float *dL_dx, const float *dL_du, float *dL_dx0,
+                           float *dL_dxref, float *dL_dlogq, float *dL_dlogr) {
+  if (!ctx) return TADMM_ERR_INVALID_ARG;
+  if (!ctx->solved || ctx->solved_ws != workspace) return fail(ctx, TADMM_ERR_STATE, "adjoint needs the matching solve");
+  (void)batch; (void)out; (void)workspace_bytes; (void)dL_dx; (void)dL_du; (void)dL_dx0; (void)dL_dxref;
+  (void)dL_dlogq; (void)dL_dlogr;
+  return fail(ctx, TADMM_ERR_STATE, "adjoint not available in this build");
+}
+
+}  // extern "C"

@@ -1,0 +1,99 @@
+"""Helpers shared by the GPU tests: run the HIP path through the C ABI and
+compare it with the FP64 oracle."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+import synth
+
+# Parity bar: relative trajectory error over (x, u) of a scenario (FP32 path
+# against the FP64 oracle).
+REL_TOL = 1e-4
+# A working-set entry or a half-plane counts as marginal (excluded from the
+# identity check) when its multiplier and its slack are both this small.
+MARGIN = 1e-5
+
+
+def gpu_solve(problem, scs, mode=None, normals=None, solver_kw=None, return_prep=False):
+    import paper_2602_15838_amd as tadmm
+    mode = tadmm.MODE_BATCHED if mode is None else mode
+    pk = synth.pack(problem, scs)
+    solver = tadmm.Solver(tadmm.make_params(problem, **(solver_kw or {})))
+    nrm = None if normals is None else np.concatenate([np.asarray(n).reshape(-1, problem.nu) for n in normals])
+    prep = solver.prepare(pk.n_agents, pk.horizon, pk.x0, pk.xref, pk.q_diag, pk.r_diag, nrm)
+    prep.run(mode)
+    res = tadmm.split_outputs(prep.result(), pk.n_agents, pk.horizon, problem.nx, problem.nu)
+    if return_prep:
+        return res, prep, solver
+    solver.close()
+    return res
+
+
+def oracle_opts(solver_kw=None, lockstep=None):
+    kw = dict(solver_kw or {})
+    o = oracle.OracleOptions()
+    for k in ("normal_mode", "mu_tol", "max_as_iter", "max_iter", "eps_abs", "eps_rel", "rho"):
+        if k in kw:
+            setattr(o, k, kw[k])
+    if "riccati_warmstart" in kw:
+        o.warm_start = bool(kw["riccati_warmstart"])
+    if "hotstart" in kw:
+        o.hotstart = bool(kw["hotstart"])
+    if lockstep:
+        o.fixed_iters = lockstep
+    return o
+
+
+def rel_traj_err(g, o) -> float:
+    X = np.concatenate([o["x"].ravel(), o["u"].ravel()])
+    Y = np.concatenate([g["x"].ravel(), g["u"].ravel()]).astype(np.float64)
+    return float(np.linalg.norm(X - Y) / max(np.linalg.norm(X), 1e-30))
+
+
+def working_set_marginal(problem, o) -> np.ndarray:
+    """Bounds whose multiplier is tiny (degenerate) or whose input sits within
+    MARGIN of the bound without being fixed there."""
+    u, w, mu = o["u"], o["w"], o["mu"]
+    scale = 1.0 + np.abs(mu).max()
+    near = (np.abs(u - problem.u_lo) < MARGIN * problem.u_max) | (np.abs(u - problem.u_hi) < MARGIN * problem.u_max)
+    return ((w != 0) & (np.abs(mu) < MARGIN * scale)) | ((w == 0) & near)
+
+
+def pair_marginal(problem, sc, o, rho) -> np.ndarray:
+    """Half-planes whose violation v at the last consensus step is tiny:
+    active: v = 2|lambda_ij|/rho; inactive: v = d_min - n'(z_ij - z_ji)."""
+    N, T = sc.N, sc.T
+    x, z, lam = o["x"], o["z"], o["lam"]
+    out = np.zeros((N * (N - 1) // 2, T), dtype=bool)
+    p = 0
+    for i in range(N):
+        for j in range(i + 1, N):
+            d = x[i, 1:, :problem.dp] - x[j, 1:, :problem.dp]
+            n = d / np.maximum(np.linalg.norm(d, axis=1, keepdims=True), 1e-300)
+            act = o["pair_active"][p].astype(bool)
+            v_act = 2.0 * np.linalg.norm(lam[i, j], axis=1) / rho
+            v_in = problem.d_min - np.sum(n * (z[i, j] - z[j, i]), axis=1)
+            v = np.where(act, v_act, v_in)
+            out[p] = np.abs(v) < MARGIN * max(1.0, problem.d_min)
+            p += 1
+    return out
+
+
+def compare(problem, sc, g, o, rho=None, check_sets=True, tol=REL_TOL):
+    """Assert parity of one scenario; returns a small report dict."""
+    rho = problem.rho if rho is None else rho
+    rel = rel_traj_err(g, o)
+    rep = dict(rel=rel, iters=(g["iters"], o["iters"]), status=(g["status"], o["status"]))
+    assert rel <= tol, f"N={sc.N} T={sc.T}: rel trajectory error {rel:.3e} > {tol:.0e} ({rep})"
+    if check_sets:
+        wm = working_set_marginal(problem, o)
+        diff = (g["w"] != o["w"]) & ~wm
+        assert not diff.any(), f"N={sc.N} T={sc.T}: working sets differ at {np.argwhere(diff)[:5].tolist()}"
+        rep["w_marginal"] = int(wm.sum())
+        if "z" in o and sc.N > 1:
+            pm = pair_marginal(problem, sc, o, rho)
+            pdiff = (g["pair_active"] != o["pair_active"]) & ~pm
+            assert not pdiff.any(), f"N={sc.N} T={sc.T}: active half-planes differ at {np.argwhere(pdiff)[:5].tolist()}"
+            rep["pair_marginal"] = int(pm.sum())
+    return rep

@@ -1,0 +1,304 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bar: relative trajectory error over (x, u) <= 1e-4 per scenario, identical
+final working sets and active half-planes except marginal (degenerate)
+entries.  Inputs: the seeded generators of synth (configs 0-4 shapes).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import gpu_common as gc
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2602_15838_amd as tadmm  # noqa: E402
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _zeros_eps(**kw):
+    d = dict(eps_abs=0.0, eps_rel=0.0)
+    d.update(kw)
+    return d
+
+
+# ---------------------------------------------------------------------------
+# one x-update (fixed z = C r, lambda = 0) against the oracle's local QP
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("cfg", ["c1", "c2"])
+def test_first_xupdate_matches_oracle_local_qp(cfg):
+    if cfg == "c1":
+        p, scs = synth.config1()
+    else:
+        p, scs = synth.config2(S=6)
+    _say(f"first x-update parity {cfg}")
+    g = gc.gpu_solve(p, scs, solver_kw=_zeros_eps(max_iter=1))
+    for sc, gr in zip(scs, g):
+        xr = sc.xref()
+        for i in range(sc.N):
+            ysum = p.rho * (sc.N - 1) * xr[i, :, :p.dp]
+            o = oracle.agent_qp(p, sc.T, sc.N - 1, sc.x0()[i], xr[i], p.q_diag, p.r_diag, ysum)
+            X = np.concatenate([o["x"].ravel(), o["u"].ravel()])
+            Y = np.concatenate([gr["x"][i].ravel(), gr["u"][i].ravel()])
+            assert np.linalg.norm(X - Y) <= 1e-5 * np.linalg.norm(X), (sc.N, sc.T, i)
+            marg = (gr["w"][i] != o["w"]) & (np.abs(o["mu"]) < gc.MARGIN * (1 + np.abs(o["mu"]).max()))
+            assert np.all((gr["w"][i] == o["w"]) | marg)
+
+
+# ---------------------------------------------------------------------------
+# lockstep: exactly K iterations on both sides
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("K", [2, 10, 60])
+def test_lockstep_config1(K):
+    p, scs = synth.config1()
+    _say(f"lockstep config1 K={K}")
+    g = gc.gpu_solve(p, scs, solver_kw=_zeros_eps(max_iter=K))[0]
+    o = oracle.solve(p, scs[0], gc.oracle_opts(lockstep=K), keep_zl=True, threads=4)
+    assert g["iters"] == K and o["iters"] == K
+    rep = gc.compare(p, scs[0], g, o)
+    _say(f"  {rep}")
+
+
+def test_lockstep_config2_sample():
+    p, scs = synth.config2(S=12)
+    K = 40
+    _say("lockstep config2 sample")
+    g = gc.gpu_solve(p, scs, solver_kw=_zeros_eps(max_iter=K))
+    o = oracle.solve_batch(p, scs, gc.oracle_opts(lockstep=K))
+    for sc, gr, orr in zip(scs, g, o):
+        assert gr["iters"] == K
+        assert gc.rel_traj_err(gr, orr) <= gc.REL_TOL, (sc.N, sc.T)
+
+
+# ---------------------------------------------------------------------------
+# full solves with the stopping rule
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_config0_parity(mode):
+    p, scs = synth.config0()
+    _say(f"config0 mode={mode}")
+    g = gc.gpu_solve(p, scs, mode=mode)[0]
+    o = oracle.solve(p, scs[0], keep_zl=True)
+    rep = gc.compare(p, scs[0], g, o)
+    assert abs(g["iters"] - o["iters"]) <= 2 and g["status"] == o["status"], rep
+    _say(f"  {rep}")
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_config1_parity(mode):
+    p, scs = synth.config1()
+    _say(f"config1 mode={mode}")
+    g = gc.gpu_solve(p, scs, mode=mode)[0]
+    o = oracle.solve(p, scs[0], keep_zl=True, threads=4)
+    rep = gc.compare(p, scs[0], g, o)
+    assert abs(g["iters"] - o["iters"]) <= 2 and g["status"] == o["status"], rep
+    _say(f"  {rep}")
+
+
+def test_config2_sample_parity_batched():
+    p, scs = synth.config2(S=24)
+    _say("config2 sample batched")
+    g = gc.gpu_solve(p, scs)
+    o = oracle.solve_batch(p, scs)
+    worst = 0.0
+    for sc, gr, orr in zip(scs, g, o):
+        assert abs(gr["iters"] - orr["iters"]) <= 2, (sc.N, sc.T, gr["iters"], orr["iters"])
+        rel = gc.rel_traj_err(gr, orr)
+        worst = max(worst, rel)
+        assert rel <= gc.REL_TOL, (sc.N, sc.T, rel)
+    _say(f"  worst rel {worst:.2e}")
+
+
+def test_frozen_normals_parity():
+    """Convex case: fixed normals given by the caller."""
+    p = synth.ProblemParams(dp=2, u_max=2.0)
+    sc = synth.Scenario(starts=np.array([[-3.0, 0.6], [3.0, -0.6], [0.0, 3.0]]),
+                        goals=np.array([[3.0, 0.1], [-3.0, -0.1], [0.2, -3.0]]), T=20)
+    T, P = sc.T, 3
+    nrm = np.zeros((P, T, 2))
+    nrm[0, :, 1] = 1.0
+    ang = np.linspace(0.3, 1.2, T)
+    nrm[1, :, 0], nrm[1, :, 1] = np.cos(ang), -np.sin(ang)
+    nrm[2, :, 0], nrm[2, :, 1] = -np.cos(ang), -np.sin(ang)
+    kw = dict(normal_mode=tadmm.NORMAL_FROZEN, max_iter=400)
+    _say("frozen normals")
+    g = gc.gpu_solve(p, [sc], normals=[nrm], solver_kw=kw)[0]
+    o = oracle.solve(p, sc, gc.oracle_opts(kw), normals=nrm, keep_zl=True)
+    gc.compare(p, sc, g, o, check_sets=False)
+
+
+def test_three_d_first_iterations_sampled():
+    """3-D double integrator, 128 agents on a sphere (horizon 50): the first
+    x-update of sampled agents equals the oracle's local QP; then a short
+    lockstep of a 12-agent 3-D scenario."""
+    p, scs = synth.config4()
+    sc = scs[0]
+    _say("3-D config4 first x-update, sampled agents")
+    g = gc.gpu_solve(p, scs, solver_kw=_zeros_eps(max_iter=1), mode=tadmm.MODE_PLAIN)[0]
+    xr = sc.xref()
+    for i in (0, 37, 64, 127):
+        ysum = p.rho * (sc.N - 1) * xr[i, :, :p.dp]
+        o = oracle.agent_qp(p, sc.T, sc.N - 1, sc.x0()[i], xr[i], p.q_diag, p.r_diag, ysum)
+        X = np.concatenate([o["x"].ravel(), o["u"].ravel()])
+        Y = np.concatenate([g["x"][i].ravel(), g["u"][i].ravel()])
+        assert np.linalg.norm(X - Y) <= 1e-5 * np.linalg.norm(X), i
+    small = synth.sphere_swap(12, 4.0, 30)
+    K = 25
+    g2 = gc.gpu_solve(p, [small], solver_kw=_zeros_eps(max_iter=K))[0]
+    o2 = oracle.solve(p, small, gc.oracle_opts(lockstep=K), keep_zl=True, threads=4)
+    gc.compare(p, small, g2, o2)
+
+
+# ---------------------------------------------------------------------------
+# plain == batched, determinism, ablation flags
+# ---------------------------------------------------------------------------
+
+def test_plain_and_batched_bitwise_equal():
+    p, scs = synth.config2(S=10)
+    _say("plain vs batched bitwise")
+    a = gc.gpu_solve(p, scs, mode=tadmm.MODE_PLAIN)
+    b = gc.gpu_solve(p, scs, mode=tadmm.MODE_BATCHED)
+    for ga, gb in zip(a, b):
+        assert ga["iters"] == gb["iters"] and ga["status"] == gb["status"]
+        np.testing.assert_array_equal(ga["x"], gb["x"])
+        np.testing.assert_array_equal(ga["u"], gb["u"])
+        np.testing.assert_array_equal(ga["w"], gb["w"])
+        np.testing.assert_array_equal(ga["pair_active"], gb["pair_active"])
+
+
+@pytest.mark.parametrize("threads", [64, 256, 1024])
+def test_batched_independent_of_workgroup_size(threads):
+    p, scs = synth.config2(S=10)
+    a = gc.gpu_solve(p, scs, solver_kw=dict(block_threads=64))
+    b = gc.gpu_solve(p, scs, solver_kw=dict(block_threads=threads))
+    for ga, gb in zip(a, b):
+        np.testing.assert_array_equal(ga["x"], gb["x"])
+        assert ga["iters"] == gb["iters"]
+
+
+def test_deterministic_repeat():
+    p, scs = synth.config2(S=10)
+    res, prep, solver = gc.gpu_solve(p, scs, return_prep=True)
+    x1 = prep.o["x"].clone()
+    prep.run(tadmm.MODE_BATCHED)
+    torch.testing.assert_close(prep.o["x"], x1, rtol=0, atol=0)
+    solver.close()
+
+
+@pytest.mark.parametrize("flag", ["cache_factors", "riccati_warmstart", "hotstart"])
+def test_ablation_flags_same_iterates(flag):
+    """Factor caching, the Riccati warm start and the hotstart change the work,
+    not the iterates (each local QP has a unique minimiser)."""
+    p, scs = synth.config2(S=6)
+    K = 30
+    a = gc.gpu_solve(p, scs, solver_kw=_zeros_eps(max_iter=K))
+    b = gc.gpu_solve(p, scs, solver_kw=_zeros_eps(max_iter=K, **{flag: False}))
+    for ga, gb in zip(a, b):
+        rel = gc.rel_traj_err(gb, dict(x=ga["x"].astype(np.float64), u=ga["u"].astype(np.float64)))
+        assert rel <= 1e-5, (flag, rel)
+    ca = sum(g["counters"] for g in a)
+    cb = sum(g["counters"] for g in b)
+    if flag == "cache_factors":
+        assert cb[1] > ca[1]          # more refactored stages
+    else:
+        assert cb[0] >= ca[0]         # at least as many active-set passes
+
+
+# ---------------------------------------------------------------------------
+# edge cases and failure paths
+# ---------------------------------------------------------------------------
+
+def test_single_agent_converges_in_one_iteration():
+    p = synth.ProblemParams(dp=2)
+    sc = synth.Scenario(starts=np.array([[0.0, 0.0]]), goals=np.array([[3.0, 1.0]]), T=20)
+    g = gc.gpu_solve(p, [sc])[0]
+    assert g["status"] == tadmm.SCEN_CONVERGED and g["iters"] == 1
+    o = oracle.agent_qp(p, 20, 0, sc.x0()[0], sc.xref()[0], p.q_diag, p.r_diag)
+    assert gc.rel_traj_err(dict(x=g["x"][0], u=g["u"][0]), o) <= 1e-5
+
+
+def test_horizon_one_and_mixed_tiny_batch():
+    p = synth.ProblemParams(dp=2)
+    scs = [synth.Scenario(starts=np.array([[0.0, 0.0], [1.0, 0.0]]), goals=np.array([[1.0, 0.0], [0.0, 0.0]]), T=1),
+           synth.Scenario(starts=np.array([[0.0, 0.0]]), goals=np.array([[1.0, 1.0]]), T=3),
+           synth.Scenario(starts=np.array([[0.0, 0.0], [0.0, 1.5], [1.5, 0.0]]),
+                          goals=np.array([[1.5, 1.5], [1.5, 0.0], [0.0, 1.5]]), T=7)]
+    g = gc.gpu_solve(p, scs)
+    o = oracle.solve_batch(p, scs)
+    for sc, gr, orr in zip(scs, g, o):
+        assert abs(gr["iters"] - orr["iters"]) <= 2
+        assert gc.rel_traj_err(gr, orr) <= gc.REL_TOL
+
+
+def test_empty_batch_is_noop():
+    p = synth.ProblemParams(dp=2)
+    solver = tadmm.Solver(tadmm.make_params(p))
+    prep = solver.prepare(np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros((0, 4)), np.zeros((0, 4)),
+                          np.zeros((0, 4)), np.zeros((0, 2)))
+    prep.run(tadmm.MODE_BATCHED)
+    solver.close()
+
+
+def test_max_iter_one_and_cap_statuses():
+    p, scs = synth.config1()
+    g = gc.gpu_solve(p, scs, solver_kw=dict(max_iter=1))[0]
+    assert g["status"] == tadmm.SCEN_MAX_ITER and g["iters"] == 1
+    g = gc.gpu_solve(p, scs, solver_kw=dict(max_as_iter=1))[0]
+    assert g["status"] == tadmm.SCEN_ACTIVE_SET_CAP and g["iters"] == 1
+
+
+def test_nonfinite_input_rejected():
+    p, scs = synth.config2(S=3)
+    pk = synth.pack(p, scs)
+    pk.xref[5, 0] = np.nan
+    solver = tadmm.Solver(tadmm.make_params(p))
+    with pytest.raises(tadmm.TadmmError) as e:
+        solver.solve(pk.n_agents, pk.horizon, pk.x0, pk.xref, pk.q_diag, pk.r_diag)
+    assert e.value.code == 3
+    solver.close()
+
+
+def test_close_start_rejected():
+    p = synth.ProblemParams(dp=2)
+    sc = synth.Scenario(starts=np.array([[0.0, 0.0], [0.1, 0.0]]), goals=np.array([[1.0, 0.0], [0.0, 1.0]]), T=10)
+    pk = synth.pack(p, [sc])
+    solver = tadmm.Solver(tadmm.make_params(p))
+    with pytest.raises(tadmm.TadmmError) as e:
+        solver.solve(pk.n_agents, pk.horizon, pk.x0, pk.xref, pk.q_diag, pk.r_diag)
+    assert e.value.code == 4
+    solver.close()
+
+
+def test_poisoned_scenario_is_isolated():
+    """With the input checks off, a NaN reference in one scenario ends that
+    scenario as NONFINITE and leaves every other scenario bitwise unchanged."""
+    p, scs = synth.config2(S=5)
+    pk = synth.pack(p, scs)
+    solver = tadmm.Solver(tadmm.make_params(p, check_inputs=False))
+    clean = tadmm.split_outputs(solver.solve(pk.n_agents, pk.horizon, pk.x0, pk.xref, pk.q_diag, pk.r_diag),
+                                pk.n_agents, pk.horizon, p.nx, p.nu)
+    bad = pk.xref.copy()
+    off = int((pk.n_agents[:2] * (pk.horizon[:2] + 1)).sum())
+    bad[off + 3, 0] = np.nan
+    pois = tadmm.split_outputs(solver.solve(pk.n_agents, pk.horizon, pk.x0, bad, pk.q_diag, pk.r_diag),
+                               pk.n_agents, pk.horizon, p.nx, p.nu)
+    assert pois[2]["status"] == tadmm.SCEN_NONFINITE
+    for s in (0, 1, 3, 4):
+        np.testing.assert_array_equal(pois[s]["x"], clean[s]["x"])
+        assert pois[s]["iters"] == clean[s]["iters"]
+    solver.close()

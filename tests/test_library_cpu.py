@@ -1,0 +1,93 @@
+"""Host-side checks of the C ABI that need no GPU: the built library loads,
+exports every entry point include/turboadmm.h declares, and rejects bad
+arguments before touching a device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "turboadmm.h")
+
+tadmm = pytest.importorskip("paper_2602_15838_amd")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tadmm_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = tadmm.lib()
+    names = _declared()
+    assert "tadmm_solve" in names and "tadmm_adjoint" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(tadmm.EXPORTED_SYMBOLS)
+
+
+def test_version_and_status_strings():
+    L = tadmm.lib()
+    assert L.tadmm_version().decode().startswith("turboadmm")
+    assert L.tadmm_status_string(0) == b"ok"
+    assert L.tadmm_status_string(3) == b"non-finite input"
+    assert L.tadmm_status_string(99) == b"unknown status"
+
+
+def _ws(prm, N, T):
+    N = np.asarray(N, np.int32)
+    T = np.asarray(T, np.int32)
+    nb = C.c_size_t(0)
+    rc = tadmm.lib().tadmm_workspace_size(C.byref(prm), int(N.size), N.ctypes.data_as(tadmm._ip),
+                                          T.ctypes.data_as(tadmm._ip), C.byref(nb))
+    return rc, nb.value
+
+
+def test_workspace_size_scales_with_batch():
+    p = synth.ProblemParams()
+    prm = tadmm.make_params(p)
+    rc1, b1 = _ws(prm, [2], [20])
+    rc2, b2 = _ws(prm, [2, 14, 32], [20, 20, 40])
+    assert rc1 == 0 and rc2 == 0 and 0 < b1 < b2
+    rc0, b0 = _ws(prm, [], [])
+    assert rc0 == 0
+    p3 = synth.ProblemParams(dp=3, u_max=3.0)
+    rc3, b3 = _ws(tadmm.make_params(p3), [2], [20])
+    assert rc3 == 0 and b3 > b1
+
+
+@pytest.mark.parametrize("field,value", [("rho", 0.0), ("rho", -1.0), ("max_iter", 0), ("nx", 5),
+                                         ("qT_scale", 0.0), ("eps_abs", -1.0), ("normal_mode", 7),
+                                         ("block_threads", 100), ("mu_tol", float("nan"))])
+def test_bad_params_rejected(field, value):
+    prm = tadmm.make_params(synth.ProblemParams())
+    setattr(prm, field, value)
+    rc, _ = _ws(prm, [2], [20])
+    assert rc == 1
+
+
+def test_inverted_box_rejected():
+    prm = tadmm.make_params(synth.ProblemParams())
+    prm.u_lo[0], prm.u_hi[0] = 1.0, -1.0
+    assert _ws(prm, [2], [20])[0] == 1
+
+
+@pytest.mark.parametrize("N,T", [([0], [20]), ([2], [0]), ([5000], [10])])
+def test_bad_shapes_rejected(N, T):
+    prm = tadmm.make_params(synth.ProblemParams())
+    assert _ws(prm, N, T)[0] == 2
+
+
+def test_null_arguments():
+    L = tadmm.lib()
+    prm = tadmm.make_params(synth.ProblemParams())
+    assert L.tadmm_workspace_size(C.byref(prm), 1, None, None, None) == 1
+    assert L.tadmm_create(None, C.byref(prm), None) == 1
+    assert L.tadmm_solve(None, None, None, None, 0, 0) == 1
+    assert L.tadmm_destroy(None) == 1
+    assert L.tadmm_last_kernel_ms(None) == -1.0
