@@ -113,6 +113,10 @@ typedef struct {
                                 scenario ends with status NONFINITE                 */
   int32_t block_threads;     /* batched mode workgroup size (64..1024, multiple of
                                 64); 0: use the context's tuned value              */
+  int32_t refine;            /* 1: one step of mixed-precision iterative refinement
+                                of every local QP solution (reduced gradient in
+                                FP64, correction with the FP32 factors) (default);
+                                0: plain FP32 solve                                */
 } tadmm_params;
 
 /* A ragged batch of S independent scenarios.  Scenario s has N_s agents and

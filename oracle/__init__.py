@@ -152,12 +152,13 @@ def make_params(problem, opts: OracleOptions) -> _Params:
 class _Holder:
     """Keeps the numpy buffers of one scenario's inputs/outputs alive."""
 
-    def __init__(self, problem, sc, opts: OracleOptions, normals=None, keep_zl=False):
+    def __init__(self, problem, sc, opts: OracleOptions, normals=None, keep_zl=False, inputs=None):
         nx, nu, dp = problem.nx, problem.nu, problem.dp
         N, T = sc.N, sc.T
         P = N * (N - 1) // 2
-        self.x0 = np.ascontiguousarray(sc.x0(), dtype=np.float64)
-        self.xref = np.ascontiguousarray(sc.xref(), dtype=np.float64)
+        x0, xref = (sc.x0(), sc.xref()) if inputs is None else inputs
+        self.x0 = np.ascontiguousarray(np.asarray(x0, dtype=np.float64).reshape(N, nx))
+        self.xref = np.ascontiguousarray(np.asarray(xref, dtype=np.float64).reshape(N, T + 1, nx))
         self.q = np.ascontiguousarray(problem.q_diag if sc.q_diag is None else sc.q_diag, dtype=np.float64)
         self.r = np.ascontiguousarray(problem.r_diag if sc.r_diag is None else sc.r_diag, dtype=np.float64)
         self.normals = None if normals is None else np.ascontiguousarray(normals, dtype=np.float64).reshape(P, T, dp)
@@ -188,13 +189,14 @@ class _Holder:
 
 
 def solve(problem, scenario, opts: Optional[OracleOptions] = None, normals=None, threads: int = 1,
-          keep_zl: bool = False) -> Dict[str, object]:
+          keep_zl: bool = False, inputs=None) -> Dict[str, object]:
     """ADMM on one scenario.  Returns numpy arrays x [N][T+1][nx], u [N][T][nu],
     w [N][T][nu] (0 free / 1 lower / 2 upper), mu, pair_active [P][T], and the
-    status, iteration count and final residuals."""
+    status, iteration count and final residuals.  `inputs` = (x0, xref)
+    replaces the scenario's own initial states and references."""
     opts = opts or OracleOptions()
     prm = make_params(problem, opts)
-    h = _Holder(problem, scenario, opts, normals, keep_zl)
+    h = _Holder(problem, scenario, opts, normals, keep_zl, inputs)
     rc = lib().orc_admm(C.byref(prm), C.byref(h.sc), C.byref(h.res), int(threads))
     if rc != 0:
         raise RuntimeError("oracle ADMM failed (allocation or singular KKT)")
@@ -202,11 +204,12 @@ def solve(problem, scenario, opts: Optional[OracleOptions] = None, normals=None,
 
 
 def solve_batch(problem, scenarios: Sequence, opts: Optional[OracleOptions] = None, threads: int = 0,
-                normals: Optional[List[np.ndarray]] = None) -> List[Dict[str, object]]:
+                normals: Optional[List[np.ndarray]] = None, inputs=None) -> List[Dict[str, object]]:
     """Independent scenarios, OpenMP over scenarios (dynamic schedule)."""
     opts = opts or OracleOptions()
     prm = make_params(problem, opts)
-    hs = [_Holder(problem, sc, opts, None if normals is None else normals[k]) for k, sc in enumerate(scenarios)]
+    hs = [_Holder(problem, sc, opts, None if normals is None else normals[k], False,
+                  None if inputs is None else inputs[k]) for k, sc in enumerate(scenarios)]
     S = len(hs)
     scs = (_Scenario * max(S, 1))(*[h.sc for h in hs])
     res = (_Result * max(S, 1))(*[h.res for h in hs])

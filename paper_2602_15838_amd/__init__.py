@@ -39,7 +39,7 @@ class Params(C.Structure):
                 ("eps_abs", C.c_float), ("eps_rel", C.c_float), ("mu_tol", C.c_float),
                 ("max_iter", C.c_int32), ("max_as_iter", C.c_int32), ("normal_mode", C.c_int32),
                 ("cache_factors", C.c_int32), ("riccati_warmstart", C.c_int32), ("hotstart", C.c_int32),
-                ("check_inputs", C.c_int32), ("block_threads", C.c_int32)]
+                ("check_inputs", C.c_int32), ("block_threads", C.c_int32), ("refine", C.c_int32)]
 
 
 _fp = C.POINTER(C.c_float)
@@ -100,7 +100,8 @@ EXPORTED_SYMBOLS = ("tadmm_workspace_size", "tadmm_create", "tadmm_solve", "tadm
 
 def make_params(problem, *, normal_mode: int = NORMAL_PER_ITER, mu_tol: float = 1e-5, max_as_iter: int = 0,
                 cache_factors: bool = True, riccati_warmstart: bool = True, hotstart: bool = True,
-                check_inputs: bool = True, block_threads: int = 0, max_iter: Optional[int] = None,
+                check_inputs: bool = True, block_threads: int = 0, refine: bool = True,
+                max_iter: Optional[int] = None,
                 eps_abs: Optional[float] = None, eps_rel: Optional[float] = None,
                 rho: Optional[float] = None) -> Params:
     """Fill the C parameter struct from a problem description (attributes
@@ -129,6 +130,7 @@ def make_params(problem, *, normal_mode: int = NORMAL_PER_ITER, mu_tol: float = 
     p.hotstart = int(bool(hotstart))
     p.check_inputs = int(bool(check_inputs))
     p.block_threads = int(block_threads)
+    p.refine = int(bool(refine))
     return p
 
 

@@ -31,11 +31,11 @@ struct Prob {
   float A[36], B[18];
   float ulo[3], uhi[3];
   float qT, dmin, rho, eps_abs, eps_rel, mu_tol;
-  int max_iter, max_as, normal_mode, cache, warm, hot;
+  int max_iter, max_as, normal_mode, cache, warm, hot, refine;
 };
 
 // Per-scenario table columns (int64).
-enum { TB_F = 0, TB_B, TB_L, TB_A, TB_XO, TB_UO, TB_PO, TB_LB, TB_NCOL };
+enum { TB_F = 0, TB_B, TB_L, TB_A, TB_XO, TB_UO, TB_PO, TB_LB, TB_D, TB_NCOL };
 // Per-scenario int32 state columns.
 enum { ST_STATUS = 0, ST_ITERS, ST_CAP, ST_DONE, ST_NCOL = 8 };
 // Per-scenario float state columns.
@@ -49,6 +49,7 @@ struct WS {
   const int *order;                  // [S] launch order (largest first)
   int *queue;                        // [1] next item of the persistent queue
   float *fr;                         // float regions
+  double *dr;                        // FP64 refinement scratch [NX][N(T+1)] per scenario
   int8_t *wr;                        // working-set regions  [NU][N(T+1)] per scenario
   int *adirty;                       // [agents] highest stale factor stage (-1: none)
   float *lam;                        // [DP][T][N][N] per scenario
@@ -65,6 +66,8 @@ struct WS {
 template <int NX, int NU>
 struct Fld {
   static constexpr int DP = NU;
+  static constexpr int NS = NU * (NU + 1) / 2;  // packed symmetric NU x NU
+  static constexpr int NP = NX * (NX + 1) / 2;  // packed symmetric NX x NX
   static constexpr int X = 0;                 // current iterate x_t        [NX]
   static constexpr int U = X + NX;            // current iterate u_t        [NU]
   static constexpr int XE = U + NU;           // equality-QP solution x_t   [NX]
@@ -81,14 +84,19 @@ struct Fld {
   static constexpr int XP = QP + DP;          // C x^k (positions of the previous iterate) [DP]
   static constexpr int ZD = XP + DP;          // sum_j z_ij - n_nbr C x^k   [DP]
   static constexpr int RED = ZD + DP;         // residual partial sums      [5]
-  static constexpr int P = RED + 5;           // value Hessian P_t          [NX*NX]
-  static constexpr int PHI = P + NX * NX;     // closed loop A + B K_t      [NX*NX]
-  static constexpr int CC = PHI + NX * NX;    // fixed-input value term c_t [NX]
-  static constexpr int GM = CC + NX;          // k_t = GM p_{t+1} + kc      [NU*NX]
-  static constexpr int KC = GM + NU * NX;     //                            [NU]
-  static constexpr int K = KC + NU;           // feedback gain K_t          [NU*NX]
-  static constexpr int NF = K + NU * NX;
+  // cached Riccati factor of stage t for the current working set
+  static constexpr int K = RED + 5;           // feedback gain K_t          [NU*NX]
+  static constexpr int SV = K + NU * NX;      // S'^-1 (zero on fixed rows) [NS]
+  static constexpr int KC = SV + NS;          // feedforward constant       [NU]
+  static constexpr int CC = KC + NU;          // value-gradient constant    [NX]
+  static constexpr int PU = CC + NX;          // value Hessian P_t (upper)  [NP]
+  static constexpr int NF = PU + NP;
 };
+
+template <int N>
+__host__ __device__ constexpr int sym_idx(int r, int c) {  // r <= c
+  return r * N - r * (r - 1) / 2 + (c - r);
+}
 
 // ---------------------------------------------------------------------------
 // small helpers
@@ -102,7 +110,7 @@ __device__ __forceinline__ float wave_sum(float v) {
 
 struct Scen {
   int s, N, T, GS;
-  long long fo, bo, lo, ao, xo, uo, po, lb;
+  long long fo, bo, lo, ao, xo, uo, po, lb, dof;
 };
 
 __device__ __forceinline__ Scen load_scen(const WS &ws, int s) {
@@ -113,7 +121,7 @@ __device__ __forceinline__ Scen load_scen(const WS &ws, int s) {
   sc.GS = sc.N * (sc.T + 1);
   const long long *tb = ws.tab + (long long)s * TB_NCOL;
   sc.fo = tb[TB_F]; sc.bo = tb[TB_B]; sc.lo = tb[TB_L]; sc.ao = tb[TB_A];
-  sc.xo = tb[TB_XO]; sc.uo = tb[TB_UO]; sc.po = tb[TB_PO]; sc.lb = tb[TB_LB];
+  sc.xo = tb[TB_XO]; sc.uo = tb[TB_UO]; sc.po = tb[TB_PO]; sc.lb = tb[TB_LB]; sc.dof = tb[TB_D];
   return sc;
 }
 
@@ -129,21 +137,21 @@ __device__ __forceinline__ void stage_hx(const Prob &pb, const float *qd, int t,
 // ---------------------------------------------------------------------------
 // Riccati factor of one stage for a working set (Eq. 7 with inputs fixed)
 // ---------------------------------------------------------------------------
-// Given P_{t+1}, the free/fixed pattern of u_t and the bound values, compute
-//   S = H_u + B'P B,  M = B'P A,  S_ff = chol of the free block,
-//   K = -S_ff^-1 M_f (zero rows on fixed inputs),  Phi = A + B K,
-//   GM = -S_ff^-1 B_f' (gain of k_t on p_{t+1}),
-//   kc = -S_ff^-1 S_fa ubar (free rows), ubar (fixed rows),
-//   c  = K' (S ubar)_f + M' ubar   (constant of p_t),
+// Given P_{t+1}, the free/fixed pattern of u_t and the bound values ubar:
+//   S = H_u + B'P B,  M = B'P A,  S' = S on the free block, identity elsewhere,
+//   Sv = S'^-1 with the fixed rows/columns zeroed (the inverse of S_ff),
+//   K = -Sv M (zero rows on fixed inputs),
+//   kc = -Sv (S ubar) on free rows, ubar on fixed rows,
+//   c = K' (S ubar)_f + M' ubar,
 //   P_t = H_x + A'P A + M'K (symmetric; only for t >= 1).
-// The free block is handled without branches: S' keeps S on free x free and
-// the identity elsewhere, so S'^-1 applied to a right-hand side that is zero
-// on the fixed rows returns zero there.
+// With these, the affine terms of the sweep are
+//   k_t = kc - Sv B'p_{t+1},   p_t = q_t + c + A'p_{t+1} + K' B'p_{t+1},
+// since A + B K is the closed loop and -Sv B' the gain of k_t on p_{t+1}.
 template <int NX, int NU>
 __device__ __forceinline__ void factor_stage(const Prob &pb, const float hx[NX], const float hu[NU],
                                              const float Pn[NX][NX], const int8_t wt[NU], bool want_P,
-                                             float Pt[NX][NX], float K[NU][NX], float Phi[NX][NX],
-                                             float Gm[NU][NX], float kc[NU], float cc[NX]) {
+                                             float Pt[NX][NX], float K[NU][NX], float Sv[NU][NU], float kc[NU],
+                                             float cc[NX]) {
   const float *A = pb.A;
   const float *B = pb.B;
   float PB[NX][NU];
@@ -183,7 +191,7 @@ __device__ __forceinline__ void factor_stage(const Prob &pb, const float hx[NX],
     fr[a] = (wt[a] == 0);
     ub[a] = (wt[a] == 1) ? pb.ulo[a] : ((wt[a] == 2) ? pb.uhi[a] : 0.f);
   }
-  // Cholesky of S' (lower), with reciprocal diagonal
+  // Cholesky of S' (lower) with reciprocal diagonal
   float L[NU][NU], Li[NU];
 #pragma unroll
   for (int a = 0; a < NU; ++a)
@@ -205,8 +213,12 @@ __device__ __forceinline__ void factor_stage(const Prob &pb, const float hx[NX],
       }
     }
   }
-  // y <- S'^-1 y
-  auto solve = [&](float y[NU]) {
+  // Sv = S'^-1 column by column, fixed rows/columns zeroed
+#pragma unroll
+  for (int b = 0; b < NU; ++b) {
+    float y[NU];
+#pragma unroll
+    for (int a = 0; a < NU; ++a) y[a] = (a == b) ? 1.f : 0.f;
 #pragma unroll
     for (int a = 0; a < NU; ++a) {
       float v = y[a];
@@ -221,24 +233,10 @@ __device__ __forceinline__ void factor_stage(const Prob &pb, const float hx[NX],
       for (int k = a + 1; k < NU; ++k) v = fmaf(-L[k][a], y[k], v);
       y[a] = v * Li[a];
     }
-  };
 #pragma unroll
-  for (int c = 0; c < NX; ++c) {
-    float y[NU], g[NU];
-#pragma unroll
-    for (int a = 0; a < NU; ++a) {
-      y[a] = fr[a] ? M[a][c] : 0.f;
-      g[a] = fr[a] ? B[c * NU + a] : 0.f;
-    }
-    solve(y);
-    solve(g);
-#pragma unroll
-    for (int a = 0; a < NU; ++a) {
-      K[a][c] = -y[a];
-      Gm[a][c] = -g[a];
-    }
+    for (int a = 0; a < NU; ++a) Sv[a][b] = (fr[a] && fr[b]) ? y[a] : 0.f;
   }
-  float su[NU];  // (S ubar) restricted to the free rows
+  float su[NU];  // (S ubar) on the free rows
 #pragma unroll
   for (int a = 0; a < NU; ++a) {
     float v = 0.f;
@@ -246,13 +244,19 @@ __device__ __forceinline__ void factor_stage(const Prob &pb, const float hx[NX],
     for (int b = 0; b < NU; ++b) v = fmaf(S[a][b], ub[b], v);
     su[a] = fr[a] ? v : 0.f;
   }
-  {
-    float y[NU];
 #pragma unroll
-    for (int a = 0; a < NU; ++a) y[a] = su[a];
-    solve(y);
+  for (int a = 0; a < NU; ++a) {
 #pragma unroll
-    for (int a = 0; a < NU; ++a) kc[a] = fr[a] ? -y[a] : ub[a];
+    for (int c = 0; c < NX; ++c) {
+      float v = 0.f;
+#pragma unroll
+      for (int b = 0; b < NU; ++b) v = fmaf(Sv[a][b], M[b][c], v);
+      K[a][c] = -v;
+    }
+    float v = 0.f;
+#pragma unroll
+    for (int b = 0; b < NU; ++b) v = fmaf(Sv[a][b], su[b], v);
+    kc[a] = fr[a] ? -v : ub[a];
   }
 #pragma unroll
   for (int r = 0; r < NX; ++r) {
@@ -261,15 +265,6 @@ __device__ __forceinline__ void factor_stage(const Prob &pb, const float hx[NX],
     for (int a = 0; a < NU; ++a) v = fmaf(K[a][r], su[a], fmaf(M[a][r], ub[a], v));
     cc[r] = v;
   }
-#pragma unroll
-  for (int r = 0; r < NX; ++r)
-#pragma unroll
-    for (int c = 0; c < NX; ++c) {
-      float v = A[r * NX + c];
-#pragma unroll
-      for (int a = 0; a < NU; ++a) v = fmaf(B[r * NU + a], K[a][c], v);
-      Phi[r][c] = v;
-    }
   if (want_P) {
     float PA[NX][NX];
 #pragma unroll

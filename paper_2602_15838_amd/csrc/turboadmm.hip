@@ -23,77 +23,96 @@ namespace tadmm {
 // ===========================================================================
 // Local QP of one agent (x-update)
 // ===========================================================================
+// Scenario-relative addressing: the scenario bases are uniform (scalar) and
+// every access uses a 32-bit offset field * GS + t * N + i.
 template <int NX, int NU>
 struct AgentMem {
-  float *R;
-  int8_t *Wb;
-  int GS, N, i;
-  __device__ __forceinline__ float &f(int field, int t) const { return R[field * GS + t * N + i]; }
-  __device__ __forceinline__ int8_t &w(int c, int t) const { return Wb[c * GS + t * N + i]; }
+  float *__restrict__ R;
+  int8_t *__restrict__ Wb;
+  double *__restrict__ D;
+  unsigned GS, N, i;
+  __device__ __forceinline__ unsigned o(int field, int t) const { return (unsigned)field * GS + (unsigned)t * N + i; }
+  __device__ __forceinline__ float &f(int field, int t) const { return R[o(field, t)]; }
+  __device__ __forceinline__ int8_t &w(int c, int t) const { return Wb[o(c, t)]; }
+  __device__ __forceinline__ double &d(int c, int t) const { return D[o(c, t)]; }
 };
 
-// Refactor stages thi..0 for the current working set (Eq. 7 with fixed inputs).
 template <int NX, int NU>
-__device__ __forceinline__ void refactor(const Prob &pb, const AgentMem<NX, NU> &m, const float *qd, const float hu[NU],
-                                         int T, int n_nbr, int thi) {
-  using F = Fld<NX, NU>;
-  float Pn[NX][NX];
+__device__ __forceinline__ void load_sym(const AgentMem<NX, NU> &m, int field, int t, float P[NX][NX]) {
 #pragma unroll
   for (int r = 0; r < NX; ++r)
 #pragma unroll
-    for (int c = 0; c < NX; ++c) Pn[r][c] = m.f(F::P + r * NX + c, thi + 1);
+    for (int c = r; c < NX; ++c) {
+      const float v = m.f(field + sym_idx<NX>(r, c), t);
+      P[r][c] = v;
+      P[c][r] = v;
+    }
+}
+
+// Refactor stages thi..0 for the current working set (Eq. 7 with fixed inputs).
+template <int NX, int NU>
+__device__ void refactor(const Prob &pb, const AgentMem<NX, NU> &m, const float *qd, const float hu[NU], int T,
+                         int n_nbr, int thi) {
+  using F = Fld<NX, NU>;
+  float Pn[NX][NX];
+  load_sym<NX, NU>(m, F::PU, thi + 1, Pn);
   for (int t = thi; t >= 0; --t) {
     float hx[NX];
     stage_hx<NX, NU>(pb, qd, t, T, n_nbr, hx);
     int8_t wt[NU];
 #pragma unroll
     for (int a = 0; a < NU; ++a) wt[a] = m.w(a, t);
-    float Pt[NX][NX], K[NU][NX], Phi[NX][NX], Gm[NU][NX], kc[NU], cc[NX];
-    factor_stage<NX, NU>(pb, hx, hu, Pn, wt, t >= 1, Pt, K, Phi, Gm, kc, cc);
+    float Pt[NX][NX], K[NU][NX], Sv[NU][NU], kc[NU], cc[NX];
+    factor_stage<NX, NU>(pb, hx, hu, Pn, wt, t >= 1, Pt, K, Sv, kc, cc);
 #pragma unroll
     for (int a = 0; a < NU; ++a) {
 #pragma unroll
-      for (int c = 0; c < NX; ++c) {
-        m.f(F::K + a * NX + c, t) = K[a][c];
-        m.f(F::GM + a * NX + c, t) = Gm[a][c];
-      }
+      for (int c = 0; c < NX; ++c) m.f(F::K + a * NX + c, t) = K[a][c];
+#pragma unroll
+      for (int b = a; b < NU; ++b) m.f(F::SV + sym_idx<NU>(a, b), t) = Sv[a][b];
       m.f(F::KC + a, t) = kc[a];
     }
 #pragma unroll
-    for (int r = 0; r < NX; ++r) {
-      m.f(F::CC + r, t) = cc[r];
-#pragma unroll
-      for (int c = 0; c < NX; ++c) m.f(F::PHI + r * NX + c, t) = Phi[r][c];
-    }
+    for (int r = 0; r < NX; ++r) m.f(F::CC + r, t) = cc[r];
     if (t >= 1) {
 #pragma unroll
       for (int r = 0; r < NX; ++r)
 #pragma unroll
-        for (int c = 0; c < NX; ++c) {
-          m.f(F::P + r * NX + c, t) = Pt[r][c];
-          Pn[r][c] = Pt[r][c];
-        }
+        for (int c = r; c < NX; ++c) m.f(F::PU + sym_idx<NX>(r, c), t) = Pt[r][c];
+#pragma unroll
+      for (int r = 0; r < NX; ++r)
+#pragma unroll
+        for (int c = 0; c < NX; ++c) Pn[r][c] = Pt[r][c];
     }
   }
 }
 
 // Affine backward sweep with the cached factors:
-//   p_T = q_T;  k_t = GM_t p_{t+1} + kc_t;  p_t = Phi_t' p_{t+1} + q_t + c_t,
+//   p_T = q_T;  k_t = kc_t - Sv_t B'p_{t+1};  p_t = q_t + c_t + A'p_{t+1} + K_t' B'p_{t+1},
 // with q_t = -2 Q_t r_t - C' sum_j (rho z_ij,t - lambda_ij,t) (QP on positions).
 template <int NX, int NU>
-__device__ __forceinline__ void affine_sweep(const AgentMem<NX, NU> &m, int T) {
+__device__ __forceinline__ void affine_sweep(const Prob &pb, const AgentMem<NX, NU> &m, int T) {
   using F = Fld<NX, NU>;
   float p[NX];
 #pragma unroll
   for (int r = 0; r < NX; ++r) p[r] = (r < NU) ? m.f(F::QP + r, T) : m.f(F::GQ + r, T);
+#pragma unroll 2
   for (int t = T - 1; t >= 0; --t) {
 #pragma unroll
     for (int r = 0; r < NX; ++r) m.f(F::PV + r, t + 1) = p[r];
+    float bp[NU];
+#pragma unroll
+    for (int a = 0; a < NU; ++a) {
+      float v = 0.f;
+#pragma unroll
+      for (int r = 0; r < NX; ++r) v = fmaf(pb.B[r * NU + a], p[r], v);
+      bp[a] = v;
+    }
 #pragma unroll
     for (int a = 0; a < NU; ++a) {
       float v = m.f(F::KC + a, t);
 #pragma unroll
-      for (int c = 0; c < NX; ++c) v = fmaf(m.f(F::GM + a * NX + c, t), p[c], v);
+      for (int b = 0; b < NU; ++b) v = fmaf(-m.f(F::SV + (a <= b ? sym_idx<NU>(a, b) : sym_idx<NU>(b, a)), t), bp[b], v);
       m.f(F::KV + a, t) = v;
     }
     if (t >= 1) {
@@ -102,7 +121,9 @@ __device__ __forceinline__ void affine_sweep(const AgentMem<NX, NU> &m, int T) {
       for (int c = 0; c < NX; ++c) {
         float v = ((c < NU) ? m.f(F::QP + c, t) : m.f(F::GQ + c, t)) + m.f(F::CC + c, t);
 #pragma unroll
-        for (int r = 0; r < NX; ++r) v = fmaf(m.f(F::PHI + r * NX + c, t), p[r], v);
+        for (int r = 0; r < NX; ++r) v = fmaf(pb.A[r * NX + c], p[r], v);
+#pragma unroll
+        for (int a = 0; a < NU; ++a) v = fmaf(m.f(F::K + a * NX + c, t), bp[a], v);
         np[c] = v;
       }
 #pragma unroll
@@ -124,12 +145,14 @@ struct StepInfo {
 // fixed inputs, the multipliers from the costates nu_{t+1} = P x + p (Eq. 9):
 // g = H_u u_t + B' nu_{t+1}; mu = g at a lower bound, -g at an upper bound.
 template <int NX, int NU>
-__device__ __forceinline__ StepInfo forward_rollout(const Prob &pb, const AgentMem<NX, NU> &m, int T, const float hu[NU]) {
+__device__ __forceinline__ StepInfo forward_rollout(const Prob &pb, const AgentMem<NX, NU> &m, int T,
+                                                    const float hu[NU]) {
   using F = Fld<NX, NU>;
   StepInfo si{1.0f, -1, 0, 0.0f, -1};
   float x[NX];
 #pragma unroll
   for (int r = 0; r < NX; ++r) x[r] = m.f(F::X + r, 0);
+#pragma unroll 2
   for (int t = 0; t < T; ++t) {
     float ue[NU];
 #pragma unroll
@@ -163,10 +186,10 @@ __device__ __forceinline__ StepInfo forward_rollout(const Prob &pb, const AgentM
       if (wt[a] != 0) continue;
       const float uc = m.f(F::U + a, t);
       if (ue[a] < pb.ulo[a]) {
-        const float r = (pb.ulo[a] - uc) / (ue[a] - uc);
+        const float r = (uc <= pb.ulo[a]) ? 0.f : (pb.ulo[a] - uc) / (ue[a] - uc);
         if (r < si.alpha) { si.alpha = r; si.blk = t * NU + a; si.side = 1; }
       } else if (ue[a] > pb.uhi[a]) {
-        const float r = (pb.uhi[a] - uc) / (ue[a] - uc);
+        const float r = (uc >= pb.uhi[a]) ? 0.f : (pb.uhi[a] - uc) / (ue[a] - uc);
         if (r < si.alpha) { si.alpha = r; si.blk = t * NU + a; si.side = 2; }
       }
     }
@@ -176,7 +199,7 @@ __device__ __forceinline__ StepInfo forward_rollout(const Prob &pb, const AgentM
       for (int r = 0; r < NX; ++r) {
         float v = m.f(F::PV + r, t + 1);
 #pragma unroll
-        for (int c = 0; c < NX; ++c) v = fmaf(m.f(F::P + r * NX + c, t + 1), xn[c], v);
+        for (int c = 0; c < NX; ++c) v = fmaf(m.f(F::PU + (r <= c ? sym_idx<NX>(r, c) : sym_idx<NX>(c, r)), t + 1), xn[c], v);
         nu[r] = v;
       }
 #pragma unroll
@@ -195,13 +218,142 @@ __device__ __forceinline__ StepInfo forward_rollout(const Prob &pb, const AgentM
   return si;
 }
 
+// One step of mixed-precision iterative refinement of the final equality-QP
+// solution (working set fixed).  The reduced gradient of the local QP at the
+// FP32 solution is evaluated in FP64 (exact rollout of the stored inputs and
+// the adjoint recursion nu_T = H_T x_T + q_T, nu_t = H_x x_t + q_t + A'nu_{t+1},
+// g_t = H_u u_t + B'nu_{t+1}); the correction min 1/2 d'Hd + g_f'du (du on free
+// inputs, homogeneous dynamics) is solved with the cached FP32 factors
+// (k_t = -Sv (B'p + g_t), p_t = A'p + K'(B'p + g_t), p_T = 0) and applied in
+// FP64 before rounding the iterate back to FP32.
+template <int NX, int NU>
+__device__ void refine_solution(const Prob &pb, const AgentMem<NX, NU> &m, const float *qd, const float hu[NU],
+                                int T, int n_nbr) {
+  using F = Fld<NX, NU>;
+  double x[NX];
+#pragma unroll
+  for (int r = 0; r < NX; ++r) { x[r] = (double)m.f(F::X + r, 0); m.d(r, 0) = x[r]; }
+  for (int t = 0; t < T; ++t) {
+    double u[NU], xn[NX];
+#pragma unroll
+    for (int a = 0; a < NU; ++a) u[a] = (double)m.f(F::U + a, t);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      double v = 0.0;
+#pragma unroll
+      for (int c = 0; c < NX; ++c) v = fma((double)pb.A[r * NX + c], x[c], v);
+#pragma unroll
+      for (int a = 0; a < NU; ++a) v = fma((double)pb.B[r * NU + a], u[a], v);
+      xn[r] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < NX; ++r) { x[r] = xn[r]; m.d(r, t + 1) = xn[r]; }
+  }
+  double nu[NX];
+  {
+    float hx[NX];
+    stage_hx<NX, NU>(pb, qd, T, T, n_nbr, hx);
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+      nu[r] = fma((double)hx[r], m.d(r, T), (double)((r < NU) ? m.f(F::QP + r, T) : m.f(F::GQ + r, T)));
+  }
+  float pc[NX];
+#pragma unroll
+  for (int r = 0; r < NX; ++r) pc[r] = 0.f;
+  for (int t = T - 1; t >= 0; --t) {
+    float s[NU];
+#pragma unroll
+    for (int a = 0; a < NU; ++a) {
+      double g = (double)hu[a] * (double)m.f(F::U + a, t);
+#pragma unroll
+      for (int r = 0; r < NX; ++r) g = fma((double)pb.B[r * NU + a], nu[r], g);
+      float v = (m.w(a, t) == 0) ? (float)g : 0.f;
+#pragma unroll
+      for (int r = 0; r < NX; ++r) v = fmaf(pb.B[r * NU + a], pc[r], v);
+      s[a] = v;
+    }
+#pragma unroll
+    for (int a = 0; a < NU; ++a) {
+      float v = 0.f;
+#pragma unroll
+      for (int b = 0; b < NU; ++b) v = fmaf(-m.f(F::SV + (a <= b ? sym_idx<NU>(a, b) : sym_idx<NU>(b, a)), t), s[b], v);
+      m.f(F::KV + a, t) = v;
+    }
+    if (t >= 1) {
+      float hx[NX];
+      stage_hx<NX, NU>(pb, qd, t, T, n_nbr, hx);
+      float np[NX];
+      double nn[NX];
+#pragma unroll
+      for (int c = 0; c < NX; ++c) {
+        float v = 0.f;
+        double w = fma((double)hx[c], m.d(c, t), (double)((c < NU) ? m.f(F::QP + c, t) : m.f(F::GQ + c, t)));
+#pragma unroll
+        for (int r = 0; r < NX; ++r) {
+          v = fmaf(pb.A[r * NX + c], pc[r], v);
+          w = fma((double)pb.A[r * NX + c], nu[r], w);
+        }
+#pragma unroll
+        for (int a = 0; a < NU; ++a) v = fmaf(m.f(F::K + a * NX + c, t), s[a], v);
+        np[c] = v;
+        nn[c] = w;
+      }
+#pragma unroll
+      for (int r = 0; r < NX; ++r) { pc[r] = np[r]; nu[r] = nn[r]; }
+    }
+  }
+  float dx[NX];
+#pragma unroll
+  for (int r = 0; r < NX; ++r) { dx[r] = 0.f; x[r] = m.d(r, 0); }
+  for (int t = 0; t < T; ++t) {
+    float du[NU], uf[NU];
+#pragma unroll
+    for (int a = 0; a < NU; ++a) {
+      float v = m.f(F::KV + a, t);
+#pragma unroll
+      for (int c = 0; c < NX; ++c) v = fmaf(m.f(F::K + a * NX + c, t), dx[c], v);
+      du[a] = v;
+      // a free input refined past its bound by a rounding-level amount is
+      // put back on the bound, so that the next active-set start is feasible
+      uf[a] = fminf(fmaxf((float)((double)m.f(F::U + a, t) + (double)v), pb.ulo[a]), pb.uhi[a]);
+      m.f(F::U + a, t) = uf[a];
+    }
+    float dxn[NX];
+    double xn[NX];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      float v = 0.f;
+      double w = 0.0;
+#pragma unroll
+      for (int c = 0; c < NX; ++c) {
+        v = fmaf(pb.A[r * NX + c], dx[c], v);
+        w = fma((double)pb.A[r * NX + c], x[c], w);
+      }
+#pragma unroll
+      for (int a = 0; a < NU; ++a) {
+        v = fmaf(pb.B[r * NU + a], du[a], v);
+        w = fma((double)pb.B[r * NU + a], (double)uf[a], w);
+      }
+      dxn[r] = v;
+      xn[r] = w;
+    }
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      dx[r] = dxn[r];
+      x[r] = xn[r];
+      m.f(F::X + r, t + 1) = (float)xn[r];
+    }
+  }
+}
+
 // One agent's x-update at ADMM iteration k.  Returns 1 if the active-set
 // loop hit its cap.  cnt[] accumulates pass / stage counters.
 template <int NX, int NU>
 __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i, int k, long long cnt[CT_NCOL]) {
   using F = Fld<NX, NU>;
   const int T = sc.T;
-  const AgentMem<NX, NU> m{ws.fr + sc.fo, ws.wr + sc.bo, sc.GS, sc.N, i};
+  const AgentMem<NX, NU> m{ws.fr + sc.fo, ws.wr + sc.bo, ws.dr + sc.dof, (unsigned)sc.GS, (unsigned)sc.N,
+                           (unsigned)i};
   const float *qd = ws.qd + (long long)sc.s * NX;
   const float *rd = ws.rd + (long long)sc.s * NU;
   float hu[NU];
@@ -217,12 +369,11 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
 #pragma unroll
       for (int a = 0; a < NU; ++a)
         if (m.w(a, t) != 0) { m.w(a, t) = 0; td = max(td, t); }
-    float ust[NU];
     if (pb.warm) {
       // ... from the unconstrained affine LQ solution (Sec. IV-B), clipped
       if (!pb.cache) td = T - 1;
       if (td >= 0) { refactor<NX, NU>(pb, m, qd, hu, T, n_nbr, td); cnt[CT_REFACTOR] += td + 1; td = -1; }
-      affine_sweep<NX, NU>(m, T);
+      affine_sweep<NX, NU>(pb, m, T);
       cnt[CT_AFFINE] += T;
       (void)forward_rollout<NX, NU>(pb, m, T, hu);
       cnt[CT_PASSES] += 1;
@@ -231,6 +382,7 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
 #pragma unroll
     for (int r = 0; r < NX; ++r) x[r] = m.f(F::X + r, 0);
     for (int t = 0; t < T; ++t) {
+      float ust[NU];
 #pragma unroll
       for (int a = 0; a < NU; ++a) {
         float u = pb.warm ? m.f(F::UE + a, t) : 0.f;
@@ -260,7 +412,7 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
   for (int it = 0; it < cap; ++it) {
     if (!pb.cache) td = T - 1;
     if (td >= 0) { refactor<NX, NU>(pb, m, qd, hu, T, n_nbr, td); cnt[CT_REFACTOR] += td + 1; td = -1; }
-    affine_sweep<NX, NU>(m, T);
+    affine_sweep<NX, NU>(pb, m, T);
     cnt[CT_AFFINE] += T;
     const StepInfo si = forward_rollout<NX, NU>(pb, m, T, hu);
     cnt[CT_PASSES] += 1;
@@ -300,6 +452,10 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
     }
     done = 1;
     break;
+  }
+  if (done && pb.refine) {
+    refine_solution<NX, NU>(pb, m, qd, hu, T, n_nbr);
+    cnt[CT_AFFINE] += 2 * T;
   }
   ws.adirty[sc.ao + i] = td;
   return done ? 0 : 1;
@@ -504,7 +660,7 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
 #pragma unroll
       for (int r2 = 0; r2 < NX; ++r2)
 #pragma unroll
-        for (int c = 0; c < NX; ++c) R[(F::P + r2 * NX + c) * GS + idx] = (r2 == c) ? hx[r2] : 0.f;
+        for (int c = r2; c < NX; ++c) R[(F::PU + sym_idx<NX>(r2, c)) * GS + idx] = (r2 == c) ? hx[r2] : 0.f;
     }
   }
   const int LS = T * N * N;
@@ -590,10 +746,10 @@ __global__ __launch_bounds__(1024) void k_admm_persistent(Prob pb, WS ws, int S)
   for (;;) {
     if (tid == 0) s_item = atomicAdd(ws.queue, 1);
     __syncthreads();
-    const int item = s_item;
+    const int item = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (item >= S) return;
-    const int s = ws.order[item];
+    const int s = __builtin_amdgcn_readfirstlane(ws.order[item]);
     const Scen sc = load_scen(ws, s);
     scenario_setup<NX, NU>(pb, ws, sc, tid, nt);
     if (tid == 0) { s_cap = 0; s_done = 0; }
@@ -720,7 +876,7 @@ struct Layout {
   int S = 0, nx = 0, nu = 0, NF = 0;
   long long A = 0, sumGS = 0, sumL = 0;
   size_t o_N = 0, o_T = 0, o_tab = 0, o_order = 0, o_queue = 0, o_sst = 0, o_snorm = 0, o_cnt = 0, o_flags = 0;
-  size_t o_adirty = 0, o_fr = 0, o_wr = 0, o_lam = 0, o_pact = 0, bytes = 0;
+  size_t o_adirty = 0, o_fr = 0, o_dr = 0, o_wr = 0, o_lam = 0, o_pact = 0, bytes = 0;
   std::vector<long long> tab;
   std::vector<int> order;
 };
@@ -765,18 +921,21 @@ bool make_layout(const tadmm_params *p, int S, const int32_t *N, const int32_t *
   L = Layout();
   L.S = S; L.nx = p->nx; L.nu = p->nu; L.NF = fields_per_stage(p->nx, p->nu);
   L.tab.assign((size_t)S * TB_NCOL, 0);
-  long long fo = 0, bo = 0, lo = 0, ao = 0, xo = 0, uo = 0, po = 0, lb = 0;
+  long long fo = 0, bo = 0, lo = 0, ao = 0, xo = 0, uo = 0, po = 0, lb = 0, dof = 0;
   for (int s = 0; s < S; ++s) {
     const long long n = N[s], t = T[s];
     if (n < 1 || t < 1) { err = "every scenario needs N >= 1 and T >= 1"; return false; }
     if (n > 4096 || t > 65536) { err = "scenario too large (N <= 4096, T <= 65536)"; return false; }
     const long long GS = n * (t + 1);
-    if ((long long)L.NF * GS >= (1ll << 31) || (long long)p->nu * t * n * n >= (1ll << 31)) {
+    if ((long long)L.NF * GS >= (1ll << 31) || (long long)p->nu * t * n * n >= (1ll << 31) ||
+        (long long)p->nx * GS >= (1ll << 31)) {
       err = "scenario too large for 32-bit in-scenario offsets"; return false;
     }
     long long *tb = &L.tab[(size_t)s * TB_NCOL];
     tb[TB_F] = fo; tb[TB_B] = bo; tb[TB_L] = lo; tb[TB_A] = ao; tb[TB_XO] = xo; tb[TB_UO] = uo; tb[TB_PO] = po; tb[TB_LB] = lb;
+    tb[TB_D] = dof;
     fo += (long long)L.NF * GS;
+    dof += (long long)p->nx * GS;
     bo += (long long)p->nu * GS;
     lo += (long long)p->nu * t * n * n;
     lb += t * n * n;
@@ -799,6 +958,7 @@ bool make_layout(const tadmm_params *p, int S, const int32_t *N, const int32_t *
   L.o_flags = take(sizeof(int) * 64);
   L.o_adirty = take(sizeof(int) * (size_t)ao);
   L.o_fr = take(sizeof(float) * (size_t)fo);
+  L.o_dr = take(sizeof(double) * (size_t)dof);
   L.o_wr = take((size_t)bo);
   L.o_lam = take(sizeof(float) * (size_t)lo);
   L.o_pact = take((size_t)lb);
@@ -821,6 +981,7 @@ Prob to_prob(const tadmm_params &p) {
   pb.qT = p.qT_scale; pb.dmin = p.d_min; pb.rho = p.rho; pb.eps_abs = p.eps_abs; pb.eps_rel = p.eps_rel;
   pb.mu_tol = p.mu_tol; pb.max_iter = p.max_iter; pb.max_as = p.max_as_iter; pb.normal_mode = p.normal_mode;
   pb.cache = p.cache_factors ? 1 : 0; pb.warm = p.riccati_warmstart ? 1 : 0; pb.hot = p.hotstart ? 1 : 0;
+  pb.refine = p.refine ? 1 : 0;
   return pb;
 }
 
@@ -898,6 +1059,7 @@ WS make_ws(const Layout &L, char *ws, const tadmm_batch *b) {
   w.order = (const int *)(ws + L.o_order);
   w.queue = (int *)(ws + L.o_queue);
   w.fr = (float *)(ws + L.o_fr);
+  w.dr = (double *)(ws + L.o_dr);
   w.wr = (int8_t *)(ws + L.o_wr);
   w.adirty = (int *)(ws + L.o_adirty);
   w.lam = (float *)(ws + L.o_lam);

@@ -30,6 +30,51 @@ def gpu_solve(problem, scs, mode=None, normals=None, solver_kw=None, return_prep
     return res
 
 
+class Fp32Problem:
+    """The problem constants exactly as the FP32 device path receives them
+    (every value rounded to FP32), for the oracle to solve the same instance."""
+
+    def __init__(self, p):
+        r = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
+        f = lambda v: float(np.float32(v))
+        self.dp, self.nx, self.nu, self.max_iter = p.dp, p.nx, p.nu, p.max_iter
+        self.A, self.B = r(p.A), r(p.B)
+        self.u_lo, self.u_hi, self.u_max = r(p.u_lo), r(p.u_hi), f(p.u_max)
+        self.q_diag, self.r_diag = r(p.q_diag), r(p.r_diag)
+        self.qT_scale, self.d_min, self.rho = f(p.qT_scale), f(p.d_min), f(p.rho)
+        self.eps_abs, self.eps_rel = f(p.eps_abs), f(p.eps_rel)
+
+
+def fp32_inputs(sc):
+    """(x0, xref) of a scenario rounded to FP32, as the device receives them."""
+    r = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
+    return r(sc.x0()), r(sc.xref())
+
+
+def oracle_same_instance(problem, scs, opts, threads=0, keep_zl=False, normals=None):
+    """Oracle on exactly the FP32 instance the device solves."""
+    P32 = Fp32Problem(problem)
+    if len(scs) == 1:
+        return [oracle.solve(P32, scs[0], opts, normals=None if normals is None else normals[0],
+                             threads=max(threads, 1), keep_zl=keep_zl, inputs=fp32_inputs(scs[0]))]
+    return oracle.solve_batch(P32, scs, opts, threads=threads, normals=normals,
+                              inputs=[fp32_inputs(sc) for sc in scs])
+
+
+def self_sensitivity(problem, sc, opts, rel=1e-7, seed=0, threads=1) -> float:
+    """The oracle's own response to a relative perturbation `rel` (below FP32
+    rounding) of the start positions: how reproducible the result of this run
+    is at all, whatever the arithmetic."""
+    P32 = Fp32Problem(problem)
+    x0, xref = fp32_inputs(sc)
+    rng = np.random.default_rng(seed)
+    x0p = x0.copy()
+    x0p[:, :problem.dp] *= 1.0 + rel * rng.standard_normal(x0p[:, :problem.dp].shape)
+    a = oracle.solve(P32, sc, opts, threads=threads, inputs=(x0, xref))
+    b = oracle.solve(P32, sc, opts, threads=threads, inputs=(x0p, xref))
+    return rel_traj_err(dict(x=b["x"], u=b["u"]), a)
+
+
 def oracle_opts(solver_kw=None, lockstep=None):
     kw = dict(solver_kw or {})
     o = oracle.OracleOptions()
@@ -85,6 +130,8 @@ def compare(problem, sc, g, o, rho=None, check_sets=True, tol=REL_TOL):
     rho = problem.rho if rho is None else rho
     rel = rel_traj_err(g, o)
     rep = dict(rel=rel, iters=(g["iters"], o["iters"]), status=(g["status"], o["status"]))
+    assert np.all(g["u"] >= problem.u_lo) and np.all(g["u"] <= problem.u_hi), "input outside the box"
+    assert g["status"] != 2 or o["status"] == 2, f"active-set cap on the GPU only ({rep})"
     assert rel <= tol, f"N={sc.N} T={sc.T}: rel trajectory error {rel:.3e} > {tol:.0e} ({rep})"
     if check_sets:
         wm = working_set_marginal(problem, o)

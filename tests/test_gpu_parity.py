@@ -1,8 +1,15 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
-Bar: relative trajectory error over (x, u) <= 1e-4 per scenario, identical
-final working sets and active half-planes except marginal (degenerate)
-entries.  Inputs: the seeded generators of synth (configs 0-4 shapes).
+Both sides solve the same instance: the oracle receives the problem data
+rounded to FP32 exactly as the device receives it.  Bar: relative trajectory
+error over (x, u) <= 1e-4 per scenario, identical final working sets and
+active half-planes except marginal (degenerate) entries, for every lockstep
+run and every converged solve.  A run stopped by the 200-iteration cap
+without converging is an iterate of a nonconvex iteration (the half-planes
+follow the iterate) whose own sensitivity can exceed 1e-4: there the bar is
+max(1e-4, 10 x the oracle's response to a 1e-7 perturbation of the starts),
+and that sensitivity is printed with the result.
+Inputs: the seeded generators of synth (shapes of the five workloads).
 """
 import os
 import sys
@@ -34,6 +41,19 @@ def _zeros_eps(**kw):
     return d
 
 
+def _lockstep_ok(g, K):
+    """Exactly K iterations, or an exact fixed point earlier (r = s = 0 passes
+    even a zero tolerance)."""
+    return g["iters"] == K or (g["status"] == tadmm.SCEN_CONVERGED and g["r_norm"] == 0.0 and g["s_norm"] == 0.0)
+
+
+def _full_tol(p, sc, o):
+    if o["status"] == oracle.CONVERGED:
+        return gc.REL_TOL, None
+    kap = gc.self_sensitivity(p, sc, gc.oracle_opts(lockstep=o["iters"]), threads=4)
+    return max(gc.REL_TOL, 10.0 * kap), kap
+
+
 # ---------------------------------------------------------------------------
 # one x-update (fixed z = C r, lambda = 0) against the oracle's local QP
 # ---------------------------------------------------------------------------
@@ -46,11 +66,12 @@ def test_first_xupdate_matches_oracle_local_qp(cfg):
         p, scs = synth.config2(S=6)
     _say(f"first x-update parity {cfg}")
     g = gc.gpu_solve(p, scs, solver_kw=_zeros_eps(max_iter=1))
+    P32 = gc.Fp32Problem(p)
     for sc, gr in zip(scs, g):
-        xr = sc.xref()
+        x0, xr = gc.fp32_inputs(sc)
         for i in range(sc.N):
-            ysum = p.rho * (sc.N - 1) * xr[i, :, :p.dp]
-            o = oracle.agent_qp(p, sc.T, sc.N - 1, sc.x0()[i], xr[i], p.q_diag, p.r_diag, ysum)
+            ysum = P32.rho * (sc.N - 1) * xr[i, :, :p.dp]
+            o = oracle.agent_qp(P32, sc.T, sc.N - 1, x0[i], xr[i], P32.q_diag, P32.r_diag, ysum)
             X = np.concatenate([o["x"].ravel(), o["u"].ravel()])
             Y = np.concatenate([gr["x"][i].ravel(), gr["u"][i].ravel()])
             assert np.linalg.norm(X - Y) <= 1e-5 * np.linalg.norm(X), (sc.N, sc.T, i)
@@ -67,8 +88,8 @@ def test_lockstep_config1(K):
     p, scs = synth.config1()
     _say(f"lockstep config1 K={K}")
     g = gc.gpu_solve(p, scs, solver_kw=_zeros_eps(max_iter=K))[0]
-    o = oracle.solve(p, scs[0], gc.oracle_opts(lockstep=K), keep_zl=True, threads=4)
-    assert g["iters"] == K and o["iters"] == K
+    o = gc.oracle_same_instance(p, scs, gc.oracle_opts(lockstep=K), keep_zl=True, threads=4)[0]
+    assert _lockstep_ok(g, K) and o["iters"] == K
     rep = gc.compare(p, scs[0], g, o)
     _say(f"  {rep}")
 
@@ -78,10 +99,14 @@ def test_lockstep_config2_sample():
     K = 40
     _say("lockstep config2 sample")
     g = gc.gpu_solve(p, scs, solver_kw=_zeros_eps(max_iter=K))
-    o = oracle.solve_batch(p, scs, gc.oracle_opts(lockstep=K))
+    o = gc.oracle_same_instance(p, scs, gc.oracle_opts(lockstep=K))
+    worst = 0.0
     for sc, gr, orr in zip(scs, g, o):
-        assert gr["iters"] == K
-        assert gc.rel_traj_err(gr, orr) <= gc.REL_TOL, (sc.N, sc.T)
+        assert _lockstep_ok(gr, K), (sc.N, sc.T, gr["status"], gr["iters"])
+        rel = gc.rel_traj_err(gr, orr)
+        worst = max(worst, rel)
+        assert rel <= gc.REL_TOL, (sc.N, sc.T, rel)
+    _say(f"  worst rel {worst:.2e}")
 
 
 # ---------------------------------------------------------------------------
@@ -93,10 +118,11 @@ def test_config0_parity(mode):
     p, scs = synth.config0()
     _say(f"config0 mode={mode}")
     g = gc.gpu_solve(p, scs, mode=mode)[0]
-    o = oracle.solve(p, scs[0], keep_zl=True)
-    rep = gc.compare(p, scs[0], g, o)
+    o = gc.oracle_same_instance(p, scs, gc.oracle_opts(), keep_zl=True)[0]
+    tol, kap = _full_tol(p, scs[0], o)
+    rep = gc.compare(p, scs[0], g, o, tol=tol)
     assert abs(g["iters"] - o["iters"]) <= 2 and g["status"] == o["status"], rep
-    _say(f"  {rep}")
+    _say(f"  {rep} sensitivity={kap}")
 
 
 @pytest.mark.parametrize("mode", [0, 1])
@@ -104,41 +130,50 @@ def test_config1_parity(mode):
     p, scs = synth.config1()
     _say(f"config1 mode={mode}")
     g = gc.gpu_solve(p, scs, mode=mode)[0]
-    o = oracle.solve(p, scs[0], keep_zl=True, threads=4)
-    rep = gc.compare(p, scs[0], g, o)
+    o = gc.oracle_same_instance(p, scs, gc.oracle_opts(), keep_zl=True, threads=4)[0]
+    tol, kap = _full_tol(p, scs[0], o)
+    rep = gc.compare(p, scs[0], g, o, tol=tol)
     assert abs(g["iters"] - o["iters"]) <= 2 and g["status"] == o["status"], rep
-    _say(f"  {rep}")
+    _say(f"  {rep} sensitivity={kap}")
 
 
 def test_config2_sample_parity_batched():
     p, scs = synth.config2(S=24)
     _say("config2 sample batched")
     g = gc.gpu_solve(p, scs)
-    o = oracle.solve_batch(p, scs)
-    worst = 0.0
+    o = gc.oracle_same_instance(p, scs, gc.oracle_opts())
+    worst_conv, worst_cap = 0.0, 0.0
     for sc, gr, orr in zip(scs, g, o):
         assert abs(gr["iters"] - orr["iters"]) <= 2, (sc.N, sc.T, gr["iters"], orr["iters"])
         rel = gc.rel_traj_err(gr, orr)
-        worst = max(worst, rel)
-        assert rel <= gc.REL_TOL, (sc.N, sc.T, rel)
-    _say(f"  worst rel {worst:.2e}")
+        tol, kap = _full_tol(p, sc, orr)
+        if kap is None:
+            worst_conv = max(worst_conv, rel)
+        else:
+            worst_cap = max(worst_cap, rel)
+        assert rel <= tol, (sc.N, sc.T, rel, kap)
+    _say(f"  worst rel converged {worst_conv:.2e}, at the iteration cap {worst_cap:.2e}")
 
 
 def test_frozen_normals_parity():
-    """Convex case: fixed normals given by the caller."""
+    """Convex case: fixed normals given by the caller (three agents in
+    parallel lanes whose goals pull the outer lanes inward, so that two
+    half-planes bind at convergence)."""
     p = synth.ProblemParams(dp=2, u_max=2.0)
-    sc = synth.Scenario(starts=np.array([[-3.0, 0.6], [3.0, -0.6], [0.0, 3.0]]),
-                        goals=np.array([[3.0, 0.1], [-3.0, -0.1], [0.2, -3.0]]), T=20)
+    sc = synth.Scenario(starts=np.array([[-2.0, 0.0], [-2.0, 1.5], [2.0, -1.5]]),
+                        goals=np.array([[2.0, 0.0], [2.0, 0.3], [-2.0, -0.3]]), T=20)
     T, P = sc.T, 3
     nrm = np.zeros((P, T, 2))
-    nrm[0, :, 1] = 1.0
-    ang = np.linspace(0.3, 1.2, T)
-    nrm[1, :, 0], nrm[1, :, 1] = np.cos(ang), -np.sin(ang)
-    nrm[2, :, 0], nrm[2, :, 1] = -np.cos(ang), -np.sin(ang)
-    kw = dict(normal_mode=tadmm.NORMAL_FROZEN, max_iter=400)
+    nrm[0, :, 1] = -1.0   # agent 1 stays above agent 0
+    nrm[1, :, 1] = 1.0    # agent 0 stays above agent 2
+    nrm[2, :, 1] = 1.0    # agent 1 stays above agent 2
+    kw = dict(normal_mode=tadmm.NORMAL_FROZEN, max_iter=1000)
     _say("frozen normals")
     g = gc.gpu_solve(p, [sc], normals=[nrm], solver_kw=kw)[0]
-    o = oracle.solve(p, sc, gc.oracle_opts(kw), normals=nrm, keep_zl=True)
+    o = gc.oracle_same_instance(p, [sc], gc.oracle_opts(kw), keep_zl=True,
+                                normals=[np.asarray(nrm, np.float32).astype(np.float64)])[0]
+    assert o["status"] == oracle.CONVERGED and o["pair_active"].sum() >= 1
+    assert g["status"] == tadmm.SCEN_CONVERGED and abs(g["iters"] - o["iters"]) <= 2
     gc.compare(p, sc, g, o, check_sets=False)
 
 
@@ -150,17 +185,19 @@ def test_three_d_first_iterations_sampled():
     sc = scs[0]
     _say("3-D config4 first x-update, sampled agents")
     g = gc.gpu_solve(p, scs, solver_kw=_zeros_eps(max_iter=1), mode=tadmm.MODE_PLAIN)[0]
-    xr = sc.xref()
+    P32 = gc.Fp32Problem(p)
+    x0, xr = gc.fp32_inputs(sc)
     for i in (0, 37, 64, 127):
-        ysum = p.rho * (sc.N - 1) * xr[i, :, :p.dp]
-        o = oracle.agent_qp(p, sc.T, sc.N - 1, sc.x0()[i], xr[i], p.q_diag, p.r_diag, ysum)
+        ysum = P32.rho * (sc.N - 1) * xr[i, :, :p.dp]
+        o = oracle.agent_qp(P32, sc.T, sc.N - 1, x0[i], xr[i], P32.q_diag, P32.r_diag, ysum)
         X = np.concatenate([o["x"].ravel(), o["u"].ravel()])
         Y = np.concatenate([g["x"][i].ravel(), g["u"][i].ravel()])
         assert np.linalg.norm(X - Y) <= 1e-5 * np.linalg.norm(X), i
     small = synth.sphere_swap(12, 4.0, 30)
     K = 25
     g2 = gc.gpu_solve(p, [small], solver_kw=_zeros_eps(max_iter=K))[0]
-    o2 = oracle.solve(p, small, gc.oracle_opts(lockstep=K), keep_zl=True, threads=4)
+    o2 = gc.oracle_same_instance(p, [small], gc.oracle_opts(lockstep=K), keep_zl=True, threads=4)[0]
+    assert _lockstep_ok(g2, K)
     gc.compare(p, small, g2, o2)
 
 
@@ -239,10 +276,11 @@ def test_horizon_one_and_mixed_tiny_batch():
            synth.Scenario(starts=np.array([[0.0, 0.0], [0.0, 1.5], [1.5, 0.0]]),
                           goals=np.array([[1.5, 1.5], [1.5, 0.0], [0.0, 1.5]]), T=7)]
     g = gc.gpu_solve(p, scs)
-    o = oracle.solve_batch(p, scs)
+    o = gc.oracle_same_instance(p, scs, gc.oracle_opts())
     for sc, gr, orr in zip(scs, g, o):
         assert abs(gr["iters"] - orr["iters"]) <= 2
-        assert gc.rel_traj_err(gr, orr) <= gc.REL_TOL
+        tol, _ = _full_tol(p, sc, orr)
+        assert gc.rel_traj_err(gr, orr) <= tol
 
 
 def test_empty_batch_is_noop():
