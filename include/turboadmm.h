@@ -111,8 +111,8 @@ typedef struct {
   int32_t check_inputs;      /* 1: reject non-finite inputs / close starts with an
                                 error code (default); 0: skip the checks, a bad
                                 scenario ends with status NONFINITE                 */
-  int32_t block_threads;     /* batched mode workgroup size (64..1024, multiple of
-                                64); 0: use the context's tuned value              */
+  int32_t block_threads;     /* batched mode workgroup size: 64, 128, 192 or 256;
+                                0: use the context's tuned value                   */
   int32_t refine;            /* 1: one step of mixed-precision iterative refinement
                                 of every local QP solution (reduced gradient in
                                 FP64, correction with the FP32 factors) (default);

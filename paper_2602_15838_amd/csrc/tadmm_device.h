@@ -29,6 +29,7 @@ enum { NORMAL_PER_ITER = 0, NORMAL_FROZEN = 1 };
 // Problem constants by value in the kernel arguments.
 struct Prob {
   float A[36], B[18];
+  float dt, h;                   // double integrator: A = [[I, dt I], [0, I]], B = [[h I], [dt I]]
   float ulo[3], uhi[3];
   float qT, dmin, rho, eps_abs, eps_rel, mu_tol;
   int max_iter, max_as, normal_mode, cache, warm, hot, refine;
@@ -61,36 +62,42 @@ struct WS {
   const float *x0, *xref, *qd, *rd, *normals;
 };
 
-// Field layout inside a scenario's float region: component f of agent i at
-// stage t is at fr[F + f * GS + t * N + i], GS = N (T + 1).
+// Layout of a scenario's float region: array of structures over the
+// agent-stages g = t * N + i (t = 0..T, agent index fastest), NF floats each,
+// every field padded to a multiple of 4 floats so that a field group is one
+// 16-byte vector load and a field is an immediate offset from the agent-stage
+// base address.  The working set is [g][4] bytes, the FP64 refinement scratch
+// [g][NX] doubles.
+__host__ __device__ constexpr int pad4(int n) { return (n + 3) & ~3; }
+
 template <int NX, int NU>
 struct Fld {
   static constexpr int DP = NU;
   static constexpr int NS = NU * (NU + 1) / 2;  // packed symmetric NU x NU
   static constexpr int NP = NX * (NX + 1) / 2;  // packed symmetric NX x NX
-  static constexpr int X = 0;                 // current iterate x_t        [NX]
-  static constexpr int U = X + NX;            // current iterate u_t        [NU]
-  static constexpr int XE = U + NU;           // equality-QP solution x_t   [NX]
-  static constexpr int UE = XE + NX;          // equality-QP solution u_t   [NU]
-  static constexpr int PV = UE + NU;          // affine value term p_t      [NX]
-  static constexpr int KV = PV + NX;          // affine feedforward k_t     [NU]
-  static constexpr int GQ = KV + NU;          // -2 Q_t r_t                 [NX]
-  // linear term of the position block of the local QP:
-  //   q_t = -2 Q_t r_t - sum_j (rho z_ij,t - lambda_ij,t)
-  //       = GQ - rho n_nbr C x^k_t - sum_j (lambda_ij^(k-1) - 2 lambda_ij^k),
-  // formed once per iteration from the small dual part (no long sums of
-  // position-sized terms in FP32)
-  static constexpr int QP = GQ + NX;          //                            [DP]
-  static constexpr int XP = QP + DP;          // C x^k (positions of the previous iterate) [DP]
-  static constexpr int ZD = XP + DP;          // sum_j z_ij - n_nbr C x^k   [DP]
-  static constexpr int RED = ZD + DP;         // residual partial sums      [5]
-  // cached Riccati factor of stage t for the current working set
-  static constexpr int K = RED + 5;           // feedback gain K_t          [NU*NX]
-  static constexpr int SV = K + NU * NX;      // S'^-1 (zero on fixed rows) [NS]
-  static constexpr int KC = SV + NS;          // feedforward constant       [NU]
-  static constexpr int CC = KC + NU;          // value-gradient constant    [NX]
-  static constexpr int PU = CC + NX;          // value Hessian P_t (upper)  [NP]
-  static constexpr int NF = PU + NP;
+  // cached Riccati factor of stage t for the current working set (read by the sweep)
+  static constexpr int K = 0;                   // feedback gain K_t              [NU*NX]
+  static constexpr int SV = K + pad4(NU * NX);  // S'^-1 (zero on fixed rows)     [NS]
+  static constexpr int KC = SV + pad4(NS);      // feedforward constant           [NU]
+  static constexpr int CC = KC + pad4(NU);      // value-gradient constant c_t    [NX]
+  // linear term of the local QP at stage t:
+  //   q_t = -2 Q_t r_t - C' sum_j (rho z_ij,t - lambda_ij,t);
+  // its position part is rewritten by every consensus step as
+  //   GQP - rho n_nbr C x^k_t - sum_j (lambda_ij^(k-1) - 2 lambda_ij^k)
+  // from the small dual part (no long sums of position-sized terms in FP32)
+  static constexpr int Q = CC + pad4(NX);       //                                [NX]
+  static constexpr int PV = Q + pad4(NX);       // affine value term p_t          [NX]
+  static constexpr int KV = PV + pad4(NX);      // affine feedforward k_t         [NU]
+  static constexpr int U = KV + pad4(NU);       // current iterate u_t            [NU]
+  static constexpr int X = U + pad4(NU);        // current iterate x_t            [NX]
+  static constexpr int XE = X + pad4(NX);       // equality-QP solution x_t       [NX]
+  static constexpr int UE = XE + pad4(NX);      // equality-QP solution u_t       [NU]
+  static constexpr int XP = UE + pad4(NU);      // C x^k (previous positions)     [DP]
+  static constexpr int ZD = XP + pad4(DP);      // sum_j z_ij - n_nbr C x^k       [DP]
+  static constexpr int GQP = ZD + pad4(DP);     // -2 Q_t r_t, positions          [DP]
+  static constexpr int PU = GQP + pad4(DP);     // value Hessian P_t (upper)      [NP]
+  static constexpr int RED = PU + pad4(NP);     // residual partial sums          [5]
+  static constexpr int NF = RED + pad4(5);
 };
 
 template <int N>
@@ -113,17 +120,114 @@ struct Scen {
   long long fo, bo, lo, ao, xo, uo, po, lb, dof;
 };
 
+// Scenario descriptors are wave-uniform; readfirstlane tells the compiler so
+// (the table is read with vector loads because the kernels also write global
+// memory), which keeps the region bases in scalar registers.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ long long uni64(long long v) {
+  const unsigned lo = (unsigned)uni((int)(unsigned)(v & 0xffffffffll));
+  const unsigned hi = (unsigned)uni((int)(unsigned)((unsigned long long)v >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
 __device__ __forceinline__ Scen load_scen(const WS &ws, int s) {
   Scen sc;
-  sc.s = s;
-  sc.N = ws.N[s];
-  sc.T = ws.T[s];
+  sc.s = uni(s);
+  sc.N = uni(ws.N[sc.s]);
+  sc.T = uni(ws.T[sc.s]);
   sc.GS = sc.N * (sc.T + 1);
-  const long long *tb = ws.tab + (long long)s * TB_NCOL;
-  sc.fo = tb[TB_F]; sc.bo = tb[TB_B]; sc.lo = tb[TB_L]; sc.ao = tb[TB_A];
-  sc.xo = tb[TB_XO]; sc.uo = tb[TB_UO]; sc.po = tb[TB_PO]; sc.lb = tb[TB_LB]; sc.dof = tb[TB_D];
+  const long long *tb = ws.tab + (long long)sc.s * TB_NCOL;
+  sc.fo = uni64(tb[TB_F]); sc.bo = uni64(tb[TB_B]); sc.lo = uni64(tb[TB_L]); sc.ao = uni64(tb[TB_A]);
+  sc.xo = uni64(tb[TB_XO]); sc.uo = uni64(tb[TB_UO]); sc.po = uni64(tb[TB_PO]); sc.lb = uni64(tb[TB_LB]);
+  sc.dof = uni64(tb[TB_D]);
   return sc;
 }
+
+// ---------------------------------------------------------------------------
+// Dynamics x_{t+1} = A x_t + B u_t: products with A, A', B, B'.  The general
+// form reads A and B from the kernel arguments; the double-integrator form
+// (A = [[I, dt I], [0, I]], B = [[dt^2/2 I], [dt I]], positions first) uses
+// only dt and h = dt^2/2 and is selected by the host when A and B have it.
+// ---------------------------------------------------------------------------
+template <int NX, int NU, bool DI>
+struct Dyn;
+
+template <int NX, int NU>
+struct Dyn<NX, NU, false> {
+  template <class R>
+  __device__ static __forceinline__ void ax(const Prob &pb, const R *x, R *y) {
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      R v = R(0);
+#pragma unroll
+      for (int c = 0; c < NX; ++c) v = fma((R)pb.A[r * NX + c], x[c], v);
+      y[r] = v;
+    }
+  }
+  template <class R>
+  __device__ static __forceinline__ void atx(const Prob &pb, const R *x, R *y) {
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      R v = R(0);
+#pragma unroll
+      for (int r = 0; r < NX; ++r) v = fma((R)pb.A[r * NX + c], x[r], v);
+      y[c] = v;
+    }
+  }
+  template <class R>
+  __device__ static __forceinline__ void add_bu(const Prob &pb, const R *u, R *y) {
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      R v = y[r];
+#pragma unroll
+      for (int a = 0; a < NU; ++a) v = fma((R)pb.B[r * NU + a], u[a], v);
+      y[r] = v;
+    }
+  }
+  template <class R>
+  __device__ static __forceinline__ void btx(const Prob &pb, const R *x, R *y) {
+#pragma unroll
+    for (int a = 0; a < NU; ++a) {
+      R v = R(0);
+#pragma unroll
+      for (int r = 0; r < NX; ++r) v = fma((R)pb.B[r * NU + a], x[r], v);
+      y[a] = v;
+    }
+  }
+};
+
+template <int NX, int NU>
+struct Dyn<NX, NU, true> {
+  template <class R>
+  __device__ static __forceinline__ void ax(const Prob &pb, const R *x, R *y) {
+#pragma unroll
+    for (int c = 0; c < NU; ++c) {
+      y[c] = fma((R)pb.dt, x[NU + c], x[c]);
+      y[NU + c] = x[NU + c];
+    }
+  }
+  template <class R>
+  __device__ static __forceinline__ void atx(const Prob &pb, const R *x, R *y) {
+#pragma unroll
+    for (int c = 0; c < NU; ++c) {
+      y[c] = x[c];
+      y[NU + c] = fma((R)pb.dt, x[c], x[NU + c]);
+    }
+  }
+  template <class R>
+  __device__ static __forceinline__ void add_bu(const Prob &pb, const R *u, R *y) {
+#pragma unroll
+    for (int c = 0; c < NU; ++c) {
+      y[c] = fma((R)pb.h, u[c], y[c]);
+      y[NU + c] = fma((R)pb.dt, u[c], y[NU + c]);
+    }
+  }
+  template <class R>
+  __device__ static __forceinline__ void btx(const Prob &pb, const R *x, R *y) {
+#pragma unroll
+    for (int a = 0; a < NU; ++a) y[a] = fma((R)pb.dt, x[NU + a], (R)pb.h * x[a]);
+  }
+};
 
 // Stage weights (cost Eq. 1 without 1/2, penalty (rho/2)||.||^2 per partner):
 // H_x,t = 2 Q_t + rho n_nbr C'C with Q_T = qT Q; H_u = 2 R.
@@ -147,43 +251,33 @@ __device__ __forceinline__ void stage_hx(const Prob &pb, const float *qd, int t,
 // With these, the affine terms of the sweep are
 //   k_t = kc - Sv B'p_{t+1},   p_t = q_t + c + A'p_{t+1} + K' B'p_{t+1},
 // since A + B K is the closed loop and -Sv B' the gain of k_t on p_{t+1}.
-template <int NX, int NU>
+template <int NX, int NU, bool DI>
 __device__ __forceinline__ void factor_stage(const Prob &pb, const float hx[NX], const float hu[NU],
                                              const float Pn[NX][NX], const int8_t wt[NU], bool want_P,
                                              float Pt[NX][NX], float K[NU][NX], float Sv[NU][NU], float kc[NU],
                                              float cc[NX]) {
-  const float *A = pb.A;
-  const float *B = pb.B;
-  float PB[NX][NU];
+  using D = Dyn<NX, NU, DI>;
+  float PB[NX][NU];  // row r of P B is B' (row r of P), P symmetric
 #pragma unroll
-  for (int r = 0; r < NX; ++r)
-#pragma unroll
-    for (int c = 0; c < NU; ++c) {
-      float v = 0.f;
-#pragma unroll
-      for (int k = 0; k < NX; ++k) v = fmaf(Pn[r][k], B[k * NU + c], v);
-      PB[r][c] = v;
-    }
+  for (int r = 0; r < NX; ++r) D::btx(pb, Pn[r], PB[r]);
   float S[NU][NU];
 #pragma unroll
-  for (int a = 0; a < NU; ++a)
+  for (int b = 0; b < NU; ++b) {
+    float col[NX], sb[NU];
 #pragma unroll
-    for (int b = 0; b < NU; ++b) {
-      float v = (a == b) ? hu[a] : 0.f;
+    for (int r = 0; r < NX; ++r) col[r] = PB[r][b];
+    D::btx(pb, col, sb);
 #pragma unroll
-      for (int r = 0; r < NX; ++r) v = fmaf(B[r * NU + a], PB[r][b], v);
-      S[a][b] = v;
-    }
-  float M[NU][NX];  // B'P A = (P B)' A
+    for (int a = 0; a < NU; ++a) S[a][b] = sb[a] + ((a == b) ? hu[a] : 0.f);
+  }
+  float M[NU][NX];  // row a of B'P A is A' (column a of P B)
 #pragma unroll
-  for (int a = 0; a < NU; ++a)
+  for (int a = 0; a < NU; ++a) {
+    float col[NX];
 #pragma unroll
-    for (int c = 0; c < NX; ++c) {
-      float v = 0.f;
-#pragma unroll
-      for (int r = 0; r < NX; ++r) v = fmaf(PB[r][a], A[r * NX + c], v);
-      M[a][c] = v;
-    }
+    for (int r = 0; r < NX; ++r) col[r] = PB[r][a];
+    D::atx(pb, col, M[a]);
+  }
   bool fr[NU];
   float ub[NU];
 #pragma unroll
@@ -266,28 +360,24 @@ __device__ __forceinline__ void factor_stage(const Prob &pb, const float hx[NX],
     cc[r] = v;
   }
   if (want_P) {
-    float PA[NX][NX];
+    float PA[NX][NX];  // row r of P A is A' (row r of P)
 #pragma unroll
-    for (int r = 0; r < NX; ++r)
+    for (int r = 0; r < NX; ++r) D::atx(pb, Pn[r], PA[r]);
 #pragma unroll
-      for (int c = 0; c < NX; ++c) {
-        float v = 0.f;
+    for (int c = 0; c < NX; ++c) {
+      float col[NX], apa[NX];
 #pragma unroll
-        for (int k = 0; k < NX; ++k) v = fmaf(Pn[r][k], A[k * NX + c], v);
-        PA[r][c] = v;
-      }
+      for (int r = 0; r < NX; ++r) col[r] = PA[r][c];
+      D::atx(pb, col, apa);   // column c of A'P A
 #pragma unroll
-    for (int r = 0; r < NX; ++r)
-#pragma unroll
-      for (int c = r; c < NX; ++c) {
-        float v = (r == c) ? hx[r] : 0.f;
-#pragma unroll
-        for (int k = 0; k < NX; ++k) v = fmaf(A[k * NX + r], PA[k][c], v);
+      for (int r = 0; r <= c; ++r) {
+        float v = apa[r] + ((r == c) ? hx[r] : 0.f);
 #pragma unroll
         for (int a = 0; a < NU; ++a) v = fmaf(M[a][r], K[a][c], v);
         Pt[r][c] = v;
         Pt[c][r] = v;
       }
+    }
   }
 }
 

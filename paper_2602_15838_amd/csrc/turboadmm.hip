@@ -23,18 +23,19 @@ namespace tadmm {
 // ===========================================================================
 // Local QP of one agent (x-update)
 // ===========================================================================
-// Scenario-relative addressing: the scenario bases are uniform (scalar) and
-// every access uses a 32-bit offset field * GS + t * N + i.
+// Addressing: the scenario region bases are uniform; agent-stage g of agent i
+// at stage t is g = t * N + i, and field f of it is at R[g * NF + f] (32-bit
+// offsets, the field an immediate).
 template <int NX, int NU>
 struct AgentMem {
   float *__restrict__ R;
   int8_t *__restrict__ Wb;
   double *__restrict__ D;
   unsigned GS, N, i;
-  __device__ __forceinline__ unsigned o(int field, int t) const { return (unsigned)field * GS + (unsigned)t * N + i; }
-  __device__ __forceinline__ float &f(int field, int t) const { return R[o(field, t)]; }
-  __device__ __forceinline__ int8_t &w(int c, int t) const { return Wb[o(c, t)]; }
-  __device__ __forceinline__ double &d(int c, int t) const { return D[o(c, t)]; }
+  __device__ __forceinline__ unsigned g(int t) const { return (unsigned)t * N + i; }
+  __device__ __forceinline__ float &f(int field, int t) const { return R[g(t) * (unsigned)Fld<NX, NU>::NF + field]; }
+  __device__ __forceinline__ int8_t &w(int c, int t) const { return Wb[g(t) * 4u + c]; }
+  __device__ __forceinline__ double &d(int c, int t) const { return D[g(t) * (unsigned)NX + c]; }
 };
 
 template <int NX, int NU>
@@ -50,7 +51,7 @@ __device__ __forceinline__ void load_sym(const AgentMem<NX, NU> &m, int field, i
 }
 
 // Refactor stages thi..0 for the current working set (Eq. 7 with fixed inputs).
-template <int NX, int NU>
+template <int NX, int NU, bool DI>
 __device__ void refactor(const Prob &pb, const AgentMem<NX, NU> &m, const float *qd, const float hu[NU], int T,
                          int n_nbr, int thi) {
   using F = Fld<NX, NU>;
@@ -63,7 +64,7 @@ __device__ void refactor(const Prob &pb, const AgentMem<NX, NU> &m, const float 
 #pragma unroll
     for (int a = 0; a < NU; ++a) wt[a] = m.w(a, t);
     float Pt[NX][NX], K[NU][NX], Sv[NU][NU], kc[NU], cc[NX];
-    factor_stage<NX, NU>(pb, hx, hu, Pn, wt, t >= 1, Pt, K, Sv, kc, cc);
+    factor_stage<NX, NU, DI>(pb, hx, hu, Pn, wt, t >= 1, Pt, K, Sv, kc, cc);
 #pragma unroll
     for (int a = 0; a < NU; ++a) {
 #pragma unroll
@@ -90,40 +91,56 @@ __device__ void refactor(const Prob &pb, const AgentMem<NX, NU> &m, const float 
 // Affine backward sweep with the cached factors:
 //   p_T = q_T;  k_t = kc_t - Sv_t B'p_{t+1};  p_t = q_t + c_t + A'p_{t+1} + K_t' B'p_{t+1},
 // with q_t = -2 Q_t r_t - C' sum_j (rho z_ij,t - lambda_ij,t) (QP on positions).
+// The factors of stage t-1 are loaded into registers before the stores of
+// stage t are issued, so the memory latency overlaps the recurrence.
 template <int NX, int NU>
+struct SweepStage {
+  float K[NU][NX], sv[Fld<NX, NU>::NS], kc[NU], cq[NX];
+  __device__ __forceinline__ void load(const AgentMem<NX, NU> &m, int t) {
+    using F = Fld<NX, NU>;
+#pragma unroll
+    for (int a = 0; a < NU; ++a) {
+#pragma unroll
+      for (int c = 0; c < NX; ++c) K[a][c] = m.f(F::K + a * NX + c, t);
+      kc[a] = m.f(F::KC + a, t);
+    }
+#pragma unroll
+    for (int k = 0; k < F::NS; ++k) sv[k] = m.f(F::SV + k, t);
+#pragma unroll
+    for (int c = 0; c < NX; ++c) cq[c] = m.f(F::Q + c, t) + m.f(F::CC + c, t);
+  }
+};
+
+template <int NX, int NU, bool DI>
 __device__ __forceinline__ void affine_sweep(const Prob &pb, const AgentMem<NX, NU> &m, int T) {
   using F = Fld<NX, NU>;
   float p[NX];
 #pragma unroll
-  for (int r = 0; r < NX; ++r) p[r] = (r < NU) ? m.f(F::QP + r, T) : m.f(F::GQ + r, T);
-#pragma unroll 2
+  for (int r = 0; r < NX; ++r) p[r] = m.f(F::Q + r, T);
+  SweepStage<NX, NU> nxt;
+  nxt.load(m, T - 1);
   for (int t = T - 1; t >= 0; --t) {
+    const SweepStage<NX, NU> cur = nxt;
+    if (t >= 1) nxt.load(m, t - 1);
 #pragma unroll
     for (int r = 0; r < NX; ++r) m.f(F::PV + r, t + 1) = p[r];
     float bp[NU];
+    Dyn<NX, NU, DI>::btx(pb, p, bp);
 #pragma unroll
     for (int a = 0; a < NU; ++a) {
-      float v = 0.f;
+      float v = cur.kc[a];
 #pragma unroll
-      for (int r = 0; r < NX; ++r) v = fmaf(pb.B[r * NU + a], p[r], v);
-      bp[a] = v;
-    }
-#pragma unroll
-    for (int a = 0; a < NU; ++a) {
-      float v = m.f(F::KC + a, t);
-#pragma unroll
-      for (int b = 0; b < NU; ++b) v = fmaf(-m.f(F::SV + (a <= b ? sym_idx<NU>(a, b) : sym_idx<NU>(b, a)), t), bp[b], v);
+      for (int b = 0; b < NU; ++b) v = fmaf(-cur.sv[a <= b ? sym_idx<NU>(a, b) : sym_idx<NU>(b, a)], bp[b], v);
       m.f(F::KV + a, t) = v;
     }
     if (t >= 1) {
       float np[NX];
+      Dyn<NX, NU, DI>::atx(pb, p, np);
 #pragma unroll
       for (int c = 0; c < NX; ++c) {
-        float v = ((c < NU) ? m.f(F::QP + c, t) : m.f(F::GQ + c, t)) + m.f(F::CC + c, t);
+        float v = cur.cq[c] + np[c];
 #pragma unroll
-        for (int r = 0; r < NX; ++r) v = fmaf(pb.A[r * NX + c], p[r], v);
-#pragma unroll
-        for (int a = 0; a < NU; ++a) v = fmaf(m.f(F::K + a * NX + c, t), bp[a], v);
+        for (int a = 0; a < NU; ++a) v = fmaf(cur.K[a][c], bp[a], v);
         np[c] = v;
       }
 #pragma unroll
@@ -144,7 +161,29 @@ struct StepInfo {
 // (UE, XE), with the ratio test against the current inputs and, on stages with
 // fixed inputs, the multipliers from the costates nu_{t+1} = P x + p (Eq. 9):
 // g = H_u u_t + B' nu_{t+1}; mu = g at a lower bound, -g at an upper bound.
+// Stage t+1 is loaded into registers before the stores of stage t.
 template <int NX, int NU>
+struct RollStage {
+  float K[NU][NX], kv[NU], uc[NU], P[Fld<NX, NU>::NP], pv[NX];
+  int8_t wt[NU];
+  __device__ __forceinline__ void load(const AgentMem<NX, NU> &m, int t) {
+    using F = Fld<NX, NU>;
+#pragma unroll
+    for (int a = 0; a < NU; ++a) {
+#pragma unroll
+      for (int c = 0; c < NX; ++c) K[a][c] = m.f(F::K + a * NX + c, t);
+      kv[a] = m.f(F::KV + a, t);
+      uc[a] = m.f(F::U + a, t);
+      wt[a] = m.w(a, t);
+    }
+#pragma unroll
+    for (int k = 0; k < F::NP; ++k) P[k] = m.f(F::PU + k, t + 1);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) pv[r] = m.f(F::PV + r, t + 1);
+  }
+};
+
+template <int NX, int NU, bool DI>
 __device__ __forceinline__ StepInfo forward_rollout(const Prob &pb, const AgentMem<NX, NU> &m, int T,
                                                     const float hu[NU]) {
   using F = Fld<NX, NU>;
@@ -152,39 +191,32 @@ __device__ __forceinline__ StepInfo forward_rollout(const Prob &pb, const AgentM
   float x[NX];
 #pragma unroll
   for (int r = 0; r < NX; ++r) x[r] = m.f(F::X + r, 0);
-#pragma unroll 2
+  RollStage<NX, NU> nxt;
+  nxt.load(m, 0);
   for (int t = 0; t < T; ++t) {
+    const RollStage<NX, NU> cur = nxt;
+    if (t + 1 < T) nxt.load(m, t + 1);
     float ue[NU];
 #pragma unroll
     for (int a = 0; a < NU; ++a) {
-      float v = m.f(F::KV + a, t);
+      float v = cur.kv[a];
 #pragma unroll
-      for (int c = 0; c < NX; ++c) v = fmaf(m.f(F::K + a * NX + c, t), x[c], v);
+      for (int c = 0; c < NX; ++c) v = fmaf(cur.K[a][c], x[c], v);
       ue[a] = v;
       m.f(F::UE + a, t) = v;
     }
     float xn[NX];
+    Dyn<NX, NU, DI>::ax(pb, x, xn);
+    Dyn<NX, NU, DI>::add_bu(pb, ue, xn);
 #pragma unroll
-    for (int r = 0; r < NX; ++r) {
-      float v = 0.f;
-#pragma unroll
-      for (int c = 0; c < NX; ++c) v = fmaf(pb.A[r * NX + c], x[c], v);
-#pragma unroll
-      for (int a = 0; a < NU; ++a) v = fmaf(pb.B[r * NU + a], ue[a], v);
-      xn[r] = v;
-      m.f(F::XE + r, t + 1) = v;
-    }
-    int8_t wt[NU];
+    for (int r = 0; r < NX; ++r) m.f(F::XE + r, t + 1) = xn[r];
     bool any = false;
 #pragma unroll
-    for (int a = 0; a < NU; ++a) {
-      wt[a] = m.w(a, t);
-      any |= (wt[a] != 0);
-    }
+    for (int a = 0; a < NU; ++a) any |= (cur.wt[a] != 0);
 #pragma unroll
     for (int a = 0; a < NU; ++a) {
-      if (wt[a] != 0) continue;
-      const float uc = m.f(F::U + a, t);
+      if (cur.wt[a] != 0) continue;
+      const float uc = cur.uc[a];
       if (ue[a] < pb.ulo[a]) {
         const float r = (uc <= pb.ulo[a]) ? 0.f : (pb.ulo[a] - uc) / (ue[a] - uc);
         if (r < si.alpha) { si.alpha = r; si.blk = t * NU + a; si.side = 1; }
@@ -197,18 +229,18 @@ __device__ __forceinline__ StepInfo forward_rollout(const Prob &pb, const AgentM
       float nu[NX];
 #pragma unroll
       for (int r = 0; r < NX; ++r) {
-        float v = m.f(F::PV + r, t + 1);
+        float v = cur.pv[r];
 #pragma unroll
-        for (int c = 0; c < NX; ++c) v = fmaf(m.f(F::PU + (r <= c ? sym_idx<NX>(r, c) : sym_idx<NX>(c, r)), t + 1), xn[c], v);
+        for (int c = 0; c < NX; ++c) v = fmaf(cur.P[r <= c ? sym_idx<NX>(r, c) : sym_idx<NX>(c, r)], xn[c], v);
         nu[r] = v;
       }
+      float bn[NU];
+      Dyn<NX, NU, DI>::btx(pb, nu, bn);
 #pragma unroll
       for (int a = 0; a < NU; ++a) {
-        if (wt[a] == 0) continue;
-        float g = hu[a] * ue[a];
-#pragma unroll
-        for (int r = 0; r < NX; ++r) g = fmaf(pb.B[r * NU + a], nu[r], g);
-        const float mu = (wt[a] == 1) ? g : -g;
+        if (cur.wt[a] == 0) continue;
+        const float g = fmaf(hu[a], ue[a], bn[a]);
+        const float mu = (cur.wt[a] == 1) ? g : -g;
         if (mu < si.mu_min) { si.mu_min = mu; si.drop = t * NU + a; }
       }
     }
@@ -226,57 +258,84 @@ __device__ __forceinline__ StepInfo forward_rollout(const Prob &pb, const AgentM
 // inputs, homogeneous dynamics) is solved with the cached FP32 factors
 // (k_t = -Sv (B'p + g_t), p_t = A'p + K'(B'p + g_t), p_T = 0) and applied in
 // FP64 before rounding the iterate back to FP32.
-template <int NX, int NU>
+template <int NX, int NU, bool DI>
 __device__ void refine_solution(const Prob &pb, const AgentMem<NX, NU> &m, const float *qd, const float hu[NU],
                                 int T, int n_nbr) {
   using F = Fld<NX, NU>;
+  using D = Dyn<NX, NU, DI>;
+  constexpr int NS = F::NS;
   double x[NX];
 #pragma unroll
   for (int r = 0; r < NX; ++r) { x[r] = (double)m.f(F::X + r, 0); m.d(r, 0) = x[r]; }
+  // (1) exact rollout of the stored inputs
+  float un[NU];
+#pragma unroll
+  for (int a = 0; a < NU; ++a) un[a] = m.f(F::U + a, 0);
   for (int t = 0; t < T; ++t) {
     double u[NU], xn[NX];
 #pragma unroll
-    for (int a = 0; a < NU; ++a) u[a] = (double)m.f(F::U + a, t);
+    for (int a = 0; a < NU; ++a) u[a] = (double)un[a];
+    if (t + 1 < T) {
 #pragma unroll
-    for (int r = 0; r < NX; ++r) {
-      double v = 0.0;
-#pragma unroll
-      for (int c = 0; c < NX; ++c) v = fma((double)pb.A[r * NX + c], x[c], v);
-#pragma unroll
-      for (int a = 0; a < NU; ++a) v = fma((double)pb.B[r * NU + a], u[a], v);
-      xn[r] = v;
+      for (int a = 0; a < NU; ++a) un[a] = m.f(F::U + a, t + 1);
     }
+    D::ax(pb, x, xn);
+    D::add_bu(pb, u, xn);
 #pragma unroll
     for (int r = 0; r < NX; ++r) { x[r] = xn[r]; m.d(r, t + 1) = xn[r]; }
   }
+  // (2) backward: FP64 adjoint (reduced gradient) and the FP32 correction sweep
   double nu[NX];
   {
     float hx[NX];
     stage_hx<NX, NU>(pb, qd, T, T, n_nbr, hx);
 #pragma unroll
     for (int r = 0; r < NX; ++r)
-      nu[r] = fma((double)hx[r], m.d(r, T), (double)((r < NU) ? m.f(F::QP + r, T) : m.f(F::GQ + r, T)));
+      nu[r] = fma((double)hx[r], m.d(r, T), (double)m.f(F::Q + r, T));
   }
   float pc[NX];
 #pragma unroll
   for (int r = 0; r < NX; ++r) pc[r] = 0.f;
-  for (int t = T - 1; t >= 0; --t) {
-    float s[NU];
+  struct BStage {
+    float u[NU], K[NU][NX], sv[NS], q[NX];
+    double xd[NX];
+    int8_t wt[NU];
+  };
+  auto bload = [&](BStage &st, int t) {
 #pragma unroll
     for (int a = 0; a < NU; ++a) {
-      double g = (double)hu[a] * (double)m.f(F::U + a, t);
+      st.u[a] = m.f(F::U + a, t);
+      st.wt[a] = m.w(a, t);
 #pragma unroll
-      for (int r = 0; r < NX; ++r) g = fma((double)pb.B[r * NU + a], nu[r], g);
-      float v = (m.w(a, t) == 0) ? (float)g : 0.f;
+      for (int c = 0; c < NX; ++c) st.K[a][c] = m.f(F::K + a * NX + c, t);
+    }
 #pragma unroll
-      for (int r = 0; r < NX; ++r) v = fmaf(pb.B[r * NU + a], pc[r], v);
-      s[a] = v;
+    for (int k = 0; k < NS; ++k) st.sv[k] = m.f(F::SV + k, t);
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      st.q[c] = m.f(F::Q + c, t);
+      st.xd[c] = m.d(c, t);
+    }
+  };
+  BStage nxt;
+  bload(nxt, T - 1);
+  for (int t = T - 1; t >= 0; --t) {
+    const BStage cur = nxt;
+    if (t >= 1) bload(nxt, t - 1);
+    double bnu[NU];
+    float bpc[NU], sg[NU];
+    D::btx(pb, nu, bnu);
+    D::btx(pb, pc, bpc);
+#pragma unroll
+    for (int a = 0; a < NU; ++a) {
+      const double g = fma((double)hu[a], (double)cur.u[a], bnu[a]);
+      sg[a] = ((cur.wt[a] == 0) ? (float)g : 0.f) + bpc[a];
     }
 #pragma unroll
     for (int a = 0; a < NU; ++a) {
       float v = 0.f;
 #pragma unroll
-      for (int b = 0; b < NU; ++b) v = fmaf(-m.f(F::SV + (a <= b ? sym_idx<NU>(a, b) : sym_idx<NU>(b, a)), t), s[b], v);
+      for (int b = 0; b < NU; ++b) v = fmaf(-cur.sv[a <= b ? sym_idx<NU>(a, b) : sym_idx<NU>(b, a)], sg[b], v);
       m.f(F::KV + a, t) = v;
     }
     if (t >= 1) {
@@ -284,59 +343,59 @@ __device__ void refine_solution(const Prob &pb, const AgentMem<NX, NU> &m, const
       stage_hx<NX, NU>(pb, qd, t, T, n_nbr, hx);
       float np[NX];
       double nn[NX];
+      D::atx(pb, pc, np);
+      D::atx(pb, nu, nn);
 #pragma unroll
       for (int c = 0; c < NX; ++c) {
-        float v = 0.f;
-        double w = fma((double)hx[c], m.d(c, t), (double)((c < NU) ? m.f(F::QP + c, t) : m.f(F::GQ + c, t)));
+        float v = np[c];
 #pragma unroll
-        for (int r = 0; r < NX; ++r) {
-          v = fmaf(pb.A[r * NX + c], pc[r], v);
-          w = fma((double)pb.A[r * NX + c], nu[r], w);
-        }
-#pragma unroll
-        for (int a = 0; a < NU; ++a) v = fmaf(m.f(F::K + a * NX + c, t), s[a], v);
-        np[c] = v;
-        nn[c] = w;
+        for (int a = 0; a < NU; ++a) v = fmaf(cur.K[a][c], sg[a], v);
+        pc[c] = v;
+        nu[c] = nn[c] + fma((double)hx[c], cur.xd[c], (double)cur.q[c]);
       }
-#pragma unroll
-      for (int r = 0; r < NX; ++r) { pc[r] = np[r]; nu[r] = nn[r]; }
     }
   }
+  // (3) correction rollout, update in FP64, round back to FP32
   float dx[NX];
 #pragma unroll
   for (int r = 0; r < NX; ++r) { dx[r] = 0.f; x[r] = m.d(r, 0); }
-  for (int t = 0; t < T; ++t) {
-    float du[NU], uf[NU];
+  struct FStage {
+    float K[NU][NX], kv[NU], u[NU];
+  };
+  auto fload = [&](FStage &st, int t) {
 #pragma unroll
     for (int a = 0; a < NU; ++a) {
-      float v = m.f(F::KV + a, t);
+      st.kv[a] = m.f(F::KV + a, t);
+      st.u[a] = m.f(F::U + a, t);
 #pragma unroll
-      for (int c = 0; c < NX; ++c) v = fmaf(m.f(F::K + a * NX + c, t), dx[c], v);
+      for (int c = 0; c < NX; ++c) st.K[a][c] = m.f(F::K + a * NX + c, t);
+    }
+  };
+  FStage fn;
+  fload(fn, 0);
+  for (int t = 0; t < T; ++t) {
+    const FStage cur = fn;
+    if (t + 1 < T) fload(fn, t + 1);
+    float du[NU], uf[NU];
+    double ud[NU];
+#pragma unroll
+    for (int a = 0; a < NU; ++a) {
+      float v = cur.kv[a];
+#pragma unroll
+      for (int c = 0; c < NX; ++c) v = fmaf(cur.K[a][c], dx[c], v);
       du[a] = v;
       // a free input refined past its bound by a rounding-level amount is
       // put back on the bound, so that the next active-set start is feasible
-      uf[a] = fminf(fmaxf((float)((double)m.f(F::U + a, t) + (double)v), pb.ulo[a]), pb.uhi[a]);
+      uf[a] = fminf(fmaxf((float)((double)cur.u[a] + (double)v), pb.ulo[a]), pb.uhi[a]);
+      ud[a] = (double)uf[a];
       m.f(F::U + a, t) = uf[a];
     }
     float dxn[NX];
     double xn[NX];
-#pragma unroll
-    for (int r = 0; r < NX; ++r) {
-      float v = 0.f;
-      double w = 0.0;
-#pragma unroll
-      for (int c = 0; c < NX; ++c) {
-        v = fmaf(pb.A[r * NX + c], dx[c], v);
-        w = fma((double)pb.A[r * NX + c], x[c], w);
-      }
-#pragma unroll
-      for (int a = 0; a < NU; ++a) {
-        v = fmaf(pb.B[r * NU + a], du[a], v);
-        w = fma((double)pb.B[r * NU + a], (double)uf[a], w);
-      }
-      dxn[r] = v;
-      xn[r] = w;
-    }
+    D::ax(pb, dx, dxn);
+    D::add_bu(pb, du, dxn);
+    D::ax(pb, x, xn);
+    D::add_bu(pb, ud, xn);
 #pragma unroll
     for (int r = 0; r < NX; ++r) {
       dx[r] = dxn[r];
@@ -348,7 +407,7 @@ __device__ void refine_solution(const Prob &pb, const AgentMem<NX, NU> &m, const
 
 // One agent's x-update at ADMM iteration k.  Returns 1 if the active-set
 // loop hit its cap.  cnt[] accumulates pass / stage counters.
-template <int NX, int NU>
+template <int NX, int NU, bool DI>
 __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i, int k, long long cnt[CT_NCOL]) {
   using F = Fld<NX, NU>;
   const int T = sc.T;
@@ -372,10 +431,10 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
     if (pb.warm) {
       // ... from the unconstrained affine LQ solution (Sec. IV-B), clipped
       if (!pb.cache) td = T - 1;
-      if (td >= 0) { refactor<NX, NU>(pb, m, qd, hu, T, n_nbr, td); cnt[CT_REFACTOR] += td + 1; td = -1; }
-      affine_sweep<NX, NU>(pb, m, T);
+      if (td >= 0) { refactor<NX, NU, DI>(pb, m, qd, hu, T, n_nbr, td); cnt[CT_REFACTOR] += td + 1; td = -1; }
+      affine_sweep<NX, NU, DI>(pb, m, T);
       cnt[CT_AFFINE] += T;
-      (void)forward_rollout<NX, NU>(pb, m, T, hu);
+      (void)forward_rollout<NX, NU, DI>(pb, m, T, hu);
       cnt[CT_PASSES] += 1;
     }
     float x[NX];
@@ -394,15 +453,8 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
         m.f(F::U + a, t) = u;
       }
       float xn[NX];
-#pragma unroll
-      for (int r = 0; r < NX; ++r) {
-        float v = 0.f;
-#pragma unroll
-        for (int c = 0; c < NX; ++c) v = fmaf(pb.A[r * NX + c], x[c], v);
-#pragma unroll
-        for (int a = 0; a < NU; ++a) v = fmaf(pb.B[r * NU + a], ust[a], v);
-        xn[r] = v;
-      }
+      Dyn<NX, NU, DI>::ax(pb, x, xn);
+      Dyn<NX, NU, DI>::add_bu(pb, ust, xn);
 #pragma unroll
       for (int r = 0; r < NX; ++r) { x[r] = xn[r]; m.f(F::X + r, t + 1) = xn[r]; }
     }
@@ -411,10 +463,10 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
   int done = 0;
   for (int it = 0; it < cap; ++it) {
     if (!pb.cache) td = T - 1;
-    if (td >= 0) { refactor<NX, NU>(pb, m, qd, hu, T, n_nbr, td); cnt[CT_REFACTOR] += td + 1; td = -1; }
-    affine_sweep<NX, NU>(pb, m, T);
+    if (td >= 0) { refactor<NX, NU, DI>(pb, m, qd, hu, T, n_nbr, td); cnt[CT_REFACTOR] += td + 1; td = -1; }
+    affine_sweep<NX, NU, DI>(pb, m, T);
     cnt[CT_AFFINE] += T;
-    const StepInfo si = forward_rollout<NX, NU>(pb, m, T, hu);
+    const StepInfo si = forward_rollout<NX, NU, DI>(pb, m, T, hu);
     cnt[CT_PASSES] += 1;
     if (si.blk >= 0) {
       // blocked: move the fraction alpha toward the EQP solution, fix the bound
@@ -454,7 +506,7 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
     break;
   }
   if (done && pb.refine) {
-    refine_solution<NX, NU>(pb, m, qd, hu, T, n_nbr);
+    refine_solution<NX, NU, DI>(pb, m, qd, hu, T, n_nbr);
     cnt[CT_AFFINE] += 2 * T;
   }
   ws.adirty[sc.ao + i] = td;
@@ -473,15 +525,15 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
 template <int NX, int NU>
 __device__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, int i, int t) {
   using F = Fld<NX, NU>;
-  const int N = sc.N, T = sc.T, GS = sc.GS;
+  const int N = sc.N, T = sc.T;
   float *R = ws.fr + sc.fo;
-  const int gi = t * N + i;
+  float *Ri = R + (unsigned)(t * N + i) * (unsigned)F::NF;   // this agent-stage
   float pi[NU];
   bool bad = false;
 #pragma unroll
-  for (int c = 0; c < NU; ++c) pi[c] = R[(F::X + c) * GS + gi];
+  for (int c = 0; c < NU; ++c) pi[c] = Ri[F::X + c];
 #pragma unroll
-  for (int c = 0; c < NX; ++c) bad |= !isfinite(R[(F::X + c) * GS + gi]);
+  for (int c = 0; c < NX; ++c) bad |= !isfinite(Ri[F::X + c]);
   float *lam = ws.lam + sc.lo;
   uint8_t *pa = ws.pact + sc.lb;
   const int LS = T * N * N;
@@ -497,7 +549,7 @@ __device__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, i
     float pj[NU], pf[NU], ps[NU];
 #pragma unroll
     for (int c = 0; c < NU; ++c) {
-      pj[c] = R[(F::X + c) * GS + t * N + j];
+      pj[c] = R[(unsigned)(t * N + j) * (unsigned)F::NF + F::X + c];
       pf[c] = first ? pi[c] : pj[c];
       ps[c] = first ? pj[c] : pi[c];
     }
@@ -560,21 +612,21 @@ __device__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, i
 #pragma unroll
   for (int c = 0; c < NU; ++c) {
     // rho sum_j (z_ij^(k+1) - z_ij^k) = rho (n_nbr (C x^(k+1) - C x^k) + ZD^(k+1) - ZD^k)
-    const float ds = rho * fmaf(nn, pi[c] - R[(F::XP + c) * GS + gi], zd[c] - R[(F::ZD + c) * GS + gi]);
+    const float ds = rho * fmaf(nn, pi[c] - Ri[F::XP + c], zd[c] - Ri[F::ZD + c]);
     s2 = fmaf(ds, ds, s2);
     ax2 = fmaf(pi[c], pi[c], ax2);
     aty2 = fmaf(ls[c], ls[c], aty2);
-    R[(F::QP + c) * GS + gi] = fmaf(-rho * nn, pi[c], R[(F::GQ + c) * GS + gi]) - es[c];
-    R[(F::XP + c) * GS + gi] = pi[c];
-    R[(F::ZD + c) * GS + gi] = zd[c];
+    Ri[F::Q + c] = fmaf(-rho * nn, pi[c], Ri[F::GQP + c]) - es[c];
+    Ri[F::XP + c] = pi[c];
+    Ri[F::ZD + c] = zd[c];
   }
   ax2 *= nn;
   if (bad) r2 = NAN;
-  R[(F::RED + 0) * GS + gi] = r2;
-  R[(F::RED + 1) * GS + gi] = s2;
-  R[(F::RED + 2) * GS + gi] = ax2;
-  R[(F::RED + 3) * GS + gi] = z2;
-  R[(F::RED + 4) * GS + gi] = aty2;
+  Ri[F::RED + 0] = r2;
+  Ri[F::RED + 1] = s2;
+  Ri[F::RED + 2] = ax2;
+  Ri[F::RED + 3] = z2;
+  Ri[F::RED + 4] = aty2;
 }
 
 // Residual norms and the stopping test of Sec. V-A (Boyd et al. 2011, Sec.
@@ -585,12 +637,12 @@ template <int NX, int NU>
 __device__ int scenario_test(const Prob &pb, const WS &ws, const Scen &sc, int k, int lane, int cap_hit) {
   using F = Fld<NX, NU>;
   const float *R = ws.fr + sc.fo;
-  const int GS = sc.GS, NT = sc.N * sc.T;
+  const int NT = sc.N * sc.T;
   float a[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
   for (int idx = lane; idx < NT; idx += 64) {
     const int g = sc.N + idx;  // stages 1..T
 #pragma unroll
-    for (int q = 0; q < 5; ++q) a[q] += R[(F::RED + q) * GS + g];
+    for (int q = 0; q < 5; ++q) a[q] += R[(unsigned)g * (unsigned)F::NF + F::RED + q];
   }
 #pragma unroll
   for (int q = 0; q < 5; ++q) a[q] = wave_sum(a[q]);
@@ -631,27 +683,30 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
   const int n_nbr = N - 1;
   for (int idx = tid; idx < GS; idx += nthreads) {
     const int t = idx / N, i = idx % N;
+    float *Rg = R + (unsigned)idx * (unsigned)F::NF;
     const float *r = ws.xref + (sc.xo + (long long)i * (T + 1) + t) * NX;
     const float w = (t == T) ? pb.qT : 1.0f;
     float gq[NX];
 #pragma unroll
     for (int c = 0; c < NX; ++c) {
       gq[c] = (t >= 1) ? -2.0f * w * qd[c] * r[c] : 0.f;
-      R[(F::GQ + c) * GS + idx] = gq[c];
+      if (c >= NU) Rg[F::Q + c] = gq[c];
     }
 #pragma unroll
     for (int c = 0; c < NU; ++c) {
       // x^0 := r so that z^0 = C r, lambda^0 = 0
-      R[(F::QP + c) * GS + idx] = fmaf(-pb.rho * (float)n_nbr, r[c], gq[c]);
-      R[(F::XP + c) * GS + idx] = r[c];
-      R[(F::ZD + c) * GS + idx] = 0.f;
-      R[(F::U + c) * GS + idx] = 0.f;
-      Wb[c * GS + idx] = 0;
+      Rg[F::GQP + c] = gq[c];
+      Rg[F::Q + c] = fmaf(-pb.rho * (float)n_nbr, r[c], gq[c]);
+      Rg[F::XP + c] = r[c];
+      Rg[F::ZD + c] = 0.f;
+      Rg[F::U + c] = 0.f;
     }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Wb[(unsigned)idx * 4u + c] = 0;
     if (t == 0) {
       const float *x0 = ws.x0 + (sc.ao + i) * NX;
 #pragma unroll
-      for (int c = 0; c < NX; ++c) { R[(F::X + c) * GS + idx] = x0[c]; R[(F::XE + c) * GS + idx] = x0[c]; }
+      for (int c = 0; c < NX; ++c) { Rg[F::X + c] = x0[c]; Rg[F::XE + c] = x0[c]; }
       ws.adirty[sc.ao + i] = T - 1;
     }
     if (t == T) {
@@ -660,7 +715,7 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
 #pragma unroll
       for (int r2 = 0; r2 < NX; ++r2)
 #pragma unroll
-        for (int c = r2; c < NX; ++c) R[(F::PU + sym_idx<NX>(r2, c)) * GS + idx] = (r2 == c) ? hx[r2] : 0.f;
+        for (int c = r2; c < NX; ++c) Rg[F::PU + sym_idx<NX>(r2, c)] = (r2 == c) ? hx[r2] : 0.f;
     }
   }
   const int LS = T * N * N;
@@ -698,13 +753,13 @@ __global__ __launch_bounds__(256) void k_setup(Prob pb, WS ws, int s) {
   if (blockIdx.x == 0 && threadIdx.x < CT_NCOL) ws.cnt[(long long)s * CT_NCOL + threadIdx.x] = 0ull;
 }
 
-template <int NX, int NU>
+template <int NX, int NU, bool DI>
 __global__ __launch_bounds__(64) void k_xupdate(Prob pb, WS ws, int s, int k) {
   const Scen sc = load_scen(ws, s);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= sc.N) return;
   long long cnt[CT_NCOL] = {0, 0, 0, 0};
-  const int capped = agent_xupdate<NX, NU>(pb, ws, sc, i, k, cnt);
+  const int capped = agent_xupdate<NX, NU, DI>(pb, ws, sc, i, k, cnt);
   if (capped) atomicOr(ws.sst + (long long)s * ST_NCOL + ST_CAP, 1);
   add_counters(ws, s, cnt);
 }
@@ -737,8 +792,8 @@ __global__ __launch_bounds__(64) void k_resid(Prob pb, WS ws, int s, int k, int 
 // scenario's own stopping test passes; the three phases are separated by
 // workgroup barriers.  Every wave reaches the queue read, so the grid drains
 // once the counter passes S.
-template <int NX, int NU>
-__global__ __launch_bounds__(1024) void k_admm_persistent(Prob pb, WS ws, int S) {
+template <int NX, int NU, bool DI>
+__global__ __launch_bounds__(256) void k_admm_persistent(Prob pb, WS ws, int S) {
   __shared__ int s_item;
   __shared__ int s_cap;
   __shared__ int s_done;
@@ -757,7 +812,7 @@ __global__ __launch_bounds__(1024) void k_admm_persistent(Prob pb, WS ws, int S)
     __syncthreads();
     for (int k = 1; k <= pb.max_iter; ++k) {
       for (int i = tid; i < sc.N; i += nt)
-        if (agent_xupdate<NX, NU>(pb, ws, sc, i, k, cnt)) atomicOr(&s_cap, 1);
+        if (agent_xupdate<NX, NU, DI>(pb, ws, sc, i, k, cnt)) atomicOr(&s_cap, 1);
       __syncthreads();
       const int cap = s_cap;
       if (!cap) {
@@ -824,19 +879,19 @@ __global__ void k_writeback(WS ws, int S, tadmm_out out) {
   using F = Fld<NX, NU>;
   for (int s = blockIdx.x; s < S; s += gridDim.x) {
     const Scen sc = load_scen(ws, s);
-    const int N = sc.N, T = sc.T, GS = sc.GS;
+    const int N = sc.N, T = sc.T;
     const float *R = ws.fr + sc.fo;
     const int8_t *Wb = ws.wr + sc.bo;
     if (out.x)
       for (int e = threadIdx.x; e < N * (T + 1) * NX; e += blockDim.x) {
         const int c = e % NX, it = e / NX, t = it % (T + 1), i = it / (T + 1);
-        out.x[sc.xo * NX + e] = R[(F::X + c) * GS + t * N + i];
+        out.x[sc.xo * NX + e] = R[(unsigned)(t * N + i) * (unsigned)F::NF + F::X + c];
       }
     if (out.u || out.w)
       for (int e = threadIdx.x; e < N * T * NU; e += blockDim.x) {
         const int c = e % NU, it = e / NU, t = it % T, i = it / T;
-        if (out.u) out.u[sc.uo * NU + e] = R[(F::U + c) * GS + t * N + i];
-        if (out.w) out.w[sc.uo * NU + e] = Wb[c * GS + t * N + i];
+        if (out.u) out.u[sc.uo * NU + e] = R[(unsigned)(t * N + i) * (unsigned)F::NF + F::U + c];
+        if (out.w) out.w[sc.uo * NU + e] = Wb[(unsigned)(t * N + i) * 4u + c];
       }
     if (out.pair_active)
       for (int e = threadIdx.x; e < N * N * T; e += blockDim.x) {
@@ -909,8 +964,8 @@ bool params_ok(const tadmm_params *p, std::string &err) {
   if (p->normal_mode != TADMM_NORMAL_PER_ITER && p->normal_mode != TADMM_NORMAL_FROZEN) {
     err = "unknown normal_mode"; return false;
   }
-  if (p->block_threads != 0 && (p->block_threads < 64 || p->block_threads > 1024 || p->block_threads % 64 != 0)) {
-    err = "block_threads must be 0 or a multiple of 64 in [64, 1024]"; return false;
+  if (p->block_threads != 0 && (p->block_threads < 64 || p->block_threads > 256 || p->block_threads % 64 != 0)) {
+    err = "block_threads must be 0, 64, 128, 192 or 256"; return false;
   }
   return true;
 }
@@ -936,7 +991,7 @@ bool make_layout(const tadmm_params *p, int S, const int32_t *N, const int32_t *
     tb[TB_D] = dof;
     fo += (long long)L.NF * GS;
     dof += (long long)p->nx * GS;
-    bo += (long long)p->nu * GS;
+    bo += 4ll * GS;
     lo += (long long)p->nu * t * n * n;
     lb += t * n * n;
     ao += n;
@@ -972,11 +1027,36 @@ bool make_layout(const tadmm_params *p, int S, const int32_t *N, const int32_t *
   return true;
 }
 
+// A = [[I, dt I], [0, I]] and B = [[h I], [dt I]] with h = dt^2/2 (as FP32),
+// positions first: the dynamics of every workload here; it selects the
+// structured products (two FMAs per position instead of dense 4x4 / 6x6).
+bool is_double_integrator(const tadmm_params &p) {
+  const int nx = p.nx, nu = p.nu;
+  const float dt = p.A[0 * nx + nu];
+  const float h = 0.5f * dt * dt;
+  for (int r = 0; r < nx; ++r)
+    for (int c = 0; c < nx; ++c) {
+      float want = (r == c) ? 1.f : 0.f;
+      if (r < nu && c == r + nu) want = dt;
+      if (p.A[r * nx + c] != want) return false;
+    }
+  for (int r = 0; r < nx; ++r)
+    for (int a = 0; a < nu; ++a) {
+      float want = 0.f;
+      if (r == a) want = h;
+      if (r == a + nu) want = dt;
+      if (p.B[r * nu + a] != want) return false;
+    }
+  return dt != 0.f;
+}
+
 Prob to_prob(const tadmm_params &p) {
   Prob pb;
   std::memset(&pb, 0, sizeof(pb));
   std::memcpy(pb.A, p.A, sizeof(pb.A));
   std::memcpy(pb.B, p.B, sizeof(pb.B));
+  pb.dt = p.A[0 * p.nx + p.nu];
+  pb.h = 0.5f * pb.dt * pb.dt;
   for (int c = 0; c < 3; ++c) { pb.ulo[c] = p.u_lo[c]; pb.uhi[c] = p.u_hi[c]; }
   pb.qT = p.qT_scale; pb.dmin = p.d_min; pb.rho = p.rho; pb.eps_abs = p.eps_abs; pb.eps_rel = p.eps_rel;
   pb.mu_tol = p.mu_tol; pb.max_iter = p.max_iter; pb.max_as = p.max_as_iter; pb.normal_mode = p.normal_mode;
@@ -1084,7 +1164,7 @@ tadmm_status run_checks(tadmm_ctx *ctx, const Prob &pb, const WS &w, int S, int 
   return TADMM_OK;
 }
 
-template <int NX, int NU>
+template <int NX, int NU, bool DI>
 tadmm_status run_plain(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layout &L, const int32_t *N,
                        const int32_t *T, int *d_flags, const tadmm_out &out) {
   HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
@@ -1094,7 +1174,7 @@ tadmm_status run_plain(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layout
     const int gsetup = (int)std::min<long long>((work + 255) / 256, 4096);
     hipLaunchKernelGGL((k_setup<NX, NU>), dim3(gsetup), dim3(256), 0, ctx->stream, pb, w, s);
     for (int k = 1; k <= pb.max_iter; ++k) {
-      hipLaunchKernelGGL((k_xupdate<NX, NU>), dim3((n + 63) / 64), dim3(64), 0, ctx->stream, pb, w, s, k);
+      hipLaunchKernelGGL((k_xupdate<NX, NU, DI>), dim3((n + 63) / 64), dim3(64), 0, ctx->stream, pb, w, s, k);
       hipLaunchKernelGGL((k_pair<NX, NU>), dim3((n * t + 255) / 256), dim3(256), 0, ctx->stream, pb, w, s);
       hipLaunchKernelGGL((k_resid<NX, NU>), dim3(1), dim3(64), 0, ctx->stream, pb, w, s, k, d_flags + 2);
       HIPCHK(hipGetLastError());
@@ -1111,12 +1191,12 @@ tadmm_status run_plain(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layout
   return TADMM_OK;
 }
 
-template <int NX, int NU>
+template <int NX, int NU, bool DI>
 tadmm_status run_batched(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layout &L, const tadmm_batch *b,
                          const tadmm_out &out, void *ws, size_t bytes) {
   const int threads = ctx->prm.block_threads ? ctx->prm.block_threads : ctx->tuned_threads;
   int per_cu = 0;
-  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_admm_persistent<NX, NU>, threads, 0));
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_admm_persistent<NX, NU, DI>, threads, 0));
   if (per_cu < 1) return fail(ctx, TADMM_ERR_HIP, "persistent kernel does not fit on a compute unit");
   const int grid = std::max(1, std::min(L.S, per_cu * ctx->n_cu));
   GraphKey key;
@@ -1135,7 +1215,7 @@ tadmm_status run_batched(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layo
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, cs, w.queue, 1, 0);
     const long long nc = (long long)L.S * CT_NCOL;
     hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, cs, w.cnt, nc);
-    hipLaunchKernelGGL((k_admm_persistent<NX, NU>), dim3(grid), dim3(threads), 0, cs, pb, w, L.S);
+    hipLaunchKernelGGL((k_admm_persistent<NX, NU, DI>), dim3(grid), dim3(threads), 0, cs, pb, w, L.S);
     hipLaunchKernelGGL((k_writeback<NX, NU>), dim3(std::min(L.S, 4096)), dim3(256), 0, cs, w, L.S, out);
     hipError_t le = hipGetLastError();
     hipError_t ce = hipStreamEndCapture(cs, &ctx->graph);
@@ -1154,7 +1234,7 @@ tadmm_status run_batched(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layo
   return TADMM_OK;
 }
 
-template <int NX, int NU>
+template <int NX, int NU, bool DI>
 tadmm_status solve_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *out, void *ws, size_t bytes, int mode) {
   Layout L;
   if (!make_layout(&ctx->prm, b->n_scen, b->n_agents, b->horizon, L, ctx->err)) return TADMM_ERR_SHAPE;
@@ -1174,8 +1254,8 @@ tadmm_status solve_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *o
     st = run_checks<NX, NU>(ctx, pb, w, L.S, d_flags);
     if (st != TADMM_OK) return st;
   }
-  if (mode == TADMM_MODE_PLAIN) st = run_plain<NX, NU>(ctx, pb, w, L, b->n_agents, b->horizon, d_flags, *out);
-  else if (mode == TADMM_MODE_BATCHED) st = run_batched<NX, NU>(ctx, pb, w, L, b, *out, ws, bytes);
+  if (mode == TADMM_MODE_PLAIN) st = run_plain<NX, NU, DI>(ctx, pb, w, L, b->n_agents, b->horizon, d_flags, *out);
+  else if (mode == TADMM_MODE_BATCHED) st = run_batched<NX, NU, DI>(ctx, pb, w, L, b, *out, ws, bytes);
   else return fail(ctx, TADMM_ERR_INVALID_ARG, "unknown mode");
   if (st != TADMM_OK) return st;
   ctx->solved = true;
@@ -1254,15 +1334,19 @@ tadmm_status tadmm_solve(tadmm_ctx *ctx, const tadmm_batch *batch, const tadmm_o
   if (!ctx) return TADMM_ERR_INVALID_ARG;
   if (!batch || !out) return fail(ctx, TADMM_ERR_INVALID_ARG, "batch / out is NULL");
   ctx->err.clear();
-  if (ctx->prm.nx == 4) return solve_impl<4, 2>(ctx, batch, out, workspace, workspace_bytes, mode);
-  return solve_impl<6, 3>(ctx, batch, out, workspace, workspace_bytes, mode);
+  const bool di = is_double_integrator(ctx->prm);
+  if (ctx->prm.nx == 4)
+    return di ? solve_impl<4, 2, true>(ctx, batch, out, workspace, workspace_bytes, mode)
+              : solve_impl<4, 2, false>(ctx, batch, out, workspace, workspace_bytes, mode);
+  return di ? solve_impl<6, 3, true>(ctx, batch, out, workspace, workspace_bytes, mode)
+            : solve_impl<6, 3, false>(ctx, batch, out, workspace, workspace_bytes, mode);
 }
 
 tadmm_status tadmm_autotune(tadmm_ctx *ctx, const tadmm_batch *batch, const tadmm_out *out, void *workspace,
                             size_t workspace_bytes, int32_t *best_threads) {
   if (!ctx) return TADMM_ERR_INVALID_ARG;
   const int saved = ctx->prm.block_threads;
-  const int cands[] = {64, 128, 256, 512, 1024};
+  const int cands[] = {64, 128, 192, 256};
   float best = 1e30f;
   int best_t = ctx->tuned_threads;
   for (int c : cands) {
