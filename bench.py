@@ -121,6 +121,8 @@ def main():
            "status_counts": {str(k): int((status == k).sum()) for k in range(4)},
            "mean_iters": round(float(iters.mean()), 2),
            "active_set_passes_per_agent_qp": round(float(cnt[:, 0].sum()) / max(agent_qp, 1.0), 4),
+           "phase_time_split": {k: round(float(cnt[:, c].sum()) / max(float(cnt[:, 4:7].sum()), 1.0), 4)
+                                for k, c in (("x_update", 4), ("pair", 5), ("test", 6))},
            "roofline": roofline}
 
     if not args.no_plain and args.plain_sample > 0:

@@ -151,8 +151,11 @@ typedef struct {
   int32_t *iters;            /* [S] ADMM iterations performed                   */
   float *r_norm, *s_norm;    /* [S] final primal / dual residual norms          */
   float *eps_pri, *eps_dual; /* [S] final tolerances of the stopping test       */
-  int64_t *counters;         /* [S][4]: active-set passes, refactored
-                                agent-stages, affine agent-stages, pair-updates */
+  int64_t *counters;         /* [S][8]: active-set passes, refactored
+                                agent-stages, affine agent-stage passes, pair-
+                                step updates; batched mode also the time spent
+                                in the x-update, pair and test phases (ticks of
+                                the 100 MHz device clock, one workgroup), 0     */
 } tadmm_out;
 
 typedef struct tadmm_ctx tadmm_ctx;

@@ -207,7 +207,7 @@ class Solver:
                  status=torch.zeros(S, dtype=torch.int32, device=dev), iters=torch.zeros(S, dtype=torch.int32, device=dev),
                  r_norm=torch.zeros(S, device=dev), s_norm=torch.zeros(S, device=dev),
                  eps_pri=torch.zeros(S, device=dev), eps_dual=torch.zeros(S, device=dev),
-                 counters=torch.zeros(S, 4, dtype=torch.int64, device=dev))
+                 counters=torch.zeros(S, 8, dtype=torch.int64, device=dev))
         nbytes = self.workspace_bytes(N, T)
         ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
         return Prepared(self, b, o, ws, nbytes)

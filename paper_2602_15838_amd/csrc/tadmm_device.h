@@ -42,7 +42,9 @@ enum { ST_STATUS = 0, ST_ITERS, ST_CAP, ST_DONE, ST_NCOL = 8 };
 // Per-scenario float state columns.
 enum { SN_R = 0, SN_S, SN_EPRI, SN_EDUAL, SN_NCOL = 4 };
 // Per-scenario counters (int64).
-enum { CT_PASSES = 0, CT_REFACTOR, CT_AFFINE, CT_PAIRS, CT_NCOL = 4 };
+// Per-scenario counters (int64): work units, and in the batched kernel the
+// time spent in each phase (ticks of the 100 MHz device real-time clock).
+enum { CT_PASSES = 0, CT_REFACTOR, CT_AFFINE, CT_PAIRS, CT_T_X, CT_T_PAIR, CT_T_TEST, CT_RESERVED, CT_NCOL = 8 };
 
 struct WS {
   const int *N, *T;                  // [S]

@@ -149,6 +149,9 @@ __device__ __forceinline__ void affine_sweep(const Prob &pb, const AgentMem<NX, 
   }
 }
 
+// relative FP32 rounding allowance of a multiplier (about 64 ulps)
+constexpr float kMuNoise = 4e-6f;
+
 struct StepInfo {
   float alpha;   // largest feasible fraction of the step toward the EQP solution
   int blk;       // flat index t*nu+c of the blocking bound (-1: none)
@@ -234,13 +237,18 @@ __device__ __forceinline__ StepInfo forward_rollout(const Prob &pb, const AgentM
         for (int c = 0; c < NX; ++c) v = fmaf(cur.P[r <= c ? sym_idx<NX>(r, c) : sym_idx<NX>(c, r)], xn[c], v);
         nu[r] = v;
       }
-      float bn[NU];
+      float bn[NU], an[NX], bs[NU];
       Dyn<NX, NU, DI>::btx(pb, nu, bn);
+#pragma unroll
+      for (int r = 0; r < NX; ++r) an[r] = fabsf(nu[r]);
+      Dyn<NX, NU, DI>::btx(pb, an, bs);   // |B|'|nu| for the general form with nonnegative B
 #pragma unroll
       for (int a = 0; a < NU; ++a) {
         if (cur.wt[a] == 0) continue;
         const float g = fmaf(hu[a], ue[a], bn[a]);
-        const float mu = (cur.wt[a] == 1) ? g : -g;
+        // a multiplier is trusted to be negative only beyond the FP32
+        // rounding of the terms it is formed from
+        const float mu = ((cur.wt[a] == 1) ? g : -g) + kMuNoise * (fabsf(hu[a] * ue[a]) + fabsf(bs[a]));
         if (mu < si.mu_min) { si.mu_min = mu; si.drop = t * NU + a; }
       }
     }
@@ -461,6 +469,7 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
   }
 
   int done = 0;
+  int last_drop = -1, last_side = 0;   // bound released by the previous pass
   for (int it = 0; it < cap; ++it) {
     if (!pb.cache) td = T - 1;
     if (td >= 0) { refactor<NX, NU, DI>(pb, m, qd, hu, T, n_nbr, td); cnt[CT_REFACTOR] += td + 1; td = -1; }
@@ -487,6 +496,14 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
       m.f(F::U + ba, bt) = (si.side == 1) ? pb.ulo[ba] : pb.uhi[ba];
       m.w(ba, bt) = (int8_t)si.side;
       td = max(td, bt);
+      if (si.blk == last_drop && si.side == last_side) {
+        // the bound released by the previous pass blocks again on the same
+        // side right away: its multiplier was negative only at rounding
+        // level; keep it and stop
+        done = 1;
+        break;
+      }
+      last_drop = -1;
       continue;
     }
     // full step: the EQP solution becomes the iterate
@@ -498,6 +515,8 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
     }
     if (si.drop >= 0 && si.mu_min < -pb.mu_tol) {
       const int dt = si.drop / NU, da = si.drop % NU;
+      last_side = m.w(da, dt);
+      last_drop = si.drop;
       m.w(da, dt) = 0;
       td = max(td, dt);
       continue;
@@ -506,6 +525,7 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
     break;
   }
   if (done && pb.refine) {
+    if (td >= 0) { refactor<NX, NU, DI>(pb, m, qd, hu, T, n_nbr, td); cnt[CT_REFACTOR] += td + 1; td = -1; }
     refine_solution<NX, NU, DI>(pb, m, qd, hu, T, n_nbr);
     cnt[CT_AFFINE] += 2 * T;
   }
@@ -523,7 +543,8 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
 // is evaluated in this closed form (no cancellation); the copies follow from
 // Eq. 5 as z_f = pf + (lambda_fs - lambda_fs_new)/rho, z_s = ps - (same).
 template <int NX, int NU>
-__device__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, int i, int t) {
+__device__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, int i, int t,
+                                 const float *__restrict__ lpos) {
   using F = Fld<NX, NU>;
   const int N = sc.N, T = sc.T;
   float *R = ws.fr + sc.fo;
@@ -542,14 +563,41 @@ __device__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, i
 #pragma unroll
   for (int c = 0; c < NU; ++c) { es[c] = 0.f; zd[c] = 0.f; ls[c] = 0.f; }
   float r2 = 0.f, z2 = 0.f;
-  for (int j = 0; j < N; ++j) {
-    if (j == i) continue;
+  // partner positions from LDS when the scenario's positions are staged there
+  auto partner = [&](int j, float pj[NU]) {
+    if (lpos) {
+#pragma unroll
+      for (int c = 0; c < NU; ++c) pj[c] = lpos[(t * N + j) * NU + c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < NU; ++c) pj[c] = R[(unsigned)(t * N + j) * (unsigned)F::NF + F::X + c];
+    }
+  };
+  const int lbase = (t - 1) * N * N + i;        // + j * N: this lane's ordered copy (i, j)
+  // the partner loop skips j == i; the duals of the next partner are loaded
+  // before the current partner's dual is stored
+  float lnx[NU];
+  if (N > 1) {
+    const int j0 = (i == 0) ? 1 : 0;
+#pragma unroll
+    for (int c = 0; c < NU; ++c) lnx[c] = lam[c * LS + lbase + j0 * N];
+  }
+  for (int jj = 0; jj < N - 1; ++jj) {
+    const int j = jj + (jj >= i);
+    float lown[NU];
+#pragma unroll
+    for (int c = 0; c < NU; ++c) lown[c] = lnx[c];
+    if (jj + 1 < N - 1) {
+      const int jn = jj + 1 + (jj + 1 >= i);
+#pragma unroll
+      for (int c = 0; c < NU; ++c) lnx[c] = lam[c * LS + lbase + jn * N];
+    }
     const bool first = i < j;
     const int f = first ? i : j, s = first ? j : i;
     float pj[NU], pf[NU], ps[NU];
+    partner(j, pj);
 #pragma unroll
     for (int c = 0; c < NU; ++c) {
-      pj[c] = R[(unsigned)(t * N + j) * (unsigned)F::NF + F::X + c];
       pf[c] = first ? pi[c] : pj[c];
       ps[c] = first ? pj[c] : pi[c];
     }
@@ -575,13 +623,10 @@ __device__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, i
         reference_normal<NX, NU>(ws, sc, f, s, t, n);
       }
     }
-    const int li = ((t - 1) * N + j) * N + i;  // this lane's ordered copy (i, j)
-    float lown[NU], lfs[NU];
+    const int li = lbase + j * N;  // this lane's ordered copy (i, j)
+    float lfs[NU];
 #pragma unroll
-    for (int c = 0; c < NU; ++c) {
-      lown[c] = lam[c * LS + li];
-      lfs[c] = first ? lown[c] : -lown[c];
-    }
+    for (int c = 0; c < NU; ++c) lfs[c] = first ? lown[c] : -lown[c];
     float g = 0.f;
 #pragma unroll
     for (int c = 0; c < NU; ++c) {
@@ -590,20 +635,19 @@ __device__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, i
     }
     const float v = pb.dmin - g;
     const float gam = 0.5f * rho * fmaxf(v, 0.f);
-    float lnew_own[NU];
 #pragma unroll
     for (int c = 0; c < NU; ++c) {
       const float lnew = -gam * n[c];                 // lambda_fs after Eq. 5
       const float dl = (lfs[c] - lnew) * irho;       // z_f - pf = -(z_s - ps)
       const float sdl = first ? dl : -dl;            // z_own - C x_i
       const float zo = pi[c] + sdl;
-      lnew_own[c] = first ? lnew : -lnew;
-      es[c] += lown[c] - 2.0f * lnew_own[c];         // rho z_own - lam_new - rho C x_i
+      const float lo = first ? lnew : -lnew;
+      es[c] += lown[c] - 2.0f * lo;                  // rho z_own - lam_new - rho C x_i
       zd[c] += sdl;
-      ls[c] += lnew_own[c];
+      ls[c] += lo;
       r2 = fmaf(dl, dl, r2);
       z2 = fmaf(zo, zo, z2);
-      lam[c * LS + li] = lnew_own[c];
+      lam[c * LS + li] = lo;
     }
     if (first) pa[li] = (uint8_t)(v > 0.f);
   }
@@ -758,7 +802,7 @@ __global__ __launch_bounds__(64) void k_xupdate(Prob pb, WS ws, int s, int k) {
   const Scen sc = load_scen(ws, s);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= sc.N) return;
-  long long cnt[CT_NCOL] = {0, 0, 0, 0};
+  long long cnt[CT_NCOL] = {};
   const int capped = agent_xupdate<NX, NU, DI>(pb, ws, sc, i, k, cnt);
   if (capped) atomicOr(ws.sst + (long long)s * ST_NCOL + ST_CAP, 1);
   add_counters(ws, s, cnt);
@@ -769,9 +813,10 @@ __global__ __launch_bounds__(256) void k_pair(Prob pb, WS ws, int s) {
   const Scen sc = load_scen(ws, s);
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= sc.N * sc.T) return;
-  pair_agent_stage<NX, NU>(pb, ws, sc, idx % sc.N, idx / sc.N + 1);
+  pair_agent_stage<NX, NU>(pb, ws, sc, idx % sc.N, idx / sc.N + 1, nullptr);
   if (idx == 0) {
-    long long c[CT_NCOL] = {0, 0, 0, (long long)sc.N * (sc.N - 1) / 2 * sc.T};
+    long long c[CT_NCOL] = {};
+    c[CT_PAIRS] = (long long)sc.N * (sc.N - 1) / 2 * sc.T;
     add_counters(ws, s, c);
   }
 }
@@ -793,7 +838,8 @@ __global__ __launch_bounds__(64) void k_resid(Prob pb, WS ws, int s, int k, int 
 // workgroup barriers.  Every wave reaches the queue read, so the grid drains
 // once the counter passes S.
 template <int NX, int NU, bool DI>
-__global__ __launch_bounds__(256) void k_admm_persistent(Prob pb, WS ws, int S) {
+__global__ __launch_bounds__(256) void k_admm_persistent(Prob pb, WS ws, int S, int lds_floats) {
+  extern __shared__ float lds_pos[];  // positions of the scenario, [t][i][c]
   __shared__ int s_item;
   __shared__ int s_cap;
   __shared__ int s_done;
@@ -808,23 +854,42 @@ __global__ __launch_bounds__(256) void k_admm_persistent(Prob pb, WS ws, int S) 
     const Scen sc = load_scen(ws, s);
     scenario_setup<NX, NU>(pb, ws, sc, tid, nt);
     if (tid == 0) { s_cap = 0; s_done = 0; }
-    long long cnt[CT_NCOL] = {0, 0, 0, 0};
+    long long cnt[CT_NCOL] = {};
     __syncthreads();
     for (int k = 1; k <= pb.max_iter; ++k) {
+      const unsigned long long c0 = wall_clock64();
       for (int i = tid; i < sc.N; i += nt)
         if (agent_xupdate<NX, NU, DI>(pb, ws, sc, i, k, cnt)) atomicOr(&s_cap, 1);
       __syncthreads();
+      const unsigned long long c1 = wall_clock64();
       const int cap = s_cap;
       if (!cap) {
-        for (int idx = tid; idx < sc.N * sc.T; idx += nt) pair_agent_stage<NX, NU>(pb, ws, sc, idx % sc.N, idx / sc.N + 1);
+        // stage every position of the scenario in LDS (the partner loop reads
+        // them N-1 times each), then the consensus and dual updates
+        const bool staged = sc.GS * NU <= lds_floats;
+        if (staged) {
+          const float *R = ws.fr + sc.fo;
+          for (int idx = tid; idx < sc.GS; idx += nt)
+#pragma unroll
+            for (int c = 0; c < NU; ++c) lds_pos[idx * NU + c] = R[(unsigned)idx * (unsigned)Fld<NX, NU>::NF + Fld<NX, NU>::X + c];
+          __syncthreads();
+        }
+        for (int idx = tid; idx < sc.N * sc.T; idx += nt)
+          pair_agent_stage<NX, NU>(pb, ws, sc, idx % sc.N, idx / sc.N + 1, staged ? lds_pos : nullptr);
         if (tid == 0) cnt[CT_PAIRS] += (long long)sc.N * (sc.N - 1) / 2 * sc.T;
       }
       __syncthreads();
+      const unsigned long long c2 = wall_clock64();
       if (tid < 64) {
         const int d = scenario_test<NX, NU>(pb, ws, sc, k, tid, cap);
         if (tid == 0) s_done = d;
       }
       __syncthreads();
+      if (tid == 0) {
+        cnt[CT_T_X] += (long long)(c1 - c0);
+        cnt[CT_T_PAIR] += (long long)(c2 - c1);
+        cnt[CT_T_TEST] += (long long)(wall_clock64() - c2);
+      }
       if (s_done) break;
     }
     add_counters(ws, s, cnt);
@@ -1027,13 +1092,14 @@ bool make_layout(const tadmm_params *p, int S, const int32_t *N, const int32_t *
   return true;
 }
 
-// A = [[I, dt I], [0, I]] and B = [[h I], [dt I]] with h = dt^2/2 (as FP32),
-// positions first: the dynamics of every workload here; it selects the
-// structured products (two FMAs per position instead of dense 4x4 / 6x6).
+// A = [[I, dt I], [0, I]] and B = [[h I], [dt I]] (positions first; h is
+// the caller's value, dt^2/2 for the exact zero-order hold): the dynamics of
+// every workload here; it selects the structured products (two FMAs per
+// position instead of dense 4x4 / 6x6 products).
 bool is_double_integrator(const tadmm_params &p) {
   const int nx = p.nx, nu = p.nu;
   const float dt = p.A[0 * nx + nu];
-  const float h = 0.5f * dt * dt;
+  const float h = p.B[0];
   for (int r = 0; r < nx; ++r)
     for (int c = 0; c < nx; ++c) {
       float want = (r == c) ? 1.f : 0.f;
@@ -1056,7 +1122,7 @@ Prob to_prob(const tadmm_params &p) {
   std::memcpy(pb.A, p.A, sizeof(pb.A));
   std::memcpy(pb.B, p.B, sizeof(pb.B));
   pb.dt = p.A[0 * p.nx + p.nu];
-  pb.h = 0.5f * pb.dt * pb.dt;
+  pb.h = p.B[0];
   for (int c = 0; c < 3; ++c) { pb.ulo[c] = p.u_lo[c]; pb.uhi[c] = p.u_hi[c]; }
   pb.qT = p.qT_scale; pb.dmin = p.d_min; pb.rho = p.rho; pb.eps_abs = p.eps_abs; pb.eps_rel = p.eps_rel;
   pb.mu_tol = p.mu_tol; pb.max_iter = p.max_iter; pb.max_as = p.max_as_iter; pb.normal_mode = p.normal_mode;
@@ -1195,8 +1261,15 @@ template <int NX, int NU, bool DI>
 tadmm_status run_batched(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layout &L, const tadmm_batch *b,
                          const tadmm_out &out, void *ws, size_t bytes) {
   const int threads = ctx->prm.block_threads ? ctx->prm.block_threads : ctx->tuned_threads;
+  // LDS for the positions of the largest scenario, up to 32 KB per workgroup
+  // (larger scenarios read positions from global memory)
+  long long max_gs = 0;
+  for (int s = 0; s < L.S; ++s) max_gs = std::max<long long>(max_gs, (long long)b->n_agents[s] * (b->horizon[s] + 1));
+  const int lds_floats = (int)std::min<long long>(max_gs * NU, 8192);
+  const size_t lds_bytes = sizeof(float) * (size_t)lds_floats;
   int per_cu = 0;
-  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_admm_persistent<NX, NU, DI>, threads, 0));
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_admm_persistent<NX, NU, DI>, threads,
+                                                      lds_bytes));
   if (per_cu < 1) return fail(ctx, TADMM_ERR_HIP, "persistent kernel does not fit on a compute unit");
   const int grid = std::max(1, std::min(L.S, per_cu * ctx->n_cu));
   GraphKey key;
@@ -1215,7 +1288,7 @@ tadmm_status run_batched(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layo
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, cs, w.queue, 1, 0);
     const long long nc = (long long)L.S * CT_NCOL;
     hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, cs, w.cnt, nc);
-    hipLaunchKernelGGL((k_admm_persistent<NX, NU, DI>), dim3(grid), dim3(threads), 0, cs, pb, w, L.S);
+    hipLaunchKernelGGL((k_admm_persistent<NX, NU, DI>), dim3(grid), dim3(threads), lds_bytes, cs, pb, w, L.S, lds_floats);
     hipLaunchKernelGGL((k_writeback<NX, NU>), dim3(std::min(L.S, 4096)), dim3(256), 0, cs, w, L.S, out);
     hipError_t le = hipGetLastError();
     hipError_t ce = hipStreamEndCapture(cs, &ctx->graph);
