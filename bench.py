@@ -115,7 +115,7 @@ def main():
                                   f"integrator, rho=1, d_min=0.5, eps_abs=eps_rel=1e-4, max_iter=200",
                       "scenarios": S, "agents": int(Ns.sum()), "agent_stages": int((Ns * Ts).sum()),
                       "pair_steps": int((Ns * (Ns - 1) // 2 * Ts).sum()), "mode": "batched persistent + hipGraph",
-                      "workgroup_threads": int(tuned or args.block_threads or 256)},
+                      "workgroup_threads": int(tuned or args.block_threads or 128)},
            "agent_qp_solves_per_s": round(agent_qp_per_s, 1),
            "converged_fraction": round(float((status == 0).mean()), 4),
            "status_counts": {str(k): int((status == k).sum()) for k in range(4)},
@@ -123,6 +123,9 @@ def main():
            "active_set_passes_per_agent_qp": round(float(cnt[:, 0].sum()) / max(agent_qp, 1.0), 4),
            "phase_time_split": {k: round(float(cnt[:, c].sum()) / max(float(cnt[:, 4:7].sum()), 1.0), 4)
                                 for k, c in (("x_update", 4), ("pair", 5), ("test", 6))},
+           # mean over scenarios of the time one workgroup spends per ADMM iteration in each phase
+           "phase_us_per_iteration": {k: round(float(np.mean(cnt[:, c] / np.maximum(iters, 1))) / 100.0, 3)
+                                      for k, c in (("x_update", 4), ("pair", 5), ("test", 6))},
            "roofline": roofline}
 
     if not args.no_plain and args.plain_sample > 0:

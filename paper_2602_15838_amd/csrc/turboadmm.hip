@@ -838,7 +838,7 @@ __global__ __launch_bounds__(64) void k_resid(Prob pb, WS ws, int s, int k, int 
 // workgroup barriers.  Every wave reaches the queue read, so the grid drains
 // once the counter passes S.
 template <int NX, int NU, bool DI>
-__global__ __launch_bounds__(256) void k_admm_persistent(Prob pb, WS ws, int S, int lds_floats) {
+__device__ __forceinline__ void persistent_body(Prob pb, WS ws, int S, int lds_floats) {
   extern __shared__ float lds_pos[];  // positions of the scenario, [t][i][c]
   __shared__ int s_item;
   __shared__ int s_cap;
@@ -895,6 +895,21 @@ __global__ __launch_bounds__(256) void k_admm_persistent(Prob pb, WS ws, int S, 
     add_counters(ws, s, cnt);
     __syncthreads();
   }
+}
+
+// Two launch shapes of the same persistent loop: workgroups of 128-256
+// threads (several waves share a scenario's consensus step), and one-wave
+// workgroups held to at most 128 VGPRs so that four waves fit per SIMD and a
+// whole batch of a few thousand scenarios is resident at once.
+template <int NX, int NU, bool DI>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_admm_persistent(Prob pb, WS ws, int S, int lds_floats) {
+  persistent_body<NX, NU, DI>(pb, ws, S, lds_floats);
+}
+
+template <int NX, int NU, bool DI>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_admm_persistent_lean(
+    Prob pb, WS ws, int S, int lds_floats) {
+  persistent_body<NX, NU, DI>(pb, ws, S, lds_floats);
 }
 
 __global__ void k_fill_i32(int *p, int n, int v) {
@@ -1149,7 +1164,7 @@ struct tadmm_ctx {
   hipStream_t cap_stream = nullptr;  // private stream used only to capture the graph
   int device = 0, n_cu = 256;
   std::string err;
-  int tuned_threads = 256;
+  int tuned_threads = 128;
   void *h_stage = nullptr;
   size_t h_stage_bytes = 0;
   int *h_flags = nullptr;
@@ -1265,11 +1280,12 @@ tadmm_status run_batched(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layo
   // (larger scenarios read positions from global memory)
   long long max_gs = 0;
   for (int s = 0; s < L.S; ++s) max_gs = std::max<long long>(max_gs, (long long)b->n_agents[s] * (b->horizon[s] + 1));
-  const int lds_floats = (int)std::min<long long>(max_gs * NU, 8192);
+  const bool lean = (threads == 64);
+  const int lds_floats = (int)std::min<long long>(max_gs * NU, lean ? 2048 : 8192);
   const size_t lds_bytes = sizeof(float) * (size_t)lds_floats;
+  const void *kfn = lean ? (const void *)k_admm_persistent_lean<NX, NU, DI> : (const void *)k_admm_persistent<NX, NU, DI>;
   int per_cu = 0;
-  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_admm_persistent<NX, NU, DI>, threads,
-                                                      lds_bytes));
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, threads, lds_bytes));
   if (per_cu < 1) return fail(ctx, TADMM_ERR_HIP, "persistent kernel does not fit on a compute unit");
   const int grid = std::max(1, std::min(L.S, per_cu * ctx->n_cu));
   GraphKey key;
@@ -1288,7 +1304,12 @@ tadmm_status run_batched(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layo
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, cs, w.queue, 1, 0);
     const long long nc = (long long)L.S * CT_NCOL;
     hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, cs, w.cnt, nc);
-    hipLaunchKernelGGL((k_admm_persistent<NX, NU, DI>), dim3(grid), dim3(threads), lds_bytes, cs, pb, w, L.S, lds_floats);
+    if (lean)
+      hipLaunchKernelGGL((k_admm_persistent_lean<NX, NU, DI>), dim3(grid), dim3(threads), lds_bytes, cs, pb, w, L.S,
+                         lds_floats);
+    else
+      hipLaunchKernelGGL((k_admm_persistent<NX, NU, DI>), dim3(grid), dim3(threads), lds_bytes, cs, pb, w, L.S,
+                         lds_floats);
     hipLaunchKernelGGL((k_writeback<NX, NU>), dim3(std::min(L.S, 4096)), dim3(256), 0, cs, w, L.S, out);
     hipError_t le = hipGetLastError();
     hipError_t ce = hipStreamEndCapture(cs, &ctx->graph);
