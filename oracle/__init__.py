@@ -8,8 +8,8 @@ generators of ``synth``.
 
 The numerical core is plain C (``tadmm_oracle.c``, FP64, OpenMP over agents or
 scenarios); this module compiles it with gcc on first use and wraps it with
-ctypes.  ``grad.py`` (dense-KKT implicit gradient) and ``monolithic.py``
-(the centralized QP solved in one piece) are NumPy.
+ctypes.  ``grad.py`` (the gradient through a converged solve, by the implicit
+function theorem on the dense KKT system of its equality QP) is NumPy.
 """
 from __future__ import annotations
 
