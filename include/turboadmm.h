@@ -18,15 +18,15 @@
  *  - Pointers marked DEVICE are device (HBM) addresses on the context's
  *    device; pointers marked HOST are ordinary host memory.  The library never
  *    frees caller memory and never keeps a caller pointer beyond the call,
- *    except that tadmm_adjoint() reads the workspace left by the matching
- *    tadmm_solve().
+ *    except that tadmm_polish() and tadmm_adjoint() read the workspace (and
+ *    the batch inputs) of the matching tadmm_solve().
  *  - All device work is ordered on the stream given to tadmm_create().
- *    tadmm_solve() and tadmm_adjoint() return after the work has completed
- *    (they synchronize the stream once at the end).
+ *    tadmm_solve(), tadmm_polish() and tadmm_adjoint() return after the work
+ *    has completed (they synchronize the stream once at the end).
  *  - A context is not thread-safe; use one context per host thread.
  *  - Return codes report argument and runtime errors only.  Per-scenario
  *    outcomes (converged, iteration cap, ...) are data in tadmm_out::status.
- *  - Floating point is FP32 on the device.
+ *  - Floating point is FP32 on the device (the derivative: see eqp_fp64).
  *
  * Problem layout (homogeneous agents; C selects the first dp = nu entries of
  * the state as the position):
@@ -55,7 +55,7 @@ typedef enum {
   TADMM_ERR_INFEASIBLE_START = 4,/* two agents start closer than d_min               */
   TADMM_ERR_HIP = 5,             /* a HIP runtime call failed                        */
   TADMM_ERR_WORKSPACE = 6,       /* workspace missing or too small                   */
-  TADMM_ERR_STATE = 7            /* call out of order (adjoint without its solve)   */
+  TADMM_ERR_STATE = 7            /* call out of order (polish/adjoint without solve) */
 } tadmm_status;
 
 /* Per-scenario outcome, written to tadmm_out::status. */
@@ -117,6 +117,10 @@ typedef struct {
                                 of every local QP solution (reduced gradient in
                                 FP64, correction with the FP32 factors) (default);
                                 0: plain FP32 solve                                */
+  int32_t eqp_fp64;          /* real type of the Riccati sweeps of tadmm_polish /
+                                tadmm_adjoint: 1 FP64 (recommended), 0 FP32;
+                                their multipliers and reductions are FP64 either
+                                way                                                 */
 } tadmm_params;
 
 /* A ragged batch of S independent scenarios.  Scenario s has N_s agents and
@@ -177,22 +181,48 @@ tadmm_status tadmm_create(tadmm_ctx **ctx, const tadmm_params *params, void *str
 tadmm_status tadmm_solve(tadmm_ctx *ctx, const tadmm_batch *batch, const tadmm_out *out, void *workspace,
                          size_t workspace_bytes, int32_t mode);
 
-/* Reverse-mode derivative of a trajectory loss through the converged solve.
- * The solution of the last tadmm_solve() on this context is treated as the
- * solution of the centralized QP with its final active sets (input bounds
- * and binding half-planes) held as equalities and the normals held constant;
- * the KKT system of that equality QP is solved by an adjoint ADMM that reuses
- * the cached Riccati factors.  Upstream gradients (DEVICE, layouts of
+/* The derivative of a converged solve (an extension: the paper defines the
+ * solve, not its derivative).  The solution of the last tadmm_solve() on this
+ * context is read as the solution of the centralized QP (Sec. III-A, Eq. 1)
+ * with its final active sets held as equalities: the inputs of the working
+ * sets (tadmm_out::w) at their bounds, and the half-planes of the last
+ * consensus step (Eq. 4) that were violated (tadmm_out::pair_active) as
+ * n'(C x_i,t - C x_j,t) = d_min, with the normals of that step frozen
+ * (PER_ITER: from the final positions; FROZEN: the given or reference ones).
+ *
+ * tadmm_polish solves that equality QP: per agent a fixed-input LQR (Riccati
+ * factors of the local QP of Eq. 3 without the consensus penalty, Eq. 7),
+ * coupled only through the held half-planes, whose multipliers solve the
+ * Schur system D H^-1 D' nu = d - D w(0) by MINRES (warm start: the duals of
+ * the last consensus step; a least-squares solution when the held rows cannot
+ * all hold, which a solve stopped at max_iter can leave).  It overwrites out->x and out->u
+ * (required, DEVICE, layouts of tadmm_out) with the polished solution and
+ * keeps it in the workspace.  Call it once per solve; TADMM_ERR_STATE without
+ * a preceding successful tadmm_solve with the same batch (pointers and
+ * shapes) and workspace, or when already called for that solve.
+ *
+ * tadmm_adjoint then back-propagates a loss L(x, u) through the polished
+ * solution by the implicit function theorem on the KKT system of the same
+ * equality QP: the adjoint system is an equality QP of the same structure
+ * (homogeneous rows, linear term -dL/dw), solved the same way with the same
+ * factors, and the parameter gradients are -wbar' dF/dtheta, accumulated in
+ * FP64.  Upstream gradients at the polished solution (DEVICE, layouts of
  * tadmm_out::x / u; dL_du may be NULL):
  *   dL_dx [sum N_s (T_s+1)][nx],  dL_du [sum N_s T_s][nu]
  * Outputs (DEVICE, any may be NULL):
  *   dL_dx0    [sum N_s][nx]          dL_dxref [sum N_s (T_s+1)][nx]
  *   dL_dlogq  [S][nx]  (w.r.t. log of q_diag)   dL_dlogr [S][nu]
- * Returns TADMM_ERR_STATE without a preceding successful solve with the
- * same batch and workspace. */
+ * TADMM_ERR_STATE without a preceding tadmm_polish of the same solve.
+ *
+ * stats (both; DEVICE float [S][4] or NULL): number of held half-planes,
+ * MINRES iterations, final relative MINRES residual, and the largest
+ * |n'(C x_i - C x_j) - d| over the held rows after the final solve (d = d_min
+ * for the polish, 0 for the adjoint).  Both calls synchronize the stream. */
+tadmm_status tadmm_polish(tadmm_ctx *ctx, const tadmm_batch *batch, const tadmm_out *out, void *workspace,
+                          size_t workspace_bytes, float *stats);
 tadmm_status tadmm_adjoint(tadmm_ctx *ctx, const tadmm_batch *batch, const tadmm_out *out, void *workspace,
                            size_t workspace_bytes, const float *dL_dx, const float *dL_du, float *dL_dx0,
-                           float *dL_dxref, float *dL_dlogq, float *dL_dlogr);
+                           float *dL_dxref, float *dL_dlogq, float *dL_dlogr, float *stats);
 
 /* Measure candidate workgroup sizes of the batched kernel on this batch and
  * keep the fastest in the context (used when params.block_threads == 0).
@@ -200,8 +230,9 @@ tadmm_status tadmm_adjoint(tadmm_ctx *ctx, const tadmm_batch *batch, const tadmm
 tadmm_status tadmm_autotune(tadmm_ctx *ctx, const tadmm_batch *batch, const tadmm_out *out, void *workspace,
                             size_t workspace_bytes, int32_t *best_threads);
 
-/* Average duration in milliseconds of the last batched kernel launch (HIP
- * events recorded around it on the context's stream), or -1 if none. */
+/* Duration in milliseconds of the last batched solve, plain solve, polish or
+ * adjoint on this context (HIP events recorded around its launches on the
+ * context's stream), or -1 if none. */
 float tadmm_last_kernel_ms(const tadmm_ctx *ctx);
 
 tadmm_status tadmm_destroy(tadmm_ctx *ctx);

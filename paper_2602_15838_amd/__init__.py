@@ -39,7 +39,8 @@ class Params(C.Structure):
                 ("eps_abs", C.c_float), ("eps_rel", C.c_float), ("mu_tol", C.c_float),
                 ("max_iter", C.c_int32), ("max_as_iter", C.c_int32), ("normal_mode", C.c_int32),
                 ("cache_factors", C.c_int32), ("riccati_warmstart", C.c_int32), ("hotstart", C.c_int32),
-                ("check_inputs", C.c_int32), ("block_threads", C.c_int32), ("refine", C.c_int32)]
+                ("check_inputs", C.c_int32), ("block_threads", C.c_int32), ("refine", C.c_int32),
+                ("eqp_fp64", C.c_int32)]
 
 
 _fp = C.POINTER(C.c_float)
@@ -75,8 +76,10 @@ def lib():
         L.tadmm_create.argtypes = [C.POINTER(vp), C.POINTER(Params), vp]
         L.tadmm_solve.restype = C.c_int
         L.tadmm_solve.argtypes = [vp, C.POINTER(Batch), C.POINTER(Out), vp, C.c_size_t, C.c_int32]
+        L.tadmm_polish.restype = C.c_int
+        L.tadmm_polish.argtypes = [vp, C.POINTER(Batch), C.POINTER(Out), vp, C.c_size_t, vp]
         L.tadmm_adjoint.restype = C.c_int
-        L.tadmm_adjoint.argtypes = [vp, C.POINTER(Batch), C.POINTER(Out), vp, C.c_size_t, vp, vp, vp, vp, vp, vp]
+        L.tadmm_adjoint.argtypes = [vp, C.POINTER(Batch), C.POINTER(Out), vp, C.c_size_t, vp, vp, vp, vp, vp, vp, vp]
         L.tadmm_autotune.restype = C.c_int
         L.tadmm_autotune.argtypes = [vp, C.POINTER(Batch), C.POINTER(Out), vp, C.c_size_t, _ip]
         L.tadmm_last_kernel_ms.restype = C.c_float
@@ -93,7 +96,8 @@ def lib():
     return _lib
 
 
-EXPORTED_SYMBOLS = ("tadmm_workspace_size", "tadmm_create", "tadmm_solve", "tadmm_adjoint", "tadmm_autotune",
+EXPORTED_SYMBOLS = ("tadmm_workspace_size", "tadmm_create", "tadmm_solve", "tadmm_polish", "tadmm_adjoint",
+                    "tadmm_autotune",
                     "tadmm_last_kernel_ms", "tadmm_destroy", "tadmm_status_string", "tadmm_last_error",
                     "tadmm_version")
 
@@ -101,7 +105,7 @@ EXPORTED_SYMBOLS = ("tadmm_workspace_size", "tadmm_create", "tadmm_solve", "tadm
 def make_params(problem, *, normal_mode: int = NORMAL_PER_ITER, mu_tol: float = 1e-5, max_as_iter: int = 0,
                 cache_factors: bool = True, riccati_warmstart: bool = True, hotstart: bool = True,
                 check_inputs: bool = True, block_threads: int = 0, refine: bool = True,
-                max_iter: Optional[int] = None,
+                eqp_fp64: bool = True, max_iter: Optional[int] = None,
                 eps_abs: Optional[float] = None, eps_rel: Optional[float] = None,
                 rho: Optional[float] = None) -> Params:
     """Fill the C parameter struct from a problem description (attributes
@@ -131,6 +135,7 @@ def make_params(problem, *, normal_mode: int = NORMAL_PER_ITER, mu_tol: float = 
     p.check_inputs = int(bool(check_inputs))
     p.block_threads = int(block_threads)
     p.refine = int(bool(refine))
+    p.eqp_fp64 = int(bool(eqp_fp64))
     return p
 
 
@@ -244,25 +249,92 @@ class Prepared:
         s._check(rc)
         return int(best.value)
 
-    def adjoint(self, dL_dx, dL_du=None):
-        """Gradients of a trajectory loss through the last solve (see
-        tadmm_adjoint).  Returns (dL_dx0, dL_dxref, dL_dlogq, dL_dlogr)."""
+    def polish(self):
+        """Replace the solution of the last run with the solution of its
+        equality QP (tadmm_polish); returns the per-scenario stats [S][4]."""
         torch = self.solver.torch
-        s, b, o = self.solver, self.b, self.o
+        s = self.solver
+        st = torch.zeros(self.b["N"].size, 4, device=s.device)
+        rc = lib().tadmm_polish(s._h, C.byref(self.batch), C.byref(self.out), C.c_void_p(self.ws.data_ptr()),
+                                C.c_size_t(self.nbytes), _ptr(st))
+        s._check(rc)
+        return st
+
+    def adjoint(self, dL_dx, dL_du=None, want_stats: bool = False):
+        """Gradients of a loss through the polished solution (tadmm_adjoint).
+        Returns (dL_dx0, dL_dxref, dL_dlogq, dL_dlogr) [, stats]."""
+        torch = self.solver.torch
+        s, b = self.solver, self.b
         dev = s.device
         gx = dL_dx.to(device=dev, dtype=torch.float32).contiguous()
         gu = None if dL_du is None else dL_du.to(device=dev, dtype=torch.float32).contiguous()
         outs = (torch.zeros_like(b["x0"]), torch.zeros_like(b["xref"]), torch.zeros_like(b["q_diag"]),
                 torch.zeros_like(b["r_diag"]))
+        st = torch.zeros(b["N"].size, 4, device=dev)
         rc = lib().tadmm_adjoint(s._h, C.byref(self.batch), C.byref(self.out), C.c_void_p(self.ws.data_ptr()),
-                                 C.c_size_t(self.nbytes), _ptr(gx), _ptr(gu), *[_ptr(t) for t in outs])
+                                 C.c_size_t(self.nbytes), _ptr(gx), _ptr(gu), *[_ptr(t) for t in outs], _ptr(st))
         s._check(rc)
-        return outs
+        return (outs + (st,)) if want_stats else outs
 
     def result(self) -> Dict:
         r = dict(self.o)
         r["kernel_ms"] = lib().tadmm_last_kernel_ms(self.solver._h)
         return r
+
+
+def straight_line_ref(starts, goals, T: int, dt: float):
+    """Constant-velocity references from rest positions to goals, as torch
+    ops (so that gradients reach the goals): r_t = (p_s + (t/T)(g - p_s),
+    (g - p_s)/(T dt)), t = 0..T.  starts, goals [N][dp] -> [N][T+1][2 dp]."""
+    import torch
+    frac = torch.arange(T + 1, device=starts.device, dtype=starts.dtype) / T
+    d = goals - starts
+    pos = starts[:, None, :] + frac[None, :, None] * d[:, None, :]
+    vel = (d / (T * dt))[:, None, :].expand(-1, T + 1, -1)
+    return torch.cat([pos, vel], dim=2)
+
+
+def _autograd_function():
+    import torch
+
+    class TurboADMMFunction(torch.autograd.Function):
+        """(x, u) = argmin of the batch (tadmm_solve + tadmm_polish); the
+        backward pass is tadmm_adjoint.  Arguments: x0 [sum N][nx], xref
+        [sum N (T+1)][nx], log_q [S][nx], log_r [S][nu] (device tensors) and a
+        config dict with keys solver (Solver), n_agents, horizon and optional
+        normals and mode.  After the call, config["prepared"] holds the batch
+        (statuses, iteration counts, polish statistics)."""
+
+        @staticmethod
+        def forward(ctx, x0, xref, log_q, log_r, config):
+            solver = config["solver"]
+            prep = solver.prepare(config["n_agents"], config["horizon"], x0.detach(), xref.detach(),
+                                  torch.exp(log_q.detach()), torch.exp(log_r.detach()), config.get("normals"))
+            prep.run(config.get("mode", MODE_BATCHED))
+            prep.polish_stats = prep.polish()
+            config["prepared"] = prep
+            ctx.prep = prep
+            return prep.o["x"].clone(), prep.o["u"].clone()
+
+        @staticmethod
+        def backward(ctx, gx, gu):
+            dx0, dxref, dlogq, dlogr = ctx.prep.adjoint(gx, gu)
+            return dx0, dxref, dlogq, dlogr, None
+
+    return TurboADMMFunction
+
+
+class _Lazy:
+    """Creates the autograd Function on first use (torch is imported lazily)."""
+    _fn = None
+
+    def __getattr__(self, name):
+        if _Lazy._fn is None:
+            _Lazy._fn = _autograd_function()
+        return getattr(_Lazy._fn, name)
+
+
+TurboADMMFunction = _Lazy()
 
 
 def split_outputs(res: Dict, n_agents: Sequence[int], horizon: Sequence[int], nx: int, nu: int):

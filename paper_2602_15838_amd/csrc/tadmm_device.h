@@ -241,7 +241,9 @@ __device__ __forceinline__ void stage_hx(const Prob &pb, const float *qd, int t,
 }
 
 // ---------------------------------------------------------------------------
-// Riccati factor of one stage for a working set (Eq. 7 with inputs fixed)
+// Riccati factor of one stage for a working set (Eq. 7 with inputs fixed),
+// in the real type R (FP32 for the ADMM iterations; the equality-QP solves of
+// the adjoint also instantiate it in FP64)
 // ---------------------------------------------------------------------------
 // Given P_{t+1}, the free/fixed pattern of u_t and the bound values ubar:
 //   S = H_u + B'P B,  M = B'P A,  S' = S on the free block, identity elsewhere,
@@ -253,57 +255,56 @@ __device__ __forceinline__ void stage_hx(const Prob &pb, const float *qd, int t,
 // With these, the affine terms of the sweep are
 //   k_t = kc - Sv B'p_{t+1},   p_t = q_t + c + A'p_{t+1} + K' B'p_{t+1},
 // since A + B K is the closed loop and -Sv B' the gain of k_t on p_{t+1}.
-template <int NX, int NU, bool DI>
-__device__ __forceinline__ void factor_stage(const Prob &pb, const float hx[NX], const float hu[NU],
-                                             const float Pn[NX][NX], const int8_t wt[NU], bool want_P,
-                                             float Pt[NX][NX], float K[NU][NX], float Sv[NU][NU], float kc[NU],
-                                             float cc[NX]) {
+template <int NX, int NU, bool DI, class R>
+__device__ __forceinline__ void factor_stage(const Prob &pb, const R hx[NX], const R hu[NU], const R Pn[NX][NX],
+                                             const int8_t wt[NU], bool want_P, R Pt[NX][NX], R K[NU][NX],
+                                             R Sv[NU][NU], R kc[NU], R cc[NX]) {
   using D = Dyn<NX, NU, DI>;
-  float PB[NX][NU];  // row r of P B is B' (row r of P), P symmetric
+  R PB[NX][NU];  // row r of P B is B' (row r of P), P symmetric
 #pragma unroll
   for (int r = 0; r < NX; ++r) D::btx(pb, Pn[r], PB[r]);
-  float S[NU][NU];
+  R S[NU][NU];
 #pragma unroll
   for (int b = 0; b < NU; ++b) {
-    float col[NX], sb[NU];
+    R col[NX], sb[NU];
 #pragma unroll
     for (int r = 0; r < NX; ++r) col[r] = PB[r][b];
     D::btx(pb, col, sb);
 #pragma unroll
-    for (int a = 0; a < NU; ++a) S[a][b] = sb[a] + ((a == b) ? hu[a] : 0.f);
+    for (int a = 0; a < NU; ++a) S[a][b] = sb[a] + ((a == b) ? hu[a] : R(0));
   }
-  float M[NU][NX];  // row a of B'P A is A' (column a of P B)
+  R M[NU][NX];  // row a of B'P A is A' (column a of P B)
 #pragma unroll
   for (int a = 0; a < NU; ++a) {
-    float col[NX];
+    R col[NX];
 #pragma unroll
     for (int r = 0; r < NX; ++r) col[r] = PB[r][a];
     D::atx(pb, col, M[a]);
   }
   bool fr[NU];
-  float ub[NU];
+  R ub[NU];
 #pragma unroll
   for (int a = 0; a < NU; ++a) {
     fr[a] = (wt[a] == 0);
-    ub[a] = (wt[a] == 1) ? pb.ulo[a] : ((wt[a] == 2) ? pb.uhi[a] : 0.f);
+    ub[a] = (wt[a] == 1) ? (R)pb.ulo[a] : ((wt[a] == 2) ? (R)pb.uhi[a] : R(0));
   }
   // Cholesky of S' (lower) with reciprocal diagonal
-  float L[NU][NU], Li[NU];
+  R L[NU][NU], Li[NU];
 #pragma unroll
   for (int a = 0; a < NU; ++a)
 #pragma unroll
-    for (int b = 0; b < NU; ++b) L[a][b] = 0.f;
+    for (int b = 0; b < NU; ++b) L[a][b] = R(0);
 #pragma unroll
   for (int a = 0; a < NU; ++a) {
 #pragma unroll
     for (int b = 0; b <= a; ++b) {
-      float v = (fr[a] && fr[b]) ? S[a][b] : (a == b ? 1.f : 0.f);
+      R v = (fr[a] && fr[b]) ? S[a][b] : (a == b ? R(1) : R(0));
 #pragma unroll
-      for (int k = 0; k < b; ++k) v = fmaf(-L[a][k], L[b][k], v);
+      for (int k = 0; k < b; ++k) v = fma(-L[a][k], L[b][k], v);
       if (a == b) {
-        const float d = sqrtf(v);
+        const R d = sqrt(v);
         L[a][a] = d;
-        Li[a] = 1.0f / d;
+        Li[a] = R(1) / d;
       } else {
         L[a][b] = v * Li[b];
       }
@@ -312,70 +313,70 @@ __device__ __forceinline__ void factor_stage(const Prob &pb, const float hx[NX],
   // Sv = S'^-1 column by column, fixed rows/columns zeroed
 #pragma unroll
   for (int b = 0; b < NU; ++b) {
-    float y[NU];
+    R y[NU];
 #pragma unroll
-    for (int a = 0; a < NU; ++a) y[a] = (a == b) ? 1.f : 0.f;
+    for (int a = 0; a < NU; ++a) y[a] = (a == b) ? R(1) : R(0);
 #pragma unroll
     for (int a = 0; a < NU; ++a) {
-      float v = y[a];
+      R v = y[a];
 #pragma unroll
-      for (int k = 0; k < a; ++k) v = fmaf(-L[a][k], y[k], v);
+      for (int k = 0; k < a; ++k) v = fma(-L[a][k], y[k], v);
       y[a] = v * Li[a];
     }
 #pragma unroll
     for (int a = NU - 1; a >= 0; --a) {
-      float v = y[a];
+      R v = y[a];
 #pragma unroll
-      for (int k = a + 1; k < NU; ++k) v = fmaf(-L[k][a], y[k], v);
+      for (int k = a + 1; k < NU; ++k) v = fma(-L[k][a], y[k], v);
       y[a] = v * Li[a];
     }
 #pragma unroll
-    for (int a = 0; a < NU; ++a) Sv[a][b] = (fr[a] && fr[b]) ? y[a] : 0.f;
+    for (int a = 0; a < NU; ++a) Sv[a][b] = (fr[a] && fr[b]) ? y[a] : R(0);
   }
-  float su[NU];  // (S ubar) on the free rows
+  R su[NU];  // (S ubar) on the free rows
 #pragma unroll
   for (int a = 0; a < NU; ++a) {
-    float v = 0.f;
+    R v = R(0);
 #pragma unroll
-    for (int b = 0; b < NU; ++b) v = fmaf(S[a][b], ub[b], v);
-    su[a] = fr[a] ? v : 0.f;
+    for (int b = 0; b < NU; ++b) v = fma(S[a][b], ub[b], v);
+    su[a] = fr[a] ? v : R(0);
   }
 #pragma unroll
   for (int a = 0; a < NU; ++a) {
 #pragma unroll
     for (int c = 0; c < NX; ++c) {
-      float v = 0.f;
+      R v = R(0);
 #pragma unroll
-      for (int b = 0; b < NU; ++b) v = fmaf(Sv[a][b], M[b][c], v);
+      for (int b = 0; b < NU; ++b) v = fma(Sv[a][b], M[b][c], v);
       K[a][c] = -v;
     }
-    float v = 0.f;
+    R v = R(0);
 #pragma unroll
-    for (int b = 0; b < NU; ++b) v = fmaf(Sv[a][b], su[b], v);
+    for (int b = 0; b < NU; ++b) v = fma(Sv[a][b], su[b], v);
     kc[a] = fr[a] ? -v : ub[a];
   }
 #pragma unroll
   for (int r = 0; r < NX; ++r) {
-    float v = 0.f;
+    R v = R(0);
 #pragma unroll
-    for (int a = 0; a < NU; ++a) v = fmaf(K[a][r], su[a], fmaf(M[a][r], ub[a], v));
+    for (int a = 0; a < NU; ++a) v = fma(K[a][r], su[a], fma(M[a][r], ub[a], v));
     cc[r] = v;
   }
   if (want_P) {
-    float PA[NX][NX];  // row r of P A is A' (row r of P)
+    R PA[NX][NX];  // row r of P A is A' (row r of P)
 #pragma unroll
     for (int r = 0; r < NX; ++r) D::atx(pb, Pn[r], PA[r]);
 #pragma unroll
     for (int c = 0; c < NX; ++c) {
-      float col[NX], apa[NX];
+      R col[NX], apa[NX];
 #pragma unroll
       for (int r = 0; r < NX; ++r) col[r] = PA[r][c];
       D::atx(pb, col, apa);   // column c of A'P A
 #pragma unroll
       for (int r = 0; r <= c; ++r) {
-        float v = apa[r] + ((r == c) ? hx[r] : 0.f);
+        R v = apa[r] + ((r == c) ? hx[r] : R(0));
 #pragma unroll
-        for (int a = 0; a < NU; ++a) v = fmaf(M[a][r], K[a][c], v);
+        for (int a = 0; a < NU; ++a) v = fma(M[a][r], K[a][c], v);
         Pt[r][c] = v;
         Pt[c][r] = v;
       }

@@ -1,0 +1,561 @@
+// Equality-QP solves behind the derivative of a converged solve (gfx950).
+//
+// The solution of the ADMM iterations is read as the solution of the
+// centralized QP of Sec. III-A with its final active sets held as equalities:
+// the inputs of the working sets W at their bounds, and the half-planes of
+// the last consensus step that were violated (A_c) as n'(C x_i,t - C x_j,t) =
+// d_min, with their normals n frozen.  That equality QP (EQP) is solved twice:
+//
+//   polish:  min sum_i J_i(w_i)            s.t. dynamics (x0), W at bounds, A_c
+//   adjoint: min sum_i 1/2 w'H_i w - g'w   s.t. the same rows, homogeneous
+//            (g = dL/dw; its solution wbar and costates give dL/dtheta by the
+//            implicit function theorem).
+//
+// Both have the same structure: per agent an LQR with fixed inputs, coupled
+// only through the held half-planes.  With multipliers nu on those rows, each
+// agent's solution is an affine function of the linear term -D'nu on its
+// positions (one Riccati sweep and rollout, factors of the agent QP without
+// the consensus penalty), and the rows themselves give the Schur system
+//   S nu = d - D w(0),   S = D H_W^-1 D'  (symmetric positive semidefinite),
+// solved by MINRES: one sweep + rollout per agent per iteration, exact after
+// |A_c| iterations in exact arithmetic, and a least-squares solution when the
+// held rows cannot all hold (a solve stopped before convergence can leave
+// such a set).  The polish starts from the multipliers of the last consensus
+// step (nu = -n'lambda_ij = gamma).
+//
+// Work decomposition: one workgroup per scenario.  The sweeps run one lane per
+// agent in the real type R (FP64, or FP32 on request); the scatter of -D'nu
+// one lane per agent-stage over its partners (fixed order); the Krylov
+// vectors, scalars and the gradient reductions are FP64 with fixed-order
+// reductions, so the result is deterministic.
+#pragma once
+
+#include "tadmm_device.h"
+
+namespace tadmm {
+
+// Per agent-stage fields of the EQP region (R values, each padded to 4).
+template <int NX, int NU>
+struct EFld {
+  static constexpr int NS = NU * (NU + 1) / 2;
+  static constexpr int K = 0;                   // feedback gain without the consensus penalty  [NU*NX]
+  static constexpr int SV = K + pad4(NU * NX);  // S'^-1, packed symmetric                     [NS]
+  static constexpr int KC = SV + pad4(NS);      // feedforward constant of the fixed inputs     [NU]
+  static constexpr int CC = KC + pad4(NU);      // value-gradient constant of the fixed inputs  [NX]
+  static constexpr int KV = CC + pad4(NX);      // affine feedforward k_t of the last sweep     [NU]
+  static constexpr int E = KV + pad4(NU);       // -D'v on the positions (coupling term)        [NU]
+  static constexpr int XT = E + pad4(NU);       // positions of the last rollout                [NU]
+  static constexpr int XS = XT + pad4(NU);      // polished x_t                                 [NX]
+  static constexpr int US = XS + pad4(NX);      // polished u_t                                 [NU]
+  static constexpr int NF = US + pad4(NU);
+};
+
+// EQP workspace (pointers into the solve's workspace).  Pair-steps are
+// indexed q = p T + (t - 1), p the lexicographic pair index (as the caller's
+// normals); held half-planes are compacted per scenario in that order.
+struct EWS {
+  void *er;          // [sum N(T+1)][EFld::NF] R
+  float *nrm;        // [sum P T][NU] frozen normals
+  int *cidx;         // [sum P T] compact index of a held half-plane, -1 otherwise
+  int2 *clist;       // [sum P T] (q, i N + j) of held half-plane k
+  double *cg;        // [sum P T][6]: per scenario nu and five MINRES vectors, each P T long
+  int *m;            // [S] number of held half-planes
+};
+
+enum { EQ_POLISH = 0, EQ_ADJOINT = 1 };
+enum { EQK_INHOM = 0, EQK_HOM = 1, EQK_ADJ = 2 };
+enum { ES_M = 0, ES_ITERS, ES_RES, ES_VIOL, ES_NCOL };
+
+struct EqpIO {
+  const float *gx, *gu;          // adjoint: upstream dL/dx, dL/du (caller layouts; gu may be null)
+  float *x, *u;                  // polish: outputs (caller layouts)
+  float *dx0, *dxref, *dlogq, *dlogr;   // adjoint outputs (any may be null)
+  float *stats;                  // [S][ES_NCOL] or null
+};
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max_d(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Workgroup-wide sum (max) in a fixed order; every thread gets the result.
+__device__ __forceinline__ double block_sum(double v, double *red) {
+  v = wave_sum_d(v);
+  const int nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < nw; ++w) s += red[w];
+  return s;
+}
+
+__device__ __forceinline__ double block_max(double v, double *red) {
+  v = wave_max_d(v);
+  const int nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < nw; ++w) s = fmax(s, red[w]);
+  return s;
+}
+
+__device__ __forceinline__ int pair_of(int f, int s, int N) { return f * N - f * (f + 1) / 2 + (s - f - 1); }
+
+// Riccati factors of agent i for its working set, without the consensus
+// penalty: H_x = 2 Q_t, H_T = 2 qT Q, H_u = 2 R (Eq. 7 with fixed inputs).
+template <int NX, int NU, bool DI, class R>
+__device__ void eqp_factor(const Prob &pb, const WS &ws, const Scen &sc, R *Er, int i) {
+  using EF = EFld<NX, NU>;
+  const int N = sc.N, T = sc.T;
+  const float *qd = ws.qd + (long long)sc.s * NX;
+  const float *rd = ws.rd + (long long)sc.s * NU;
+  const int8_t *Wb = ws.wr + sc.bo;
+  R hu[NU];
+#pragma unroll
+  for (int a = 0; a < NU; ++a) hu[a] = R(2) * (R)rd[a];
+  R Pn[NX][NX];
+#pragma unroll
+  for (int r = 0; r < NX; ++r)
+#pragma unroll
+    for (int c = 0; c < NX; ++c) Pn[r][c] = (r == c) ? R(2) * (R)pb.qT * (R)qd[r] : R(0);
+  for (int t = T - 1; t >= 0; --t) {
+    R hx[NX];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) hx[r] = R(2) * (R)qd[r];
+    int8_t wt[NU];
+#pragma unroll
+    for (int a = 0; a < NU; ++a) wt[a] = Wb[(unsigned)(t * N + i) * 4u + a];
+    R Pt[NX][NX], K[NU][NX], Sv[NU][NU], kc[NU], cc[NX];
+    factor_stage<NX, NU, DI, R>(pb, hx, hu, Pn, wt, t >= 1, Pt, K, Sv, kc, cc);
+    R *f = Er + (size_t)(t * N + i) * EF::NF;
+#pragma unroll
+    for (int a = 0; a < NU; ++a) {
+#pragma unroll
+      for (int c = 0; c < NX; ++c) f[EF::K + a * NX + c] = K[a][c];
+#pragma unroll
+      for (int b = a; b < NU; ++b) f[EF::SV + sym_idx<NU>(a, b)] = Sv[a][b];
+      f[EF::KC + a] = kc[a];
+    }
+#pragma unroll
+    for (int r = 0; r < NX; ++r) f[EF::CC + r] = cc[r];
+    if (t >= 1) {
+#pragma unroll
+      for (int r = 0; r < NX; ++r)
+#pragma unroll
+        for (int c = 0; c < NX; ++c) Pn[r][c] = Pt[r][c];
+    }
+  }
+}
+
+// One agent's EQP solve for the coupling term stored in the E field.
+//   kind EQK_INHOM: x_0 = x0, fixed inputs at their bounds, tracking terms
+//                   -2 Q_t r_t (the polish);
+//   kind EQK_HOM:   x_0 = 0, fixed inputs 0, no other term (a product with S);
+//   kind EQK_ADJ:   x_0 = 0, fixed inputs 0, linear terms -dL/dx_t, -dL/du_t.
+// Backward sweep p_T = q_T; s = B'p_{t+1} + r_t; k_t = kc_t - Sv_t s;
+// p_t = q_t + c_t + A'p_{t+1} + K_t' s (kc, c only for EQK_INHOM); then the
+// rollout u_t = K_t x_t + k_t.  With `final` the solution is stored (polish)
+// or turned into the parameter gradients (adjoint): with xbar, ubar the
+// adjoint solution and p_0 its value gradient at stage 0,
+//   dL/dx0      = dL/dx_0 - p_0,
+//   dL/dxref_t  = 2 w_t q * xbar_t                       (t >= 1; 0 at t = 0),
+//   dL/dlog q_k = -sum_t 2 w_t q_k xbar_t,k (x_t,k - r_t,k),
+//   dL/dlog r_a = -sum_t 2 r_a ubar_t,a u_t,a,
+// i.e. -wbar' dF/dtheta for the KKT map F = H w + c + E'y of the EQP.
+template <int NX, int NU, bool DI, class R>
+__device__ void eqp_agent(const Prob &pb, const WS &ws, const Scen &sc, R *Er, int i, int kind, bool final,
+                          const EqpIO &io, double gq[NX], double gr[NU]) {
+  using EF = EFld<NX, NU>;
+  using D = Dyn<NX, NU, DI>;
+  const int N = sc.N, T = sc.T;
+  const float *qd = ws.qd + (long long)sc.s * NX;
+  const float *rd = ws.rd + (long long)sc.s * NU;
+  const long long xrow = sc.xo + (long long)i * (T + 1);   // caller row of (agent, t = 0)
+  const long long urow = sc.uo + (long long)i * T;
+  auto F = [&](int t) -> R * { return Er + (size_t)(t * N + i) * EF::NF; };
+  auto qlin = [&](int t, R q[NX]) {
+    const R *f = F(t);
+    const R w = (t == T) ? (R)pb.qT : R(1);
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      R v = R(0);
+      if (kind == EQK_INHOM) v = R(-2) * w * (R)qd[c] * (R)ws.xref[(xrow + t) * NX + c];
+      else if (kind == EQK_ADJ) v = -(R)io.gx[(xrow + t) * NX + c];
+      if (c < NU) v += f[EF::E + c];
+      q[c] = v;
+    }
+  };
+  R p[NX];
+  qlin(T, p);
+  for (int t = T - 1; t >= 0; --t) {
+    R *f = F(t);
+    R s[NU];
+    D::btx(pb, p, s);
+    if (kind == EQK_ADJ && io.gu) {
+#pragma unroll
+      for (int a = 0; a < NU; ++a) s[a] -= (R)io.gu[(urow + t) * NU + a];
+    }
+    R pn[NX];
+    D::atx(pb, p, pn);
+#pragma unroll
+    for (int a = 0; a < NU; ++a) {
+      R k = (kind == EQK_INHOM) ? f[EF::KC + a] : R(0);
+#pragma unroll
+      for (int b = 0; b < NU; ++b) k = fma(-f[EF::SV + (a <= b ? sym_idx<NU>(a, b) : sym_idx<NU>(b, a))], s[b], k);
+      f[EF::KV + a] = k;
+#pragma unroll
+      for (int c = 0; c < NX; ++c) pn[c] = fma(f[EF::K + a * NX + c], s[a], pn[c]);
+    }
+    if (kind == EQK_INHOM) {
+#pragma unroll
+      for (int c = 0; c < NX; ++c) pn[c] += f[EF::CC + c];
+    }
+    if (t >= 1) {
+      R q[NX];
+      qlin(t, q);
+#pragma unroll
+      for (int c = 0; c < NX; ++c) pn[c] += q[c];
+    }
+#pragma unroll
+    for (int c = 0; c < NX; ++c) p[c] = pn[c];
+  }
+  R x[NX];
+#pragma unroll
+  for (int c = 0; c < NX; ++c) x[c] = (kind == EQK_INHOM) ? (R)ws.x0[(sc.ao + i) * NX + c] : R(0);
+  if (final && kind == EQK_INHOM) {
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      F(0)[EF::XS + c] = x[c];
+      io.x[(xrow + 0) * NX + c] = (float)x[c];
+    }
+  }
+  if (final && kind == EQK_ADJ) {
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      if (io.dx0) io.dx0[(sc.ao + i) * NX + c] = (float)((double)io.gx[(xrow + 0) * NX + c] - (double)p[c]);
+      if (io.dxref) io.dxref[(xrow + 0) * NX + c] = 0.f;
+    }
+  }
+  for (int t = 0; t < T; ++t) {
+    const R *f = F(t);
+    R u[NU];
+#pragma unroll
+    for (int a = 0; a < NU; ++a) {
+      R v = f[EF::KV + a];
+#pragma unroll
+      for (int c = 0; c < NX; ++c) v = fma(f[EF::K + a * NX + c], x[c], v);
+      u[a] = v;
+    }
+    R xn[NX];
+    D::ax(pb, x, xn);
+    D::add_bu(pb, u, xn);
+    R *fn = F(t + 1);
+#pragma unroll
+    for (int c = 0; c < NU; ++c) fn[EF::XT + c] = xn[c];
+    if (final && kind == EQK_INHOM) {
+#pragma unroll
+      for (int a = 0; a < NU; ++a) {
+        F(t)[EF::US + a] = u[a];
+        io.u[(urow + t) * NU + a] = (float)u[a];
+      }
+#pragma unroll
+      for (int c = 0; c < NX; ++c) {
+        fn[EF::XS + c] = xn[c];
+        io.x[(xrow + t + 1) * NX + c] = (float)xn[c];
+      }
+    }
+    if (final && kind == EQK_ADJ) {
+      const R *fs = F(t);
+#pragma unroll
+      for (int a = 0; a < NU; ++a) gr[a] -= 2.0 * (double)rd[a] * (double)u[a] * (double)fs[EF::US + a];
+      const double w = (t + 1 == T) ? (double)pb.qT : 1.0;
+#pragma unroll
+      for (int c = 0; c < NX; ++c) {
+        const double wq = 2.0 * w * (double)qd[c];
+        const double dev = (double)fn[EF::XS + c] - (double)ws.xref[(xrow + t + 1) * NX + c];
+        gq[c] -= wq * (double)xn[c] * dev;
+        if (io.dxref) io.dxref[(xrow + t + 1) * NX + c] = (float)(wq * (double)xn[c]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NX; ++c) x[c] = xn[c];
+  }
+}
+
+// E_i,t = -sum_j sigma_ij v_k n_k over the held half-planes k = (i, j, t)
+// (sigma = +1 when i is the pair's first agent): the linear term -D'v.
+template <int NX, int NU, class R>
+__device__ void eqp_scatter(const Scen &sc, R *Er, const float *nrm, const int *cidx, const double *v, double scale,
+                            int tid, int nth) {
+  using EF = EFld<NX, NU>;
+  const int N = sc.N, T = sc.T;
+  for (int idx = tid; idx < N * T; idx += nth) {
+    const int t = idx / N + 1, i = idx % N;
+    double e[NU];
+#pragma unroll
+    for (int c = 0; c < NU; ++c) e[c] = 0.0;
+    for (int j = 0; j < N; ++j) {
+      if (j == i) continue;
+      const int f = i < j ? i : j, s = i < j ? j : i;
+      const int q = pair_of(f, s, N) * T + (t - 1);
+      const int k = cidx[q];
+      if (k < 0) continue;
+      const double sv = (i < j) ? scale * v[k] : -scale * v[k];
+#pragma unroll
+      for (int c = 0; c < NU; ++c) e[c] -= sv * (double)nrm[(long long)q * NU + c];
+    }
+    R *f = Er + (size_t)(t * N + i) * EF::NF;
+#pragma unroll
+    for (int c = 0; c < NU; ++c) f[EF::E + c] = (R)e[c];
+  }
+}
+
+// (D xt)_k = n_k'(XT_i,t - XT_j,t) for held half-plane k.
+template <int NX, int NU, class R>
+__device__ __forceinline__ double eqp_row(const Scen &sc, const R *Er, const float *nrm, int2 ent) {
+  using EF = EFld<NX, NU>;
+  const int N = sc.N, T = sc.T;
+  const int q = ent.x, i = ent.y / N, j = ent.y % N, t = q % T + 1;
+  const R *fi = Er + (size_t)(t * N + i) * EF::NF;
+  const R *fj = Er + (size_t)(t * N + j) * EF::NF;
+  double g = 0.0;
+#pragma unroll
+  for (int c = 0; c < NU; ++c) g = fma((double)nrm[(long long)q * NU + c], (double)fi[EF::XT + c] - (double)fj[EF::XT + c], g);
+  return g;
+}
+
+// Freeze the normals of the last consensus step and compact the held
+// half-planes (contiguous chunks per thread, exclusive scan: a fixed order);
+// the polish starts from nu = -n'lambda_ij.
+template <int NX, int NU>
+__device__ void eqp_freeze(const Prob &pb, const WS &ws, const EWS &ew, const Scen &sc, int *scan, int tid, int nth) {
+  using F = Fld<NX, NU>;
+  const int N = sc.N, T = sc.T, P = N * (N - 1) / 2, TP = P * T;
+  const float *R = ws.fr + sc.fo;
+  float *nrm = ew.nrm + sc.po * NU;
+  int *cidx = ew.cidx + sc.po;
+  int2 *cl = ew.clist + sc.po;
+  double *nu = ew.cg + 6 * sc.po;
+  const float *lam = ws.lam + sc.lo;
+  const uint8_t *pa = ws.pact + sc.lb;
+  const int LS = T * N * N;
+  const int per = (TP + nth - 1) / nth;
+  const int q0 = min(TP, tid * per), q1 = min(TP, q0 + per);
+  int cnt = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    int k = (pass == 1) ? scan[tid] : 0;
+    int i = 0, j = 1, pcur = -1;
+    for (int q = q0; q < q1; ++q) {
+      const int p = q / T, t = q % T + 1;
+      if (p != pcur) {   // decode the pair (i, j) of index p
+        int r = p;
+        i = 0;
+        while (r >= N - 1 - i) { r -= N - 1 - i; ++i; }
+        j = i + 1 + r;
+        pcur = p;
+      }
+      const int e = (t - 1) * N * N + j * N + i;   // ordered copy (i, j), i first
+      const bool act = pa[e] != 0;
+      if (pass == 0) {
+        float n[NU];
+        if (pb.normal_mode == NORMAL_FROZEN) {
+          if (ws.normals) {
+            const float *nv = ws.normals + (sc.po + (long long)q) * NU;
+#pragma unroll
+            for (int c = 0; c < NU; ++c) n[c] = nv[c];
+          } else {
+            reference_normal<NX, NU>(ws, sc, i, j, t, n);
+          }
+        } else {   // the normal of the last consensus step, from the final positions
+          float d[NU], dd = 0.f;
+#pragma unroll
+          for (int c = 0; c < NU; ++c) {
+            d[c] = R[(unsigned)(t * N + i) * (unsigned)F::NF + F::X + c] - R[(unsigned)(t * N + j) * (unsigned)F::NF + F::X + c];
+            dd = fmaf(d[c], d[c], dd);
+          }
+          dd = sqrtf(dd);
+          if (dd >= 1e-6f) {
+#pragma unroll
+            for (int c = 0; c < NU; ++c) n[c] = d[c] / dd;
+          } else {
+            reference_normal<NX, NU>(ws, sc, i, j, t, n);
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < NU; ++c) nrm[(long long)q * NU + c] = n[c];
+        cnt += act;
+      } else {
+        if (act) {
+          double g = 0.0;
+#pragma unroll
+          for (int c = 0; c < NU; ++c) g = fma((double)nrm[(long long)q * NU + c], (double)lam[c * LS + e], g);
+          cidx[q] = k;
+          cl[k] = make_int2(q, i * N + j);
+          nu[k] = -g;
+          ++k;
+        } else {
+          cidx[q] = -1;
+        }
+      }
+    }
+    if (pass == 0) {
+      __syncthreads();
+      scan[tid] = cnt;
+      __syncthreads();
+      if (tid == 0) {
+        int acc = 0;
+        for (int w = 0; w < nth; ++w) { const int c = scan[w]; scan[w] = acc; acc += c; }
+        ew.m[sc.s] = acc;
+        scan[nth] = acc;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <int NX, int NU, bool DI, class R>
+__device__ void eqp_scenario(const Prob &pb, const WS &ws, const EWS &ew, const EqpIO &io, int s, int mode, int max_cg,
+                             double tol, double *red, int *scan) {
+  using EF = EFld<NX, NU>;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const Scen sc = load_scen(ws, s);
+  const int N = sc.N, T = sc.T, TP = N * (N - 1) / 2 * T;
+  R *Er = (R *)ew.er + (size_t)sc.xo * EF::NF;
+  const float *nrm = ew.nrm + sc.po * NU;
+  const int *cidx = ew.cidx + sc.po;
+  const int2 *cl = ew.clist + sc.po;
+  double *nu = ew.cg + 6 * sc.po, *sd = nu + TP;
+  if (mode == EQ_POLISH) {
+    eqp_freeze<NX, NU>(pb, ws, ew, sc, scan, tid, nth);
+    for (int i = tid; i < N; i += nth) eqp_factor<NX, NU, DI, R>(pb, ws, sc, Er, i);
+  }
+  __syncthreads();
+  const int m = (mode == EQ_POLISH) ? scan[nth] : ew.m[s];
+  if (mode == EQ_ADJOINT)
+    for (int k = tid; k < m; k += nth) nu[k] = 0.0;
+  __syncthreads();
+  const int kind = (mode == EQ_POLISH) ? EQK_INHOM : EQK_ADJ;
+  const double dval = (mode == EQ_POLISH) ? (double)pb.dmin : 0.0;
+  double gq[NX], gr[NU];
+  // residual of the held rows at the starting multipliers
+  eqp_scatter<NX, NU, R>(sc, Er, nrm, cidx, nu, 1.0, tid, nth);
+  __syncthreads();
+  for (int i = tid; i < N; i += nth) eqp_agent<NX, NU, DI, R>(pb, ws, sc, Er, i, kind, false, io, gq, gr);
+  __syncthreads();
+  // MINRES (Paige and Saunders 1975) on S nu = d - D w(0): Lanczos vectors
+  // r1, r2 (r2 = beta v), the product y = S v, and the directions w_{k-2},
+  // w_{k-1}; the residual norm phibar never increases, and on a singular,
+  // inconsistent system (held rows that cannot all hold with the fixed
+  // inputs) the iterate tends to a least-squares solution.
+  double *b0 = sd, *b1 = b0 + TP, *b2 = b1 + TP, *wa = b2 + TP, *wb = wa + TP;
+  double *r1 = b0, *r2 = b1, *y = b2;
+  double acc = 0.0;
+  for (int k = tid; k < m; k += nth) {
+    const double r = dval - eqp_row<NX, NU, R>(sc, Er, nrm, cl[k]);
+    r2[k] = r;
+    r1[k] = 0.0;
+    wa[k] = 0.0;
+    wb[k] = 0.0;
+    acc = fma(r, r, acc);
+  }
+  const double beta1 = sqrt(block_sum(acc, red));
+  const double ref = (mode == EQ_POLISH) ? fmax((double)pb.dmin * sqrt((double)m), beta1) : beta1;
+  const int cap = min(max_cg, 2 * m + 20);
+  double beta = beta1, oldb = 0.0, dbar = 0.0, epsln = 0.0, phibar = beta1, cs = -1.0, sn = 0.0, gmax = 0.0;
+  int it = 0;
+  while (m > 0 && it < cap && phibar > tol * ref && beta > 1e-30 * beta1) {
+    eqp_scatter<NX, NU, R>(sc, Er, nrm, cidx, r2, 1.0 / beta, tid, nth);   // v = r2 / beta
+    __syncthreads();
+    for (int i = tid; i < N; i += nth) eqp_agent<NX, NU, DI, R>(pb, ws, sc, Er, i, EQK_HOM, false, io, gq, gr);
+    __syncthreads();
+    acc = 0.0;
+    for (int k = tid; k < m; k += nth) {
+      double v = eqp_row<NX, NU, R>(sc, Er, nrm, cl[k]);
+      if (it >= 1) v = fma(-beta / oldb, r1[k], v);
+      y[k] = v;
+      acc = fma(r2[k] / beta, v, acc);
+    }
+    const double alfa = block_sum(acc, red);
+    acc = 0.0;
+    for (int k = tid; k < m; k += nth) {
+      const double v = fma(-alfa / beta, r2[k], y[k]);
+      y[k] = v;
+      acc = fma(v, v, acc);
+    }
+    { double *t = r1; r1 = r2; r2 = y; y = t; }   // r1 <- r2, r2 <- y
+    oldb = beta;
+    beta = sqrt(block_sum(acc, red));
+    const double oldeps = epsln;
+    const double delta = cs * dbar + sn * alfa;
+    const double gbar = sn * dbar - cs * alfa;
+    epsln = sn * beta;
+    dbar = -cs * beta;
+    const double gamma = sqrt(gbar * gbar + beta * beta);
+    gmax = fmax(gmax, gamma);
+    if (!(gamma > 1e-13 * gmax)) break;   // the Krylov space is exhausted on a singular system
+    cs = gbar / gamma;
+    sn = beta / gamma;
+    const double phi = cs * phibar;
+    phibar = sn * phibar;
+    for (int k = tid; k < m; k += nth) {
+      const double w = (r1[k] / oldb - oldeps * wa[k] - delta * wb[k]) / gamma;   // w_k into the w_{k-2} slot
+      wa[k] = w;
+      nu[k] = fma(phi, w, nu[k]);
+    }
+    { double *t = wa; wa = wb; wb = t; }
+    ++it;
+    __syncthreads();
+  }
+  // final solve with the converged multipliers
+  eqp_scatter<NX, NU, R>(sc, Er, nrm, cidx, nu, 1.0, tid, nth);
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < NX; ++c) gq[c] = 0.0;
+#pragma unroll
+  for (int a = 0; a < NU; ++a) gr[a] = 0.0;
+  for (int i = tid; i < N; i += nth) eqp_agent<NX, NU, DI, R>(pb, ws, sc, Er, i, kind, true, io, gq, gr);
+  __syncthreads();
+  double viol = 0.0;
+  for (int k = tid; k < m; k += nth) viol = fmax(viol, fabs(dval - eqp_row<NX, NU, R>(sc, Er, nrm, cl[k])));
+  viol = block_max(viol, red);
+  if (mode == EQ_ADJOINT) {
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      const double g = block_sum(gq[c], red);
+      if (tid == 0 && io.dlogq) io.dlogq[(long long)s * NX + c] = (float)g;
+    }
+#pragma unroll
+    for (int a = 0; a < NU; ++a) {
+      const double g = block_sum(gr[a], red);
+      if (tid == 0 && io.dlogr) io.dlogr[(long long)s * NU + a] = (float)g;
+    }
+  }
+  if (tid == 0 && io.stats) {
+    float *st = io.stats + (long long)s * ES_NCOL;
+    st[ES_M] = (float)m;
+    st[ES_ITERS] = (float)it;
+    st[ES_RES] = (float)(ref > 0.0 ? phibar / ref : 0.0);
+    st[ES_VIOL] = (float)viol;
+  }
+  __syncthreads();
+}
+
+template <int NX, int NU, bool DI, class R>
+__global__ __launch_bounds__(256) void k_eqp(Prob pb, WS ws, EWS ew, EqpIO io, int S, int mode, int max_cg,
+                                             double tol) {
+  __shared__ double red[4];
+  __shared__ int scan[257];
+  for (int s = blockIdx.x; s < S; s += gridDim.x)
+    eqp_scenario<NX, NU, DI, R>(pb, ws, ew, io, s, mode, max_cg, tol, red, scan);
+}
+
+}  // namespace tadmm

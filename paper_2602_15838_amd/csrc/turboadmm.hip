@@ -17,6 +17,7 @@
 
 #include "../../include/turboadmm.h"
 #include "tadmm_device.h"
+#include "tadmm_eqp.h"
 
 namespace tadmm {
 
@@ -1012,6 +1013,8 @@ struct Layout {
   long long A = 0, sumGS = 0, sumL = 0;
   size_t o_N = 0, o_T = 0, o_tab = 0, o_order = 0, o_queue = 0, o_sst = 0, o_snorm = 0, o_cnt = 0, o_flags = 0;
   size_t o_adirty = 0, o_fr = 0, o_dr = 0, o_wr = 0, o_lam = 0, o_pact = 0, bytes = 0;
+  size_t o_er = 0, o_nrm = 0, o_cidx = 0, o_clist = 0, o_cg = 0, o_m = 0;
+  long long sumPT = 0;
   std::vector<long long> tab;
   std::vector<int> order;
 };
@@ -1020,6 +1023,8 @@ int fields_per_stage(int nx, int nu) {
   return (nx == 4) ? Fld<4, 2>::NF : Fld<6, 3>::NF;
   (void)nu;
 }
+
+int eqp_fields_per_stage(int nx) { return (nx == 4) ? EFld<4, 2>::NF : EFld<6, 3>::NF; }
 
 const char *kStatusStr[] = {"ok", "invalid argument", "shape error", "non-finite input", "infeasible start",
                             "HIP runtime error", "workspace error", "state error"};
@@ -1097,6 +1102,14 @@ bool make_layout(const tadmm_params *p, int S, const int32_t *N, const int32_t *
   L.o_wr = take((size_t)bo);
   L.o_lam = take(sizeof(float) * (size_t)lo);
   L.o_pact = take((size_t)lb);
+  // equality-QP solves of the derivative (sized for FP64)
+  L.sumPT = po;
+  L.o_er = take(sizeof(double) * (size_t)eqp_fields_per_stage(p->nx) * (size_t)xo);
+  L.o_nrm = take(sizeof(float) * (size_t)p->nu * (size_t)po);
+  L.o_cidx = take(sizeof(int) * (size_t)po);
+  L.o_clist = take(sizeof(int2) * (size_t)po);
+  L.o_cg = take(sizeof(double) * 6 * (size_t)po);
+  L.o_m = take(sizeof(int) * S);
   L.bytes = off;
   // launch order for the persistent queue: largest N^2 T first (LPT)
   L.order.resize(S);
@@ -1173,9 +1186,11 @@ struct tadmm_ctx {
   GraphKey key{};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   float last_ms = -1.f;
-  // adjoint bookkeeping: the last successful solve
-  bool solved = false;
+  // derivative bookkeeping: the last successful solve and its polish
+  bool solved = false, polished = false;
   const void *solved_ws = nullptr;
+  size_t solved_bytes = 0;
+  tadmm_batch solved_batch{};
   std::vector<int> solved_N, solved_T;
 };
 
@@ -1335,6 +1350,7 @@ tadmm_status solve_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *o
   if (!ws || bytes < L.bytes) return fail(ctx, TADMM_ERR_WORKSPACE, "workspace missing or smaller than tadmm_workspace_size()");
   if (((uintptr_t)ws) % kAlign) return fail(ctx, TADMM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   ctx->solved = false;
+  ctx->polished = false;
   if (L.S == 0) return TADMM_OK;
   if (!b->x0 || !b->xref || !b->q_diag || !b->r_diag) return fail(ctx, TADMM_ERR_INVALID_ARG, "batch input pointer is NULL");
   if (!out->status || !out->iters) return fail(ctx, TADMM_ERR_INVALID_ARG, "out.status and out.iters are required");
@@ -1354,9 +1370,73 @@ tadmm_status solve_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *o
   if (st != TADMM_OK) return st;
   ctx->solved = true;
   ctx->solved_ws = ws;
+  ctx->solved_bytes = bytes;
+  ctx->solved_batch = *b;
   ctx->solved_N.assign(b->n_agents, b->n_agents + L.S);
   ctx->solved_T.assign(b->horizon, b->horizon + L.S);
   return TADMM_OK;
+}
+
+EWS make_ews(const Layout &L, char *ws) {
+  EWS e;
+  e.er = (void *)(ws + L.o_er);
+  e.nrm = (float *)(ws + L.o_nrm);
+  e.cidx = (int *)(ws + L.o_cidx);
+  e.clist = (int2 *)(ws + L.o_clist);
+  e.cg = (double *)(ws + L.o_cg);
+  e.m = (int *)(ws + L.o_m);
+  return e;
+}
+
+// Polish (mode EQ_POLISH) or adjoint (EQ_ADJOINT) of the last solve.
+template <int NX, int NU, bool DI>
+tadmm_status eqp_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *out, void *ws, size_t bytes, int mode,
+                      const EqpIO &io) {
+  if (!ctx->solved || ctx->solved_ws != ws || ctx->solved_bytes != bytes)
+    return fail(ctx, TADMM_ERR_STATE, "needs a successful tadmm_solve with this workspace first");
+  const tadmm_batch &sb = ctx->solved_batch;
+  if (b->n_scen != sb.n_scen || b->x0 != sb.x0 || b->xref != sb.xref || b->q_diag != sb.q_diag ||
+      b->r_diag != sb.r_diag || b->normals != sb.normals)
+    return fail(ctx, TADMM_ERR_STATE, "batch differs from the one of the last tadmm_solve");
+  for (int s = 0; s < b->n_scen; ++s)
+    if (b->n_agents[s] != ctx->solved_N[s] || b->horizon[s] != ctx->solved_T[s])
+      return fail(ctx, TADMM_ERR_STATE, "batch shape differs from the one of the last tadmm_solve");
+  if (mode == EQ_POLISH && ctx->polished) return fail(ctx, TADMM_ERR_STATE, "this solve is already polished");
+  if (mode == EQ_ADJOINT && !ctx->polished) return fail(ctx, TADMM_ERR_STATE, "call tadmm_polish before tadmm_adjoint");
+  Layout L;
+  if (!make_layout(&ctx->prm, b->n_scen, b->n_agents, b->horizon, L, ctx->err)) return TADMM_ERR_SHAPE;
+  if (L.S == 0) {
+    if (mode == EQ_POLISH) ctx->polished = true;
+    return TADMM_OK;
+  }
+  char *w8 = (char *)ws;
+  const Prob pb = to_prob(ctx->prm);
+  const WS w = make_ws(L, w8, b);
+  const EWS ew = make_ews(L, w8);
+  const int grid = std::min(L.S, 65535);
+  const int max_cg = 4000;
+  HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
+  if (ctx->prm.eqp_fp64)
+    hipLaunchKernelGGL((k_eqp<NX, NU, DI, double>), dim3(grid), dim3(256), 0, ctx->stream, pb, w, ew, io, L.S, mode,
+                       max_cg, 1e-12);
+  else
+    hipLaunchKernelGGL((k_eqp<NX, NU, DI, float>), dim3(grid), dim3(256), 0, ctx->stream, pb, w, ew, io, L.S, mode,
+                       max_cg, 1e-7);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventRecord(ctx->ev1, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  HIPCHK(hipEventElapsedTime(&ctx->last_ms, ctx->ev0, ctx->ev1));
+  if (mode == EQ_POLISH) ctx->polished = true;
+  (void)out;
+  return TADMM_OK;
+}
+
+tadmm_status eqp_dispatch(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *out, void *ws, size_t bytes, int mode,
+                          const EqpIO &io) {
+  const bool di = is_double_integrator(ctx->prm);
+  if (ctx->prm.nx == 4)
+    return di ? eqp_impl<4, 2, true>(ctx, b, out, ws, bytes, mode, io) : eqp_impl<4, 2, false>(ctx, b, out, ws, bytes, mode, io);
+  return di ? eqp_impl<6, 3, true>(ctx, b, out, ws, bytes, mode, io) : eqp_impl<6, 3, false>(ctx, b, out, ws, bytes, mode, io);
 }
 
 }  // namespace
@@ -1457,14 +1537,35 @@ tadmm_status tadmm_autotune(tadmm_ctx *ctx, const tadmm_batch *batch, const tadm
   return TADMM_OK;
 }
 
+tadmm_status tadmm_polish(tadmm_ctx *ctx, const tadmm_batch *batch, const tadmm_out *out, void *workspace,
+                          size_t workspace_bytes, float *stats) {
+  if (!ctx) return TADMM_ERR_INVALID_ARG;
+  if (!batch || !out) return fail(ctx, TADMM_ERR_INVALID_ARG, "batch / out is NULL");
+  if (!out->x || !out->u) return fail(ctx, TADMM_ERR_INVALID_ARG, "out.x and out.u are required");
+  ctx->err.clear();
+  EqpIO io{};
+  io.x = out->x;
+  io.u = out->u;
+  io.stats = stats;
+  return eqp_dispatch(ctx, batch, out, workspace, workspace_bytes, EQ_POLISH, io);
+}
+
 tadmm_status tadmm_adjoint(tadmm_ctx *ctx, const tadmm_batch *batch, const tadmm_out *out, void *workspace,
                            size_t workspace_bytes, const float *dL_dx, const float *dL_du, float *dL_dx0,
-                           float *dL_dxref, float *dL_dlogq, float *dL_dlogr) {
+                           float *dL_dxref, float *dL_dlogq, float *dL_dlogr, float *stats) {
   if (!ctx) return TADMM_ERR_INVALID_ARG;
-  if (!ctx->solved || ctx->solved_ws != workspace) return fail(ctx, TADMM_ERR_STATE, "adjoint needs the matching solve");
-  (void)batch; (void)out; (void)workspace_bytes; (void)dL_dx; (void)dL_du; (void)dL_dx0; (void)dL_dxref;
-  (void)dL_dlogq; (void)dL_dlogr;
-  return fail(ctx, TADMM_ERR_STATE, "adjoint not available in this build");
+  if (!batch) return fail(ctx, TADMM_ERR_INVALID_ARG, "batch is NULL");
+  if (!dL_dx) return fail(ctx, TADMM_ERR_INVALID_ARG, "dL_dx is required");
+  ctx->err.clear();
+  EqpIO io{};
+  io.gx = dL_dx;
+  io.gu = dL_du;
+  io.dx0 = dL_dx0;
+  io.dxref = dL_dxref;
+  io.dlogq = dL_dlogq;
+  io.dlogr = dL_dlogr;
+  io.stats = stats;
+  return eqp_dispatch(ctx, batch, out, workspace, workspace_bytes, EQ_ADJOINT, io);
 }
 
 }  // extern "C"

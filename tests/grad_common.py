@@ -85,6 +85,8 @@ def build_cases(problem, scenarios: Sequence, ids: Sequence[int], want: int, thr
     r1 = oracle.solve_batch(P, scenarios, o1, threads=threads, inputs=inputs)
     keep = [k for k, r in enumerate(r1) if r["status"] == oracle.CONVERGED]
     nrm = [final_normals(r1[k]["x"], inputs[k][1], problem.dp) for k in keep]
+    if fp32:   # the device receives the normals in FP32
+        nrm = [n.astype(np.float32).astype(np.float64) for n in nrm]
     o2 = oracle.OracleOptions()
     o2.normal_mode = oracle.NORMAL_FROZEN
     o2.eps_abs = o2.eps_rel = frozen_eps

@@ -1,0 +1,341 @@
+"""GPU tests of the derivative: tadmm_polish and tadmm_adjoint against the
+oracle's dense-KKT gradient (oracle/grad.py) and against central finite
+differences of the oracle's equality QP, on the differentiation workload
+(8 agents, T = 20, random box; 16 scenarios chosen by seed among those whose
+equality QP is certified, see tests/grad_common.py).
+
+The equality QP is defined by the normals (frozen; here the normals of the
+oracle's own converged solve, given to both sides) and by the active sets at
+the solution of the frozen-normal QP.  The device's solve must identify the
+same active sets as the oracle's; the gradient comparisons run on the
+scenarios where it does."""
+import ctypes as C
+import functools
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import grad as G
+from tests import grad_common as GC
+
+pytestmark = pytest.mark.gpu
+
+IDS = list(range(48))
+WANT = 16
+GRAD_TOL = 1e-5          # relative, per parameter block (the workload's bar)
+POLISH_TOL = {False: 1e-5, True: 1e-7}   # the outputs are FP32
+FROZEN_KW = dict(normal_mode=1, max_iter=4000, eps_abs=1e-6, eps_rel=1e-6)
+
+
+@functools.lru_cache(maxsize=1)
+def _cases():
+    p, scs = synth.config3(S=len(IDS), scenario_ids=IDS)
+    cases = GC.build_cases(p, scs, IDS, want=WANT, threads=0)
+    assert len(cases) == WANT, len(cases)
+    return p, cases
+
+
+def _pack(problem, cases):
+    scs = [c.sc for c in cases]
+    pk = synth.pack(problem, scs)
+    nrm = np.concatenate([c.normals.reshape(-1, problem.nu) for c in cases])
+    return pk, nrm
+
+
+@functools.lru_cache(maxsize=2)
+def _gpu_run(fp64: bool):
+    """Frozen-normal solve of the cases on the device, then the polish."""
+    import paper_2602_15838_amd as tadmm
+    p, cases = _cases()
+    pk, nrm = _pack(p, cases)
+    solver = tadmm.Solver(tadmm.make_params(p, eqp_fp64=fp64, **FROZEN_KW))
+    prep = solver.prepare(pk.n_agents, pk.horizon, pk.x0, pk.xref, pk.q_diag, pk.r_diag, nrm)
+    prep.run(tadmm.MODE_BATCHED)
+    pre = tadmm.split_outputs(prep.result(), pk.n_agents, pk.horizon, p.nx, p.nu)
+    st = prep.polish().cpu().numpy()
+    post = tadmm.split_outputs(prep.result(), pk.n_agents, pk.horizon, p.nx, p.nu)
+    return solver, prep, pk, pre, post, st
+
+
+def _matching(pre, cases):
+    out = []
+    for k, (g, c) in enumerate(zip(pre, cases)):
+        act = np.zeros_like(g["pair_active"])
+        for (i, j, t) in c.ins.active:
+            act[GC.pair_index(c.sc.N).index((i, j)), t - 1] = 1
+        if np.array_equal(g["w"].astype(np.int64), c.ins.W) and np.array_equal(g["pair_active"], act):
+            out.append(k)
+    return out
+
+
+@functools.lru_cache(maxsize=1)
+def _oracle_solutions():
+    _, cases = _cases()
+    sols = []
+    for c in cases:
+        w, _ = G.solve(c.ins)
+        sols.append(G.trajectories(c.ins, w))
+    return sols
+
+
+def _tracking(c, x, u):
+    return GC.tracking_loss_grads(c.ins, x, u, c.ins.xref[:, :, :c.ins.nu])
+
+
+@functools.lru_cache(maxsize=1)
+def _oracle_grads():
+    _, cases = _cases()
+    out = []
+    for c, (x, u) in zip(cases, _oracle_solutions()):
+        _, gx, gu = _tracking(c, x, u)
+        out.append((gx, gu, G.implicit_gradient(c.ins, gx, gu)))
+    return out
+
+
+def _flat_upstream(pk, per_case, nx, nu):
+    gx = np.concatenate([g[0].reshape(-1, nx) for g in per_case])
+    gu = np.concatenate([g[1].reshape(-1, nu) for g in per_case])
+    return gx, gu
+
+
+def _split_grads(pk, outs, nx, nu):
+    dx0, dxref, dlq, dlr = [o.cpu().numpy().astype(np.float64) for o in outs]
+    ao, to = pk.agent_off(), pk.traj_off()
+    res = []
+    for s in range(pk.S):
+        N, T = int(pk.n_agents[s]), int(pk.horizon[s])
+        res.append(dict(x0=dx0[ao[s]:ao[s + 1]].reshape(N, nx), xref=dxref[to[s]:to[s + 1]].reshape(N, T + 1, nx),
+                        logq=dlq[s], logr=dlr[s]))
+    return res
+
+
+def test_frozen_solve_identifies_the_oracle_active_sets():
+    _, cases = _cases()
+    for fp64 in (False, True):
+        _, _, _, pre, _, _ = _gpu_run(fp64)
+        m = _matching(pre, cases)
+        print(f"eqp_fp64={fp64}: active sets identical on {len(m)}/{len(cases)} scenarios "
+              f"(ids {[cases[k].sid for k in m]})")
+        assert len(m) >= WANT // 2
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_polish_is_the_equality_qp_solution(fp64):
+    p, cases = _cases()
+    _, _, _, pre, post, st = _gpu_run(fp64)
+    sols = _oracle_solutions()
+    worst = 0.0
+    for k in _matching(pre, cases):
+        c = cases[k]
+        x, u = sols[k]
+        rel = GC.rel_err(np.concatenate([post[k]["x"].ravel(), post[k]["u"].ravel()]),
+                         np.concatenate([x.ravel(), u.ravel()]))
+        worst = max(worst, rel)
+        assert rel <= POLISH_TOL[fp64], (c.sid, rel)
+        assert st[k][0] == len(c.ins.active)
+        assert st[k][3] <= (1e-5 if not fp64 else 1e-10) * 10.0, (c.sid, st[k])
+    print(f"eqp_fp64={fp64}: worst polish error {worst:.2e}, MINRES iterations {st[:, 1].tolist()}")
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_adjoint_matches_dense_kkt_gradient(fp64):
+    import torch
+    p, cases = _cases()
+    solver, prep, pk, pre, post, _ = _gpu_run(fp64)
+    og = _oracle_grads()
+    gx, gu = _flat_upstream(pk, og, p.nx, p.nu)
+    outs = prep.adjoint(torch.tensor(gx, dtype=torch.float32), torch.tensor(gu, dtype=torch.float32))
+    gg = _split_grads(pk, outs, p.nx, p.nu)
+    worst = {n: 0.0 for n in G.PARAMS}
+    for k in _matching(pre, cases):
+        for n in G.PARAMS:
+            rel = GC.rel_err(gg[k][n], og[k][2][n])
+            worst[n] = max(worst[n], rel)
+            assert rel <= GRAD_TOL, (cases[k].sid, n, rel)
+    print(f"eqp_fp64={fp64}: worst relative gradient error {worst}")
+
+
+def test_adjoint_matches_finite_differences():
+    """GPU gradient vs central FD of the oracle's equality QP (step 1e-6 on x0
+    and the references, 1e-4 on the log-weights), sampled entries."""
+    import torch
+    p, cases = _cases()
+    solver, prep, pk, pre, post, _ = _gpu_run(True)
+    og = _oracle_grads()
+    gx, gu = _flat_upstream(pk, og, p.nx, p.nu)
+    outs = prep.adjoint(torch.tensor(gx, dtype=torch.float32), torch.tensor(gu, dtype=torch.float32))
+    gg = _split_grads(pk, outs, p.nx, p.nu)
+    rng = np.random.default_rng(5)
+    for k in _matching(pre, cases)[:3]:
+        ins = cases[k].ins
+        pref = ins.xref[:, :, :ins.nu].copy()
+        loss = lambda x, u, th: float(np.sum((x[:, :, :ins.nu] - pref) ** 2))
+        ent = dict(x0=rng.choice(ins.x0.size, 8, replace=False), xref=rng.choice(ins.xref.size, 16, replace=False))
+        fd = G.fd_gradient(ins, loss, entries=ent)
+        for n in G.PARAMS:
+            idx = np.arange(fd[n].size) if n not in ent else np.asarray(ent[n])
+            a, b = gg[k][n].reshape(-1)[idx], fd[n].reshape(-1)[idx]
+            rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-12)
+            assert rel <= GRAD_TOL, (cases[k].sid, n, rel)
+
+
+def test_adjoint_with_input_and_initial_state_terms():
+    """A random linear loss reaches u and x_0 directly (dL/du, dL/dx_0).
+    FP64 sweeps (FP32 sweeps reach ~2e-5 on log R here: the sum over
+    2 r ubar u cancels)."""
+    import torch
+    p, cases = _cases()
+    solver, prep, pk, pre, post, _ = _gpu_run(True)
+    rng = np.random.default_rng(6)
+    per = []
+    for c in cases:
+        N, T = c.sc.N, c.sc.T
+        per.append((rng.normal(size=(N, T + 1, p.nx)), rng.normal(size=(N, T, p.nu))))
+    gx, gu = _flat_upstream(pk, per, p.nx, p.nu)
+    gx32, gu32 = gx.astype(np.float32), gu.astype(np.float32)
+    outs = prep.adjoint(torch.tensor(gx32), torch.tensor(gu32))
+    gg = _split_grads(pk, outs, p.nx, p.nu)
+    # the oracle takes the same (FP32-rounded) upstream gradients
+    off_x, off_u = np.concatenate([[0], np.cumsum([c.sc.N * (c.sc.T + 1) for c in cases])]), \
+        np.concatenate([[0], np.cumsum([c.sc.N * c.sc.T for c in cases])])
+    for k in _matching(pre, cases)[:4]:
+        c = cases[k]
+        N, T = c.sc.N, c.sc.T
+        ax = gx32[off_x[k]:off_x[k + 1]].astype(np.float64).reshape(N, T + 1, p.nx)
+        au = gu32[off_u[k]:off_u[k + 1]].astype(np.float64).reshape(N, T, p.nu)
+        want = G.implicit_gradient(c.ins, ax, au)
+        for n in G.PARAMS:
+            rel = GC.rel_err(gg[k][n], want[n])
+            assert rel <= GRAD_TOL, (c.sid, n, rel)
+
+
+def test_autograd_function_through_goals():
+    """TurboADMMFunction: loss of the differentiation workload built in torch
+    from starts and goals (straight-line references), back-propagated to the
+    goals, the starts and the log-weights; compared with the oracle's implicit
+    gradient chained through the same (linear) reference construction."""
+    import torch
+    import paper_2602_15838_amd as tadmm
+    p, cases = _cases()
+    _, _, _, pre, _, _ = _gpu_run(False)
+    ks = _matching(pre, cases)[:4]
+    sub = [cases[k] for k in ks]
+    pk, nrm = _pack(p, sub)
+    dev = torch.device("cuda", 0)
+    f32 = lambda a: torch.tensor(np.asarray(a, np.float32), device=dev)
+    starts = [f32(c.sc.starts).requires_grad_() for c in sub]
+    goals = [f32(c.sc.goals).requires_grad_() for c in sub]
+    log_q = f32(np.log(pk.q_diag)).requires_grad_()
+    log_r = f32(np.log(pk.r_diag)).requires_grad_()
+    x0 = torch.cat([torch.cat([s, torch.zeros_like(s)], 1) for s in starts])
+    refs = [tadmm.straight_line_ref(s, g, c.sc.T, c.sc.dt) for s, g, c in zip(starts, goals, sub)]
+    xref = torch.cat([r.reshape(-1, p.nx) for r in refs])
+    solver = tadmm.Solver(tadmm.make_params(p, **FROZEN_KW))
+    cfg = dict(solver=solver, n_agents=pk.n_agents, horizon=pk.horizon, normals=nrm)
+    x, u = tadmm.TurboADMMFunction.apply(x0, xref, log_q, log_r, cfg)
+    loss = x.new_zeros(())
+    off = 0
+    for r, c in zip(refs, sub):
+        n = c.sc.N * (c.sc.T + 1)
+        xs = x[off:off + n].reshape(c.sc.N, c.sc.T + 1, p.nx)
+        loss = loss + ((xs[:, :, :p.nu] - r[:, :, :p.nu]) ** 2).sum()
+        off += n
+    loss.backward()
+    # the oracle: gradient w.r.t. (x0, xref, logq, logr) at the EQP solution,
+    # chained through r = straight_line_ref(starts, goals) (linear, so unit
+    # perturbations give its exact Jacobian), plus the direct dependence of
+    # the loss on the reference positions
+    sols = _oracle_solutions()
+    for k, c, s_t, g_t in zip(ks, sub, starts, goals):
+        ins = c.ins
+        x_o, u_o = sols[k]
+        pref = ins.xref[:, :, :p.nu]
+        _, gx, gu = GC.tracking_loss_grads(ins, x_o, u_o, pref)
+        g = G.implicit_gradient(ins, gx, gu)
+        direct = np.zeros_like(ins.xref)
+        direct[:, :, :p.nu] = -2.0 * (x_o[:, :, :p.nu] - pref)
+        dref = g["xref"] + direct
+        N, T = c.sc.N, c.sc.T
+        base = synth.straight_line_ref(c.sc.starts, c.sc.goals, T, c.sc.dt)
+        want_goal = np.zeros((N, p.nu))
+        want_start = g["x0"][:, :p.nu].copy()
+        for i in range(N):
+            for a in range(p.nu):
+                e = np.zeros((N, p.nu))
+                e[i, a] = 1.0
+                jg = synth.straight_line_ref(c.sc.starts, c.sc.goals + e, T, c.sc.dt) - base
+                js = synth.straight_line_ref(c.sc.starts + e, c.sc.goals, T, c.sc.dt) - base
+                want_goal[i, a] = np.sum(dref * jg)
+                want_start[i, a] += np.sum(dref * js)
+        assert GC.rel_err(g_t.grad.cpu().numpy(), want_goal) <= GRAD_TOL
+        assert GC.rel_err(s_t.grad.cpu().numpy(), want_start) <= GRAD_TOL
+    og_q = np.stack([G.implicit_gradient(c.ins, *_tracking(c, *sols[k])[1:])["logq"] for k, c in zip(ks, sub)])
+    assert GC.rel_err(log_q.grad.cpu().numpy(), og_q) <= GRAD_TOL
+    solver.close()
+
+
+def test_polish_and_adjoint_call_order():
+    import torch
+    import paper_2602_15838_amd as tadmm
+    p, scs = synth.config3(S=2, scenario_ids=[0, 1])
+    pk = synth.pack(p, scs)
+    solver = tadmm.Solver(tadmm.make_params(p))
+    prep = solver.prepare(pk.n_agents, pk.horizon, pk.x0, pk.xref, pk.q_diag, pk.r_diag)
+    gx = torch.zeros_like(prep.o["x"])
+    with pytest.raises(tadmm.TadmmError) as e:   # no solve yet
+        prep.polish()
+    assert e.value.code == 7
+    prep.run()
+    with pytest.raises(tadmm.TadmmError) as e:   # adjoint before polish
+        prep.adjoint(gx)
+    assert e.value.code == 7
+    prep.polish()
+    with pytest.raises(tadmm.TadmmError) as e:   # a second polish of the same solve
+        prep.polish()
+    assert e.value.code == 7
+    other = solver.prepare(pk.n_agents, pk.horizon, pk.x0, pk.xref, pk.q_diag, pk.r_diag)
+    other.ws = prep.ws   # the workspace of the solve, another batch
+    with pytest.raises(tadmm.TadmmError) as e:
+        other.adjoint(gx)
+    assert e.value.code == 7
+    outs = prep.adjoint(gx)
+    assert all(float(o.abs().max()) == 0.0 for o in outs)   # zero upstream, zero gradient
+    solver.close()
+
+
+def test_per_iteration_normals_polish_and_adjoint():
+    """Normals re-linearized every iteration (the default): the polish holds
+    the half-planes of the last consensus step with the normals of the final
+    positions.  After a converged solve every held row is satisfied; after one
+    stopped at max_iter the held rows may be inconsistent, and the polish and
+    the gradients must still be finite (least-squares multipliers)."""
+    import torch
+    import paper_2602_15838_amd as tadmm
+    p, scs = synth.config3(S=32, scenario_ids=range(32))
+    pk = synth.pack(p, scs)
+    for fp64 in (False, True):
+        solver = tadmm.Solver(tadmm.make_params(p, eqp_fp64=fp64))
+        prep = solver.prepare(pk.n_agents, pk.horizon, pk.x0, pk.xref, pk.q_diag, pk.r_diag)
+        prep.run()
+        act = prep.o["pair_active"].clone()
+        st = prep.polish().cpu().numpy()
+        res = tadmm.split_outputs(prep.result(), pk.n_agents, pk.horizon, p.nx, p.nu)
+        po = pk.pair_step_off()
+        for s in range(pk.S):
+            assert st[s][0] == float(act[po[s]:po[s + 1]].sum())
+            assert np.all(np.isfinite(st[s])) and np.all(np.isfinite(res[s]["x"]))
+            if res[s]["status"] == tadmm.SCEN_CONVERGED:
+                # the held rows of a converged solve are consistent
+                assert st[s][3] <= (1e-4 if not fp64 else 1e-9), (s, st[s])
+            # dynamics hold exactly enough, inputs in W sit at their bounds
+            w = res[s]["w"]
+            assert np.all(np.abs(res[s]["u"][w == 1] - p.u_lo[np.nonzero(w == 1)[2]]) < 1e-6)
+            assert np.all(np.abs(res[s]["u"][w == 2] - p.u_hi[np.nonzero(w == 2)[2]]) < 1e-6)
+        pref = torch.tensor(np.concatenate([sc.xref().reshape(-1, p.nx) for sc in scs]), dtype=torch.float32,
+                            device=prep.o["x"].device)
+        gx = torch.zeros_like(prep.o["x"])
+        gx[:, :p.nu] = 2.0 * (prep.o["x"][:, :p.nu] - pref[:, :p.nu])
+        outs = prep.adjoint(gx)
+        assert all(bool(torch.isfinite(o).all()) for o in outs)
+        solver.close()
