@@ -12,6 +12,8 @@ per-scenario path on a sample, the roofline of the persistent kernel and the
 FP64 oracle timed on the host cores on a bounded sample.
 """
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -22,15 +24,53 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work per unit (FP32 flops, 2-D double integrator; 3-D in
-# parentheses), counted from the operations the method must perform:
+# Algorithmic work per unit, counted from the operations the method must
+# perform (2-D double integrator; 3-D in parentheses):
 #   affine agent-stage pass (backward affine sweep + forward rollout + ratio
-#   test + costate/multiplier on fixed inputs):   190 (380)
+#   test + costate/multiplier on fixed inputs):   190 (380) FP32 flops
 #   refactored agent-stage (Riccati factor with a working set): 520 (1400)
 #   pair-step (consensus projection + dual update + residual pieces): 40 (55)
+# and the bytes it must move when the per-stage factors stream from HBM:
+#   agent-stage pass (affine or refactor): 152 (324) B; pair-step: 8 B (the
+#   collapsed dual gamma read and written).
 FLOPS_PER_UNIT = {2: dict(affine=190.0, refactor=520.0, pair=40.0), 3: dict(affine=380.0, refactor=1400.0, pair=55.0)}
+BYTES_PER_UNIT = {2: dict(affine=152.0, refactor=152.0, pair=8.0), 3: dict(affine=324.0, refactor=324.0, pair=8.0)}
+PEAK_HBM_GBS = 8000.0             # MI355X HBM3E
 PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector (packed) peak
 PEAK_FP32_UNPACKED_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+METRIC = "ADMM scenario solves/s + agent-QP solves/s at 1e-4 residual, batched vs plain"
+# HBM traffic of one persistent-kernel launch, from rocprofv3 counter runs
+# (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size); valid
+# only for the kernel sources it was measured on
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_admm_persistent_config2_hbm_traffic.txt")
+COPY_BYTES = 256 << 20
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2602_15838_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(scenarios: int):
+    """Bytes per launch from the committed counter summary, or None when it is
+    missing, for another batch size, or older than the kernel sources."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    kv = {}
+    for line in open(PMC_SUMMARY):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        if kv.get("source_sha256") != source_digest() or int(kv.get("scenarios", -1)) != scenarios:
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -40,12 +80,14 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--scenarios", type=int, default=4096)
     ap.add_argument("--plain-sample", type=int, default=32)
-    ap.add_argument("--cpu-sample", type=int, default=128)
+    ap.add_argument("--cpu-sample", type=int, default=640)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--profile-steps", action="store_true", help="print one line per step (for profiler runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of 256 MiB (the reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -94,20 +136,26 @@ def main():
     agent_qp = float((Ns * iters).sum())
     agent_qp_per_s = agent_qp / (ms_step / 1e3)
 
-    # roofline of the persistent kernel (events around its graph launch)
+    # roofline of the persistent kernel (HIP events around its graph launch on
+    # the context's stream).  At ~1.9 algorithmic flop/B it sits below the
+    # FP32 ridge (157.3 TF / 8 TB/s = 19.7 flop/B): HBM is the bound.
     kernel_ms = float(np.mean(kms))
-    fu = FLOPS_PER_UNIT[problem.dp]
+    fu, bu = FLOPS_PER_UNIT[problem.dp], BYTES_PER_UNIT[problem.dp]
     units = dict(affine=float(cnt[:, 2].sum()), refactor=float(cnt[:, 1].sum()), pair=float(cnt[:, 3].sum()))
-    flops = fu["affine"] * units["affine"] + fu["refactor"] * units["refactor"] + fu["pair"] * units["pair"]
-    achieved = flops / (kernel_ms / 1e3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 6),
-                "frac_of_unpacked_fp32": round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 6),
-                "traffic": None, "kernel": "k_admm_persistent<4,2>", "kernel_ms": round(kernel_ms, 4),
-                "algorithmic_gflop_per_launch": round(flops / 1e9, 4),
+    flops = sum(fu[k] * units[k] for k in units)
+    nbytes = sum(bu[k] * units[k] for k in units)
+    gbs = nbytes / (kernel_ms / 1e3) / 1e9
+    tflops = flops / (kernel_ms / 1e3) / 1e12
+    roofline = {"bound": "hbm", "achieved": round(gbs, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(gbs / PEAK_HBM_GBS, 5), "traffic": measured_traffic(S),
+                "kernel": "k_admm_persistent<4,2>", "kernel_ms": round(kernel_ms, 4),
+                "algorithmic_bytes_per_launch": round(nbytes), "algorithmic_gflop_per_launch": round(flops / 1e9, 4),
+                "alu": {"achieved": round(tflops, 4), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(tflops / PEAK_FP32_TFLOPS, 6),
+                        "frac_of_unpacked_fp32": round(tflops / PEAK_FP32_UNPACKED_TFLOPS, 6)},
                 "units_per_launch": {k: int(v) for k, v in units.items()}}
 
-    out = {"metric": "ADMM scenario solves/s at 1e-4 residual (batched)", "value": round(scen_per_s, 2),
+    out = {"metric": METRIC, "value": round(scen_per_s, 2),
            "unit": "scenario solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32", "data": "synthetic",
@@ -170,6 +218,21 @@ def main():
                                          f"over scenarios, {dtc:.1f}s",
                                "agent_qp_solves_per_s": round(float((np.array([s.N for s in sub]) * oit).sum()) / dtc, 1)}
         print(f"# cpu oracle sample {len(ids)} scenarios in {dtc:.1f}s on {th} threads", file=sys.stderr, flush=True)
+
+    if args.copy_calibration:
+        src = torch.ones(COPY_BYTES // 4, device="cuda")
+        dst = torch.empty_like(src)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        ev0.record()
+        dst.copy_(src)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        out["copy_calibration"] = {"bytes_read": COPY_BYTES, "bytes_written": COPY_BYTES, "ms": round(ms, 4),
+                                   "GB_per_s": round(2 * COPY_BYTES / (ms / 1e3) / 1e9, 1), "dispatches": 2}
+        print(f"# copy calibration {COPY_BYTES} B in {ms:.3f} ms", file=sys.stderr, flush=True)
 
     print(json.dumps(out))
     solver.close()
