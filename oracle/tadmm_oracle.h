@@ -17,6 +17,12 @@
  *     dual update Eq. (5), both on plain (uncollapsed) z and lambda for every
  *     ordered pair;
  *   - Boyd-style primal/dual residuals and the stopping test (Sec. V-A).
+ *
+ * Parity unpinned: with normals re-linearized every iteration, which side two
+ * agents pass on is path-dependent, and so are runs stopped at max_iter and
+ * degenerate ties of the active set.  No closed form or brute force fixes
+ * those results; they are held only by lockstep agreement of the first
+ * iterations and by the oracle's own sensitivity to perturbed starts.
  */
 #ifndef TADMM_ORACLE_H
 #define TADMM_ORACLE_H
