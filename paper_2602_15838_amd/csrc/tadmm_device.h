@@ -64,13 +64,26 @@ struct WS {
   const float *x0, *xref, *qd, *rd, *normals;
 };
 
-// Layout of a scenario's float region: array of structures over the
-// agent-stages g = t * N + i (t = 0..T, agent index fastest), NF floats each,
-// every field padded to a multiple of 4 floats so that a field group is one
-// 16-byte vector load and a field is an immediate offset from the agent-stage
-// base address.  The working set is [g][4] bytes, the FP64 refinement scratch
-// [g][NX] doubles.
+// Layout of a scenario's float region: structure of arrays of 4-float groups
+// over the agent-stages g = t * N + i (t = 0..T, agent index fastest).  Every
+// field is padded to a multiple of 4 floats; group q = field / 4 is an array
+// [GS][4] of 16-byte vectors, so the lanes of a wave (consecutive agents)
+// read a group as one contiguous run and a pass over the stages fetches only
+// the groups it uses.  The working set is [g][4] bytes, the FP64 refinement
+// scratch [g][NX] doubles.
 __host__ __device__ constexpr int pad4(int n) { return (n + 3) & ~3; }
+
+// index of element `field` of agent-stage g in a region of GS agent-stages
+__device__ __forceinline__ unsigned fidx(unsigned GS, unsigned g, int field) {
+  return (unsigned)(field >> 2) * (GS * 4u) + g * 4u + (unsigned)(field & 3);
+}
+
+// the same element as (uniform group base) + (per-lane offset g * 4): the
+// group base can stay in scalar registers and every group shares one offset
+__device__ __forceinline__ float &fref(float *R, unsigned GS, unsigned g, int field) {
+  float *grp = R + (size_t)((unsigned)(field >> 2) * (GS * 4u));
+  return grp[g * 4u + (unsigned)(field & 3)];
+}
 
 template <int NX, int NU>
 struct Fld {

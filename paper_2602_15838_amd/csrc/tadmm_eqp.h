@@ -379,7 +379,8 @@ __device__ void eqp_freeze(const Prob &pb, const WS &ws, const EWS &ew, const Sc
           float d[NU], dd = 0.f;
 #pragma unroll
           for (int c = 0; c < NU; ++c) {
-            d[c] = R[(unsigned)(t * N + i) * (unsigned)F::NF + F::X + c] - R[(unsigned)(t * N + j) * (unsigned)F::NF + F::X + c];
+            d[c] = R[fidx((unsigned)sc.GS, (unsigned)(t * N + i), F::X + c)] -
+                   R[fidx((unsigned)sc.GS, (unsigned)(t * N + j), F::X + c)];
             dd = fmaf(d[c], d[c], dd);
           }
           dd = sqrtf(dd);

@@ -25,8 +25,8 @@ namespace tadmm {
 // Local QP of one agent (x-update)
 // ===========================================================================
 // Addressing: the scenario region bases are uniform; agent-stage g of agent i
-// at stage t is g = t * N + i, and field f of it is at R[g * NF + f] (32-bit
-// offsets, the field an immediate).
+// at stage t is g = t * N + i, and field f of it is at R[fidx(GS, g, f)]
+// (32-bit offsets; the group base (f / 4) * 4 GS is uniform).
 template <int NX, int NU>
 struct AgentMem {
   float *__restrict__ R;
@@ -34,7 +34,7 @@ struct AgentMem {
   double *__restrict__ D;
   unsigned GS, N, i;
   __device__ __forceinline__ unsigned g(int t) const { return (unsigned)t * N + i; }
-  __device__ __forceinline__ float &f(int field, int t) const { return R[g(t) * (unsigned)Fld<NX, NU>::NF + field]; }
+  __device__ __forceinline__ float &f(int field, int t) const { return fref(R, GS, g(t), field); }
   __device__ __forceinline__ int8_t &w(int c, int t) const { return Wb[g(t) * 4u + c]; }
   __device__ __forceinline__ double &d(int c, int t) const { return D[g(t) * (unsigned)NX + c]; }
 };
@@ -549,13 +549,14 @@ __device__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, i
   using F = Fld<NX, NU>;
   const int N = sc.N, T = sc.T;
   float *R = ws.fr + sc.fo;
-  float *Ri = R + (unsigned)(t * N + i) * (unsigned)F::NF;   // this agent-stage
+  const unsigned GS = (unsigned)sc.GS, gi = (unsigned)(t * N + i);   // this agent-stage
+  auto Ri = [&](int f) -> float & { return fref(R, GS, gi, f); };
   float pi[NU];
   bool bad = false;
 #pragma unroll
-  for (int c = 0; c < NU; ++c) pi[c] = Ri[F::X + c];
+  for (int c = 0; c < NU; ++c) pi[c] = Ri(F::X + c);
 #pragma unroll
-  for (int c = 0; c < NX; ++c) bad |= !isfinite(Ri[F::X + c]);
+  for (int c = 0; c < NX; ++c) bad |= !isfinite(Ri(F::X + c));
   float *lam = ws.lam + sc.lo;
   uint8_t *pa = ws.pact + sc.lb;
   const int LS = T * N * N;
@@ -571,7 +572,7 @@ __device__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, i
       for (int c = 0; c < NU; ++c) pj[c] = lpos[(t * N + j) * NU + c];
     } else {
 #pragma unroll
-      for (int c = 0; c < NU; ++c) pj[c] = R[(unsigned)(t * N + j) * (unsigned)F::NF + F::X + c];
+      for (int c = 0; c < NU; ++c) pj[c] = R[fidx(GS, (unsigned)(t * N + j), F::X + c)];
     }
   };
   const int lbase = (t - 1) * N * N + i;        // + j * N: this lane's ordered copy (i, j)
@@ -657,21 +658,21 @@ __device__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, i
 #pragma unroll
   for (int c = 0; c < NU; ++c) {
     // rho sum_j (z_ij^(k+1) - z_ij^k) = rho (n_nbr (C x^(k+1) - C x^k) + ZD^(k+1) - ZD^k)
-    const float ds = rho * fmaf(nn, pi[c] - Ri[F::XP + c], zd[c] - Ri[F::ZD + c]);
+    const float ds = rho * fmaf(nn, pi[c] - Ri(F::XP + c), zd[c] - Ri(F::ZD + c));
     s2 = fmaf(ds, ds, s2);
     ax2 = fmaf(pi[c], pi[c], ax2);
     aty2 = fmaf(ls[c], ls[c], aty2);
-    Ri[F::Q + c] = fmaf(-rho * nn, pi[c], Ri[F::GQP + c]) - es[c];
-    Ri[F::XP + c] = pi[c];
-    Ri[F::ZD + c] = zd[c];
+    Ri(F::Q + c) = fmaf(-rho * nn, pi[c], Ri(F::GQP + c)) - es[c];
+    Ri(F::XP + c) = pi[c];
+    Ri(F::ZD + c) = zd[c];
   }
   ax2 *= nn;
   if (bad) r2 = NAN;
-  Ri[F::RED + 0] = r2;
-  Ri[F::RED + 1] = s2;
-  Ri[F::RED + 2] = ax2;
-  Ri[F::RED + 3] = z2;
-  Ri[F::RED + 4] = aty2;
+  Ri(F::RED + 0) = r2;
+  Ri(F::RED + 1) = s2;
+  Ri(F::RED + 2) = ax2;
+  Ri(F::RED + 3) = z2;
+  Ri(F::RED + 4) = aty2;
 }
 
 // Residual norms and the stopping test of Sec. V-A (Boyd et al. 2011, Sec.
@@ -687,7 +688,7 @@ __device__ int scenario_test(const Prob &pb, const WS &ws, const Scen &sc, int k
   for (int idx = lane; idx < NT; idx += 64) {
     const int g = sc.N + idx;  // stages 1..T
 #pragma unroll
-    for (int q = 0; q < 5; ++q) a[q] += R[(unsigned)g * (unsigned)F::NF + F::RED + q];
+    for (int q = 0; q < 5; ++q) a[q] += R[fidx((unsigned)sc.GS, (unsigned)g, F::RED + q)];
   }
 #pragma unroll
   for (int q = 0; q < 5; ++q) a[q] = wave_sum(a[q]);
@@ -728,30 +729,30 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
   const int n_nbr = N - 1;
   for (int idx = tid; idx < GS; idx += nthreads) {
     const int t = idx / N, i = idx % N;
-    float *Rg = R + (unsigned)idx * (unsigned)F::NF;
+    auto Rg = [&](int f) -> float & { return R[fidx((unsigned)GS, (unsigned)idx, f)]; };
     const float *r = ws.xref + (sc.xo + (long long)i * (T + 1) + t) * NX;
     const float w = (t == T) ? pb.qT : 1.0f;
     float gq[NX];
 #pragma unroll
     for (int c = 0; c < NX; ++c) {
       gq[c] = (t >= 1) ? -2.0f * w * qd[c] * r[c] : 0.f;
-      if (c >= NU) Rg[F::Q + c] = gq[c];
+      if (c >= NU) Rg(F::Q + c) = gq[c];
     }
 #pragma unroll
     for (int c = 0; c < NU; ++c) {
       // x^0 := r so that z^0 = C r, lambda^0 = 0
-      Rg[F::GQP + c] = gq[c];
-      Rg[F::Q + c] = fmaf(-pb.rho * (float)n_nbr, r[c], gq[c]);
-      Rg[F::XP + c] = r[c];
-      Rg[F::ZD + c] = 0.f;
-      Rg[F::U + c] = 0.f;
+      Rg(F::GQP + c) = gq[c];
+      Rg(F::Q + c) = fmaf(-pb.rho * (float)n_nbr, r[c], gq[c]);
+      Rg(F::XP + c) = r[c];
+      Rg(F::ZD + c) = 0.f;
+      Rg(F::U + c) = 0.f;
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) Wb[(unsigned)idx * 4u + c] = 0;
     if (t == 0) {
       const float *x0 = ws.x0 + (sc.ao + i) * NX;
 #pragma unroll
-      for (int c = 0; c < NX; ++c) { Rg[F::X + c] = x0[c]; Rg[F::XE + c] = x0[c]; }
+      for (int c = 0; c < NX; ++c) { Rg(F::X + c) = x0[c]; Rg(F::XE + c) = x0[c]; }
       ws.adirty[sc.ao + i] = T - 1;
     }
     if (t == T) {
@@ -760,7 +761,7 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
 #pragma unroll
       for (int r2 = 0; r2 < NX; ++r2)
 #pragma unroll
-        for (int c = r2; c < NX; ++c) Rg[F::PU + sym_idx<NX>(r2, c)] = (r2 == c) ? hx[r2] : 0.f;
+        for (int c = r2; c < NX; ++c) Rg(F::PU + sym_idx<NX>(r2, c)) = (r2 == c) ? hx[r2] : 0.f;
     }
   }
   const int LS = T * N * N;
@@ -872,7 +873,7 @@ __device__ __forceinline__ void persistent_body(Prob pb, WS ws, int S, int lds_f
           const float *R = ws.fr + sc.fo;
           for (int idx = tid; idx < sc.GS; idx += nt)
 #pragma unroll
-            for (int c = 0; c < NU; ++c) lds_pos[idx * NU + c] = R[(unsigned)idx * (unsigned)Fld<NX, NU>::NF + Fld<NX, NU>::X + c];
+            for (int c = 0; c < NU; ++c) lds_pos[idx * NU + c] = R[fidx((unsigned)sc.GS, (unsigned)idx, Fld<NX, NU>::X + c)];
           __syncthreads();
         }
         for (int idx = tid; idx < sc.N * sc.T; idx += nt)
@@ -966,12 +967,12 @@ __global__ void k_writeback(WS ws, int S, tadmm_out out) {
     if (out.x)
       for (int e = threadIdx.x; e < N * (T + 1) * NX; e += blockDim.x) {
         const int c = e % NX, it = e / NX, t = it % (T + 1), i = it / (T + 1);
-        out.x[sc.xo * NX + e] = R[(unsigned)(t * N + i) * (unsigned)F::NF + F::X + c];
+        out.x[sc.xo * NX + e] = R[fidx((unsigned)sc.GS, (unsigned)(t * N + i), F::X + c)];
       }
     if (out.u || out.w)
       for (int e = threadIdx.x; e < N * T * NU; e += blockDim.x) {
         const int c = e % NU, it = e / NU, t = it % T, i = it / T;
-        if (out.u) out.u[sc.uo * NU + e] = R[(unsigned)(t * N + i) * (unsigned)F::NF + F::U + c];
+        if (out.u) out.u[sc.uo * NU + e] = R[fidx((unsigned)sc.GS, (unsigned)(t * N + i), F::U + c)];
         if (out.w) out.w[sc.uo * NU + e] = Wb[(unsigned)(t * N + i) * 4u + c];
       }
     if (out.pair_active)
