@@ -91,14 +91,19 @@ __device__ void refactor(const Prob &pb, const AgentMem<NX, NU> &m, const float 
 
 // Affine backward sweep with the cached factors:
 //   p_T = q_T;  k_t = kc_t - Sv_t B'p_{t+1};  p_t = q_t + c_t + A'p_{t+1} + K_t' B'p_{t+1},
+// storing k_t for the rollout and p_{t+1} where stage t has a fixed input,
 // with q_t = -2 Q_t r_t - C' sum_j (rho z_ij,t - lambda_ij,t) (QP on positions).
 // The factors of stage t-1 are loaded into registers before the stores of
 // stage t are issued, so the memory latency overlaps the recurrence.
 template <int NX, int NU>
 struct SweepStage {
   float K[NU][NX], sv[Fld<NX, NU>::NS], kc[NU], cq[NX];
+  bool fixed;   // the stage has an input in the working set
   __device__ __forceinline__ void load(const AgentMem<NX, NU> &m, int t) {
     using F = Fld<NX, NU>;
+    fixed = false;
+#pragma unroll
+    for (int a = 0; a < NU; ++a) fixed |= (m.w(a, t) != 0);
 #pragma unroll
     for (int a = 0; a < NU; ++a) {
 #pragma unroll
@@ -123,8 +128,11 @@ __device__ __forceinline__ void affine_sweep(const Prob &pb, const AgentMem<NX, 
   for (int t = T - 1; t >= 0; --t) {
     const SweepStage<NX, NU> cur = nxt;
     if (t >= 1) nxt.load(m, t - 1);
+    // p_{t+1} is read back only for the costates of a stage with a fixed input
+    if (cur.fixed) {
 #pragma unroll
-    for (int r = 0; r < NX; ++r) m.f(F::PV + r, t + 1) = p[r];
+      for (int r = 0; r < NX; ++r) m.f(F::PV + r, t + 1) = p[r];
+    }
     float bp[NU];
     Dyn<NX, NU, DI>::btx(pb, p, bp);
 #pragma unroll
@@ -172,6 +180,7 @@ struct RollStage {
   int8_t wt[NU];
   __device__ __forceinline__ void load(const AgentMem<NX, NU> &m, int t) {
     using F = Fld<NX, NU>;
+    bool fixed = false;
 #pragma unroll
     for (int a = 0; a < NU; ++a) {
 #pragma unroll
@@ -179,22 +188,33 @@ struct RollStage {
       kv[a] = m.f(F::KV + a, t);
       uc[a] = m.f(F::U + a, t);
       wt[a] = m.w(a, t);
+      fixed |= (wt[a] != 0);
     }
+    if (fixed) {   // the costates are needed only where an input is fixed
 #pragma unroll
-    for (int k = 0; k < F::NP; ++k) P[k] = m.f(F::PU + k, t + 1);
+      for (int k = 0; k < F::NP; ++k) P[k] = m.f(F::PU + k, t + 1);
 #pragma unroll
-    for (int r = 0; r < NX; ++r) pv[r] = m.f(F::PV + r, t + 1);
+      for (int r = 0; r < NX; ++r) pv[r] = m.f(F::PV + r, t + 1);
+    }
   }
 };
 
+// With `fp64_states` the same inputs are also rolled out in FP64 into the
+// refinement scratch (the first step of refine_solution, done here when this
+// pass turns out to be the last one).
 template <int NX, int NU, bool DI>
 __device__ __forceinline__ StepInfo forward_rollout(const Prob &pb, const AgentMem<NX, NU> &m, int T,
-                                                    const float hu[NU]) {
+                                                    const float hu[NU], bool fp64_states) {
   using F = Fld<NX, NU>;
   StepInfo si{1.0f, -1, 0, 0.0f, -1};
   float x[NX];
+  double xd[NX];
 #pragma unroll
-  for (int r = 0; r < NX; ++r) x[r] = m.f(F::X + r, 0);
+  for (int r = 0; r < NX; ++r) {
+    x[r] = m.f(F::X + r, 0);
+    xd[r] = (double)x[r];
+    if (fp64_states) m.d(r, 0) = xd[r];
+  }
   RollStage<NX, NU> nxt;
   nxt.load(m, 0);
   for (int t = 0; t < T; ++t) {
@@ -214,6 +234,15 @@ __device__ __forceinline__ StepInfo forward_rollout(const Prob &pb, const AgentM
     Dyn<NX, NU, DI>::add_bu(pb, ue, xn);
 #pragma unroll
     for (int r = 0; r < NX; ++r) m.f(F::XE + r, t + 1) = xn[r];
+    if (fp64_states) {
+      double ud[NU], xdn[NX];
+#pragma unroll
+      for (int a = 0; a < NU; ++a) ud[a] = (double)ue[a];
+      Dyn<NX, NU, DI>::ax(pb, xd, xdn);
+      Dyn<NX, NU, DI>::add_bu(pb, ud, xdn);
+#pragma unroll
+      for (int r = 0; r < NX; ++r) { xd[r] = xdn[r]; m.d(r, t + 1) = xdn[r]; }
+    }
     bool any = false;
 #pragma unroll
     for (int a = 0; a < NU; ++a) any |= (cur.wt[a] != 0);
@@ -267,31 +296,37 @@ __device__ __forceinline__ StepInfo forward_rollout(const Prob &pb, const AgentM
 // inputs, homogeneous dynamics) is solved with the cached FP32 factors
 // (k_t = -Sv (B'p + g_t), p_t = A'p + K'(B'p + g_t), p_T = 0) and applied in
 // FP64 before rounding the iterate back to FP32.
-template <int NX, int NU, bool DI>
+// UI is the field holding the inputs to refine: U, or UE when the last
+// active-set pass took the full step and its EQP solution was not copied
+// (the refined solution is written to U and X either way).  With
+// `states_ready` the FP64 rollout of those inputs is already in the scratch.
+template <int NX, int NU, bool DI, int UI>
 __device__ void refine_solution(const Prob &pb, const AgentMem<NX, NU> &m, const float *qd, const float hu[NU],
-                                int T, int n_nbr) {
+                                int T, int n_nbr, bool states_ready) {
   using F = Fld<NX, NU>;
   using D = Dyn<NX, NU, DI>;
   constexpr int NS = F::NS;
   double x[NX];
+  if (!states_ready) {
 #pragma unroll
-  for (int r = 0; r < NX; ++r) { x[r] = (double)m.f(F::X + r, 0); m.d(r, 0) = x[r]; }
-  // (1) exact rollout of the stored inputs
-  float un[NU];
+    for (int r = 0; r < NX; ++r) { x[r] = (double)m.f(F::X + r, 0); m.d(r, 0) = x[r]; }
+    // (1) exact rollout of the stored inputs
+    float un[NU];
 #pragma unroll
-  for (int a = 0; a < NU; ++a) un[a] = m.f(F::U + a, 0);
-  for (int t = 0; t < T; ++t) {
-    double u[NU], xn[NX];
+    for (int a = 0; a < NU; ++a) un[a] = m.f(UI + a, 0);
+    for (int t = 0; t < T; ++t) {
+      double u[NU], xn[NX];
 #pragma unroll
-    for (int a = 0; a < NU; ++a) u[a] = (double)un[a];
-    if (t + 1 < T) {
+      for (int a = 0; a < NU; ++a) u[a] = (double)un[a];
+      if (t + 1 < T) {
 #pragma unroll
-      for (int a = 0; a < NU; ++a) un[a] = m.f(F::U + a, t + 1);
+        for (int a = 0; a < NU; ++a) un[a] = m.f(UI + a, t + 1);
+      }
+      D::ax(pb, x, xn);
+      D::add_bu(pb, u, xn);
+#pragma unroll
+      for (int r = 0; r < NX; ++r) { x[r] = xn[r]; m.d(r, t + 1) = xn[r]; }
     }
-    D::ax(pb, x, xn);
-    D::add_bu(pb, u, xn);
-#pragma unroll
-    for (int r = 0; r < NX; ++r) { x[r] = xn[r]; m.d(r, t + 1) = xn[r]; }
   }
   // (2) backward: FP64 adjoint (reduced gradient) and the FP32 correction sweep
   double nu[NX];
@@ -313,7 +348,7 @@ __device__ void refine_solution(const Prob &pb, const AgentMem<NX, NU> &m, const
   auto bload = [&](BStage &st, int t) {
 #pragma unroll
     for (int a = 0; a < NU; ++a) {
-      st.u[a] = m.f(F::U + a, t);
+      st.u[a] = m.f(UI + a, t);
       st.wt[a] = m.w(a, t);
 #pragma unroll
       for (int c = 0; c < NX; ++c) st.K[a][c] = m.f(F::K + a * NX + c, t);
@@ -375,7 +410,7 @@ __device__ void refine_solution(const Prob &pb, const AgentMem<NX, NU> &m, const
 #pragma unroll
     for (int a = 0; a < NU; ++a) {
       st.kv[a] = m.f(F::KV + a, t);
-      st.u[a] = m.f(F::U + a, t);
+      st.u[a] = m.f(UI + a, t);
 #pragma unroll
       for (int c = 0; c < NX; ++c) st.K[a][c] = m.f(F::K + a * NX + c, t);
     }
@@ -443,7 +478,7 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
       if (td >= 0) { refactor<NX, NU, DI>(pb, m, qd, hu, T, n_nbr, td); cnt[CT_REFACTOR] += td + 1; td = -1; }
       affine_sweep<NX, NU, DI>(pb, m, T);
       cnt[CT_AFFINE] += T;
-      (void)forward_rollout<NX, NU, DI>(pb, m, T, hu);
+      (void)forward_rollout<NX, NU, DI>(pb, m, T, hu, false);
       cnt[CT_PASSES] += 1;
     }
     float x[NX];
@@ -470,13 +505,14 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
   }
 
   int done = 0;
+  bool full = false;   // the last pass took the full step: its EQP solution is in (UE, XE)
   int last_drop = -1, last_side = 0;   // bound released by the previous pass
   for (int it = 0; it < cap; ++it) {
     if (!pb.cache) td = T - 1;
     if (td >= 0) { refactor<NX, NU, DI>(pb, m, qd, hu, T, n_nbr, td); cnt[CT_REFACTOR] += td + 1; td = -1; }
     affine_sweep<NX, NU, DI>(pb, m, T);
     cnt[CT_AFFINE] += T;
-    const StepInfo si = forward_rollout<NX, NU, DI>(pb, m, T, hu);
+    const StepInfo si = forward_rollout<NX, NU, DI>(pb, m, T, hu, pb.refine != 0);
     cnt[CT_PASSES] += 1;
     if (si.blk >= 0) {
       // blocked: move the fraction alpha toward the EQP solution, fix the bound
@@ -507,14 +543,18 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
       last_drop = -1;
       continue;
     }
-    // full step: the EQP solution becomes the iterate
-    for (int t = 0; t < T; ++t) {
+    // full step: the EQP solution becomes the iterate (copied unless the
+    // refinement below reads it from (UE, XE) and writes the result)
+    const bool drop = si.drop >= 0 && si.mu_min < -pb.mu_tol;
+    if (drop || !pb.refine) {
+      for (int t = 0; t < T; ++t) {
 #pragma unroll
-      for (int a = 0; a < NU; ++a) m.f(F::U + a, t) = m.f(F::UE + a, t);
+        for (int a = 0; a < NU; ++a) m.f(F::U + a, t) = m.f(F::UE + a, t);
 #pragma unroll
-      for (int r = 0; r < NX; ++r) m.f(F::X + r, t + 1) = m.f(F::XE + r, t + 1);
+        for (int r = 0; r < NX; ++r) m.f(F::X + r, t + 1) = m.f(F::XE + r, t + 1);
+      }
     }
-    if (si.drop >= 0 && si.mu_min < -pb.mu_tol) {
+    if (drop) {
       const int dt = si.drop / NU, da = si.drop % NU;
       last_side = m.w(da, dt);
       last_drop = si.drop;
@@ -523,11 +563,13 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
       continue;
     }
     done = 1;
+    full = true;
     break;
   }
   if (done && pb.refine) {
     if (td >= 0) { refactor<NX, NU, DI>(pb, m, qd, hu, T, n_nbr, td); cnt[CT_REFACTOR] += td + 1; td = -1; }
-    refine_solution<NX, NU, DI>(pb, m, qd, hu, T, n_nbr);
+    if (full) refine_solution<NX, NU, DI, Fld<NX, NU>::UE>(pb, m, qd, hu, T, n_nbr, true);
+    else refine_solution<NX, NU, DI, Fld<NX, NU>::U>(pb, m, qd, hu, T, n_nbr, false);
     cnt[CT_AFFINE] += 2 * T;
   }
   ws.adirty[sc.ao + i] = td;
