@@ -55,7 +55,7 @@ struct WS {
   double *dr;                        // FP64 refinement scratch [NX][N(T+1)] per scenario
   int8_t *wr;                        // working-set regions  [NU][N(T+1)] per scenario
   int *adirty;                       // [agents] highest stale factor stage (-1: none)
-  float *lam;                        // [DP][T][N][N] per scenario
+  float *gam;                        // [T][N][N] per scenario: gamma of ordered copy (i, j) at [t][j][i]
   uint8_t *pact;                     // [T][N][N] per scenario
   int *sst;                          // [S][ST_NCOL]
   float *snorm;                      // [S][SN_NCOL]

@@ -335,7 +335,7 @@ __device__ __forceinline__ double eqp_row(const Scen &sc, const R *Er, const flo
 
 // Freeze the normals of the last consensus step and compact the held
 // half-planes (contiguous chunks per thread, exclusive scan: a fixed order);
-// the polish starts from nu = -n'lambda_ij.
+// the polish starts from nu = gamma of the last consensus step.
 template <int NX, int NU>
 __device__ void eqp_freeze(const Prob &pb, const WS &ws, const EWS &ew, const Scen &sc, int *scan, int tid, int nth) {
   using F = Fld<NX, NU>;
@@ -345,9 +345,8 @@ __device__ void eqp_freeze(const Prob &pb, const WS &ws, const EWS &ew, const Sc
   int *cidx = ew.cidx + sc.po;
   int2 *cl = ew.clist + sc.po;
   double *nu = ew.cg + 6 * sc.po;
-  const float *lam = ws.lam + sc.lo;
+  const float *gm = ws.gam + sc.lo;
   const uint8_t *pa = ws.pact + sc.lb;
-  const int LS = T * N * N;
   const int per = (TP + nth - 1) / nth;
   const int q0 = min(TP, tid * per), q1 = min(TP, q0 + per);
   int cnt = 0;
@@ -396,12 +395,9 @@ __device__ void eqp_freeze(const Prob &pb, const WS &ws, const EWS &ew, const Sc
         cnt += act;
       } else {
         if (act) {
-          double g = 0.0;
-#pragma unroll
-          for (int c = 0; c < NU; ++c) g = fma((double)nrm[(long long)q * NU + c], (double)lam[c * LS + e], g);
           cidx[q] = k;
           cl[k] = make_int2(q, i * N + j);
-          nu[k] = -g;
+          nu[k] = (double)gm[e];   // lambda_ij = -gamma n: the half-plane's multiplier
           ++k;
         } else {
           cidx[q] = -1;

@@ -582,95 +582,119 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
 // Canonical pair (f < s) with positions pf, ps and lambda_fs (lambda_sf =
 // -lambda_fs): a = pf + lambda_fs/rho, b = ps - lambda_fs/rho,
 // v = d_min - n'(a - b); the projection onto {n'(a-b) >= d_min} moves a and b
-// by +-(v+/2) n, and Eq. 5 then gives lambda_fs <- -(rho/2) max(v, 0) n, which
-// is evaluated in this closed form (no cancellation); the copies follow from
-// Eq. 5 as z_f = pf + (lambda_fs - lambda_fs_new)/rho, z_s = ps - (same).
+// by +-(v+/2) n, and Eq. 5 then gives lambda_fs <- -(rho/2) max(v, 0) n =
+// -gamma n, which is evaluated in this closed form (no cancellation); the
+// copies follow from Eq. 5 as z_f = pf + (lambda_fs - lambda_fs_new)/rho,
+// z_s = ps - (same).  Only gamma is stored (one float per ordered copy, both
+// copies equal); lambda_fs of the previous step is rebuilt as -gamma n_prev
+// with n_prev the normal of that step, recomputed from the previous positions
+// C x^k (XP) with the same arithmetic, so the rebuilt value is bitwise the
+// stored one of a vector layout.
+template <int NX, int NU>
+__device__ __forceinline__ void pair_normal(const Prob &pb, const WS &ws, const Scen &sc, int f, int s, int t,
+                                            const float pf[NU], const float ps[NU], float n[NU]) {
+  if (pb.normal_mode == NORMAL_FROZEN) {
+    if (ws.normals) {
+      const int pidx = f * sc.N - f * (f + 1) / 2 + (s - f - 1);
+      const float *nv = ws.normals + (sc.po + (long long)pidx * sc.T + (t - 1)) * NU;
+#pragma unroll
+      for (int c = 0; c < NU; ++c) n[c] = nv[c];
+    } else {
+      reference_normal<NX, NU>(ws, sc, f, s, t, n);
+    }
+  } else {
+    float d[NU], dd = 0.f;
+#pragma unroll
+    for (int c = 0; c < NU; ++c) { d[c] = pf[c] - ps[c]; dd = fmaf(d[c], d[c], dd); }
+    dd = sqrtf(dd);
+    if (dd >= 1e-6f) {
+#pragma unroll
+      for (int c = 0; c < NU; ++c) n[c] = d[c] / dd;
+    } else {
+      reference_normal<NX, NU>(ws, sc, f, s, t, n);
+    }
+  }
+}
+
 template <int NX, int NU>
 __device__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, int i, int t,
-                                 const float *__restrict__ lpos) {
+                                 const float *__restrict__ lpos, const float *__restrict__ lprev) {
   using F = Fld<NX, NU>;
-  const int N = sc.N, T = sc.T;
+  const int N = sc.N;
   float *R = ws.fr + sc.fo;
   const unsigned GS = (unsigned)sc.GS, gi = (unsigned)(t * N + i);   // this agent-stage
   auto Ri = [&](int f) -> float & { return fref(R, GS, gi, f); };
-  float pi[NU];
+  float pi[NU], qi[NU];   // positions of this step and of the previous one
   bool bad = false;
 #pragma unroll
-  for (int c = 0; c < NU; ++c) pi[c] = Ri(F::X + c);
+  for (int c = 0; c < NU; ++c) { pi[c] = Ri(F::X + c); qi[c] = Ri(F::XP + c); }
 #pragma unroll
   for (int c = 0; c < NX; ++c) bad |= !isfinite(Ri(F::X + c));
-  float *lam = ws.lam + sc.lo;
+  float *gm = ws.gam + sc.lo;
   uint8_t *pa = ws.pact + sc.lb;
-  const int LS = T * N * N;
   const float rho = pb.rho, irho = 1.0f / pb.rho;
+  const bool frozen = pb.normal_mode == NORMAL_FROZEN;
   float es[NU], zd[NU], ls[NU];   // sum (lam_old - 2 lam_new), sum (z - C x), sum lam_new
 #pragma unroll
   for (int c = 0; c < NU; ++c) { es[c] = 0.f; zd[c] = 0.f; ls[c] = 0.f; }
   float r2 = 0.f, z2 = 0.f;
-  // partner positions from LDS when the scenario's positions are staged there
-  auto partner = [&](int j, float pj[NU]) {
+  // partner positions (this step and the previous one) from LDS when the
+  // scenario's positions are staged there
+  auto partner = [&](int j, float pj[NU], float qj[NU]) {
     if (lpos) {
 #pragma unroll
-      for (int c = 0; c < NU; ++c) pj[c] = lpos[(t * N + j) * NU + c];
+      for (int c = 0; c < NU; ++c) { pj[c] = lpos[(t * N + j) * NU + c]; qj[c] = lprev[(t * N + j) * NU + c]; }
     } else {
 #pragma unroll
-      for (int c = 0; c < NU; ++c) pj[c] = R[fidx(GS, (unsigned)(t * N + j), F::X + c)];
+      for (int c = 0; c < NU; ++c) {
+        pj[c] = R[fidx(GS, (unsigned)(t * N + j), F::X + c)];
+        qj[c] = R[fidx(GS, (unsigned)(t * N + j), F::XP + c)];
+      }
     }
   };
-  const int lbase = (t - 1) * N * N + i;        // + j * N: this lane's ordered copy (i, j)
-  // the partner loop skips j == i; the duals of the next partner are loaded
+  const int gbase = (t - 1) * N * N + i;        // + j * N: this lane's ordered copy (i, j)
+  // the partner loop skips j == i; the dual of the next partner is loaded
   // before the current partner's dual is stored
-  float lnx[NU];
-  if (N > 1) {
-    const int j0 = (i == 0) ? 1 : 0;
-#pragma unroll
-    for (int c = 0; c < NU; ++c) lnx[c] = lam[c * LS + lbase + j0 * N];
-  }
+  float gnx = 0.f;
+  if (N > 1) gnx = gm[gbase + ((i == 0) ? 1 : 0) * N];
   for (int jj = 0; jj < N - 1; ++jj) {
     const int j = jj + (jj >= i);
-    float lown[NU];
-#pragma unroll
-    for (int c = 0; c < NU; ++c) lown[c] = lnx[c];
+    const float gold = gnx;
     if (jj + 1 < N - 1) {
       const int jn = jj + 1 + (jj + 1 >= i);
-#pragma unroll
-      for (int c = 0; c < NU; ++c) lnx[c] = lam[c * LS + lbase + jn * N];
+      gnx = gm[gbase + jn * N];
     }
     const bool first = i < j;
     const int f = first ? i : j, s = first ? j : i;
-    float pj[NU], pf[NU], ps[NU];
-    partner(j, pj);
+    float pj[NU], qj[NU], pf[NU], ps[NU];
+    partner(j, pj, qj);
 #pragma unroll
     for (int c = 0; c < NU; ++c) {
       pf[c] = first ? pi[c] : pj[c];
       ps[c] = first ? pj[c] : pi[c];
     }
     float n[NU];
-    if (pb.normal_mode == NORMAL_FROZEN) {
-      if (ws.normals) {
-        const int pidx = f * N - f * (f + 1) / 2 + (s - f - 1);
-        const float *nv = ws.normals + (sc.po + (long long)pidx * T + (t - 1)) * NU;
-#pragma unroll
-        for (int c = 0; c < NU; ++c) n[c] = nv[c];
-      } else {
-        reference_normal<NX, NU>(ws, sc, f, s, t, n);
-      }
-    } else {
-      float d[NU], dd = 0.f;
-#pragma unroll
-      for (int c = 0; c < NU; ++c) { d[c] = pf[c] - ps[c]; dd = fmaf(d[c], d[c], dd); }
-      dd = sqrtf(dd);
-      if (dd >= 1e-6f) {
-#pragma unroll
-        for (int c = 0; c < NU; ++c) n[c] = d[c] / dd;
-      } else {
-        reference_normal<NX, NU>(ws, sc, f, s, t, n);
-      }
-    }
-    const int li = lbase + j * N;  // this lane's ordered copy (i, j)
+    pair_normal<NX, NU>(pb, ws, sc, f, s, t, pf, ps, n);
+    // lambda_fs of the previous step, -gamma_prev n_prev
     float lfs[NU];
+    {
+      float np[NU];
+      if (frozen) {
 #pragma unroll
-    for (int c = 0; c < NU; ++c) lfs[c] = first ? lown[c] : -lown[c];
+        for (int c = 0; c < NU; ++c) np[c] = n[c];
+      } else {
+        float qf[NU], qs[NU];
+#pragma unroll
+        for (int c = 0; c < NU; ++c) {
+          qf[c] = first ? qi[c] : qj[c];
+          qs[c] = first ? qj[c] : qi[c];
+        }
+        pair_normal<NX, NU>(pb, ws, sc, f, s, t, qf, qs, np);
+      }
+#pragma unroll
+      for (int c = 0; c < NU; ++c) lfs[c] = -gold * np[c];
+    }
+    const int li = gbase + j * N;  // this lane's ordered copy (i, j)
     float g = 0.f;
 #pragma unroll
     for (int c = 0; c < NU; ++c) {
@@ -681,18 +705,19 @@ __device__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, i
     const float gam = 0.5f * rho * fmaxf(v, 0.f);
 #pragma unroll
     for (int c = 0; c < NU; ++c) {
+      const float lown = first ? lfs[c] : -lfs[c];    // this lane's lambda_ij before Eq. 5
       const float lnew = -gam * n[c];                 // lambda_fs after Eq. 5
       const float dl = (lfs[c] - lnew) * irho;       // z_f - pf = -(z_s - ps)
       const float sdl = first ? dl : -dl;            // z_own - C x_i
       const float zo = pi[c] + sdl;
       const float lo = first ? lnew : -lnew;
-      es[c] += lown[c] - 2.0f * lo;                  // rho z_own - lam_new - rho C x_i
+      es[c] += lown - 2.0f * lo;                     // rho z_own - lam_new - rho C x_i
       zd[c] += sdl;
       ls[c] += lo;
       r2 = fmaf(dl, dl, r2);
       z2 = fmaf(zo, zo, z2);
-      lam[c * LS + li] = lo;
     }
+    gm[li] = gam;
     if (first) pa[li] = (uint8_t)(v > 0.f);
   }
   float s2 = 0.f, ax2 = 0.f, aty2 = 0.f;
@@ -700,12 +725,11 @@ __device__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, i
 #pragma unroll
   for (int c = 0; c < NU; ++c) {
     // rho sum_j (z_ij^(k+1) - z_ij^k) = rho (n_nbr (C x^(k+1) - C x^k) + ZD^(k+1) - ZD^k)
-    const float ds = rho * fmaf(nn, pi[c] - Ri(F::XP + c), zd[c] - Ri(F::ZD + c));
+    const float ds = rho * fmaf(nn, pi[c] - qi[c], zd[c] - Ri(F::ZD + c));
     s2 = fmaf(ds, ds, s2);
     ax2 = fmaf(pi[c], pi[c], ax2);
     aty2 = fmaf(ls[c], ls[c], aty2);
     Ri(F::Q + c) = fmaf(-rho * nn, pi[c], Ri(F::GQP + c)) - es[c];
-    Ri(F::XP + c) = pi[c];
     Ri(F::ZD + c) = zd[c];
   }
   ax2 *= nn;
@@ -715,6 +739,19 @@ __device__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, i
   Ri(F::RED + 2) = ax2;
   Ri(F::RED + 3) = z2;
   Ri(F::RED + 4) = aty2;
+}
+
+// After a consensus step: the positions of this step become the previous
+// positions (XP) of the next one.  Kept out of the partner loop, which reads
+// every partner's previous positions.
+template <int NX, int NU>
+__device__ __forceinline__ void commit_positions(const WS &ws, const Scen &sc, int tid, int nthreads) {
+  using F = Fld<NX, NU>;
+  float *R = ws.fr + sc.fo;
+  const unsigned GS = (unsigned)sc.GS;
+  for (int idx = sc.N + tid; idx < sc.GS; idx += nthreads)
+#pragma unroll
+    for (int c = 0; c < NU; ++c) fref(R, GS, (unsigned)idx, F::XP + c) = fref(R, GS, (unsigned)idx, F::X + c);
 }
 
 // Residual norms and the stopping test of Sec. V-A (Boyd et al. 2011, Sec.
@@ -807,11 +844,10 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
     }
   }
   const int LS = T * N * N;
-  float *lam = ws.lam + sc.lo;
+  float *gm = ws.gam + sc.lo;
   uint8_t *pa = ws.pact + sc.lb;
   for (int idx = tid; idx < LS; idx += nthreads) {
-#pragma unroll
-    for (int c = 0; c < NU; ++c) lam[c * LS + idx] = 0.f;
+    gm[idx] = 0.f;
     pa[idx] = 0;
   }
   if (tid == 0) {
@@ -857,7 +893,7 @@ __global__ __launch_bounds__(256) void k_pair(Prob pb, WS ws, int s) {
   const Scen sc = load_scen(ws, s);
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= sc.N * sc.T) return;
-  pair_agent_stage<NX, NU>(pb, ws, sc, idx % sc.N, idx / sc.N + 1, nullptr);
+  pair_agent_stage<NX, NU>(pb, ws, sc, idx % sc.N, idx / sc.N + 1, nullptr, nullptr);
   if (idx == 0) {
     long long c[CT_NCOL] = {};
     c[CT_PAIRS] = (long long)sc.N * (sc.N - 1) / 2 * sc.T;
@@ -871,6 +907,7 @@ __global__ __launch_bounds__(64) void k_resid(Prob pb, WS ws, int s, int k, int 
   const int cap = ws.sst[(long long)s * ST_NCOL + ST_CAP];
   const int done = scenario_test<NX, NU>(pb, ws, sc, k, threadIdx.x, cap);
   if (threadIdx.x == 0) *done_out = done;
+  if (!cap) commit_positions<NX, NU>(ws, sc, threadIdx.x, blockDim.x);
 }
 
 // ===========================================================================
@@ -883,7 +920,7 @@ __global__ __launch_bounds__(64) void k_resid(Prob pb, WS ws, int s, int k, int 
 // once the counter passes S.
 template <int NX, int NU, bool DI>
 __device__ __forceinline__ void persistent_body(Prob pb, WS ws, int S, int lds_floats) {
-  extern __shared__ float lds_pos[];  // positions of the scenario, [t][i][c]
+  extern __shared__ float lds_pos[];  // positions of the scenario and the previous ones, [t][i][c] each
   __shared__ int s_item;
   __shared__ int s_cap;
   __shared__ int s_done;
@@ -910,17 +947,25 @@ __device__ __forceinline__ void persistent_body(Prob pb, WS ws, int S, int lds_f
       if (!cap) {
         // stage every position of the scenario in LDS (the partner loop reads
         // them N-1 times each), then the consensus and dual updates
-        const bool staged = sc.GS * NU <= lds_floats;
+        const bool staged = 2 * sc.GS * NU <= lds_floats;
+        float *lds_prev = lds_pos + sc.GS * NU;
         if (staged) {
-          const float *R = ws.fr + sc.fo;
+          float *R = ws.fr + sc.fo;
+          const unsigned GS = (unsigned)sc.GS;
           for (int idx = tid; idx < sc.GS; idx += nt)
 #pragma unroll
-            for (int c = 0; c < NU; ++c) lds_pos[idx * NU + c] = R[fidx((unsigned)sc.GS, (unsigned)idx, Fld<NX, NU>::X + c)];
+            for (int c = 0; c < NU; ++c) {
+              lds_pos[idx * NU + c] = fref(R, GS, (unsigned)idx, Fld<NX, NU>::X + c);
+              lds_prev[idx * NU + c] = fref(R, GS, (unsigned)idx, Fld<NX, NU>::XP + c);
+            }
           __syncthreads();
         }
         for (int idx = tid; idx < sc.N * sc.T; idx += nt)
-          pair_agent_stage<NX, NU>(pb, ws, sc, idx % sc.N, idx / sc.N + 1, staged ? lds_pos : nullptr);
+          pair_agent_stage<NX, NU>(pb, ws, sc, idx % sc.N, idx / sc.N + 1, staged ? lds_pos : nullptr,
+                                   staged ? lds_prev : nullptr);
         if (tid == 0) cnt[CT_PAIRS] += (long long)sc.N * (sc.N - 1) / 2 * sc.T;
+        __syncthreads();
+        commit_positions<NX, NU>(ws, sc, tid, nt);
       }
       __syncthreads();
       const unsigned long long c2 = wall_clock64();
@@ -1055,7 +1100,7 @@ struct Layout {
   int S = 0, nx = 0, nu = 0, NF = 0;
   long long A = 0, sumGS = 0, sumL = 0;
   size_t o_N = 0, o_T = 0, o_tab = 0, o_order = 0, o_queue = 0, o_sst = 0, o_snorm = 0, o_cnt = 0, o_flags = 0;
-  size_t o_adirty = 0, o_fr = 0, o_dr = 0, o_wr = 0, o_lam = 0, o_pact = 0, bytes = 0;
+  size_t o_adirty = 0, o_fr = 0, o_dr = 0, o_wr = 0, o_gam = 0, o_pact = 0, bytes = 0;
   size_t o_er = 0, o_nrm = 0, o_cidx = 0, o_clist = 0, o_cg = 0, o_m = 0;
   long long sumPT = 0;
   std::vector<long long> tab;
@@ -1120,7 +1165,7 @@ bool make_layout(const tadmm_params *p, int S, const int32_t *N, const int32_t *
     fo += (long long)L.NF * GS;
     dof += (long long)p->nx * GS;
     bo += 4ll * GS;
-    lo += (long long)p->nu * t * n * n;
+    lo += t * n * n;
     lb += t * n * n;
     ao += n;
     xo += GS;
@@ -1143,7 +1188,7 @@ bool make_layout(const tadmm_params *p, int S, const int32_t *N, const int32_t *
   L.o_fr = take(sizeof(float) * (size_t)fo);
   L.o_dr = take(sizeof(double) * (size_t)dof);
   L.o_wr = take((size_t)bo);
-  L.o_lam = take(sizeof(float) * (size_t)lo);
+  L.o_gam = take(sizeof(float) * (size_t)lo);
   L.o_pact = take((size_t)lb);
   // equality-QP solves of the derivative (sized for FP64)
   L.sumPT = po;
@@ -1281,7 +1326,7 @@ WS make_ws(const Layout &L, char *ws, const tadmm_batch *b) {
   w.dr = (double *)(ws + L.o_dr);
   w.wr = (int8_t *)(ws + L.o_wr);
   w.adirty = (int *)(ws + L.o_adirty);
-  w.lam = (float *)(ws + L.o_lam);
+  w.gam = (float *)(ws + L.o_gam);
   w.pact = (uint8_t *)(ws + L.o_pact);
   w.sst = (int *)(ws + L.o_sst);
   w.snorm = (float *)(ws + L.o_snorm);
@@ -1339,7 +1384,7 @@ tadmm_status run_batched(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layo
   long long max_gs = 0;
   for (int s = 0; s < L.S; ++s) max_gs = std::max<long long>(max_gs, (long long)b->n_agents[s] * (b->horizon[s] + 1));
   const bool lean = (threads == 64);
-  const int lds_floats = (int)std::min<long long>(max_gs * NU, lean ? 2048 : 8192);
+  const int lds_floats = (int)std::min<long long>(2 * max_gs * NU, lean ? 4096 : 8192);
   const size_t lds_bytes = sizeof(float) * (size_t)lds_floats;
   const void *kfn = lean ? (const void *)k_admm_persistent_lean<NX, NU, DI> : (const void *)k_admm_persistent<NX, NU, DI>;
   int per_cu = 0;
