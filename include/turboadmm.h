@@ -117,6 +117,13 @@ typedef struct {
                                 of every local QP solution (reduced gradient in
                                 FP64, correction with the FP32 factors) (default);
                                 0: plain FP32 solve                                */
+  float refine_band;         /* with refine = 1: refine in every iteration (0), or
+                                only once the primal and dual residuals of the
+                                last stopping test are both within refine_band
+                                times their tolerances (> 0; 10 is the binding's
+                                default: before that the FP32 rounding of the
+                                local QPs is far below what the iteration
+                                resolves)                                           */
   int32_t eqp_fp64;          /* real type of the Riccati sweeps of tadmm_polish /
                                 tadmm_adjoint: 1 FP64 (recommended), 0 FP32;
                                 their multipliers and reductions are FP64 either

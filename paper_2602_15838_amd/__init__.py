@@ -40,7 +40,7 @@ class Params(C.Structure):
                 ("max_iter", C.c_int32), ("max_as_iter", C.c_int32), ("normal_mode", C.c_int32),
                 ("cache_factors", C.c_int32), ("riccati_warmstart", C.c_int32), ("hotstart", C.c_int32),
                 ("check_inputs", C.c_int32), ("block_threads", C.c_int32), ("refine", C.c_int32),
-                ("eqp_fp64", C.c_int32)]
+                ("refine_band", C.c_float), ("eqp_fp64", C.c_int32)]
 
 
 _fp = C.POINTER(C.c_float)
@@ -105,7 +105,7 @@ EXPORTED_SYMBOLS = ("tadmm_workspace_size", "tadmm_create", "tadmm_solve", "tadm
 def make_params(problem, *, normal_mode: int = NORMAL_PER_ITER, mu_tol: float = 1e-5, max_as_iter: int = 0,
                 cache_factors: bool = True, riccati_warmstart: bool = True, hotstart: bool = True,
                 check_inputs: bool = True, block_threads: int = 0, refine: bool = True,
-                eqp_fp64: bool = True, max_iter: Optional[int] = None,
+                refine_band: float = 10.0, eqp_fp64: bool = True, max_iter: Optional[int] = None,
                 eps_abs: Optional[float] = None, eps_rel: Optional[float] = None,
                 rho: Optional[float] = None) -> Params:
     """Fill the C parameter struct from a problem description (attributes
@@ -135,6 +135,7 @@ def make_params(problem, *, normal_mode: int = NORMAL_PER_ITER, mu_tol: float = 
     p.check_inputs = int(bool(check_inputs))
     p.block_threads = int(block_threads)
     p.refine = int(bool(refine))
+    p.refine_band = float(refine_band)
     p.eqp_fp64 = int(bool(eqp_fp64))
     return p
 

@@ -32,13 +32,14 @@ struct Prob {
   float dt, h;                   // double integrator: A = [[I, dt I], [0, I]], B = [[h I], [dt I]]
   float ulo[3], uhi[3];
   float qT, dmin, rho, eps_abs, eps_rel, mu_tol;
+  float refine_band;             // refine when both residuals are within this factor of their tolerances (0: always)
   int max_iter, max_as, normal_mode, cache, warm, hot, refine;
 };
 
 // Per-scenario table columns (int64).
 enum { TB_F = 0, TB_B, TB_L, TB_A, TB_XO, TB_UO, TB_PO, TB_LB, TB_D, TB_NCOL };
 // Per-scenario int32 state columns.
-enum { ST_STATUS = 0, ST_ITERS, ST_CAP, ST_DONE, ST_NCOL = 8 };
+enum { ST_STATUS = 0, ST_ITERS, ST_CAP, ST_DONE, ST_NEAR, ST_NCOL = 8 };
 // Per-scenario float state columns.
 enum { SN_R = 0, SN_S, SN_EPRI, SN_EDUAL, SN_NCOL = 4 };
 // Per-scenario counters (int64).

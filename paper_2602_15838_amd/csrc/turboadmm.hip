@@ -465,6 +465,10 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
   const int n_nbr = sc.N - 1;
   int td = ws.adirty[sc.ao + i];
   const int cap = pb.max_as > 0 ? pb.max_as : 10 * T * NU;
+  // the FP64-residual refinement, every iteration or once the residuals of
+  // the last test are within refine_band of their tolerances (before that the
+  // FP32 rounding of the local QP is far below what the iteration resolves)
+  const bool refine = pb.refine && (pb.refine_band <= 0.f || uni(ws.sst[(long long)sc.s * ST_NCOL + ST_NEAR]) != 0);
 
   if (k == 1 || !pb.hot) {
     // fresh start: empty working set ...
@@ -512,7 +516,7 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
     if (td >= 0) { refactor<NX, NU, DI>(pb, m, qd, hu, T, n_nbr, td); cnt[CT_REFACTOR] += td + 1; td = -1; }
     affine_sweep<NX, NU, DI>(pb, m, T);
     cnt[CT_AFFINE] += T;
-    const StepInfo si = forward_rollout<NX, NU, DI>(pb, m, T, hu, pb.refine != 0);
+    const StepInfo si = forward_rollout<NX, NU, DI>(pb, m, T, hu, refine);
     cnt[CT_PASSES] += 1;
     if (si.blk >= 0) {
       // blocked: move the fraction alpha toward the EQP solution, fix the bound
@@ -546,7 +550,7 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
     // full step: the EQP solution becomes the iterate (copied unless the
     // refinement below reads it from (UE, XE) and writes the result)
     const bool drop = si.drop >= 0 && si.mu_min < -pb.mu_tol;
-    if (drop || !pb.refine) {
+    if (drop || !refine) {
       for (int t = 0; t < T; ++t) {
 #pragma unroll
         for (int a = 0; a < NU; ++a) m.f(F::U + a, t) = m.f(F::UE + a, t);
@@ -566,7 +570,7 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
     full = true;
     break;
   }
-  if (done && pb.refine) {
+  if (done && refine) {
     if (td >= 0) { refactor<NX, NU, DI>(pb, m, qd, hu, T, n_nbr, td); cnt[CT_REFACTOR] += td + 1; td = -1; }
     if (full) refine_solution<NX, NU, DI, Fld<NX, NU>::UE>(pb, m, qd, hu, T, n_nbr, true);
     else refine_solution<NX, NU, DI, Fld<NX, NU>::U>(pb, m, qd, hu, T, n_nbr, false);
@@ -788,6 +792,7 @@ __device__ int scenario_test(const Prob &pb, const WS &ws, const Scen &sc, int k
     if (!cap_hit) {
       sn_out[SN_R] = rn; sn_out[SN_S] = sn; sn_out[SN_EPRI] = epri; sn_out[SN_EDUAL] = edual;
     }
+    st[ST_NEAR] = (rn <= pb.refine_band * epri && sn <= pb.refine_band * edual) ? 1 : 0;
     st[ST_STATUS] = status;
     st[ST_ITERS] = k;
     st[ST_DONE] = done;
@@ -856,6 +861,7 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
     st[ST_ITERS] = 0;
     st[ST_CAP] = 0;
     st[ST_DONE] = 0;
+    st[ST_NEAR] = 0;
     float *sn = ws.snorm + (long long)sc.s * SN_NCOL;
     sn[SN_R] = sn[SN_S] = sn[SN_EPRI] = sn[SN_EDUAL] = 0.f;
   }
@@ -1133,6 +1139,7 @@ bool params_ok(const tadmm_params *p, std::string &err) {
     err = "eps_abs/eps_rel must be >= 0"; return false;
   }
   if (!(std::isfinite(p->mu_tol) && p->mu_tol >= 0.f)) { err = "mu_tol must be >= 0"; return false; }
+  if (!(std::isfinite(p->refine_band) && p->refine_band >= 0.f)) { err = "refine_band must be >= 0"; return false; }
   if (p->max_iter < 1) { err = "max_iter must be >= 1"; return false; }
   if (p->normal_mode != TADMM_NORMAL_PER_ITER && p->normal_mode != TADMM_NORMAL_FROZEN) {
     err = "unknown normal_mode"; return false;
@@ -1244,6 +1251,7 @@ Prob to_prob(const tadmm_params &p) {
   pb.mu_tol = p.mu_tol; pb.max_iter = p.max_iter; pb.max_as = p.max_as_iter; pb.normal_mode = p.normal_mode;
   pb.cache = p.cache_factors ? 1 : 0; pb.warm = p.riccati_warmstart ? 1 : 0; pb.hot = p.hotstart ? 1 : 0;
   pb.refine = p.refine ? 1 : 0;
+  pb.refine_band = p.refine_band;
   return pb;
 }
 

@@ -63,7 +63,8 @@ def test_workspace_size_scales_with_batch():
 
 @pytest.mark.parametrize("field,value", [("rho", 0.0), ("rho", -1.0), ("max_iter", 0), ("nx", 5),
                                          ("qT_scale", 0.0), ("eps_abs", -1.0), ("normal_mode", 7),
-                                         ("block_threads", 100), ("block_threads", 512), ("mu_tol", float("nan"))])
+                                         ("block_threads", 100), ("block_threads", 512), ("mu_tol", float("nan")),
+                                         ("refine_band", -1.0)])
 def test_bad_params_rejected(field, value):
     prm = tadmm.make_params(synth.ProblemParams())
     setattr(prm, field, value)
