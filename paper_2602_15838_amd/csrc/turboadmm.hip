@@ -177,9 +177,14 @@ struct StepInfo {
 template <int NX, int NU>
 struct RollStage {
   float K[NU][NX], kv[NU], uc[NU], P[Fld<NX, NU>::NP], pv[NX];
+  float ueo[NU];   // a pending partial step: the previous pass's UE
   int8_t wt[NU];
-  __device__ __forceinline__ void load(const AgentMem<NX, NU> &m, int t) {
+  __device__ __forceinline__ void load(const AgentMem<NX, NU> &m, int t, bool pending) {
     using F = Fld<NX, NU>;
+    if (pending) {
+#pragma unroll
+      for (int a = 0; a < NU; ++a) ueo[a] = m.f(F::UE + a, t);
+    }
     bool fixed = false;
 #pragma unroll
     for (int a = 0; a < NU; ++a) {
@@ -199,12 +204,52 @@ struct RollStage {
   }
 };
 
+// A blocked active-set pass moves the inputs the fraction alpha toward its
+// EQP solution and fixes the blocking input at its bound.  That update is
+// applied by the next pass's rollout as it reaches each stage (the refactor
+// and the sweep in between do not read U), or by settle_iterate() when the
+// loop ends right after the blocked pass.  Inside the loop no pass reads the
+// states X beyond x_0 (every rollout starts from x_0), so X is set once, when
+// the loop ends.
+struct PendingStep {
+  bool on;
+  float alpha;   // step fraction
+  int bt, ba;    // stage and component of the blocking input
+  float bound;   // its bound value
+};
+
+// The loop ended on a blocked pass (or at its cap): apply a pending step to U
+// and roll the states out from the inputs.
+template <int NX, int NU, bool DI>
+__device__ void settle_iterate(const Prob &pb, const AgentMem<NX, NU> &m, int T, const PendingStep &pd) {
+  using F = Fld<NX, NU>;
+  float x[NX];
+#pragma unroll
+  for (int r = 0; r < NX; ++r) x[r] = m.f(F::X + r, 0);
+  for (int t = 0; t < T; ++t) {
+    float u[NU];
+#pragma unroll
+    for (int a = 0; a < NU; ++a) {
+      u[a] = m.f(F::U + a, t);
+      if (pd.on) {
+        u[a] = (t == pd.bt && a == pd.ba) ? pd.bound : fmaf(pd.alpha, m.f(F::UE + a, t) - u[a], u[a]);
+        m.f(F::U + a, t) = u[a];
+      }
+    }
+    float xn[NX];
+    Dyn<NX, NU, DI>::ax(pb, x, xn);
+    Dyn<NX, NU, DI>::add_bu(pb, u, xn);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) { x[r] = xn[r]; m.f(F::X + r, t + 1) = xn[r]; }
+  }
+}
+
 // With `fp64_states` the same inputs are also rolled out in FP64 into the
 // refinement scratch (the first step of refine_solution, done here when this
 // pass turns out to be the last one).
 template <int NX, int NU, bool DI>
 __device__ __forceinline__ StepInfo forward_rollout(const Prob &pb, const AgentMem<NX, NU> &m, int T,
-                                                    const float hu[NU], bool fp64_states) {
+                                                    const float hu[NU], bool fp64_states, const PendingStep &pd) {
   using F = Fld<NX, NU>;
   StepInfo si{1.0f, -1, 0, 0.0f, -1};
   float x[NX];
@@ -216,10 +261,17 @@ __device__ __forceinline__ StepInfo forward_rollout(const Prob &pb, const AgentM
     if (fp64_states) m.d(r, 0) = xd[r];
   }
   RollStage<NX, NU> nxt;
-  nxt.load(m, 0);
+  nxt.load(m, 0, pd.on);
   for (int t = 0; t < T; ++t) {
-    const RollStage<NX, NU> cur = nxt;
-    if (t + 1 < T) nxt.load(m, t + 1);
+    RollStage<NX, NU> cur = nxt;
+    if (t + 1 < T) nxt.load(m, t + 1, pd.on);
+    if (pd.on) {   // the previous pass's partial step, at this stage
+#pragma unroll
+      for (int a = 0; a < NU; ++a) {
+        cur.uc[a] = (t == pd.bt && a == pd.ba) ? pd.bound : fmaf(pd.alpha, cur.ueo[a] - cur.uc[a], cur.uc[a]);
+        m.f(F::U + a, t) = cur.uc[a];
+      }
+    }
     float ue[NU];
 #pragma unroll
     for (int a = 0; a < NU; ++a) {
@@ -482,7 +534,7 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
       if (td >= 0) { refactor<NX, NU, DI>(pb, m, qd, hu, T, n_nbr, td); cnt[CT_REFACTOR] += td + 1; td = -1; }
       affine_sweep<NX, NU, DI>(pb, m, T);
       cnt[CT_AFFINE] += T;
-      (void)forward_rollout<NX, NU, DI>(pb, m, T, hu, false);
+      (void)forward_rollout<NX, NU, DI>(pb, m, T, hu, false, PendingStep{false, 0.f, -1, 0, 0.f});
       cnt[CT_PASSES] += 1;
     }
     float x[NX];
@@ -511,30 +563,20 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
   int done = 0;
   bool full = false;   // the last pass took the full step: its EQP solution is in (UE, XE)
   int last_drop = -1, last_side = 0;   // bound released by the previous pass
+  PendingStep pd{false, 0.f, -1, 0, 0.f};
   for (int it = 0; it < cap; ++it) {
     if (!pb.cache) td = T - 1;
     if (td >= 0) { refactor<NX, NU, DI>(pb, m, qd, hu, T, n_nbr, td); cnt[CT_REFACTOR] += td + 1; td = -1; }
     affine_sweep<NX, NU, DI>(pb, m, T);
     cnt[CT_AFFINE] += T;
-    const StepInfo si = forward_rollout<NX, NU, DI>(pb, m, T, hu, refine);
+    const StepInfo si = forward_rollout<NX, NU, DI>(pb, m, T, hu, refine, pd);
+    pd.on = false;
     cnt[CT_PASSES] += 1;
     if (si.blk >= 0) {
-      // blocked: move the fraction alpha toward the EQP solution, fix the bound
-      const float al = fmaxf(si.alpha, 0.f);
-      for (int t = 0; t < T; ++t) {
-#pragma unroll
-        for (int a = 0; a < NU; ++a) {
-          const float u = m.f(F::U + a, t);
-          m.f(F::U + a, t) = fmaf(al, m.f(F::UE + a, t) - u, u);
-        }
-#pragma unroll
-        for (int r = 0; r < NX; ++r) {
-          const float x = m.f(F::X + r, t + 1);
-          m.f(F::X + r, t + 1) = fmaf(al, m.f(F::XE + r, t + 1) - x, x);
-        }
-      }
+      // blocked: move the fraction alpha toward the EQP solution and fix the
+      // bound (the move itself is applied by the next rollout)
       const int bt = si.blk / NU, ba = si.blk % NU;
-      m.f(F::U + ba, bt) = (si.side == 1) ? pb.ulo[ba] : pb.uhi[ba];
+      pd = PendingStep{true, fmaxf(si.alpha, 0.f), bt, ba, (si.side == 1) ? pb.ulo[ba] : pb.uhi[ba]};
       m.w(ba, bt) = (int8_t)si.side;
       td = max(td, bt);
       if (si.blk == last_drop && si.side == last_side) {
@@ -554,8 +596,10 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
       for (int t = 0; t < T; ++t) {
 #pragma unroll
         for (int a = 0; a < NU; ++a) m.f(F::U + a, t) = m.f(F::UE + a, t);
+        if (!drop) {   // the final iterate: its states too
 #pragma unroll
-        for (int r = 0; r < NX; ++r) m.f(F::X + r, t + 1) = m.f(F::XE + r, t + 1);
+          for (int r = 0; r < NX; ++r) m.f(F::X + r, t + 1) = m.f(F::XE + r, t + 1);
+        }
       }
     }
     if (drop) {
@@ -570,6 +614,7 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
     full = true;
     break;
   }
+  if (!full) settle_iterate<NX, NU, DI>(pb, m, T, pd);   // ended on a blocked pass or at the cap
   if (done && refine) {
     if (td >= 0) { refactor<NX, NU, DI>(pb, m, qd, hu, T, n_nbr, td); cnt[CT_REFACTOR] += td + 1; td = -1; }
     if (full) refine_solution<NX, NU, DI, Fld<NX, NU>::UE>(pb, m, qd, hu, T, n_nbr, true);
