@@ -106,8 +106,7 @@ struct Fld {
   static constexpr int KV = PV + pad4(NX);      // affine feedforward k_t         [NU]
   static constexpr int U = KV + pad4(NU);       // current iterate u_t            [NU]
   static constexpr int X = U + pad4(NU);        // current iterate x_t            [NX]
-  static constexpr int XE = X + pad4(NX);       // equality-QP solution x_t       [NX]
-  static constexpr int UE = XE + pad4(NX);      // equality-QP solution u_t       [NU]
+  static constexpr int UE = X + pad4(NX);       // equality-QP solution u_t       [NU]
   static constexpr int XP = UE + pad4(NU);      // C x^k (previous positions)     [DP]
   static constexpr int ZD = XP + pad4(DP);      // sum_j z_ij - n_nbr C x^k       [DP]
   static constexpr int GQP = ZD + pad4(DP);     // -2 Q_t r_t, positions          [DP]

@@ -170,7 +170,7 @@ struct StepInfo {
 };
 
 // Forward rollout u_t = K_t x_t + k_t, x_{t+1} = A x_t + B u_t (Eq. 8) into
-// (UE, XE), with the ratio test against the current inputs and, on stages with
+// (UE, X), with the ratio test against the current inputs and, on stages with
 // fixed inputs, the multipliers from the costates nu_{t+1} = P x + p (Eq. 9):
 // g = H_u u_t + B' nu_{t+1}; mu = g at a lower bound, -g at an upper bound.
 // Stage t+1 is loaded into registers before the stores of stage t.
@@ -285,7 +285,7 @@ __device__ __forceinline__ StepInfo forward_rollout(const Prob &pb, const AgentM
     Dyn<NX, NU, DI>::ax(pb, x, xn);
     Dyn<NX, NU, DI>::add_bu(pb, ue, xn);
 #pragma unroll
-    for (int r = 0; r < NX; ++r) m.f(F::XE + r, t + 1) = xn[r];
+    for (int r = 0; r < NX; ++r) m.f(F::X + r, t + 1) = xn[r];   // the states are read only at the loop's end
     if (fp64_states) {
       double ud[NU], xdn[NX];
 #pragma unroll
@@ -592,14 +592,10 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
     // full step: the EQP solution becomes the iterate (copied unless the
     // refinement below reads it from (UE, XE) and writes the result)
     const bool drop = si.drop >= 0 && si.mu_min < -pb.mu_tol;
-    if (drop || !refine) {
+    if (drop || !refine) {   // (the rollout wrote its states into X already)
       for (int t = 0; t < T; ++t) {
 #pragma unroll
         for (int a = 0; a < NU; ++a) m.f(F::U + a, t) = m.f(F::UE + a, t);
-        if (!drop) {   // the final iterate: its states too
-#pragma unroll
-          for (int r = 0; r < NX; ++r) m.f(F::X + r, t + 1) = m.f(F::XE + r, t + 1);
-        }
       }
     }
     if (drop) {
@@ -881,7 +877,7 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
     if (t == 0) {
       const float *x0 = ws.x0 + (sc.ao + i) * NX;
 #pragma unroll
-      for (int c = 0; c < NX; ++c) { Rg(F::X + c) = x0[c]; Rg(F::XE + c) = x0[c]; }
+      for (int c = 0; c < NX; ++c) Rg(F::X + c) = x0[c];
       ws.adirty[sc.ao + i] = T - 1;
     }
     if (t == T) {
