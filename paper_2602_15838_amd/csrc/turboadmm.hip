@@ -593,9 +593,19 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
     // refinement below reads it from (UE, XE) and writes the result)
     const bool drop = si.drop >= 0 && si.mu_min < -pb.mu_tol;
     if (drop || !refine) {   // (the rollout wrote its states into X already)
-      for (int t = 0; t < T; ++t) {
+      // 8 stages per batch: their loads are all in flight before the stores
+      for (int t0 = 0; t0 < T; t0 += 8) {
+        float ub[8][NU];
 #pragma unroll
-        for (int a = 0; a < NU; ++a) m.f(F::U + a, t) = m.f(F::UE + a, t);
+        for (int q = 0; q < 8; ++q)
+#pragma unroll
+          for (int a = 0; a < NU; ++a) ub[q][a] = (t0 + q < T) ? m.f(F::UE + a, t0 + q) : 0.f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (t0 + q < T) {
+#pragma unroll
+            for (int a = 0; a < NU; ++a) m.f(F::U + a, t0 + q) = ub[q][a];
+          }
       }
     }
     if (drop) {
