@@ -708,17 +708,21 @@ __device__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, i
     }
   };
   const int gbase = (t - 1) * N * N + i;        // + j * N: this lane's ordered copy (i, j)
-  // the partner loop skips j == i; the dual of the next partner is loaded
-  // before the current partner's dual is stored
-  float gnx = 0.f;
-  if (N > 1) gnx = gm[gbase + ((i == 0) ? 1 : 0) * N];
-  for (int jj = 0; jj < N - 1; ++jj) {
-    const int j = jj + (jj >= i);
-    const float gold = gnx;
-    if (jj + 1 < N - 1) {
-      const int jn = jj + 1 + (jj + 1 >= i);
-      gnx = gm[gbase + jn * N];
-    }
+  // the partner loop skips j == i; the duals of the next kPre partners are in
+  // flight while the current one is processed (each is loaded before any
+  // store of this loop to its own word)
+  constexpr int kPre = 4;
+  const int np = N - 1;
+  auto jof = [&](int jj) { return jj + (jj >= i); };
+  float gq[kPre];
+#pragma unroll
+  for (int q = 0; q < kPre; ++q) gq[q] = (q < np) ? gm[gbase + jof(q) * N] : 0.f;
+  for (int jj = 0; jj < np; ++jj) {
+    const int j = jof(jj);
+    const float gold = gq[0];
+#pragma unroll
+    for (int q = 0; q + 1 < kPre; ++q) gq[q] = gq[q + 1];
+    gq[kPre - 1] = (jj + kPre < np) ? gm[gbase + jof(jj + kPre) * N] : 0.f;
     const bool first = i < j;
     const int f = first ? i : j, s = first ? j : i;
     float pj[NU], qj[NU], pf[NU], ps[NU];
