@@ -201,6 +201,20 @@ def test_three_d_first_iterations_sampled():
     gc.compare(p, small, g2, o2)
 
 
+def test_three_d_full_size_lockstep():
+    """The 3-D scale workload at full size (128 agents, T = 50, 8128 pairs x
+    50 steps): the first iterations in lockstep with the oracle, every agent
+    (the warm start alone takes ~190 active-set passes per agent)."""
+    p, scs = synth.config4()
+    K = 3
+    _say(f"3-D config4 full-size lockstep K={K}")
+    g = gc.gpu_solve(p, scs, solver_kw=_zeros_eps(max_iter=K))[0]
+    o = gc.oracle_same_instance(p, scs, gc.oracle_opts(lockstep=K), keep_zl=True, threads=0)[0]
+    assert _lockstep_ok(g, K) and o["iters"] == K
+    rep = gc.compare(p, scs[0], g, o)
+    _say(f"  {rep}")
+
+
 # ---------------------------------------------------------------------------
 # plain == batched, determinism, ablation flags
 # ---------------------------------------------------------------------------
