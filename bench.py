@@ -86,6 +86,7 @@ def parse():
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--profile-steps", action="store_true", help="print one line per step (for profiler runs)")
+    ap.add_argument("--no-scale", action="store_true", help="skip the 3-D single-scenario (128 agents) line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of 256 MiB (the reference for HBM counters)")
     return ap.parse_args()
@@ -218,6 +219,30 @@ def main():
                                          f"over scenarios, {dtc:.1f}s",
                                "agent_qp_solves_per_s": round(float((np.array([s.N for s in sub]) * oit).sum()) / dtc, 1)}
         print(f"# cpu oracle sample {len(ids)} scenarios in {dtc:.1f}s on {th} threads", file=sys.stderr, flush=True)
+
+    if not args.no_scale:
+        # the 3-D scale workload: one scenario of 128 agents, T = 50 (8128 pairs
+        # x 50 steps), through the many-workgroup mode and, for comparison,
+        # the persistent kernel (one workgroup) and the plain host loop
+        p4, sc4 = synth.config4()
+        k4 = synth.pack(p4, sc4)
+        s4 = tadmm.Solver(tadmm.make_params(p4))
+        pr4 = s4.prepare(k4.n_agents, k4.horizon, k4.x0, k4.xref, k4.q_diag, k4.r_diag)
+        scale = {"workload": "1 scenario, 128 agents on a radius-12 Fibonacci sphere to antipodes, 3-D double "
+                             "integrator, T=50, |u|<=3, max_iter=200"}
+        for name, mode in (("wide", tadmm.MODE_WIDE), ("persistent", tadmm.MODE_BATCHED), ("plain", tadmm.MODE_PLAIN)):
+            pr4.run(mode)
+            torch.cuda.synchronize()
+            t4 = time.perf_counter()
+            pr4.run(mode)
+            torch.cuda.synchronize()
+            scale[f"{name}_ms_per_solve"] = round(1e3 * (time.perf_counter() - t4), 2)
+        it4 = int(pr4.o["iters"][0])
+        scale["iterations"] = it4
+        scale["agent_qp_solves_per_s_wide"] = round(128 * it4 / (scale["wide_ms_per_solve"] / 1e3), 1)
+        out["scale_workload"] = scale
+        s4.close()
+        print(f"# 3-D scale workload: {scale}", file=sys.stderr, flush=True)
 
     if args.copy_calibration:
         src = torch.ones(COPY_BYTES // 4, device="cuda")

@@ -84,7 +84,17 @@ typedef enum {
   /* All scenarios in one persistent kernel: workgroups take scenarios from an
    * atomic queue (largest first) and iterate ADMM on the device until each
    * scenario's own stopping test passes; launched through a cached hipGraph. */
-  TADMM_MODE_BATCHED = 1
+  TADMM_MODE_BATCHED = 1,
+  /* Scenarios one after another, every phase spread over many workgroups:
+   * the x-update one lane per agent, the consensus step one lane per
+   * agent-stage (each block staging the positions of its stages in LDS), the
+   * test one wavefront; iterations run in cached hipGraphs of 8 with the
+   * iteration number and scenario index in device memory, launched until the
+   * scenario stops (one 4-byte read-back per launch).  For a few large
+   * scenarios (a single scenario of 128 agents), where one workgroup per
+   * scenario would leave most compute units idle.  Results are bitwise those
+   * of the other modes. */
+  TADMM_MODE_WIDE = 2
 } tadmm_mode;
 
 /* Problem constants and solver options (host struct, passed by pointer and

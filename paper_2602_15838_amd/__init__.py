@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "ok", 1: "invalid argument", 2: "shape error", 3: "non-finite
                 5: "HIP runtime error", 6: "workspace error", 7: "state error"}
 SCEN_CONVERGED, SCEN_MAX_ITER, SCEN_ACTIVE_SET_CAP, SCEN_NONFINITE = 0, 1, 2, 3
 NORMAL_PER_ITER, NORMAL_FROZEN = 0, 1
-MODE_PLAIN, MODE_BATCHED = 0, 1
+MODE_PLAIN, MODE_BATCHED, MODE_WIDE = 0, 1, 2
 
 
 class TadmmError(RuntimeError):

@@ -673,7 +673,7 @@ __device__ __forceinline__ void pair_normal(const Prob &pb, const WS &ws, const 
 
 template <int NX, int NU>
 __device__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, int i, int t,
-                                 const float *__restrict__ lpos, const float *__restrict__ lprev) {
+                                 const float *__restrict__ lpos, const float *__restrict__ lprev, int lofs = 0) {
   using F = Fld<NX, NU>;
   const int N = sc.N;
   float *R = ws.fr + sc.fo;
@@ -694,11 +694,14 @@ __device__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, i
   for (int c = 0; c < NU; ++c) { es[c] = 0.f; zd[c] = 0.f; ls[c] = 0.f; }
   float r2 = 0.f, z2 = 0.f;
   // partner positions (this step and the previous one) from LDS when the
-  // scenario's positions are staged there
+  // scenario's positions (from agent-stage lofs on) are staged there
   auto partner = [&](int j, float pj[NU], float qj[NU]) {
     if (lpos) {
 #pragma unroll
-      for (int c = 0; c < NU; ++c) { pj[c] = lpos[(t * N + j) * NU + c]; qj[c] = lprev[(t * N + j) * NU + c]; }
+      for (int c = 0; c < NU; ++c) {
+        pj[c] = lpos[(t * N + j - lofs) * NU + c];
+        qj[c] = lprev[(t * N + j - lofs) * NU + c];
+      }
     } else {
 #pragma unroll
       for (int c = 0; c < NU; ++c) {
@@ -1073,6 +1076,90 @@ __global__ void k_fill_u64(unsigned long long *p, long long n) {
 }
 
 // ===========================================================================
+// Kernels: one scenario spread over many workgroups (few, large scenarios)
+// ===========================================================================
+// The plain path's phases without its per-iteration host round trip: the
+// scenario index and the iteration number live in device memory (wide[1],
+// wide[0]) so that a captured graph of several iterations serves every
+// scenario of the batch; once a scenario has stopped, the remaining kernels
+// of the graph return at once.
+template <int NX, int NU>
+__global__ __launch_bounds__(256) void k_wide_setup(Prob pb, WS ws, int *wide) {
+  const Scen sc = load_scen(ws, uni(wide[1]));
+  scenario_setup<NX, NU>(pb, ws, sc, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+  if (blockIdx.x == 0 && threadIdx.x < CT_NCOL) ws.cnt[(long long)sc.s * CT_NCOL + threadIdx.x] = 0ull;
+  if (blockIdx.x == 0 && threadIdx.x == 0) wide[0] = 1;
+}
+
+template <int NX, int NU, bool DI>
+__global__ __launch_bounds__(64) void k_wide_x(Prob pb, WS ws, const int *wide) {
+  const int s = uni(wide[1]);
+  int *st = ws.sst + (long long)s * ST_NCOL;
+  if (uni(st[ST_DONE])) return;
+  const Scen sc = load_scen(ws, s);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= sc.N) return;
+  long long cnt[CT_NCOL] = {};
+  if (agent_xupdate<NX, NU, DI>(pb, ws, sc, i, uni(wide[0]), cnt)) atomicOr(st + ST_CAP, 1);
+  add_counters(ws, s, cnt);
+}
+
+// one lane per agent-stage; a block stages the current and previous
+// positions of the stages its agent-stages belong to (every partner of
+// agent-stage (i, t) is at stage t)
+template <int NX, int NU>
+__global__ __launch_bounds__(256) void k_wide_pair(Prob pb, WS ws, const int *wide, int lds_floats) {
+  extern __shared__ float lds_pos[];
+  const int s = uni(wide[1]);
+  const int *st = ws.sst + (long long)s * ST_NCOL;
+  if (uni(st[ST_DONE]) | uni(st[ST_CAP])) return;
+  const Scen sc = load_scen(ws, s);
+  const int N = sc.N, NT = N * sc.T;
+  const int idx0 = blockIdx.x * blockDim.x;
+  if (idx0 >= NT) return;
+  const int idx1 = min(NT, idx0 + (int)blockDim.x);
+  const int g0 = (idx0 / N + 1) * N, g1 = ((idx1 - 1) / N + 2) * N;   // agent-stages of those stages
+  const int ng = g1 - g0;
+  const bool staged = 2 * ng * NU <= lds_floats;
+  float *lds_prev = lds_pos + ng * NU;
+  if (staged) {
+    float *R = ws.fr + sc.fo;
+    const unsigned GS = (unsigned)sc.GS;
+    for (int e = threadIdx.x; e < ng; e += blockDim.x)
+#pragma unroll
+      for (int c = 0; c < NU; ++c) {
+        lds_pos[e * NU + c] = fref(R, GS, (unsigned)(g0 + e), Fld<NX, NU>::X + c);
+        lds_prev[e * NU + c] = fref(R, GS, (unsigned)(g0 + e), Fld<NX, NU>::XP + c);
+      }
+    __syncthreads();
+  }
+  const int idx = idx0 + threadIdx.x;
+  if (idx < idx1)
+    pair_agent_stage<NX, NU>(pb, ws, sc, idx % N, idx / N + 1, staged ? lds_pos : nullptr,
+                             staged ? lds_prev : nullptr, g0);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    long long c[CT_NCOL] = {};
+    c[CT_PAIRS] = (long long)N * (N - 1) / 2 * sc.T;
+    add_counters(ws, s, c);
+  }
+}
+
+template <int NX, int NU>
+__global__ __launch_bounds__(64) void k_wide_test(Prob pb, WS ws, const int *wide) {
+  const int s = uni(wide[1]);
+  const int *st = ws.sst + (long long)s * ST_NCOL;
+  if (uni(st[ST_DONE])) return;
+  const Scen sc = load_scen(ws, s);
+  const int cap = uni(st[ST_CAP]);
+  (void)scenario_test<NX, NU>(pb, ws, sc, uni(wide[0]), threadIdx.x, cap);
+  if (!cap) commit_positions<NX, NU>(ws, sc, threadIdx.x, blockDim.x);
+}
+
+__global__ void k_wide_next(int *wide) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) wide[0] += 1;
+}
+
+// ===========================================================================
 // Input checks and output write-back
 // ===========================================================================
 template <int NX, int NU>
@@ -1163,6 +1250,7 @@ struct Layout {
   size_t o_N = 0, o_T = 0, o_tab = 0, o_order = 0, o_queue = 0, o_sst = 0, o_snorm = 0, o_cnt = 0, o_flags = 0;
   size_t o_adirty = 0, o_fr = 0, o_dr = 0, o_wr = 0, o_gam = 0, o_pact = 0, bytes = 0;
   size_t o_er = 0, o_nrm = 0, o_cidx = 0, o_clist = 0, o_cg = 0, o_m = 0;
+  size_t o_wide = 0;   // wide mode: iteration number, scenario index
   long long sumPT = 0;
   std::vector<long long> tab;
   std::vector<int> order;
@@ -1260,6 +1348,7 @@ bool make_layout(const tadmm_params *p, int S, const int32_t *N, const int32_t *
   L.o_clist = take(sizeof(int2) * (size_t)po);
   L.o_cg = take(sizeof(double) * 6 * (size_t)po);
   L.o_m = take(sizeof(int) * S);
+  L.o_wide = take(sizeof(int) * 64);
   L.bytes = off;
   // launch order for the persistent queue: largest N^2 T first (LPT)
   L.order.resize(S);
@@ -1335,6 +1424,10 @@ struct tadmm_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   GraphKey key{};
+  // wide mode: a setup graph and a graph of kWideChunk iterations
+  hipGraph_t wgraph[2] = {nullptr, nullptr};
+  hipGraphExec_t wexec[2] = {nullptr, nullptr};
+  GraphKey wkey{};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   float last_ms = -1.f;
   // derivative bookkeeping: the last successful solve and its polish
@@ -1494,6 +1587,88 @@ tadmm_status run_batched(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layo
   return TADMM_OK;
 }
 
+constexpr int kWideChunk = 8;   // ADMM iterations per launch of the wide-mode graph
+
+// One scenario at a time, every phase over many workgroups
+// (TADMM_MODE_WIDE): per scenario a setup graph, then a graph of kWideChunk
+// iterations launched until the scenario has stopped (its done flag read back
+// once per launch).
+template <int NX, int NU, bool DI>
+tadmm_status run_wide(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layout &L, const tadmm_batch *b,
+                      const tadmm_out &out, void *ws, size_t bytes) {
+  char *w8 = (char *)ws;
+  int *d_wide = (int *)(w8 + L.o_wide);
+  long long max_n = 1, max_nt = 1, max_work = 1;
+  for (int s = 0; s < L.S; ++s) {
+    const long long n = b->n_agents[s], t = b->horizon[s];
+    max_n = std::max(max_n, n);
+    max_nt = std::max(max_nt, n * t);
+    max_work = std::max(max_work, std::max(n * (t + 1), t * n * n));
+  }
+  const int gx = (int)((max_n + 63) / 64), gp = (int)((max_nt + 255) / 256);
+  const int gsetup = (int)std::min<long long>((max_work + 255) / 256, 4096);
+  // LDS of a pair block: the stages of 256 agent-stages, current and previous positions
+  long long max_ng = 0;
+  for (int s = 0; s < L.S; ++s) {
+    const long long n = b->n_agents[s];
+    max_ng = std::max(max_ng, (256 / n + 2) * n);
+  }
+  const int lds_floats = (int)std::min<long long>(2 * max_ng * NU, 8192);
+  const size_t lds_bytes = sizeof(float) * (size_t)lds_floats;
+  GraphKey key;
+  std::memset(&key, 0, sizeof(key));
+  key.ws = ws; key.out = out; key.x0 = b->x0; key.xref = b->xref; key.qd = b->q_diag; key.rd = b->r_diag;
+  key.normals = b->normals; key.S = L.S; key.threads = gp; key.grid = gx; key.bytes = bytes; key.prm = ctx->prm;
+  if (!(ctx->wexec[0] && key == ctx->wkey)) {
+    for (int q = 0; q < 2; ++q) {
+      if (ctx->wexec[q]) { (void)hipGraphExecDestroy(ctx->wexec[q]); ctx->wexec[q] = nullptr; }
+      if (ctx->wgraph[q]) { (void)hipGraphDestroy(ctx->wgraph[q]); ctx->wgraph[q] = nullptr; }
+    }
+    hipStream_t cs = ctx->cap_stream;
+    for (int q = 0; q < 2; ++q) {
+      HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      if (q == 0) {
+        hipLaunchKernelGGL((k_wide_setup<NX, NU>), dim3(gsetup), dim3(256), 0, cs, pb, w, d_wide);
+      } else {
+        for (int it = 0; it < kWideChunk; ++it) {
+          hipLaunchKernelGGL((k_wide_x<NX, NU, DI>), dim3(gx), dim3(64), 0, cs, pb, w, (const int *)d_wide);
+          hipLaunchKernelGGL((k_wide_pair<NX, NU>), dim3(gp), dim3(256), lds_bytes, cs, pb, w, (const int *)d_wide,
+                             lds_floats);
+          hipLaunchKernelGGL((k_wide_test<NX, NU>), dim3(1), dim3(64), 0, cs, pb, w, (const int *)d_wide);
+          hipLaunchKernelGGL(k_wide_next, dim3(1), dim3(64), 0, cs, d_wide);
+        }
+      }
+      hipError_t le = hipGetLastError();
+      hipError_t ce = hipStreamEndCapture(cs, &ctx->wgraph[q]);
+      if (le != hipSuccess || ce != hipSuccess) {
+        ctx->err = std::string("graph capture failed: ") + hipGetErrorString(le != hipSuccess ? le : ce);
+        return TADMM_ERR_HIP;
+      }
+      HIPCHK(hipGraphInstantiate(&ctx->wexec[q], ctx->wgraph[q], nullptr, nullptr, 0));
+    }
+    ctx->wkey = key;
+  }
+  HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
+  for (int s = 0; s < L.S; ++s) {
+    ctx->h_flags[8] = s;
+    HIPCHK(hipMemcpyAsync(d_wide + 1, ctx->h_flags + 8, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipGraphLaunch(ctx->wexec[0], ctx->stream));
+    for (int done_iters = 0; done_iters < pb.max_iter; done_iters += kWideChunk) {
+      HIPCHK(hipGraphLaunch(ctx->wexec[1], ctx->stream));
+      HIPCHK(hipMemcpyAsync(ctx->h_flags + 9, w.sst + (long long)s * ST_NCOL + ST_DONE, sizeof(int),
+                            hipMemcpyDeviceToHost, ctx->stream));
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      if (ctx->h_flags[9]) break;
+    }
+  }
+  hipLaunchKernelGGL((k_writeback<NX, NU>), dim3(std::min(L.S, 4096)), dim3(256), 0, ctx->stream, w, L.S, out);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventRecord(ctx->ev1, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  HIPCHK(hipEventElapsedTime(&ctx->last_ms, ctx->ev0, ctx->ev1));
+  return TADMM_OK;
+}
+
 template <int NX, int NU, bool DI>
 tadmm_status solve_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *out, void *ws, size_t bytes, int mode) {
   Layout L;
@@ -1517,6 +1692,7 @@ tadmm_status solve_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *o
   }
   if (mode == TADMM_MODE_PLAIN) st = run_plain<NX, NU, DI>(ctx, pb, w, L, b->n_agents, b->horizon, d_flags, *out);
   else if (mode == TADMM_MODE_BATCHED) st = run_batched<NX, NU, DI>(ctx, pb, w, L, b, *out, ws, bytes);
+  else if (mode == TADMM_MODE_WIDE) st = run_wide<NX, NU, DI>(ctx, pb, w, L, b, *out, ws, bytes);
   else return fail(ctx, TADMM_ERR_INVALID_ARG, "unknown mode");
   if (st != TADMM_OK) return st;
   ctx->solved = true;
@@ -1645,6 +1821,10 @@ tadmm_status tadmm_destroy(tadmm_ctx *ctx) {
   if (!ctx) return TADMM_ERR_INVALID_ARG;
   if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
   if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  for (int q = 0; q < 2; ++q) {
+    if (ctx->wexec[q]) (void)hipGraphExecDestroy(ctx->wexec[q]);
+    if (ctx->wgraph[q]) (void)hipGraphDestroy(ctx->wgraph[q]);
+  }
   if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
   if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);

@@ -113,7 +113,7 @@ def test_lockstep_config2_sample():
 # full solves with the stopping rule
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_config0_parity(mode):
     p, scs = synth.config0()
     _say(f"config0 mode={mode}")
@@ -125,7 +125,7 @@ def test_config0_parity(mode):
     _say(f"  {rep} sensitivity={kap}")
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_config1_parity(mode):
     p, scs = synth.config1()
     _say(f"config1 mode={mode}")
@@ -219,17 +219,34 @@ def test_three_d_full_size_lockstep():
 # plain == batched, determinism, ablation flags
 # ---------------------------------------------------------------------------
 
-def test_plain_and_batched_bitwise_equal():
+@pytest.mark.parametrize("mode", [1, 2])
+def test_plain_and_batched_bitwise_equal(mode):
+    """The persistent kernel (1) and the many-workgroup graphs (2) run the
+    plain path's per-scenario arithmetic: identical iterates, bit for bit."""
     p, scs = synth.config2(S=10)
-    _say("plain vs batched bitwise")
+    _say(f"plain vs mode {mode} bitwise")
     a = gc.gpu_solve(p, scs, mode=tadmm.MODE_PLAIN)
-    b = gc.gpu_solve(p, scs, mode=tadmm.MODE_BATCHED)
+    b = gc.gpu_solve(p, scs, mode=mode)
     for ga, gb in zip(a, b):
         assert ga["iters"] == gb["iters"] and ga["status"] == gb["status"]
         np.testing.assert_array_equal(ga["x"], gb["x"])
         np.testing.assert_array_equal(ga["u"], gb["u"])
         np.testing.assert_array_equal(ga["w"], gb["w"])
         np.testing.assert_array_equal(ga["pair_active"], gb["pair_active"])
+        np.testing.assert_array_equal(ga["counters"][:4], gb["counters"][:4])
+
+
+def test_wide_mode_three_d_scale_equals_plain():
+    """The 3-D scale workload (one scenario of 128 agents) through the
+    many-workgroup mode: bitwise the plain path's iterates, 40 iterations."""
+    p, scs = synth.config4()
+    _say("config4 wide vs plain, 40 iterations")
+    kw = dict(max_iter=40)
+    a = gc.gpu_solve(p, scs, mode=tadmm.MODE_PLAIN, solver_kw=kw)[0]
+    b = gc.gpu_solve(p, scs, mode=tadmm.MODE_WIDE, solver_kw=kw)[0]
+    assert a["iters"] == b["iters"] == 40
+    np.testing.assert_array_equal(a["x"], b["x"])
+    np.testing.assert_array_equal(a["pair_active"], b["pair_active"])
 
 
 @pytest.mark.parametrize("threads", [64, 128, 256])
