@@ -55,7 +55,7 @@ struct WS {
   float *fr;                         // float regions
   double *dr;                        // FP64 refinement scratch [NX][N(T+1)] per scenario
   int8_t *wr;                        // working-set regions  [NU][N(T+1)] per scenario
-  int *adirty;                       // [agents] highest stale factor stage (-1: none)
+  int *adirty;                       // [agents][nu] highest stale factor stage of each local QP (-1: none)
   float *gam;                        // [T][N][N] per scenario: gamma of ordered copy (i, j) at [t][j][i]
   uint8_t *pact;                     // [T][N][N] per scenario
   int *sst;                          // [S][ST_NCOL]
@@ -258,7 +258,8 @@ __device__ __forceinline__ void stage_hx(const Prob &pb, const float *qd, int t,
 // in the real type R (FP32 for the ADMM iterations; the equality-QP solves of
 // the adjoint also instantiate it in FP64)
 // ---------------------------------------------------------------------------
-// Given P_{t+1}, the free/fixed pattern of u_t and the bound values ubar:
+// Given P_{t+1}, the free/fixed pattern of u_t and the bound values ubar
+// (lo[a] or hi[a] on a fixed input):
 //   S = H_u + B'P B,  M = B'P A,  S' = S on the free block, identity elsewhere,
 //   Sv = S'^-1 with the fixed rows/columns zeroed (the inverse of S_ff),
 //   K = -Sv M (zero rows on fixed inputs),
@@ -270,8 +271,8 @@ __device__ __forceinline__ void stage_hx(const Prob &pb, const float *qd, int t,
 // since A + B K is the closed loop and -Sv B' the gain of k_t on p_{t+1}.
 template <int NX, int NU, bool DI, class R>
 __device__ __forceinline__ void factor_stage(const Prob &pb, const R hx[NX], const R hu[NU], const R Pn[NX][NX],
-                                             const int8_t wt[NU], bool want_P, R Pt[NX][NX], R K[NU][NX],
-                                             R Sv[NU][NU], R kc[NU], R cc[NX]) {
+                                             const int8_t wt[NU], const float *lo, const float *hi, bool want_P,
+                                             R Pt[NX][NX], R K[NU][NX], R Sv[NU][NU], R kc[NU], R cc[NX]) {
   using D = Dyn<NX, NU, DI>;
   R PB[NX][NU];  // row r of P B is B' (row r of P), P symmetric
 #pragma unroll
@@ -299,7 +300,7 @@ __device__ __forceinline__ void factor_stage(const Prob &pb, const R hx[NX], con
 #pragma unroll
   for (int a = 0; a < NU; ++a) {
     fr[a] = (wt[a] == 0);
-    ub[a] = (wt[a] == 1) ? (R)pb.ulo[a] : ((wt[a] == 2) ? (R)pb.uhi[a] : R(0));
+    ub[a] = (wt[a] == 1) ? (R)lo[a] : ((wt[a] == 2) ? (R)hi[a] : R(0));
   }
   // Cholesky of S' (lower) with reciprocal diagonal
   R L[NU][NU], Li[NU];

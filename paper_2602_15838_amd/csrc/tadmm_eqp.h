@@ -135,7 +135,7 @@ __device__ void eqp_factor(const Prob &pb, const WS &ws, const Scen &sc, R *Er, 
 #pragma unroll
     for (int a = 0; a < NU; ++a) wt[a] = Wb[(unsigned)(t * N + i) * 4u + a];
     R Pt[NX][NX], K[NU][NX], Sv[NU][NU], kc[NU], cc[NX];
-    factor_stage<NX, NU, DI, R>(pb, hx, hu, Pn, wt, t >= 1, Pt, K, Sv, kc, cc);
+    factor_stage<NX, NU, DI, R>(pb, hx, hu, Pn, wt, pb.ulo, pb.uhi, t >= 1, Pt, K, Sv, kc, cc);
     R *f = Er + (size_t)(t * N + i) * EF::NF;
 #pragma unroll
     for (int a = 0; a < NU; ++a) {

@@ -22,69 +22,190 @@
 namespace tadmm {
 
 // ===========================================================================
-// Local QP of one agent (x-update)
+// Local QP (x-update)
 // ===========================================================================
-// Addressing: the scenario region bases are uniform; agent-stage g of agent i
-// at stage t is g = t * N + i, and field f of it is at R[fidx(GS, g, f)]
-// (32-bit offsets; the group base (f / 4) * 4 GS is uniform).
-template <int NX, int NU>
-struct AgentMem {
+// The x-update routines are written against a view V of one local QP: its
+// dimensions (V::NX states, V::NU inputs), its fields at (component, stage),
+// its input bounds, stage weights and working set.  There are two views.
+//
+// AgentView: the QP of agent i, for any dynamics.  Its fields are those of the
+//   agent-stage region: agent-stage g = t * N + i, field f at R[fidx(GS, g, f)]
+//   (32-bit offsets; the group base (f / 4) * 4 GS is uniform).
+//
+// AxisView: coordinate axis c of agent i's QP.  With double-integrator
+//   dynamics the stage costs (diagonal Q, R), the consensus penalty (on the
+//   positions, coordinate by coordinate) and the input box all act per
+//   coordinate, so the local QP separates exactly into dp problems in the
+//   (position, velocity; acceleration) of one axis.  Each one has its own
+//   working set, factors and active-set loop and is solved by one lane; the
+//   minimiser is unique, so together they give the joint QP's solution.  An
+//   axis problem's private fields (factors, affine terms, equality-QP
+//   inputs) live in a region of 16-byte groups over the axis-stages
+//   a = (t * N + i) * dp + c, so consecutive lanes read consecutive groups;
+//   its iterate, linear term, working set and FP64 scratch are the agent's
+//   fields of that axis.
+//
+// V::kBatch stages are loaded per batch in the sweeps: all their loads are
+// issued before the first one is used, so a batch costs about one memory
+// round trip instead of one per stage.
+template <int NX_, int NU_, bool DI_>
+struct AgentView {
+  static constexpr int NX = NX_, NU = NU_, NS = NU_ * (NU_ + 1) / 2, NP = NX_ * (NX_ + 1) / 2;
+  static constexpr bool DI = DI_;
+  static constexpr int kBatch = 2;
+  using F = Fld<NX, NU>;
   float *__restrict__ R;
   int8_t *__restrict__ Wb;
   double *__restrict__ D;
+  int *dirty;                 // highest stage whose factor is stale (-1: none)
+  const float *qd;            // diagonal of Q
   unsigned GS, N, i;
+  float lo[NU], hi[NU], hu[NU];
+  __device__ __forceinline__ AgentView(const Prob &pb, const WS &ws, const Scen &sc, int i_)
+      : R(ws.fr + sc.fo), Wb(ws.wr + sc.bo), D(ws.dr + sc.dof), dirty(ws.adirty + (sc.ao + i_) * NU_),
+        qd(ws.qd + (long long)sc.s * NX), GS((unsigned)sc.GS), N((unsigned)sc.N), i((unsigned)i_) {
+    const float *rd = ws.rd + (long long)sc.s * NU;
+#pragma unroll
+    for (int a = 0; a < NU; ++a) { lo[a] = pb.ulo[a]; hi[a] = pb.uhi[a]; hu[a] = 2.0f * rd[a]; }
+  }
   __device__ __forceinline__ unsigned g(int t) const { return (unsigned)t * N + i; }
   __device__ __forceinline__ float &f(int field, int t) const { return fref(R, GS, g(t), field); }
-  __device__ __forceinline__ int8_t &w(int c, int t) const { return Wb[g(t) * 4u + c]; }
-  __device__ __forceinline__ double &d(int c, int t) const { return D[g(t) * (unsigned)NX + c]; }
+  __device__ __forceinline__ float &K(int a, int c, int t) const { return f(F::K + a * NX + c, t); }
+  __device__ __forceinline__ float &SV(int k, int t) const { return f(F::SV + k, t); }
+  __device__ __forceinline__ float &KC(int a, int t) const { return f(F::KC + a, t); }
+  __device__ __forceinline__ float &CC(int r, int t) const { return f(F::CC + r, t); }
+  __device__ __forceinline__ float &PU(int k, int t) const { return f(F::PU + k, t); }
+  __device__ __forceinline__ float &PV(int r, int t) const { return f(F::PV + r, t); }
+  __device__ __forceinline__ float &KV(int a, int t) const { return f(F::KV + a, t); }
+  __device__ __forceinline__ float &UE(int a, int t) const { return f(F::UE + a, t); }
+  __device__ __forceinline__ float &Q(int r, int t) const { return f(F::Q + r, t); }
+  __device__ __forceinline__ float &X(int r, int t) const { return f(F::X + r, t); }
+  __device__ __forceinline__ float &U(int a, int t) const { return f(F::U + a, t); }
+  __device__ __forceinline__ int8_t &w(int a, int t) const { return Wb[g(t) * 4u + a]; }
+  __device__ __forceinline__ double &d(int r, int t) const { return D[g(t) * (unsigned)NX + r]; }
+  __device__ __forceinline__ void hx(const Prob &pb, int t, int T, int n_nbr, float h[NX]) const {
+    stage_hx<NX, NU>(pb, qd, t, T, n_nbr, h);
+  }
 };
 
-template <int NX, int NU>
-__device__ __forceinline__ void load_sym(const AgentMem<NX, NU> &m, int field, int t, float P[NX][NX]) {
+// Groups of an axis-stage: factor (K_0, K_1, S'^-1, kc), value terms
+// (c_0, c_1, p_0, p_1), affine terms (k, equality-QP input, -, -) and the
+// packed value Hessian (P_00, P_01, P_11, -).
+enum { AXG_FAC = 0, AXG_VAL, AXG_AFF, AXG_P, AXG_N };
+// floats of a scenario's axis-stage region (GS agent-stages, dp axes)
+__host__ __device__ constexpr long long axis_region_floats(long long GS, int dp) { return 4ll * AXG_N * GS * dp; }
+
+template <int NXF, int NUF>
+struct AxisView {
+  static constexpr int NX = 2, NU = 1, NS = 1, NP = 3;
+  static constexpr bool DI = true;
+  static constexpr int kBatch = 4;
+  using F = Fld<NXF, NUF>;
+  float *__restrict__ R;      // agent-stage region
+  float *__restrict__ AX;     // axis-stage region
+  int8_t *__restrict__ Wb;
+  double *__restrict__ D;
+  int *dirty;
+  unsigned GS, N, i, c;
+  float qd[2], lo[1], hi[1], hu[1];
+  __device__ __forceinline__ AxisView(const Prob &pb, const WS &ws, const Scen &sc, int i_, int c_)
+      : R(ws.fr + sc.fo), AX(ws.fr + sc.fo + (long long)Fld<NXF, NUF>::NF * sc.GS), Wb(ws.wr + sc.bo),
+        D(ws.dr + sc.dof), dirty(ws.adirty + (sc.ao + i_) * NUF + c_), GS((unsigned)sc.GS), N((unsigned)sc.N),
+        i((unsigned)i_), c((unsigned)c_) {
+    const float *q = ws.qd + (long long)sc.s * NXF;
+    const float *rd = ws.rd + (long long)sc.s * NUF;
+    qd[0] = q[c];
+    qd[1] = q[NUF + c];
+    hu[0] = 2.0f * rd[c];
+    // the bounds of this axis, selected without indexing the argument arrays
+    float l = pb.ulo[0], h = pb.uhi[0];
 #pragma unroll
-  for (int r = 0; r < NX; ++r)
+    for (int a = 1; a < NUF; ++a)
+      if (c_ == a) { l = pb.ulo[a]; h = pb.uhi[a]; }
+    lo[0] = l;
+    hi[0] = h;
+  }
+  __device__ __forceinline__ unsigned g(int t) const { return (unsigned)t * N + i; }
+  __device__ __forceinline__ unsigned st(int r) const { return r ? NUF + c : c; }   // state index in the agent
+  __device__ __forceinline__ float &ax(int grp, int slot, int t) const {
+    float *base = AX + (size_t)((unsigned)grp * (GS * (unsigned)NUF * 4u));
+    return base[(g(t) * (unsigned)NUF + c) * 4u + (unsigned)slot];
+  }
+  __device__ __forceinline__ float &K(int, int col, int t) const { return ax(AXG_FAC, col, t); }
+  __device__ __forceinline__ float &SV(int, int t) const { return ax(AXG_FAC, 2, t); }
+  __device__ __forceinline__ float &KC(int, int t) const { return ax(AXG_FAC, 3, t); }
+  __device__ __forceinline__ float &CC(int r, int t) const { return ax(AXG_VAL, r, t); }
+  __device__ __forceinline__ float &PV(int r, int t) const { return ax(AXG_VAL, 2 + r, t); }
+  __device__ __forceinline__ float &KV(int, int t) const { return ax(AXG_AFF, 0, t); }
+  __device__ __forceinline__ float &UE(int, int t) const { return ax(AXG_AFF, 1, t); }
+  __device__ __forceinline__ float &PU(int k, int t) const { return ax(AXG_P, k, t); }
+  __device__ __forceinline__ float &Q(int r, int t) const { return fref(R, GS, g(t), F::Q + (int)st(r)); }
+  __device__ __forceinline__ float &X(int r, int t) const { return fref(R, GS, g(t), F::X + (int)st(r)); }
+  __device__ __forceinline__ float &U(int, int t) const { return fref(R, GS, g(t), F::U + (int)c); }
+  __device__ __forceinline__ int8_t &w(int, int t) const { return Wb[g(t) * 4u + c]; }
+  __device__ __forceinline__ double &d(int r, int t) const { return D[g(t) * (unsigned)NXF + st(r)]; }
+  // stage_hx of the axis: 2 w q_pos + rho n_nbr on the position, 2 w q_vel
+  __device__ __forceinline__ void hx(const Prob &pb, int t, int T, int n_nbr, float h[2]) const {
+    const float w = (t == T) ? pb.qT : 1.0f;
+    h[0] = 2.0f * w * qd[0] + pb.rho * (float)n_nbr;
+    h[1] = 2.0f * w * qd[1];
+  }
+};
+
+template <class V>
+__device__ __forceinline__ void load_sym(const V &m, int t, float P[V::NX][V::NX]) {
 #pragma unroll
-    for (int c = r; c < NX; ++c) {
-      const float v = m.f(field + sym_idx<NX>(r, c), t);
+  for (int r = 0; r < V::NX; ++r)
+#pragma unroll
+    for (int c = r; c < V::NX; ++c) {
+      const float v = m.PU(sym_idx<V::NX>(r, c), t);
       P[r][c] = v;
       P[c][r] = v;
     }
 }
 
-// Refactor stages thi..0 for the current working set (Eq. 7 with fixed inputs).
-template <int NX, int NU, bool DI>
-__device__ void refactor(const Prob &pb, const AgentMem<NX, NU> &m, const float *qd, const float hu[NU], int T,
-                         int n_nbr, int thi) {
-  using F = Fld<NX, NU>;
+// Refactor stages thi..0 for the current working set (Eq. 7 with fixed
+// inputs).  The working-set entries of a batch of stages are read at once;
+// the recurrence itself is in registers.
+template <class V>
+__device__ void refactor(const Prob &pb, const V &m, int T, int n_nbr, int thi) {
+  constexpr int NX = V::NX, NU = V::NU, B = V::kBatch;
   float Pn[NX][NX];
-  load_sym<NX, NU>(m, F::PU, thi + 1, Pn);
-  for (int t = thi; t >= 0; --t) {
-    float hx[NX];
-    stage_hx<NX, NU>(pb, qd, t, T, n_nbr, hx);
-    int8_t wt[NU];
+  load_sym(m, thi + 1, Pn);
+  for (int t0 = thi; t0 >= 0; t0 -= B) {
+    int8_t wb[B][NU];
 #pragma unroll
-    for (int a = 0; a < NU; ++a) wt[a] = m.w(a, t);
-    float Pt[NX][NX], K[NU][NX], Sv[NU][NU], kc[NU], cc[NX];
-    factor_stage<NX, NU, DI>(pb, hx, hu, Pn, wt, t >= 1, Pt, K, Sv, kc, cc);
+    for (int q = 0; q < B; ++q)
 #pragma unroll
-    for (int a = 0; a < NU; ++a) {
+      for (int a = 0; a < NU; ++a) wb[q][a] = (t0 - q >= 0) ? m.w(a, t0 - q) : (int8_t)0;
 #pragma unroll
-      for (int c = 0; c < NX; ++c) m.f(F::K + a * NX + c, t) = K[a][c];
+    for (int q = 0; q < B; ++q) {
+      const int t = t0 - q;
+      if (t < 0) break;
+      float hx[NX];
+      m.hx(pb, t, T, n_nbr, hx);
+      float Pt[NX][NX], K[NU][NX], Sv[NU][NU], kc[NU], cc[NX];
+      factor_stage<NX, NU, V::DI>(pb, hx, m.hu, Pn, wb[q], m.lo, m.hi, t >= 1, Pt, K, Sv, kc, cc);
 #pragma unroll
-      for (int b = a; b < NU; ++b) m.f(F::SV + sym_idx<NU>(a, b), t) = Sv[a][b];
-      m.f(F::KC + a, t) = kc[a];
-    }
+      for (int a = 0; a < NU; ++a) {
 #pragma unroll
-    for (int r = 0; r < NX; ++r) m.f(F::CC + r, t) = cc[r];
-    if (t >= 1) {
+        for (int c = 0; c < NX; ++c) m.K(a, c, t) = K[a][c];
 #pragma unroll
-      for (int r = 0; r < NX; ++r)
+        for (int b = a; b < NU; ++b) m.SV(sym_idx<NU>(a, b), t) = Sv[a][b];
+        m.KC(a, t) = kc[a];
+      }
 #pragma unroll
-        for (int c = r; c < NX; ++c) m.f(F::PU + sym_idx<NX>(r, c), t) = Pt[r][c];
+      for (int r = 0; r < NX; ++r) m.CC(r, t) = cc[r];
+      if (t >= 1) {
 #pragma unroll
-      for (int r = 0; r < NX; ++r)
+        for (int r = 0; r < NX; ++r)
 #pragma unroll
-        for (int c = 0; c < NX; ++c) Pn[r][c] = Pt[r][c];
+          for (int c = r; c < NX; ++c) m.PU(sym_idx<NX>(r, c), t) = Pt[r][c];
+#pragma unroll
+        for (int r = 0; r < NX; ++r)
+#pragma unroll
+          for (int c = 0; c < NX; ++c) Pn[r][c] = Pt[r][c];
+      }
     }
   }
 }
@@ -93,67 +214,75 @@ __device__ void refactor(const Prob &pb, const AgentMem<NX, NU> &m, const float 
 //   p_T = q_T;  k_t = kc_t - Sv_t B'p_{t+1};  p_t = q_t + c_t + A'p_{t+1} + K_t' B'p_{t+1},
 // storing k_t for the rollout and p_{t+1} where stage t has a fixed input,
 // with q_t = -2 Q_t r_t - C' sum_j (rho z_ij,t - lambda_ij,t) (QP on positions).
-// The factors of stage t-1 are loaded into registers before the stores of
-// stage t are issued, so the memory latency overlaps the recurrence.
-template <int NX, int NU>
+template <class V>
 struct SweepStage {
-  float K[NU][NX], sv[Fld<NX, NU>::NS], kc[NU], cq[NX];
-  bool fixed;   // the stage has an input in the working set
-  __device__ __forceinline__ void load(const AgentMem<NX, NU> &m, int t) {
-    using F = Fld<NX, NU>;
-    fixed = false;
+  float K[V::NU][V::NX], sv[V::NS], kc[V::NU], q[V::NX], cc[V::NX];
+  int8_t wt[V::NU];
+  __device__ __forceinline__ void load(const V &m, int t) {
 #pragma unroll
-    for (int a = 0; a < NU; ++a) fixed |= (m.w(a, t) != 0);
+    for (int a = 0; a < V::NU; ++a) {
+      wt[a] = m.w(a, t);
 #pragma unroll
-    for (int a = 0; a < NU; ++a) {
-#pragma unroll
-      for (int c = 0; c < NX; ++c) K[a][c] = m.f(F::K + a * NX + c, t);
-      kc[a] = m.f(F::KC + a, t);
+      for (int c = 0; c < V::NX; ++c) K[a][c] = m.K(a, c, t);
+      kc[a] = m.KC(a, t);
     }
 #pragma unroll
-    for (int k = 0; k < F::NS; ++k) sv[k] = m.f(F::SV + k, t);
+    for (int k = 0; k < V::NS; ++k) sv[k] = m.SV(k, t);
 #pragma unroll
-    for (int c = 0; c < NX; ++c) cq[c] = m.f(F::Q + c, t) + m.f(F::CC + c, t);
+    for (int c = 0; c < V::NX; ++c) {
+      q[c] = m.Q(c, t);
+      cc[c] = m.CC(c, t);
+    }
   }
 };
 
-template <int NX, int NU, bool DI>
-__device__ __forceinline__ void affine_sweep(const Prob &pb, const AgentMem<NX, NU> &m, int T) {
-  using F = Fld<NX, NU>;
+template <class V>
+__device__ __forceinline__ void affine_sweep(const Prob &pb, const V &m, int T) {
+  constexpr int NX = V::NX, NU = V::NU, B = V::kBatch;
+  using D = Dyn<NX, NU, V::DI>;
   float p[NX];
 #pragma unroll
-  for (int r = 0; r < NX; ++r) p[r] = m.f(F::Q + r, T);
-  SweepStage<NX, NU> nxt;
-  nxt.load(m, T - 1);
-  for (int t = T - 1; t >= 0; --t) {
-    const SweepStage<NX, NU> cur = nxt;
-    if (t >= 1) nxt.load(m, t - 1);
-    // p_{t+1} is read back only for the costates of a stage with a fixed input
-    if (cur.fixed) {
+  for (int r = 0; r < NX; ++r) p[r] = m.Q(r, T);
+  for (int t0 = T - 1; t0 >= 0; t0 -= B) {
+    SweepStage<V> st[B];
 #pragma unroll
-      for (int r = 0; r < NX; ++r) m.f(F::PV + r, t + 1) = p[r];
-    }
-    float bp[NU];
-    Dyn<NX, NU, DI>::btx(pb, p, bp);
+    for (int q = 0; q < B; ++q)
+      if (t0 - q >= 0) st[q].load(m, t0 - q);
 #pragma unroll
-    for (int a = 0; a < NU; ++a) {
-      float v = cur.kc[a];
+    for (int q = 0; q < B; ++q) {
+      const int t = t0 - q;
+      if (t < 0) break;
+      const SweepStage<V> &cur = st[q];
+      bool fixed = false;
 #pragma unroll
-      for (int b = 0; b < NU; ++b) v = fmaf(-cur.sv[a <= b ? sym_idx<NU>(a, b) : sym_idx<NU>(b, a)], bp[b], v);
-      m.f(F::KV + a, t) = v;
-    }
-    if (t >= 1) {
-      float np[NX];
-      Dyn<NX, NU, DI>::atx(pb, p, np);
+      for (int a = 0; a < NU; ++a) fixed |= (cur.wt[a] != 0);
+      // p_{t+1} is read back only for the costates of a stage with a fixed input
+      if (fixed) {
 #pragma unroll
-      for (int c = 0; c < NX; ++c) {
-        float v = cur.cq[c] + np[c];
-#pragma unroll
-        for (int a = 0; a < NU; ++a) v = fmaf(cur.K[a][c], bp[a], v);
-        np[c] = v;
+        for (int r = 0; r < NX; ++r) m.PV(r, t + 1) = p[r];
       }
+      float bp[NU];
+      D::btx(pb, p, bp);
 #pragma unroll
-      for (int r = 0; r < NX; ++r) p[r] = np[r];
+      for (int a = 0; a < NU; ++a) {
+        float v = cur.kc[a];
+#pragma unroll
+        for (int b = 0; b < NU; ++b) v = fmaf(-cur.sv[a <= b ? sym_idx<NU>(a, b) : sym_idx<NU>(b, a)], bp[b], v);
+        m.KV(a, t) = v;
+      }
+      if (t >= 1) {
+        float np[NX];
+        D::atx(pb, p, np);
+#pragma unroll
+        for (int c = 0; c < NX; ++c) {
+          float v = (cur.q[c] + cur.cc[c]) + np[c];
+#pragma unroll
+          for (int a = 0; a < NU; ++a) v = fmaf(cur.K[a][c], bp[a], v);
+          np[c] = v;
+        }
+#pragma unroll
+        for (int r = 0; r < NX; ++r) p[r] = np[r];
+      }
     }
   }
 }
@@ -173,33 +302,39 @@ struct StepInfo {
 // (UE, X), with the ratio test against the current inputs and, on stages with
 // fixed inputs, the multipliers from the costates nu_{t+1} = P x + p (Eq. 9):
 // g = H_u u_t + B' nu_{t+1}; mu = g at a lower bound, -g at an upper bound.
-// Stage t+1 is loaded into registers before the stores of stage t.
-template <int NX, int NU>
+// A batch first reads the working sets and the per-stage data, then the
+// costate data of its stages with a fixed input.
+template <class V>
 struct RollStage {
-  float K[NU][NX], kv[NU], uc[NU], P[Fld<NX, NU>::NP], pv[NX];
-  float ueo[NU];   // a pending partial step: the previous pass's UE
-  int8_t wt[NU];
-  __device__ __forceinline__ void load(const AgentMem<NX, NU> &m, int t, bool pending) {
-    using F = Fld<NX, NU>;
+  float K[V::NU][V::NX], kv[V::NU], uc[V::NU], P[V::NP], pv[V::NX];
+  float ueo[V::NU];   // a pending partial step: the previous pass's UE
+  int8_t wt[V::NU];
+  __device__ __forceinline__ void load(const V &m, int t, bool pending) {
     if (pending) {
 #pragma unroll
-      for (int a = 0; a < NU; ++a) ueo[a] = m.f(F::UE + a, t);
+      for (int a = 0; a < V::NU; ++a) ueo[a] = m.UE(a, t);
     }
-    bool fixed = false;
 #pragma unroll
-    for (int a = 0; a < NU; ++a) {
+    for (int a = 0; a < V::NU; ++a) {
 #pragma unroll
-      for (int c = 0; c < NX; ++c) K[a][c] = m.f(F::K + a * NX + c, t);
-      kv[a] = m.f(F::KV + a, t);
-      uc[a] = m.f(F::U + a, t);
-      wt[a] = m.w(a, t);
-      fixed |= (wt[a] != 0);
+      for (int c = 0; c < V::NX; ++c) K[a][c] = m.K(a, c, t);
+      kv[a] = m.KV(a, t);
+      uc[a] = m.U(a, t);
     }
-    if (fixed) {   // the costates are needed only where an input is fixed
+  }
+  __device__ __forceinline__ bool fixed() const {
+    bool f = false;
 #pragma unroll
-      for (int k = 0; k < F::NP; ++k) P[k] = m.f(F::PU + k, t + 1);
+    for (int a = 0; a < V::NU; ++a) f |= (wt[a] != 0);
+    return f;
+  }
+  // the costates are needed only where an input is fixed
+  __device__ __forceinline__ void load_costate(const V &m, int t) {
+    if (fixed()) {
 #pragma unroll
-      for (int r = 0; r < NX; ++r) pv[r] = m.f(F::PV + r, t + 1);
+      for (int k = 0; k < V::NP; ++k) P[k] = m.PU(k, t + 1);
+#pragma unroll
+      for (int r = 0; r < V::NX; ++r) pv[r] = m.PV(r, t + 1);
     }
   }
 };
@@ -220,122 +355,151 @@ struct PendingStep {
 
 // The loop ended on a blocked pass (or at its cap): apply a pending step to U
 // and roll the states out from the inputs.
-template <int NX, int NU, bool DI>
-__device__ void settle_iterate(const Prob &pb, const AgentMem<NX, NU> &m, int T, const PendingStep &pd) {
-  using F = Fld<NX, NU>;
+template <class V>
+__device__ void settle_iterate(const Prob &pb, const V &m, int T, const PendingStep &pd) {
+  constexpr int NX = V::NX, NU = V::NU, B = V::kBatch;
+  using D = Dyn<NX, NU, V::DI>;
   float x[NX];
 #pragma unroll
-  for (int r = 0; r < NX; ++r) x[r] = m.f(F::X + r, 0);
-  for (int t = 0; t < T; ++t) {
-    float u[NU];
+  for (int r = 0; r < NX; ++r) x[r] = m.X(r, 0);
+  for (int t0 = 0; t0 < T; t0 += B) {
+    float ub[B][NU], ue[B][NU];
 #pragma unroll
-    for (int a = 0; a < NU; ++a) {
-      u[a] = m.f(F::U + a, t);
-      if (pd.on) {
-        u[a] = (t == pd.bt && a == pd.ba) ? pd.bound : fmaf(pd.alpha, m.f(F::UE + a, t) - u[a], u[a]);
-        m.f(F::U + a, t) = u[a];
+    for (int q = 0; q < B; ++q)
+      if (t0 + q < T) {
+#pragma unroll
+        for (int a = 0; a < NU; ++a) {
+          ub[q][a] = m.U(a, t0 + q);
+          ue[q][a] = pd.on ? m.UE(a, t0 + q) : 0.f;
+        }
       }
-    }
-    float xn[NX];
-    Dyn<NX, NU, DI>::ax(pb, x, xn);
-    Dyn<NX, NU, DI>::add_bu(pb, u, xn);
 #pragma unroll
-    for (int r = 0; r < NX; ++r) { x[r] = xn[r]; m.f(F::X + r, t + 1) = xn[r]; }
+    for (int q = 0; q < B; ++q) {
+      const int t = t0 + q;
+      if (t >= T) break;
+      float u[NU];
+#pragma unroll
+      for (int a = 0; a < NU; ++a) {
+        u[a] = ub[q][a];
+        if (pd.on) {
+          u[a] = (t == pd.bt && a == pd.ba) ? pd.bound : fmaf(pd.alpha, ue[q][a] - u[a], u[a]);
+          m.U(a, t) = u[a];
+        }
+      }
+      float xn[NX];
+      D::ax(pb, x, xn);
+      D::add_bu(pb, u, xn);
+#pragma unroll
+      for (int r = 0; r < NX; ++r) { x[r] = xn[r]; m.X(r, t + 1) = xn[r]; }
+    }
   }
 }
 
 // With `fp64_states` the same inputs are also rolled out in FP64 into the
 // refinement scratch (the first step of refine_solution, done here when this
 // pass turns out to be the last one).
-template <int NX, int NU, bool DI>
-__device__ __forceinline__ StepInfo forward_rollout(const Prob &pb, const AgentMem<NX, NU> &m, int T,
-                                                    const float hu[NU], bool fp64_states, const PendingStep &pd) {
-  using F = Fld<NX, NU>;
+template <class V>
+__device__ __forceinline__ StepInfo forward_rollout(const Prob &pb, const V &m, int T, bool fp64_states,
+                                                    const PendingStep &pd) {
+  constexpr int NX = V::NX, NU = V::NU, B = V::kBatch;
+  using D = Dyn<NX, NU, V::DI>;
   StepInfo si{1.0f, -1, 0, 0.0f, -1};
   float x[NX];
   double xd[NX];
 #pragma unroll
   for (int r = 0; r < NX; ++r) {
-    x[r] = m.f(F::X + r, 0);
+    x[r] = m.X(r, 0);
     xd[r] = (double)x[r];
     if (fp64_states) m.d(r, 0) = xd[r];
   }
-  RollStage<NX, NU> nxt;
-  nxt.load(m, 0, pd.on);
-  for (int t = 0; t < T; ++t) {
-    RollStage<NX, NU> cur = nxt;
-    if (t + 1 < T) nxt.load(m, t + 1, pd.on);
-    if (pd.on) {   // the previous pass's partial step, at this stage
+  for (int t0 = 0; t0 < T; t0 += B) {
+    RollStage<V> st[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q)
+      if (t0 + q < T) {
+#pragma unroll
+        for (int a = 0; a < NU; ++a) st[q].wt[a] = m.w(a, t0 + q);
+      }
+#pragma unroll
+    for (int q = 0; q < B; ++q)
+      if (t0 + q < T) st[q].load(m, t0 + q, pd.on);
+#pragma unroll
+    for (int q = 0; q < B; ++q)
+      if (t0 + q < T) st[q].load_costate(m, t0 + q);
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      const int t = t0 + q;
+      if (t >= T) break;
+      RollStage<V> &cur = st[q];
+      if (pd.on) {   // the previous pass's partial step, at this stage
+#pragma unroll
+        for (int a = 0; a < NU; ++a) {
+          cur.uc[a] = (t == pd.bt && a == pd.ba) ? pd.bound : fmaf(pd.alpha, cur.ueo[a] - cur.uc[a], cur.uc[a]);
+          m.U(a, t) = cur.uc[a];
+        }
+      }
+      float ue[NU];
 #pragma unroll
       for (int a = 0; a < NU; ++a) {
-        cur.uc[a] = (t == pd.bt && a == pd.ba) ? pd.bound : fmaf(pd.alpha, cur.ueo[a] - cur.uc[a], cur.uc[a]);
-        m.f(F::U + a, t) = cur.uc[a];
+        float v = cur.kv[a];
+#pragma unroll
+        for (int c = 0; c < NX; ++c) v = fmaf(cur.K[a][c], x[c], v);
+        ue[a] = v;
+        m.UE(a, t) = v;
       }
-    }
-    float ue[NU];
+      float xn[NX];
+      D::ax(pb, x, xn);
+      D::add_bu(pb, ue, xn);
 #pragma unroll
-    for (int a = 0; a < NU; ++a) {
-      float v = cur.kv[a];
+      for (int r = 0; r < NX; ++r) m.X(r, t + 1) = xn[r];   // the states are read only at the loop's end
+      if (fp64_states) {
+        double ud[NU], xdn[NX];
 #pragma unroll
-      for (int c = 0; c < NX; ++c) v = fmaf(cur.K[a][c], x[c], v);
-      ue[a] = v;
-      m.f(F::UE + a, t) = v;
-    }
-    float xn[NX];
-    Dyn<NX, NU, DI>::ax(pb, x, xn);
-    Dyn<NX, NU, DI>::add_bu(pb, ue, xn);
+        for (int a = 0; a < NU; ++a) ud[a] = (double)ue[a];
+        D::ax(pb, xd, xdn);
+        D::add_bu(pb, ud, xdn);
 #pragma unroll
-    for (int r = 0; r < NX; ++r) m.f(F::X + r, t + 1) = xn[r];   // the states are read only at the loop's end
-    if (fp64_states) {
-      double ud[NU], xdn[NX];
-#pragma unroll
-      for (int a = 0; a < NU; ++a) ud[a] = (double)ue[a];
-      Dyn<NX, NU, DI>::ax(pb, xd, xdn);
-      Dyn<NX, NU, DI>::add_bu(pb, ud, xdn);
-#pragma unroll
-      for (int r = 0; r < NX; ++r) { xd[r] = xdn[r]; m.d(r, t + 1) = xdn[r]; }
-    }
-    bool any = false;
-#pragma unroll
-    for (int a = 0; a < NU; ++a) any |= (cur.wt[a] != 0);
-#pragma unroll
-    for (int a = 0; a < NU; ++a) {
-      if (cur.wt[a] != 0) continue;
-      const float uc = cur.uc[a];
-      if (ue[a] < pb.ulo[a]) {
-        const float r = (uc <= pb.ulo[a]) ? 0.f : (pb.ulo[a] - uc) / (ue[a] - uc);
-        if (r < si.alpha) { si.alpha = r; si.blk = t * NU + a; si.side = 1; }
-      } else if (ue[a] > pb.uhi[a]) {
-        const float r = (uc >= pb.uhi[a]) ? 0.f : (pb.uhi[a] - uc) / (ue[a] - uc);
-        if (r < si.alpha) { si.alpha = r; si.blk = t * NU + a; si.side = 2; }
+        for (int r = 0; r < NX; ++r) { xd[r] = xdn[r]; m.d(r, t + 1) = xdn[r]; }
       }
-    }
-    if (any) {
-      float nu[NX];
-#pragma unroll
-      for (int r = 0; r < NX; ++r) {
-        float v = cur.pv[r];
-#pragma unroll
-        for (int c = 0; c < NX; ++c) v = fmaf(cur.P[r <= c ? sym_idx<NX>(r, c) : sym_idx<NX>(c, r)], xn[c], v);
-        nu[r] = v;
-      }
-      float bn[NU], an[NX], bs[NU];
-      Dyn<NX, NU, DI>::btx(pb, nu, bn);
-#pragma unroll
-      for (int r = 0; r < NX; ++r) an[r] = fabsf(nu[r]);
-      Dyn<NX, NU, DI>::btx(pb, an, bs);   // |B|'|nu| for the general form with nonnegative B
 #pragma unroll
       for (int a = 0; a < NU; ++a) {
-        if (cur.wt[a] == 0) continue;
-        const float g = fmaf(hu[a], ue[a], bn[a]);
-        // a multiplier is trusted to be negative only beyond the FP32
-        // rounding of the terms it is formed from
-        const float mu = ((cur.wt[a] == 1) ? g : -g) + kMuNoise * (fabsf(hu[a] * ue[a]) + fabsf(bs[a]));
-        if (mu < si.mu_min) { si.mu_min = mu; si.drop = t * NU + a; }
+        if (cur.wt[a] != 0) continue;
+        const float uc = cur.uc[a];
+        if (ue[a] < m.lo[a]) {
+          const float r = (uc <= m.lo[a]) ? 0.f : (m.lo[a] - uc) / (ue[a] - uc);
+          if (r < si.alpha) { si.alpha = r; si.blk = t * NU + a; si.side = 1; }
+        } else if (ue[a] > m.hi[a]) {
+          const float r = (uc >= m.hi[a]) ? 0.f : (m.hi[a] - uc) / (ue[a] - uc);
+          if (r < si.alpha) { si.alpha = r; si.blk = t * NU + a; si.side = 2; }
+        }
       }
-    }
+      if (cur.fixed()) {
+        float nu[NX];
 #pragma unroll
-    for (int r = 0; r < NX; ++r) x[r] = xn[r];
+        for (int r = 0; r < NX; ++r) {
+          float v = cur.pv[r];
+#pragma unroll
+          for (int c = 0; c < NX; ++c) v = fmaf(cur.P[r <= c ? sym_idx<NX>(r, c) : sym_idx<NX>(c, r)], xn[c], v);
+          nu[r] = v;
+        }
+        float bn[NU], an[NX], bs[NU];
+        D::btx(pb, nu, bn);
+#pragma unroll
+        for (int r = 0; r < NX; ++r) an[r] = fabsf(nu[r]);
+        D::btx(pb, an, bs);   // |B|'|nu| for the general form with nonnegative B
+#pragma unroll
+        for (int a = 0; a < NU; ++a) {
+          if (cur.wt[a] == 0) continue;
+          const float g = fmaf(m.hu[a], ue[a], bn[a]);
+          // a multiplier is trusted to be negative only beyond the FP32
+          // rounding of the terms it is formed from
+          const float mu = ((cur.wt[a] == 1) ? g : -g) + kMuNoise * (fabsf(m.hu[a] * ue[a]) + fabsf(bs[a]));
+          if (mu < si.mu_min) { si.mu_min = mu; si.drop = t * NU + a; }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < NX; ++r) x[r] = xn[r];
+    }
   }
   return si;
 }
@@ -348,31 +512,30 @@ __device__ __forceinline__ StepInfo forward_rollout(const Prob &pb, const AgentM
 // inputs, homogeneous dynamics) is solved with the cached FP32 factors
 // (k_t = -Sv (B'p + g_t), p_t = A'p + K'(B'p + g_t), p_T = 0) and applied in
 // FP64 before rounding the iterate back to FP32.
-// UI is the field holding the inputs to refine: U, or UE when the last
-// active-set pass took the full step and its EQP solution was not copied
-// (the refined solution is written to U and X either way).  With
+// FROM_UE: the inputs to refine are the equality-QP inputs UE (the last
+// active-set pass took the full step and its EQP solution was not copied),
+// else U (the refined solution is written to U and X either way).  With
 // `states_ready` the FP64 rollout of those inputs is already in the scratch.
-template <int NX, int NU, bool DI, int UI>
-__device__ void refine_solution(const Prob &pb, const AgentMem<NX, NU> &m, const float *qd, const float hu[NU],
-                                int T, int n_nbr, bool states_ready) {
-  using F = Fld<NX, NU>;
-  using D = Dyn<NX, NU, DI>;
-  constexpr int NS = F::NS;
+template <class V, bool FROM_UE>
+__device__ void refine_solution(const Prob &pb, const V &m, int T, int n_nbr, bool states_ready) {
+  constexpr int NX = V::NX, NU = V::NU, NS = V::NS;
+  using D = Dyn<NX, NU, V::DI>;
+  auto uin = [&](int a, int t) -> float { return FROM_UE ? m.UE(a, t) : m.U(a, t); };
   double x[NX];
   if (!states_ready) {
 #pragma unroll
-    for (int r = 0; r < NX; ++r) { x[r] = (double)m.f(F::X + r, 0); m.d(r, 0) = x[r]; }
+    for (int r = 0; r < NX; ++r) { x[r] = (double)m.X(r, 0); m.d(r, 0) = x[r]; }
     // (1) exact rollout of the stored inputs
     float un[NU];
 #pragma unroll
-    for (int a = 0; a < NU; ++a) un[a] = m.f(UI + a, 0);
+    for (int a = 0; a < NU; ++a) un[a] = uin(a, 0);
     for (int t = 0; t < T; ++t) {
       double u[NU], xn[NX];
 #pragma unroll
       for (int a = 0; a < NU; ++a) u[a] = (double)un[a];
       if (t + 1 < T) {
 #pragma unroll
-        for (int a = 0; a < NU; ++a) un[a] = m.f(UI + a, t + 1);
+        for (int a = 0; a < NU; ++a) un[a] = uin(a, t + 1);
       }
       D::ax(pb, x, xn);
       D::add_bu(pb, u, xn);
@@ -384,10 +547,9 @@ __device__ void refine_solution(const Prob &pb, const AgentMem<NX, NU> &m, const
   double nu[NX];
   {
     float hx[NX];
-    stage_hx<NX, NU>(pb, qd, T, T, n_nbr, hx);
+    m.hx(pb, T, T, n_nbr, hx);
 #pragma unroll
-    for (int r = 0; r < NX; ++r)
-      nu[r] = fma((double)hx[r], m.d(r, T), (double)m.f(F::Q + r, T));
+    for (int r = 0; r < NX; ++r) nu[r] = fma((double)hx[r], m.d(r, T), (double)m.Q(r, T));
   }
   float pc[NX];
 #pragma unroll
@@ -400,16 +562,16 @@ __device__ void refine_solution(const Prob &pb, const AgentMem<NX, NU> &m, const
   auto bload = [&](BStage &st, int t) {
 #pragma unroll
     for (int a = 0; a < NU; ++a) {
-      st.u[a] = m.f(UI + a, t);
+      st.u[a] = uin(a, t);
       st.wt[a] = m.w(a, t);
 #pragma unroll
-      for (int c = 0; c < NX; ++c) st.K[a][c] = m.f(F::K + a * NX + c, t);
+      for (int c = 0; c < NX; ++c) st.K[a][c] = m.K(a, c, t);
     }
 #pragma unroll
-    for (int k = 0; k < NS; ++k) st.sv[k] = m.f(F::SV + k, t);
+    for (int k = 0; k < NS; ++k) st.sv[k] = m.SV(k, t);
 #pragma unroll
     for (int c = 0; c < NX; ++c) {
-      st.q[c] = m.f(F::Q + c, t);
+      st.q[c] = m.Q(c, t);
       st.xd[c] = m.d(c, t);
     }
   };
@@ -424,7 +586,7 @@ __device__ void refine_solution(const Prob &pb, const AgentMem<NX, NU> &m, const
     D::btx(pb, pc, bpc);
 #pragma unroll
     for (int a = 0; a < NU; ++a) {
-      const double g = fma((double)hu[a], (double)cur.u[a], bnu[a]);
+      const double g = fma((double)m.hu[a], (double)cur.u[a], bnu[a]);
       sg[a] = ((cur.wt[a] == 0) ? (float)g : 0.f) + bpc[a];
     }
 #pragma unroll
@@ -432,11 +594,11 @@ __device__ void refine_solution(const Prob &pb, const AgentMem<NX, NU> &m, const
       float v = 0.f;
 #pragma unroll
       for (int b = 0; b < NU; ++b) v = fmaf(-cur.sv[a <= b ? sym_idx<NU>(a, b) : sym_idx<NU>(b, a)], sg[b], v);
-      m.f(F::KV + a, t) = v;
+      m.KV(a, t) = v;
     }
     if (t >= 1) {
       float hx[NX];
-      stage_hx<NX, NU>(pb, qd, t, T, n_nbr, hx);
+      m.hx(pb, t, T, n_nbr, hx);
       float np[NX];
       double nn[NX];
       D::atx(pb, pc, np);
@@ -461,10 +623,10 @@ __device__ void refine_solution(const Prob &pb, const AgentMem<NX, NU> &m, const
   auto fload = [&](FStage &st, int t) {
 #pragma unroll
     for (int a = 0; a < NU; ++a) {
-      st.kv[a] = m.f(F::KV + a, t);
-      st.u[a] = m.f(UI + a, t);
+      st.kv[a] = m.KV(a, t);
+      st.u[a] = uin(a, t);
 #pragma unroll
-      for (int c = 0; c < NX; ++c) st.K[a][c] = m.f(F::K + a * NX + c, t);
+      for (int c = 0; c < NX; ++c) st.K[a][c] = m.K(a, c, t);
     }
   };
   FStage fn;
@@ -482,9 +644,9 @@ __device__ void refine_solution(const Prob &pb, const AgentMem<NX, NU> &m, const
       du[a] = v;
       // a free input refined past its bound by a rounding-level amount is
       // put back on the bound, so that the next active-set start is feasible
-      uf[a] = fminf(fmaxf((float)((double)cur.u[a] + (double)v), pb.ulo[a]), pb.uhi[a]);
+      uf[a] = fminf(fmaxf((float)((double)cur.u[a] + (double)v), m.lo[a]), m.hi[a]);
       ud[a] = (double)uf[a];
-      m.f(F::U + a, t) = uf[a];
+      m.U(a, t) = uf[a];
     }
     float dxn[NX];
     double xn[NX];
@@ -496,26 +658,22 @@ __device__ void refine_solution(const Prob &pb, const AgentMem<NX, NU> &m, const
     for (int r = 0; r < NX; ++r) {
       dx[r] = dxn[r];
       x[r] = xn[r];
-      m.f(F::X + r, t + 1) = (float)xn[r];
+      m.X(r, t + 1) = (float)xn[r];
     }
   }
 }
 
-// One agent's x-update at ADMM iteration k.  Returns 1 if the active-set
-// loop hit its cap.  cnt[] accumulates pass / stage counters.
-template <int NX, int NU, bool DI>
-__device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i, int k, long long cnt[CT_NCOL]) {
-  using F = Fld<NX, NU>;
+// One local QP's x-update at ADMM iteration k.  Returns 1 if the active-set
+// loop hit its cap.  cnt[] accumulates pass / stage counters (in units of the
+// view's stages: agent-stages or axis-stages).
+template <class V>
+__device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, const V &m, int k,
+                             long long cnt[CT_NCOL]) {
+  constexpr int NX = V::NX, NU = V::NU;
+  using D = Dyn<NX, NU, V::DI>;
   const int T = sc.T;
-  const AgentMem<NX, NU> m{ws.fr + sc.fo, ws.wr + sc.bo, ws.dr + sc.dof, (unsigned)sc.GS, (unsigned)sc.N,
-                           (unsigned)i};
-  const float *qd = ws.qd + (long long)sc.s * NX;
-  const float *rd = ws.rd + (long long)sc.s * NU;
-  float hu[NU];
-#pragma unroll
-  for (int a = 0; a < NU; ++a) hu[a] = 2.0f * rd[a];
   const int n_nbr = sc.N - 1;
-  int td = ws.adirty[sc.ao + i];
+  int td = *m.dirty;
   const int cap = pb.max_as > 0 ? pb.max_as : 10 * T * NU;
   // the FP64-residual refinement, every iteration or once the residuals of
   // the last test are within refine_band of their tolerances (before that the
@@ -531,52 +689,67 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
     if (pb.warm) {
       // ... from the unconstrained affine LQ solution (Sec. IV-B), clipped
       if (!pb.cache) td = T - 1;
-      if (td >= 0) { refactor<NX, NU, DI>(pb, m, qd, hu, T, n_nbr, td); cnt[CT_REFACTOR] += td + 1; td = -1; }
-      affine_sweep<NX, NU, DI>(pb, m, T);
+      if (td >= 0) { refactor(pb, m, T, n_nbr, td); cnt[CT_REFACTOR] += td + 1; td = -1; }
+      affine_sweep(pb, m, T);
       cnt[CT_AFFINE] += T;
-      (void)forward_rollout<NX, NU, DI>(pb, m, T, hu, false, PendingStep{false, 0.f, -1, 0, 0.f});
+      (void)forward_rollout(pb, m, T, false, PendingStep{false, 0.f, -1, 0, 0.f});
       cnt[CT_PASSES] += 1;
     }
     float x[NX];
 #pragma unroll
-    for (int r = 0; r < NX; ++r) x[r] = m.f(F::X + r, 0);
-    for (int t = 0; t < T; ++t) {
-      float ust[NU];
+    for (int r = 0; r < NX; ++r) x[r] = m.X(r, 0);
+    constexpr int B = V::kBatch;
+    for (int t0 = 0; t0 < T; t0 += B) {
+      float ub[B][NU];
 #pragma unroll
-      for (int a = 0; a < NU; ++a) {
-        float u = pb.warm ? m.f(F::UE + a, t) : 0.f;
-        int8_t s = 0;
-        if (u < pb.ulo[a]) { u = pb.ulo[a]; s = 1; }
-        else if (u > pb.uhi[a]) { u = pb.uhi[a]; s = 2; }
-        if (s) { m.w(a, t) = s; td = max(td, t); }
-        ust[a] = u;
-        m.f(F::U + a, t) = u;
+      for (int q = 0; q < B; ++q)
+#pragma unroll
+        for (int a = 0; a < NU; ++a) ub[q][a] = (pb.warm && t0 + q < T) ? m.UE(a, t0 + q) : 0.f;
+#pragma unroll
+      for (int q = 0; q < B; ++q) {
+        const int t = t0 + q;
+        if (t >= T) break;
+        float ust[NU];
+#pragma unroll
+        for (int a = 0; a < NU; ++a) {
+          float u = ub[q][a];
+          int8_t s = 0;
+          if (u < m.lo[a]) { u = m.lo[a]; s = 1; }
+          else if (u > m.hi[a]) { u = m.hi[a]; s = 2; }
+          if (s) { m.w(a, t) = s; td = max(td, t); }
+          ust[a] = u;
+          m.U(a, t) = u;
+        }
+        float xn[NX];
+        D::ax(pb, x, xn);
+        D::add_bu(pb, ust, xn);
+#pragma unroll
+        for (int r = 0; r < NX; ++r) { x[r] = xn[r]; m.X(r, t + 1) = xn[r]; }
       }
-      float xn[NX];
-      Dyn<NX, NU, DI>::ax(pb, x, xn);
-      Dyn<NX, NU, DI>::add_bu(pb, ust, xn);
-#pragma unroll
-      for (int r = 0; r < NX; ++r) { x[r] = xn[r]; m.f(F::X + r, t + 1) = xn[r]; }
     }
   }
 
   int done = 0;
-  bool full = false;   // the last pass took the full step: its EQP solution is in (UE, XE)
+  bool full = false;   // the last pass took the full step: its EQP solution is in (UE, X)
   int last_drop = -1, last_side = 0;   // bound released by the previous pass
   PendingStep pd{false, 0.f, -1, 0, 0.f};
   for (int it = 0; it < cap; ++it) {
     if (!pb.cache) td = T - 1;
-    if (td >= 0) { refactor<NX, NU, DI>(pb, m, qd, hu, T, n_nbr, td); cnt[CT_REFACTOR] += td + 1; td = -1; }
-    affine_sweep<NX, NU, DI>(pb, m, T);
+    if (td >= 0) { refactor(pb, m, T, n_nbr, td); cnt[CT_REFACTOR] += td + 1; td = -1; }
+    affine_sweep(pb, m, T);
     cnt[CT_AFFINE] += T;
-    const StepInfo si = forward_rollout<NX, NU, DI>(pb, m, T, hu, refine, pd);
+    const StepInfo si = forward_rollout(pb, m, T, refine, pd);
     pd.on = false;
     cnt[CT_PASSES] += 1;
     if (si.blk >= 0) {
       // blocked: move the fraction alpha toward the EQP solution and fix the
       // bound (the move itself is applied by the next rollout)
       const int bt = si.blk / NU, ba = si.blk % NU;
-      pd = PendingStep{true, fmaxf(si.alpha, 0.f), bt, ba, (si.side == 1) ? pb.ulo[ba] : pb.uhi[ba]};
+      float bnd = 0.f;   // the bound, selected without indexing the bound arrays
+#pragma unroll
+      for (int a = 0; a < NU; ++a)
+        if (a == ba) bnd = (si.side == 1) ? m.lo[a] : m.hi[a];
+      pd = PendingStep{true, fmaxf(si.alpha, 0.f), bt, ba, bnd};
       m.w(ba, bt) = (int8_t)si.side;
       td = max(td, bt);
       if (si.blk == last_drop && si.side == last_side) {
@@ -590,7 +763,7 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
       continue;
     }
     // full step: the EQP solution becomes the iterate (copied unless the
-    // refinement below reads it from (UE, XE) and writes the result)
+    // refinement below reads it from (UE, X) and writes the result)
     const bool drop = si.drop >= 0 && si.mu_min < -pb.mu_tol;
     if (drop || !refine) {   // (the rollout wrote its states into X already)
       // 8 stages per batch: their loads are all in flight before the stores
@@ -599,12 +772,12 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
 #pragma unroll
         for (int q = 0; q < 8; ++q)
 #pragma unroll
-          for (int a = 0; a < NU; ++a) ub[q][a] = (t0 + q < T) ? m.f(F::UE + a, t0 + q) : 0.f;
+          for (int a = 0; a < NU; ++a) ub[q][a] = (t0 + q < T) ? m.UE(a, t0 + q) : 0.f;
 #pragma unroll
         for (int q = 0; q < 8; ++q)
           if (t0 + q < T) {
 #pragma unroll
-            for (int a = 0; a < NU; ++a) m.f(F::U + a, t0 + q) = ub[q][a];
+            for (int a = 0; a < NU; ++a) m.U(a, t0 + q) = ub[q][a];
           }
       }
     }
@@ -620,15 +793,32 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int i
     full = true;
     break;
   }
-  if (!full) settle_iterate<NX, NU, DI>(pb, m, T, pd);   // ended on a blocked pass or at the cap
+  if (!full) settle_iterate(pb, m, T, pd);   // ended on a blocked pass or at the cap
   if (done && refine) {
-    if (td >= 0) { refactor<NX, NU, DI>(pb, m, qd, hu, T, n_nbr, td); cnt[CT_REFACTOR] += td + 1; td = -1; }
-    if (full) refine_solution<NX, NU, DI, Fld<NX, NU>::UE>(pb, m, qd, hu, T, n_nbr, true);
-    else refine_solution<NX, NU, DI, Fld<NX, NU>::U>(pb, m, qd, hu, T, n_nbr, false);
+    if (td >= 0) { refactor(pb, m, T, n_nbr, td); cnt[CT_REFACTOR] += td + 1; td = -1; }
+    if (full) refine_solution<V, true>(pb, m, T, n_nbr, true);
+    else refine_solution<V, false>(pb, m, T, n_nbr, false);
     cnt[CT_AFFINE] += 2 * T;
   }
-  ws.adirty[sc.ao + i] = td;
+  *m.dirty = td;
   return done ? 0 : 1;
+}
+
+// Lanes of a scenario's x-update: one per agent, or, with the separable
+// double-integrator QP, one per (agent, axis), agents outer.
+template <int NX, int NU, bool DI>
+__host__ __device__ constexpr int xupdate_lanes(int N) { return DI ? N * NU : N; }
+
+template <int NX, int NU, bool DI>
+__device__ __forceinline__ int local_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int l, int k,
+                                             long long cnt[CT_NCOL]) {
+  if constexpr (DI) {
+    const AxisView<NX, NU> m(pb, ws, sc, l / NU, l % NU);
+    return agent_xupdate(pb, ws, sc, m, k, cnt);
+  } else {
+    const AgentView<NX, NU, false> m(pb, ws, sc, l);
+    return agent_xupdate(pb, ws, sc, m, k, cnt);
+  }
 }
 
 // ===========================================================================
@@ -895,7 +1085,8 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
       const float *x0 = ws.x0 + (sc.ao + i) * NX;
 #pragma unroll
       for (int c = 0; c < NX; ++c) Rg(F::X + c) = x0[c];
-      ws.adirty[sc.ao + i] = T - 1;
+#pragma unroll
+      for (int c = 0; c < NU; ++c) ws.adirty[(sc.ao + i) * NU + c] = T - 1;
     }
     if (t == T) {
       float hx[NX];
@@ -904,6 +1095,15 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
       for (int r2 = 0; r2 < NX; ++r2)
 #pragma unroll
         for (int c = r2; c < NX; ++c) Rg(F::PU + sym_idx<NX>(r2, c)) = (r2 == c) ? hx[r2] : 0.f;
+      // and of each axis problem (the axis-stage region follows the fields)
+      float *AP = R + (size_t)F::NF * GS + (size_t)AXG_P * GS * NU * 4;
+#pragma unroll
+      for (int c = 0; c < NU; ++c) {
+        float *e = AP + ((size_t)idx * NU + c) * 4;
+        e[0] = hx[c];
+        e[1] = 0.f;
+        e[2] = hx[NU + c];
+      }
     }
   }
   const int LS = T * N * N;
@@ -944,10 +1144,10 @@ __global__ __launch_bounds__(256) void k_setup(Prob pb, WS ws, int s) {
 template <int NX, int NU, bool DI>
 __global__ __launch_bounds__(64) void k_xupdate(Prob pb, WS ws, int s, int k) {
   const Scen sc = load_scen(ws, s);
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= sc.N) return;
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= xupdate_lanes<NX, NU, DI>(sc.N)) return;
   long long cnt[CT_NCOL] = {};
-  const int capped = agent_xupdate<NX, NU, DI>(pb, ws, sc, i, k, cnt);
+  const int capped = local_xupdate<NX, NU, DI>(pb, ws, sc, l, k, cnt);
   if (capped) atomicOr(ws.sst + (long long)s * ST_NCOL + ST_CAP, 1);
   add_counters(ws, s, cnt);
 }
@@ -1003,8 +1203,8 @@ __device__ __forceinline__ void persistent_body(Prob pb, WS ws, int S, int lds_f
     __syncthreads();
     for (int k = 1; k <= pb.max_iter; ++k) {
       const unsigned long long c0 = wall_clock64();
-      for (int i = tid; i < sc.N; i += nt)
-        if (agent_xupdate<NX, NU, DI>(pb, ws, sc, i, k, cnt)) atomicOr(&s_cap, 1);
+      for (int l = tid; l < xupdate_lanes<NX, NU, DI>(sc.N); l += nt)
+        if (local_xupdate<NX, NU, DI>(pb, ws, sc, l, k, cnt)) atomicOr(&s_cap, 1);
       __syncthreads();
       const unsigned long long c1 = wall_clock64();
       const int cap = s_cap;
@@ -1097,10 +1297,10 @@ __global__ __launch_bounds__(64) void k_wide_x(Prob pb, WS ws, const int *wide) 
   int *st = ws.sst + (long long)s * ST_NCOL;
   if (uni(st[ST_DONE])) return;
   const Scen sc = load_scen(ws, s);
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= sc.N) return;
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= xupdate_lanes<NX, NU, DI>(sc.N)) return;
   long long cnt[CT_NCOL] = {};
-  if (agent_xupdate<NX, NU, DI>(pb, ws, sc, i, uni(wide[0]), cnt)) atomicOr(st + ST_CAP, 1);
+  if (local_xupdate<NX, NU, DI>(pb, ws, sc, l, uni(wide[0]), cnt)) atomicOr(st + ST_CAP, 1);
   add_counters(ws, s, cnt);
 }
 
@@ -1305,14 +1505,15 @@ bool make_layout(const tadmm_params *p, int S, const int32_t *N, const int32_t *
     if (n < 1 || t < 1) { err = "every scenario needs N >= 1 and T >= 1"; return false; }
     if (n > 4096 || t > 65536) { err = "scenario too large (N <= 4096, T <= 65536)"; return false; }
     const long long GS = n * (t + 1);
-    if ((long long)L.NF * GS >= (1ll << 31) || (long long)p->nu * t * n * n >= (1ll << 31) ||
+    if ((long long)L.NF * GS + axis_region_floats(GS, p->nu) >= (1ll << 31) ||
+        (long long)p->nu * t * n * n >= (1ll << 31) ||
         (long long)p->nx * GS >= (1ll << 31)) {
       err = "scenario too large for 32-bit in-scenario offsets"; return false;
     }
     long long *tb = &L.tab[(size_t)s * TB_NCOL];
     tb[TB_F] = fo; tb[TB_B] = bo; tb[TB_L] = lo; tb[TB_A] = ao; tb[TB_XO] = xo; tb[TB_UO] = uo; tb[TB_PO] = po; tb[TB_LB] = lb;
     tb[TB_D] = dof;
-    fo += (long long)L.NF * GS;
+    fo += (long long)L.NF * GS + axis_region_floats(GS, p->nu);
     dof += (long long)p->nx * GS;
     bo += 4ll * GS;
     lo += t * n * n;
@@ -1334,7 +1535,7 @@ bool make_layout(const tadmm_params *p, int S, const int32_t *N, const int32_t *
   L.o_snorm = take(sizeof(float) * S * SN_NCOL);
   L.o_cnt = take(sizeof(unsigned long long) * S * CT_NCOL);
   L.o_flags = take(sizeof(int) * 64);
-  L.o_adirty = take(sizeof(int) * (size_t)ao);
+  L.o_adirty = take(sizeof(int) * (size_t)ao * (size_t)p->nu);
   L.o_fr = take(sizeof(float) * (size_t)fo);
   L.o_dr = take(sizeof(double) * (size_t)dof);
   L.o_wr = take((size_t)bo);
@@ -1514,7 +1715,8 @@ tadmm_status run_plain(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layout
     const int gsetup = (int)std::min<long long>((work + 255) / 256, 4096);
     hipLaunchKernelGGL((k_setup<NX, NU>), dim3(gsetup), dim3(256), 0, ctx->stream, pb, w, s);
     for (int k = 1; k <= pb.max_iter; ++k) {
-      hipLaunchKernelGGL((k_xupdate<NX, NU, DI>), dim3((n + 63) / 64), dim3(64), 0, ctx->stream, pb, w, s, k);
+      hipLaunchKernelGGL((k_xupdate<NX, NU, DI>), dim3((xupdate_lanes<NX, NU, DI>(n) + 63) / 64), dim3(64), 0,
+                         ctx->stream, pb, w, s, k);
       hipLaunchKernelGGL((k_pair<NX, NU>), dim3((n * t + 255) / 256), dim3(256), 0, ctx->stream, pb, w, s);
       hipLaunchKernelGGL((k_resid<NX, NU>), dim3(1), dim3(64), 0, ctx->stream, pb, w, s, k, d_flags + 2);
       HIPCHK(hipGetLastError());
@@ -1605,7 +1807,7 @@ tadmm_status run_wide(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layout 
     max_nt = std::max(max_nt, n * t);
     max_work = std::max(max_work, std::max(n * (t + 1), t * n * n));
   }
-  const int gx = (int)((max_n + 63) / 64), gp = (int)((max_nt + 255) / 256);
+  const int gx = (int)((xupdate_lanes<NX, NU, DI>((int)max_n) + 63) / 64), gp = (int)((max_nt + 255) / 256);
   const int gsetup = (int)std::min<long long>((max_work + 255) / 256, 4096);
   // LDS of a pair block: the stages of 256 agent-stages, current and previous positions
   long long max_ng = 0;
