@@ -24,17 +24,23 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work per unit, counted from the operations the method must
-# perform (2-D double integrator; 3-D in parentheses):
-#   affine agent-stage pass (backward affine sweep + forward rollout + ratio
-#   test + costate/multiplier on fixed inputs):   190 (380) FP32 flops
-#   refactored agent-stage (Riccati factor with a working set): 520 (1400)
-#   pair-step (consensus projection + dual update + residual pieces): 40 (55)
-# and the bytes it must move when the per-stage factors stream from HBM:
-#   agent-stage pass (affine or refactor): 152 (324) B; pair-step: 8 B (the
-#   collapsed dual gamma read and written).
-FLOPS_PER_UNIT = {2: dict(affine=190.0, refactor=520.0, pair=40.0), 3: dict(affine=380.0, refactor=1400.0, pair=55.0)}
-BYTES_PER_UNIT = {2: dict(affine=152.0, refactor=152.0, pair=8.0), 3: dict(affine=324.0, refactor=324.0, pair=8.0)}
+# Algorithmic work per unit.  With double-integrator dynamics (every workload
+# here) each local QP separates into one problem per coordinate axis, solved
+# by its own lane, and the kernel's counters count axis-stages: one axis of
+# one agent at one stage (2 per agent-stage in 2-D, 3 in 3-D).  Per unit,
+# from the operations the per-axis solve must perform and the bytes it must
+# move when the per-stage data stream from HBM:
+#   affine axis-stage pass: sweep (k = kc - Sv B'p, p = q + c + A'p + K'B'p)
+#   15 flops, reads K, Sv, kc (16 B), c (8 B), q (8 B), W (1 B), writes k
+#   (4 B); rollout (u = K x + k, x' = A x + B u, ratio test) 12 flops, reads
+#   W (1 B), K (8 B), k and u (8 B), writes the equality-QP input (4 B) and
+#   the states (8 B): 27 flops, 66 B (costates on fixed stages not counted);
+#   refactored axis-stage (2x2 Riccati step with a scalar input): 42 flops,
+#   37 B (reads W, writes K, Sv, kc, c and P);
+#   pair-step (consensus projection + dual update + residual pieces): 40 (55
+#   in 3-D) flops, 8 B (the collapsed dual gamma read and written).
+FLOPS_PER_UNIT = {2: dict(affine=27.0, refactor=42.0, pair=40.0), 3: dict(affine=27.0, refactor=42.0, pair=55.0)}
+BYTES_PER_UNIT = {2: dict(affine=66.0, refactor=37.0, pair=8.0), 3: dict(affine=66.0, refactor=37.0, pair=8.0)}
 PEAK_HBM_GBS = 8000.0             # MI355X HBM3E
 PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector (packed) peak
 PEAK_FP32_UNPACKED_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
@@ -138,7 +144,7 @@ def main():
     agent_qp_per_s = agent_qp / (ms_step / 1e3)
 
     # roofline of the persistent kernel (HIP events around its graph launch on
-    # the context's stream).  At ~1.9 algorithmic flop/B it sits below the
+    # the context's stream).  Below 1 algorithmic flop/B it sits far below the
     # FP32 ridge (157.3 TF / 8 TB/s = 19.7 flop/B): HBM is the bound.
     kernel_ms = float(np.mean(kms))
     fu, bu = FLOPS_PER_UNIT[problem.dp], BYTES_PER_UNIT[problem.dp]
@@ -169,7 +175,8 @@ def main():
            "converged_fraction": round(float((status == 0).mean()), 4),
            "status_counts": {str(k): int((status == k).sum()) for k in range(4)},
            "mean_iters": round(float(iters.mean()), 2),
-           "active_set_passes_per_agent_qp": round(float(cnt[:, 0].sum()) / max(agent_qp, 1.0), 4),
+           # passes of the per-axis problems, per axis problem solved
+           "active_set_passes_per_axis_qp": round(float(cnt[:, 0].sum()) / max(agent_qp * problem.dp, 1.0), 4),
            "phase_time_split": {k: round(float(cnt[:, c].sum()) / max(float(cnt[:, 4:7].sum()), 1.0), 4)
                                 for k, c in (("x_update", 4), ("pair", 5), ("test", 6))},
            # mean over scenarios of the time one workgroup spends per ADMM iteration in each phase

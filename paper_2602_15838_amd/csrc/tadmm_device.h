@@ -404,6 +404,23 @@ __device__ __forceinline__ void factor_stage(const Prob &pb, const R hx[NX], con
 // reference velocity turned by 90 degrees (2-D) or crossed with the axis of
 // its smallest component (3-D); else e_1.
 // ---------------------------------------------------------------------------
+// Unit vector n = d / |d| of a position difference, by one hardware
+// reciprocal square root (about 1 ulp) and NU products instead of a rounded
+// square root and NU divisions; false (n untouched) when |d| < 1e-6.  The
+// pair phase and the polish both take their normals from here, so a normal
+// recomputed from the same positions is bitwise the same everywhere.
+template <int NU>
+__device__ __forceinline__ bool unit_normal(const float d[NU], float n[NU]) {
+  float dd = 0.f;
+#pragma unroll
+  for (int c = 0; c < NU; ++c) dd = fmaf(d[c], d[c], dd);
+  if (!(dd >= 1e-12f)) return false;
+  const float r = __builtin_amdgcn_rsqf(dd);
+#pragma unroll
+  for (int c = 0; c < NU; ++c) n[c] = d[c] * r;
+  return true;
+}
+
 template <int NX, int NU>
 __device__ __forceinline__ void reference_normal(const WS &ws, const Scen &sc, int a, int b, int t, float n[NU]) {
   const float *ra = ws.xref + (sc.xo + (long long)a * (sc.T + 1) + t) * NX;

@@ -375,20 +375,12 @@ __device__ void eqp_freeze(const Prob &pb, const WS &ws, const EWS &ew, const Sc
             reference_normal<NX, NU>(ws, sc, i, j, t, n);
           }
         } else {   // the normal of the last consensus step, from the final positions
-          float d[NU], dd = 0.f;
+          float d[NU];
 #pragma unroll
-          for (int c = 0; c < NU; ++c) {
+          for (int c = 0; c < NU; ++c)
             d[c] = R[fidx((unsigned)sc.GS, (unsigned)(t * N + i), F::X + c)] -
                    R[fidx((unsigned)sc.GS, (unsigned)(t * N + j), F::X + c)];
-            dd = fmaf(d[c], d[c], dd);
-          }
-          dd = sqrtf(dd);
-          if (dd >= 1e-6f) {
-#pragma unroll
-            for (int c = 0; c < NU; ++c) n[c] = d[c] / dd;
-          } else {
-            reference_normal<NX, NU>(ws, sc, i, j, t, n);
-          }
+          if (!unit_normal<NU>(d, n)) reference_normal<NX, NU>(ws, sc, i, j, t, n);
         }
 #pragma unroll
         for (int c = 0; c < NU; ++c) nrm[(long long)q * NU + c] = n[c];

@@ -848,16 +848,10 @@ __device__ __forceinline__ void pair_normal(const Prob &pb, const WS &ws, const 
       reference_normal<NX, NU>(ws, sc, f, s, t, n);
     }
   } else {
-    float d[NU], dd = 0.f;
+    float d[NU];
 #pragma unroll
-    for (int c = 0; c < NU; ++c) { d[c] = pf[c] - ps[c]; dd = fmaf(d[c], d[c], dd); }
-    dd = sqrtf(dd);
-    if (dd >= 1e-6f) {
-#pragma unroll
-      for (int c = 0; c < NU; ++c) n[c] = d[c] / dd;
-    } else {
-      reference_normal<NX, NU>(ws, sc, f, s, t, n);
-    }
+    for (int c = 0; c < NU; ++c) d[c] = pf[c] - ps[c];
+    if (!unit_normal<NU>(d, n)) reference_normal<NX, NU>(ws, sc, f, s, t, n);
   }
 }
 
@@ -901,76 +895,81 @@ __device__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, i
     }
   };
   const int gbase = (t - 1) * N * N + i;        // + j * N: this lane's ordered copy (i, j)
-  // the partner loop skips j == i; the duals of the next kPre partners are in
-  // flight while the current one is processed (each is loaded before any
-  // store of this loop to its own word)
-  constexpr int kPre = 4;
+  // The partner loop skips j == i and runs in batches of kPB partners: the
+  // duals and positions of a batch are all read before the first is used
+  // (each dual is read before this loop stores its own word).
+  constexpr int kPB = 8;
   const int np = N - 1;
   auto jof = [&](int jj) { return jj + (jj >= i); };
-  float gq[kPre];
+  for (int j0 = 0; j0 < np; j0 += kPB) {
+    float gb[kPB], pjb[kPB][NU], qjb[kPB][NU];
 #pragma unroll
-  for (int q = 0; q < kPre; ++q) gq[q] = (q < np) ? gm[gbase + jof(q) * N] : 0.f;
-  for (int jj = 0; jj < np; ++jj) {
-    const int j = jof(jj);
-    const float gold = gq[0];
-#pragma unroll
-    for (int q = 0; q + 1 < kPre; ++q) gq[q] = gq[q + 1];
-    gq[kPre - 1] = (jj + kPre < np) ? gm[gbase + jof(jj + kPre) * N] : 0.f;
-    const bool first = i < j;
-    const int f = first ? i : j, s = first ? j : i;
-    float pj[NU], qj[NU], pf[NU], ps[NU];
-    partner(j, pj, qj);
-#pragma unroll
-    for (int c = 0; c < NU; ++c) {
-      pf[c] = first ? pi[c] : pj[c];
-      ps[c] = first ? pj[c] : pi[c];
-    }
-    float n[NU];
-    pair_normal<NX, NU>(pb, ws, sc, f, s, t, pf, ps, n);
-    // lambda_fs of the previous step, -gamma_prev n_prev
-    float lfs[NU];
-    {
-      float np[NU];
-      if (frozen) {
-#pragma unroll
-        for (int c = 0; c < NU; ++c) np[c] = n[c];
-      } else {
-        float qf[NU], qs[NU];
-#pragma unroll
-        for (int c = 0; c < NU; ++c) {
-          qf[c] = first ? qi[c] : qj[c];
-          qs[c] = first ? qj[c] : qi[c];
-        }
-        pair_normal<NX, NU>(pb, ws, sc, f, s, t, qf, qs, np);
+    for (int q = 0; q < kPB; ++q)
+      if (j0 + q < np) {
+        gb[q] = gm[gbase + jof(j0 + q) * N];
+        partner(jof(j0 + q), pjb[q], qjb[q]);
       }
 #pragma unroll
-      for (int c = 0; c < NU; ++c) lfs[c] = -gold * np[c];
-    }
-    const int li = gbase + j * N;  // this lane's ordered copy (i, j)
-    float g = 0.f;
+    for (int q = 0; q < kPB; ++q) {
+      if (j0 + q >= np) break;
+      const int j = jof(j0 + q);
+      const float gold = gb[q];
+      const bool first = i < j;
+      const int f = first ? i : j, s = first ? j : i;
+      const float *pj = pjb[q], *qj = qjb[q];
+      float pf[NU], ps[NU];
 #pragma unroll
-    for (int c = 0; c < NU; ++c) {
-      const float ab = (pf[c] - ps[c]) + 2.0f * irho * lfs[c];  // a - b
-      g = fmaf(n[c], ab, g);
-    }
-    const float v = pb.dmin - g;
-    const float gam = 0.5f * rho * fmaxf(v, 0.f);
+      for (int c = 0; c < NU; ++c) {
+        pf[c] = first ? pi[c] : pj[c];
+        ps[c] = first ? pj[c] : pi[c];
+      }
+      float n[NU];
+      pair_normal<NX, NU>(pb, ws, sc, f, s, t, pf, ps, n);
+      // lambda_fs of the previous step, -gamma_prev n_prev
+      float lfs[NU];
+      {
+        float np_[NU];
+        if (frozen) {
 #pragma unroll
-    for (int c = 0; c < NU; ++c) {
-      const float lown = first ? lfs[c] : -lfs[c];    // this lane's lambda_ij before Eq. 5
-      const float lnew = -gam * n[c];                 // lambda_fs after Eq. 5
-      const float dl = (lfs[c] - lnew) * irho;       // z_f - pf = -(z_s - ps)
-      const float sdl = first ? dl : -dl;            // z_own - C x_i
-      const float zo = pi[c] + sdl;
-      const float lo = first ? lnew : -lnew;
-      es[c] += lown - 2.0f * lo;                     // rho z_own - lam_new - rho C x_i
-      zd[c] += sdl;
-      ls[c] += lo;
-      r2 = fmaf(dl, dl, r2);
-      z2 = fmaf(zo, zo, z2);
+          for (int c = 0; c < NU; ++c) np_[c] = n[c];
+        } else {
+          float qf[NU], qs[NU];
+#pragma unroll
+          for (int c = 0; c < NU; ++c) {
+            qf[c] = first ? qi[c] : qj[c];
+            qs[c] = first ? qj[c] : qi[c];
+          }
+          pair_normal<NX, NU>(pb, ws, sc, f, s, t, qf, qs, np_);
+        }
+#pragma unroll
+        for (int c = 0; c < NU; ++c) lfs[c] = -gold * np_[c];
+      }
+      const int li = gbase + j * N;  // this lane's ordered copy (i, j)
+      float g = 0.f;
+#pragma unroll
+      for (int c = 0; c < NU; ++c) {
+        const float ab = (pf[c] - ps[c]) + 2.0f * irho * lfs[c];  // a - b
+        g = fmaf(n[c], ab, g);
+      }
+      const float v = pb.dmin - g;
+      const float gam = 0.5f * rho * fmaxf(v, 0.f);
+#pragma unroll
+      for (int c = 0; c < NU; ++c) {
+        const float lown = first ? lfs[c] : -lfs[c];    // this lane's lambda_ij before Eq. 5
+        const float lnew = -gam * n[c];                 // lambda_fs after Eq. 5
+        const float dl = (lfs[c] - lnew) * irho;       // z_f - pf = -(z_s - ps)
+        const float sdl = first ? dl : -dl;            // z_own - C x_i
+        const float zo = pi[c] + sdl;
+        const float lo = first ? lnew : -lnew;
+        es[c] += lown - 2.0f * lo;                     // rho z_own - lam_new - rho C x_i
+        zd[c] += sdl;
+        ls[c] += lo;
+        r2 = fmaf(dl, dl, r2);
+        z2 = fmaf(zo, zo, z2);
+      }
+      gm[li] = gam;
+      if (first) pa[li] = (uint8_t)(v > 0.f);
     }
-    gm[li] = gam;
-    if (first) pa[li] = (uint8_t)(v > 0.f);
   }
   float s2 = 0.f, ax2 = 0.f, aty2 = 0.f;
   const float nn = (float)(N - 1);
