@@ -824,20 +824,29 @@ __device__ __forceinline__ int local_xupdate(const Prob &pb, const WS &ws, const
 // ===========================================================================
 // Consensus (Eq. 4) + dual update (Eq. 5) for agent i at step t, all partners
 // ===========================================================================
-// Canonical pair (f < s) with positions pf, ps and lambda_fs (lambda_sf =
-// -lambda_fs): a = pf + lambda_fs/rho, b = ps - lambda_fs/rho,
-// v = d_min - n'(a - b); the projection onto {n'(a-b) >= d_min} moves a and b
-// by +-(v+/2) n, and Eq. 5 then gives lambda_fs <- -(rho/2) max(v, 0) n =
-// -gamma n, which is evaluated in this closed form (no cancellation); the
-// copies follow from Eq. 5 as z_f = pf + (lambda_fs - lambda_fs_new)/rho,
-// z_s = ps - (same).  Only gamma is stored (one float per ordered copy, both
-// copies equal); lambda_fs of the previous step is rebuilt as -gamma n_prev
-// with n_prev the normal of that step, recomputed from the previous positions
-// C x^k (XP) with the same arithmetic, so the rebuilt value is bitwise the
-// stored one of a vector layout.
+// Ordered copy (i, j) of a pair, positions p_i, p_j, lambda_ij (lambda_ji =
+// -lambda_ij): a = p_i + lambda_ij/rho, b = p_j - lambda_ij/rho,
+// v = d_min - n_ij'(a - b); the projection onto {n_ij'(a-b) >= d_min} moves a
+// and b by +-(v+/2) n_ij, and Eq. 5 then gives lambda_ij <- -(rho/2) max(v, 0)
+// n_ij = -gamma n_ij, which is evaluated in this closed form (no
+// cancellation); the copy follows from Eq. 5 as z_ij = p_i + (lambda_ij -
+// lambda_ij_new)/rho.  Lane (i, t) handles its own copies; the copy (j, i)
+// computes every vector exactly negated and the same gamma, so only gamma is
+// stored (one float per ordered copy, both equal).  lambda_ij of the previous
+// step is rebuilt as -gamma n_prev with n_prev the normal of that step,
+// recomputed from the previous positions C x^k (XP) with the same arithmetic,
+// so the rebuilt value is bitwise the stored one of a vector layout.
+// Normal of the ordered copy (i, j): n_ij = (p_i - p_j) / |p_i - p_j|, the
+// negation of n_ji.  The given normals and the reference fallback are those
+// of the canonical pair (f < s), negated for i > j.  Negation, subtraction
+// and rounding commute exactly, so the two copies of a pair compute exactly
+// opposite normals and, below, the same dual.
 template <int NX, int NU>
-__device__ __forceinline__ void pair_normal(const Prob &pb, const WS &ws, const Scen &sc, int f, int s, int t,
-                                            const float pf[NU], const float ps[NU], float n[NU]) {
+__device__ __forceinline__ void pair_normal(const Prob &pb, const WS &ws, const Scen &sc, int i, int j, int t,
+                                            const float pi[NU], const float pj[NU], float n[NU]) {
+  const bool first = i < j;
+  const int f = first ? i : j, s = first ? j : i;
+  bool canonical = true;
   if (pb.normal_mode == NORMAL_FROZEN) {
     if (ws.normals) {
       const int pidx = f * sc.N - f * (f + 1) / 2 + (s - f - 1);
@@ -850,8 +859,13 @@ __device__ __forceinline__ void pair_normal(const Prob &pb, const WS &ws, const 
   } else {
     float d[NU];
 #pragma unroll
-    for (int c = 0; c < NU; ++c) d[c] = pf[c] - ps[c];
-    if (!unit_normal<NU>(d, n)) reference_normal<NX, NU>(ws, sc, f, s, t, n);
+    for (int c = 0; c < NU; ++c) d[c] = pi[c] - pj[c];
+    canonical = !unit_normal<NU>(d, n);
+    if (canonical) reference_normal<NX, NU>(ws, sc, f, s, t, n);
+  }
+  if (canonical && !first) {
+#pragma unroll
+    for (int c = 0; c < NU; ++c) n[c] = -n[c];
   }
 }
 
@@ -914,59 +928,43 @@ __device__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, i
       if (j0 + q >= np) break;
       const int j = jof(j0 + q);
       const float gold = gb[q];
-      const bool first = i < j;
-      const int f = first ? i : j, s = first ? j : i;
       const float *pj = pjb[q], *qj = qjb[q];
-      float pf[NU], ps[NU];
-#pragma unroll
-      for (int c = 0; c < NU; ++c) {
-        pf[c] = first ? pi[c] : pj[c];
-        ps[c] = first ? pj[c] : pi[c];
-      }
       float n[NU];
-      pair_normal<NX, NU>(pb, ws, sc, f, s, t, pf, ps, n);
-      // lambda_fs of the previous step, -gamma_prev n_prev
-      float lfs[NU];
+      pair_normal<NX, NU>(pb, ws, sc, i, j, t, pi, pj, n);
+      // lambda_ij of the previous step, -gamma_prev n_prev
+      float lown[NU];
       {
         float np_[NU];
         if (frozen) {
 #pragma unroll
           for (int c = 0; c < NU; ++c) np_[c] = n[c];
         } else {
-          float qf[NU], qs[NU];
-#pragma unroll
-          for (int c = 0; c < NU; ++c) {
-            qf[c] = first ? qi[c] : qj[c];
-            qs[c] = first ? qj[c] : qi[c];
-          }
-          pair_normal<NX, NU>(pb, ws, sc, f, s, t, qf, qs, np_);
+          pair_normal<NX, NU>(pb, ws, sc, i, j, t, qi, qj, np_);
         }
 #pragma unroll
-        for (int c = 0; c < NU; ++c) lfs[c] = -gold * np_[c];
+        for (int c = 0; c < NU; ++c) lown[c] = -gold * np_[c];
       }
       const int li = gbase + j * N;  // this lane's ordered copy (i, j)
       float g = 0.f;
 #pragma unroll
       for (int c = 0; c < NU; ++c) {
-        const float ab = (pf[c] - ps[c]) + 2.0f * irho * lfs[c];  // a - b
+        const float ab = (pi[c] - pj[c]) + 2.0f * irho * lown[c];  // a - b
         g = fmaf(n[c], ab, g);
       }
       const float v = pb.dmin - g;
       const float gam = 0.5f * rho * fmaxf(v, 0.f);
 #pragma unroll
       for (int c = 0; c < NU; ++c) {
-        const float lown = first ? lfs[c] : -lfs[c];    // this lane's lambda_ij before Eq. 5
-        const float lnew = -gam * n[c];                 // lambda_fs after Eq. 5
-        const float dl = (lfs[c] - lnew) * irho;       // z_f - pf = -(z_s - ps)
-        const float sdl = first ? dl : -dl;            // z_own - C x_i
-        const float zo = pi[c] + sdl;
-        const float lo = first ? lnew : -lnew;
-        es[c] += lown - 2.0f * lo;                     // rho z_own - lam_new - rho C x_i
-        zd[c] += sdl;
+        const float lo = -gam * n[c];                  // lambda_ij after Eq. 5
+        const float dl = (lown[c] - lo) * irho;        // z_ij - C x_i
+        const float zo = pi[c] + dl;
+        es[c] += lown[c] - 2.0f * lo;                  // rho z_ij - lam_new - rho C x_i
+        zd[c] += dl;
         ls[c] += lo;
         r2 = fmaf(dl, dl, r2);
         z2 = fmaf(zo, zo, z2);
       }
+      const bool first = i < j;
       gm[li] = gam;
       if (first) pa[li] = (uint8_t)(v > 0.f);
     }
