@@ -52,7 +52,7 @@ template <int NX_, int NU_, bool DI_>
 struct AgentView {
   static constexpr int NX = NX_, NU = NU_, NS = NU_ * (NU_ + 1) / 2, NP = NX_ * (NX_ + 1) / 2;
   static constexpr bool DI = DI_;
-  static constexpr int kBatch = 2;
+  static constexpr int kBatch = 2, kSweepBatch = 2;
   using F = Fld<NX, NU>;
   float *__restrict__ R;
   int8_t *__restrict__ Wb;
@@ -99,7 +99,7 @@ template <int NXF, int NUF>
 struct AxisView {
   static constexpr int NX = 2, NU = 1, NS = 1, NP = 3;
   static constexpr bool DI = true;
-  static constexpr int kBatch = 4;
+  static constexpr int kBatch = 4, kSweepBatch = 4;
   using F = Fld<NXF, NUF>;
   float *__restrict__ R;      // agent-stage region
   float *__restrict__ AX;     // axis-stage region
@@ -238,7 +238,7 @@ struct SweepStage {
 
 template <class V>
 __device__ __forceinline__ void affine_sweep(const Prob &pb, const V &m, int T) {
-  constexpr int NX = V::NX, NU = V::NU, B = V::kBatch;
+  constexpr int NX = V::NX, NU = V::NU, B = V::kSweepBatch;
   using D = Dyn<NX, NU, V::DI>;
   float p[NX];
 #pragma unroll
