@@ -241,6 +241,38 @@ tadmm_status tadmm_adjoint(tadmm_ctx *ctx, const tadmm_batch *batch, const tadmm
                            size_t workspace_bytes, const float *dL_dx, const float *dL_du, float *dL_dx0,
                            float *dL_dxref, float *dL_dlogq, float *dL_dlogr, float *stats);
 
+/* SQP outer loop around the solve: the separation constraints of Eq. 1,
+ * convexified as half-planes with frozen normals (Sec. III-A), re-linearized
+ * about each round's solution.
+ *   Round 0 solves with the batch's normals (batch->normals; NULL: those of
+ *   the reference trajectories), whatever params->normal_mode says; every
+ *   later round takes the normals of the previous round's positions,
+ *   n = (p_i - p_j)/|p_i - p_j| (the reference normal where two positions
+ *   coincide), and continues from the previous round's iterate, duals,
+ *   working sets and Riccati factors (a warm start) instead of the
+ *   references.  Each round runs the ADMM in `mode` (tadmm_mode) to its
+ *   stopping test or max_iter.
+ *   A scenario leaves the loop, as under the stopping rule of Sec. V-A, after
+ *   a round (other than the first) whose objective of Eq. 1,
+ *     sum_i sum_{t<T} ||x_t - r_t||_Q^2 + ||u_t||_R^2 + ||x_T - r_T||_{Q_T}^2,
+ *   differs from the previous round's by at most rtol times its magnitude,
+ *   and whose positions keep every pair at least d_min - sep_tol apart at
+ *   every step t = 1..T; otherwise after max_rounds (>= 1).  rtol, sep_tol:
+ *   finite, >= 0 (the paper's rule: rtol = 1e-4; sep_tol absorbs the ADMM
+ *   tolerance, e.g. 1e-2).
+ *   out receives the last round's solution of every scenario (as
+ *   tadmm_solve; out->counters sum over the rounds).  stats (DEVICE, [S][4]
+ *   floats, may be NULL): rounds solved, 1 if the stopping rule was met, the
+ *   last round's objective, its smallest distance between two agents.
+ *   Errors: as tadmm_solve, and TADMM_ERR_INVALID_ARG for a bad max_rounds,
+ *   rtol, sep_tol or mode.  The workspace's normals region holds the last
+ *   round's normals afterwards; tadmm_polish()/tadmm_adjoint() then return
+ *   TADMM_ERR_STATE (the derivative is defined for tadmm_solve() results).
+ *   tadmm_last_kernel_ms() gives the summed time of the rounds' solves. */
+tadmm_status tadmm_sqp(tadmm_ctx *ctx, const tadmm_batch *batch, const tadmm_out *out, void *workspace,
+                       size_t workspace_bytes, int32_t mode, int32_t max_rounds, float rtol, float sep_tol,
+                       float *stats);
+
 /* Measure candidate workgroup sizes of the batched kernel on this batch and
  * keep the fastest in the context (used when params.block_threads == 0).
  * Writes the chosen size to *best_threads (HOST, may be NULL). */

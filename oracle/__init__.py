@@ -91,6 +91,8 @@ def lib():
             L.orc_admm_batch.argtypes = [C.POINTER(_Params), C.c_int, C.POINTER(_Scenario),
                                          C.POINTER(_Result), C.c_int]
             L.orc_max_threads.restype = C.c_int
+            L.orc_relinearize.restype = C.c_int
+            L.orc_relinearize.argtypes = [C.POINTER(_Params), C.POINTER(_Scenario), _dp, _dp]
             _lib = L
     return _lib
 
@@ -245,3 +247,19 @@ def agent_qp(problem, T: int, n_nbr: int, x0, xref, q_diag, r_diag, ysum=None, s
     if rc < 0:
         raise RuntimeError("oracle agent QP failed")
     return dict(x=X, u=U, w=Wb, mu=mu, capped=(rc == 1), passes=int(passes.value), facts=int(facts.value))
+
+
+def relinearize(problem, scenario, x, inputs=None) -> np.ndarray:
+    """Normals [P][T][dp] of every pair (i < j) and step t = 1..T linearized
+    about the positions of x [N][T+1][nx] (the reference normal where two
+    positions coincide)."""
+    opts = OracleOptions(normal_mode=NORMAL_FROZEN)
+    prm = make_params(problem, opts)
+    h = _Holder(problem, scenario, opts, None, False, inputs)
+    N, T, dp = scenario.N, scenario.T, problem.dp
+    xx = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(N, T + 1, problem.nx))
+    out = np.zeros((N * (N - 1) // 2, T, dp))
+    rc = lib().orc_relinearize(C.byref(prm), C.byref(h.sc), _ptr(xx), _ptr(out))
+    if rc != 0:
+        raise RuntimeError("oracle relinearize failed")
+    return out

@@ -572,3 +572,28 @@ int orc_admm_batch(const orc_params *prm, int S, const orc_scenario *scs, orc_re
   for (int s = 0; s < S; ++s) fail |= (orc_admm(prm, &scs[s], &res[s], 1) != 0);
   return fail ? -1 : 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* SQP re-linearization (the outer loop around the ADMM, Sec. V-A)           */
+/* ------------------------------------------------------------------------ */
+/* The half-plane of pair (i < j) at step t, linearized about positions x:
+ * n = (p_i - p_j) / |p_i - p_j|, or the reference normal when the two
+ * positions are closer than 1e-6 (the convexification of Sec. III-A taken
+ * about the current trajectories instead of the references). */
+int orc_relinearize(const orc_params *prm, const orc_scenario *sc, const double *x, double *normals) {
+  const int N = sc->N, T = sc->T, nx = prm->nx, dp = prm->dp;
+  int p = 0;
+  for (int i = 0; i < N; ++i)
+    for (int j = i + 1; j < N; ++j, ++p)
+      for (int t = 1; t <= T; ++t) {
+        const double *pi = x + ((size_t)i * (T + 1) + t) * nx;
+        const double *pj = x + ((size_t)j * (T + 1) + t) * nx;
+        double *n = normals + ((size_t)p * T + (t - 1)) * dp;
+        double d[3] = {0, 0, 0}, nn = 0.0;
+        for (int k = 0; k < dp; ++k) { d[k] = pi[k] - pj[k]; nn += d[k] * d[k]; }
+        nn = sqrt(nn);
+        if (nn >= 1e-6) for (int k = 0; k < dp; ++k) n[k] = d[k] / nn;
+        else reference_normal(prm, sc, i, j, t, n);
+      }
+  return 0;
+}

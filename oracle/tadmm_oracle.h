@@ -93,6 +93,12 @@ int orc_admm_batch(const orc_params *prm, int S, const orc_scenario *scs, orc_re
 
 int orc_max_threads(void);
 
+/* Normals of every pair (i < j) and step t = 1..T linearized about the
+ * positions of x [N][T+1][nx]: (p_i - p_j)/|p_i - p_j|, or the reference
+ * normal when |p_i - p_j| < 1e-6.  normals [P][T][dp], P = N(N-1)/2 in
+ * lexicographic pair order (the layout of orc_scenario.normals). */
+int orc_relinearize(const orc_params *prm, const orc_scenario *sc, const double *x, double *normals);
+
 #ifdef __cplusplus
 }
 #endif

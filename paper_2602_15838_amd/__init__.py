@@ -80,6 +80,9 @@ def lib():
         L.tadmm_polish.argtypes = [vp, C.POINTER(Batch), C.POINTER(Out), vp, C.c_size_t, vp]
         L.tadmm_adjoint.restype = C.c_int
         L.tadmm_adjoint.argtypes = [vp, C.POINTER(Batch), C.POINTER(Out), vp, C.c_size_t, vp, vp, vp, vp, vp, vp, vp]
+        L.tadmm_sqp.restype = C.c_int
+        L.tadmm_sqp.argtypes = [vp, C.POINTER(Batch), C.POINTER(Out), vp, C.c_size_t, C.c_int32, C.c_int32,
+                                C.c_float, C.c_float, vp]
         L.tadmm_autotune.restype = C.c_int
         L.tadmm_autotune.argtypes = [vp, C.POINTER(Batch), C.POINTER(Out), vp, C.c_size_t, _ip]
         L.tadmm_last_kernel_ms.restype = C.c_float
@@ -96,8 +99,8 @@ def lib():
     return _lib
 
 
-EXPORTED_SYMBOLS = ("tadmm_workspace_size", "tadmm_create", "tadmm_solve", "tadmm_polish", "tadmm_adjoint",
-                    "tadmm_autotune",
+EXPORTED_SYMBOLS = ("tadmm_workspace_size", "tadmm_create", "tadmm_solve", "tadmm_sqp", "tadmm_polish",
+                    "tadmm_adjoint", "tadmm_autotune",
                     "tadmm_last_kernel_ms", "tadmm_destroy", "tadmm_status_string", "tadmm_last_error",
                     "tadmm_version")
 
@@ -241,6 +244,18 @@ class Prepared:
                                C.c_size_t(self.nbytes), int(mode))
         s._check(rc)
         return lib().tadmm_last_kernel_ms(s._h)
+
+    def sqp(self, mode: int = MODE_BATCHED, max_rounds: int = 10, rtol: float = 1e-4, sep_tol: float = 1e-2):
+        """SQP outer loop (tadmm_sqp): rounds of frozen-normal solves,
+        re-linearized about each solution.  Returns the per-scenario stats
+        [S][4]: rounds, stopping rule met, objective, smallest distance."""
+        torch = self.solver.torch
+        s = self.solver
+        st = torch.zeros(self.b["N"].size, 4, device=s.device)
+        rc = lib().tadmm_sqp(s._h, C.byref(self.batch), C.byref(self.out), C.c_void_p(self.ws.data_ptr()),
+                             C.c_size_t(self.nbytes), int(mode), int(max_rounds), float(rtol), float(sep_tol), _ptr(st))
+        s._check(rc)
+        return st
 
     def autotune(self) -> int:
         s = self.solver

@@ -34,12 +34,15 @@ struct Prob {
   float qT, dmin, rho, eps_abs, eps_rel, mu_tol;
   float refine_band;             // refine when both residuals are within this factor of their tolerances (0: always)
   int max_iter, max_as, normal_mode, cache, warm, hot, refine;
+  int cont;                      // continue from the workspace's state (a later SQP round)
 };
 
 // Per-scenario table columns (int64).
 enum { TB_F = 0, TB_B, TB_L, TB_A, TB_XO, TB_UO, TB_PO, TB_LB, TB_D, TB_NCOL };
 // Per-scenario int32 state columns.
-enum { ST_STATUS = 0, ST_ITERS, ST_CAP, ST_DONE, ST_NEAR, ST_NCOL = 8 };
+// ST_COLD: a continuing SQP round restarts the duals (the previous round did
+// not converge); written by the round's bookkeeping, read by the setup.
+enum { ST_STATUS = 0, ST_ITERS, ST_CAP, ST_DONE, ST_NEAR, ST_COLD, ST_NCOL = 8 };
 // Per-scenario float state columns.
 enum { SN_R = 0, SN_S, SN_EPRI, SN_EDUAL, SN_NCOL = 4 };
 // Per-scenario counters (int64).
@@ -61,6 +64,7 @@ struct WS {
   int *sst;                          // [S][ST_NCOL]
   float *snorm;                      // [S][SN_NCOL]
   unsigned long long *cnt;           // [S][CT_NCOL]
+  int *skip;                         // [S] SQP: scenario converged, not solved again
   // inputs (caller layouts)
   const float *x0, *xref, *qd, *rd, *normals;
 };

@@ -680,7 +680,7 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, const
   // FP32 rounding of the local QP is far below what the iteration resolves)
   const bool refine = pb.refine && (pb.refine_band <= 0.f || uni(ws.sst[(long long)sc.s * ST_NCOL + ST_NEAR]) != 0);
 
-  if (k == 1 || !pb.hot) {
+  if ((k == 1 && !pb.cont) || !pb.hot) {
     // fresh start: empty working set ...
     for (int t = 0; t < T; ++t)
 #pragma unroll
@@ -1032,7 +1032,9 @@ __device__ int scenario_test(const Prob &pb, const WS &ws, const Scen &sc, int k
     int status = SCEN_MAX_ITER;
     if (cap_hit) { status = SCEN_CAP; done = 1; }
     else if (!isfinite(rn) || !isfinite(sn)) { status = SCEN_NONFINITE; done = 1; }
-    else if (rn <= epri && sn <= edual) { status = SCEN_CONVERGED; done = 1; }
+    // (a continuing SQP round's first x-update still used the linear term of
+    // the previous round's normals: its residuals prove nothing yet)
+    else if (rn <= epri && sn <= edual && (k >= 2 || !pb.cont)) { status = SCEN_CONVERGED; done = 1; }
     else if (k >= pb.max_iter) { done = 1; }
     if (!cap_hit) {
       sn_out[SN_R] = rn; sn_out[SN_S] = sn; sn_out[SN_EPRI] = epri; sn_out[SN_EDUAL] = edual;
@@ -1056,6 +1058,40 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
   int8_t *Wb = ws.wr + sc.bo;
   const float *qd = ws.qd + (long long)sc.s * NX;
   const int n_nbr = N - 1;
+  if (pb.cont) {
+    // A later SQP round: the iterate, working sets and factors carry over,
+    // and so do the duals if the previous round converged.  Otherwise (its
+    // half-planes may have been infeasible, the duals grown without bound)
+    // the duals restart at zero with z = C x: gamma = 0, ZD = 0 and the
+    // position part of the linear term -2 Q r - rho n_nbr C x.
+    if (uni(ws.sst[(long long)sc.s * ST_NCOL + ST_COLD])) {
+      for (int idx = tid; idx < GS; idx += nthreads) {
+        auto Rg = [&](int f) -> float & { return R[fidx((unsigned)GS, (unsigned)idx, f)]; };
+#pragma unroll
+        for (int c = 0; c < NU; ++c) {
+          Rg(F::Q + c) = fmaf(-pb.rho * (float)n_nbr, Rg(F::X + c), Rg(F::GQP + c));
+          Rg(F::ZD + c) = 0.f;
+        }
+      }
+      float *gm = ws.gam + sc.lo;
+      uint8_t *pa = ws.pact + sc.lb;
+      for (int idx = tid; idx < T * N * N; idx += nthreads) {
+        gm[idx] = 0.f;
+        pa[idx] = 0;
+      }
+    }
+    if (tid == 0) {
+      int *st = ws.sst + (long long)sc.s * ST_NCOL;
+      st[ST_STATUS] = SCEN_MAX_ITER;
+      st[ST_ITERS] = 0;
+      st[ST_CAP] = 0;
+      st[ST_DONE] = 0;
+      st[ST_NEAR] = 0;
+      float *sn = ws.snorm + (long long)sc.s * SN_NCOL;
+      sn[SN_R] = sn[SN_S] = sn[SN_EPRI] = sn[SN_EDUAL] = 0.f;
+    }
+    return;
+  }
   for (int idx = tid; idx < GS; idx += nthreads) {
     const int t = idx / N, i = idx % N;
     auto Rg = [&](int f) -> float & { return R[fidx((unsigned)GS, (unsigned)idx, f)]; };
@@ -1135,7 +1171,7 @@ template <int NX, int NU>
 __global__ __launch_bounds__(256) void k_setup(Prob pb, WS ws, int s) {
   const Scen sc = load_scen(ws, s);
   scenario_setup<NX, NU>(pb, ws, sc, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
-  if (blockIdx.x == 0 && threadIdx.x < CT_NCOL) ws.cnt[(long long)s * CT_NCOL + threadIdx.x] = 0ull;
+  if (!pb.cont && blockIdx.x == 0 && threadIdx.x < CT_NCOL) ws.cnt[(long long)s * CT_NCOL + threadIdx.x] = 0ull;
 }
 
 template <int NX, int NU, bool DI>
@@ -1193,6 +1229,7 @@ __device__ __forceinline__ void persistent_body(Prob pb, WS ws, int S, int lds_f
     __syncthreads();
     if (item >= S) return;
     const int s = __builtin_amdgcn_readfirstlane(ws.order[item]);
+    if (pb.cont && uni(ws.skip[s])) continue;   // converged in an earlier SQP round
     const Scen sc = load_scen(ws, s);
     scenario_setup<NX, NU>(pb, ws, sc, tid, nt);
     if (tid == 0) { s_cap = 0; s_done = 0; }
@@ -1284,7 +1321,7 @@ template <int NX, int NU>
 __global__ __launch_bounds__(256) void k_wide_setup(Prob pb, WS ws, int *wide) {
   const Scen sc = load_scen(ws, uni(wide[1]));
   scenario_setup<NX, NU>(pb, ws, sc, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
-  if (blockIdx.x == 0 && threadIdx.x < CT_NCOL) ws.cnt[(long long)sc.s * CT_NCOL + threadIdx.x] = 0ull;
+  if (!pb.cont && blockIdx.x == 0 && threadIdx.x < CT_NCOL) ws.cnt[(long long)sc.s * CT_NCOL + threadIdx.x] = 0ull;
   if (blockIdx.x == 0 && threadIdx.x == 0) wide[0] = 1;
 }
 
@@ -1388,6 +1425,143 @@ __global__ void k_check(Prob pb, WS ws, int S, int *flags) {
   }
 }
 
+// ===========================================================================
+// SQP outer loop: the half-planes re-linearized about each round's solution
+// ===========================================================================
+// The separation constraints of Eq. 1 are convexified as half-planes with
+// frozen normals (Sec. III-A); every round solves that QP with the ADMM, and
+// the next one re-linearizes about its solution.  A scenario leaves the loop,
+// as under the stopping rule of Sec. V-A, once the objective of Eq. 1 moved
+// by at most rtol (relative) since the previous round and every pair is at
+// least d_min - sep_tol apart at every step t = 1..T.
+
+__device__ __forceinline__ float block_min_f(float v, float *red) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+  const int nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float m = red[0];
+  for (int w = 1; w < nw; ++w) m = fminf(m, red[w]);
+  return m;
+}
+
+// Normals of the next round for the scenarios still in the loop: every pair
+// (i < j) and step t, n = (p_i - p_j)/|p_i - p_j| at the current positions
+// (the reference normal where they coincide), written to nrm in the layout
+// of the caller's frozen normals, [pair-step po + p T + t - 1][NU].
+template <int NX, int NU>
+__global__ __launch_bounds__(256) void k_sqp_relin(WS ws, float *nrm, int S) {
+  using F = Fld<NX, NU>;
+  for (int s = blockIdx.x; s < S; s += gridDim.x) {
+    if (uni(ws.skip[s])) continue;
+    const Scen sc = load_scen(ws, s);
+    const int N = sc.N, T = sc.T;
+    const float *R = ws.fr + sc.fo;
+    for (int e = threadIdx.x; e < N * T; e += blockDim.x) {
+      const int t = e / N + 1, i = e % N;
+      float pi[NU];
+#pragma unroll
+      for (int c = 0; c < NU; ++c) pi[c] = R[fidx((unsigned)sc.GS, (unsigned)(t * N + i), F::X + c)];
+      const int base = i * N - i * (i + 1) / 2;   // pair index of (i, i + 1)
+      for (int j = i + 1; j < N; ++j) {
+        float d[NU], n[NU];
+#pragma unroll
+        for (int c = 0; c < NU; ++c) d[c] = pi[c] - R[fidx((unsigned)sc.GS, (unsigned)(t * N + j), F::X + c)];
+        if (!unit_normal<NU>(d, n)) reference_normal<NX, NU>(ws, sc, i, j, t, n);
+        float *o = nrm + (sc.po + (long long)(base + j - i - 1) * T + (t - 1)) * NU;
+#pragma unroll
+        for (int c = 0; c < NU; ++c) o[c] = n[c];
+      }
+    }
+  }
+}
+
+// End of a round for the scenarios still in the loop: the objective of Eq. 1
+// at the solution, sum_i sum_{t<T} ||x - r||_Q^2 + ||u||_R^2 + ||x_T - r_T||_{Q_T}^2
+// (FP64, fixed-order sums), the smallest distance between two agents over
+// t = 1..T, and the stopping rule.  jprev: objective of the previous round;
+// rounds: rounds solved; *active: scenarios still in the loop.
+template <int NX, int NU>
+__global__ __launch_bounds__(256) void k_sqp_eval(Prob pb, WS ws, double *jprev, int *rounds, float *minsep, int S,
+                                                  int round, float rtol, float sep_tol, int *active) {
+  using F = Fld<NX, NU>;
+  __shared__ double red[4];
+  __shared__ float redf[4];
+  for (int s = blockIdx.x; s < S; s += gridDim.x) {
+    if (uni(ws.skip[s])) continue;
+    const Scen sc = load_scen(ws, s);
+    const int N = sc.N, T = sc.T;
+    const unsigned GS = (unsigned)sc.GS;
+    const float *R = ws.fr + sc.fo;
+    const float *qd = ws.qd + (long long)s * NX, *rd = ws.rd + (long long)s * NU;
+    double J = 0.0;
+    for (int e = threadIdx.x; e < sc.GS; e += blockDim.x) {
+      const int t = e / N, i = e % N;
+      const float *r = ws.xref + (sc.xo + (long long)i * (T + 1) + t) * NX;
+      double v = 0.0;
+#pragma unroll
+      for (int c = 0; c < NX; ++c) {
+        const double d = (double)R[fidx(GS, (unsigned)e, F::X + c)] - (double)r[c];
+        v = fma((double)qd[c] * d, d, v);
+      }
+      if (t == T) {
+        v *= (double)pb.qT;
+      } else {
+#pragma unroll
+        for (int a = 0; a < NU; ++a) {
+          const double u = (double)R[fidx(GS, (unsigned)e, F::U + a)];
+          v = fma((double)rd[a] * u, u, v);
+        }
+      }
+      J += v;
+    }
+    J = block_sum(J, red);
+    float m2 = INFINITY;   // smallest squared distance
+    for (int e = threadIdx.x; e < N * T; e += blockDim.x) {
+      const int t = e / N + 1, i = e % N;
+      float pi[NU];
+#pragma unroll
+      for (int c = 0; c < NU; ++c) pi[c] = R[fidx(GS, (unsigned)(t * N + i), F::X + c)];
+      for (int j = i + 1; j < N; ++j) {
+        float d2 = 0.f;
+#pragma unroll
+        for (int c = 0; c < NU; ++c) {
+          const float d = pi[c] - R[fidx(GS, (unsigned)(t * N + j), F::X + c)];
+          d2 = fmaf(d, d, d2);
+        }
+        m2 = fminf(m2, d2);
+      }
+    }
+    m2 = block_min_f(m2, redf);
+    if (threadIdx.x == 0) {
+      const float sep = sqrtf(m2);
+      const bool done = round >= 1 && fabs(J - jprev[s]) <= (double)rtol * fmax(fabs(J), 1e-300) &&
+                        sep >= pb.dmin - sep_tol;
+      int *sst = ws.sst + (long long)s * ST_NCOL;
+      sst[ST_COLD] = sst[ST_STATUS] != SCEN_CONVERGED;   // for the next round's setup
+      jprev[s] = J;
+      rounds[s] = round + 1;
+      minsep[s] = sep;
+      ws.skip[s] = done ? 1 : 0;
+      if (!done) atomicAdd(active, 1);
+    }
+    __syncthreads();
+  }
+}
+
+// stats [S][4]: rounds solved, 1 if the stopping rule was met, the objective
+// of the last round, its smallest distance between two agents
+__global__ void k_sqp_stats(WS ws, const double *jprev, const int *rounds, const float *minsep, int S, float *stats) {
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < S; s += gridDim.x * blockDim.x) {
+    stats[4 * s + 0] = (float)rounds[s];
+    stats[4 * s + 1] = (float)ws.skip[s];
+    stats[4 * s + 2] = (float)jprev[s];
+    stats[4 * s + 3] = minsep[s];
+  }
+}
+
 template <int NX, int NU>
 __global__ void k_writeback(WS ws, int S, tadmm_out out) {
   using F = Fld<NX, NU>;
@@ -1448,6 +1622,7 @@ struct Layout {
   size_t o_adirty = 0, o_fr = 0, o_dr = 0, o_wr = 0, o_gam = 0, o_pact = 0, bytes = 0;
   size_t o_er = 0, o_nrm = 0, o_cidx = 0, o_clist = 0, o_cg = 0, o_m = 0;
   size_t o_wide = 0;   // wide mode: iteration number, scenario index
+  size_t o_sqpj = 0, o_sqpi = 0, o_sqpf = 0;   // SQP: objective [S] (FP64); skip, rounds [2][S]; min distance [S]
   long long sumPT = 0;
   std::vector<long long> tab;
   std::vector<int> order;
@@ -1547,6 +1722,9 @@ bool make_layout(const tadmm_params *p, int S, const int32_t *N, const int32_t *
   L.o_cg = take(sizeof(double) * 6 * (size_t)po);
   L.o_m = take(sizeof(int) * S);
   L.o_wide = take(sizeof(int) * 64);
+  L.o_sqpj = take(sizeof(double) * S);
+  L.o_sqpi = take(sizeof(int) * 2 * S);
+  L.o_sqpf = take(sizeof(float) * S);
   L.bytes = off;
   // launch order for the persistent queue: largest N^2 T first (LPT)
   L.order.resize(S);
@@ -1602,6 +1780,7 @@ struct GraphKey {
   tadmm_out out{};
   const float *x0 = nullptr, *xref = nullptr, *qd = nullptr, *rd = nullptr, *normals = nullptr;
   int S = 0, threads = 0, grid = 0;
+  int variant = 0;   // 0: a solve; SQP rounds: 2 (first) or 3 (later, continuing)
   size_t bytes = 0;
   tadmm_params prm{};
   bool operator==(const GraphKey &o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
@@ -1687,6 +1866,7 @@ WS make_ws(const Layout &L, char *ws, const tadmm_batch *b) {
   w.cnt = (unsigned long long *)(ws + L.o_cnt);
   w.x0 = b->x0; w.xref = b->xref; w.qd = b->q_diag; w.rd = b->r_diag;
   w.normals = (b->normals && true) ? b->normals : nullptr;
+  w.skip = (int *)(ws + L.o_sqpi);
   return w;
 }
 
@@ -1704,9 +1884,10 @@ tadmm_status run_checks(tadmm_ctx *ctx, const Prob &pb, const WS &w, int S, int 
 
 template <int NX, int NU, bool DI>
 tadmm_status run_plain(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layout &L, const int32_t *N,
-                       const int32_t *T, int *d_flags, const tadmm_out &out) {
+                       const int32_t *T, int *d_flags, const tadmm_out &out, const int *skip = nullptr) {
   HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
   for (int s = 0; s < L.S; ++s) {
+    if (skip && skip[s]) continue;
     const int n = N[s], t = T[s];
     const long long work = std::max<long long>((long long)n * (t + 1), (long long)t * n * n);
     const int gsetup = (int)std::min<long long>((work + 255) / 256, 4096);
@@ -1732,7 +1913,7 @@ tadmm_status run_plain(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layout
 
 template <int NX, int NU, bool DI>
 tadmm_status run_batched(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layout &L, const tadmm_batch *b,
-                         const tadmm_out &out, void *ws, size_t bytes) {
+                         const tadmm_out &out, void *ws, size_t bytes, int variant = 0) {
   const int threads = ctx->prm.block_threads ? ctx->prm.block_threads : ctx->tuned_threads;
   // LDS for the positions of the largest scenario, up to 32 KB per workgroup
   // (larger scenarios read positions from global memory)
@@ -1749,7 +1930,8 @@ tadmm_status run_batched(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layo
   GraphKey key;
   std::memset(&key, 0, sizeof(key));
   key.ws = ws; key.out = out; key.x0 = b->x0; key.xref = b->xref; key.qd = b->q_diag; key.rd = b->r_diag;
-  key.normals = b->normals; key.S = L.S; key.threads = threads; key.grid = grid; key.bytes = bytes; key.prm = ctx->prm;
+  key.normals = w.normals; key.S = L.S; key.threads = threads; key.grid = grid; key.bytes = bytes; key.prm = ctx->prm;
+  key.variant = variant;
   if (!(ctx->gexec && key == ctx->key)) {
     if (ctx->gexec) { (void)hipGraphExecDestroy(ctx->gexec); ctx->gexec = nullptr; }
     if (ctx->graph) { (void)hipGraphDestroy(ctx->graph); ctx->graph = nullptr; }
@@ -1761,7 +1943,8 @@ tadmm_status run_batched(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layo
     // counters and the queue are cleared by fill kernels (no memset nodes)
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, cs, w.queue, 1, 0);
     const long long nc = (long long)L.S * CT_NCOL;
-    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, cs, w.cnt, nc);
+    if (!pb.cont)   // a continuing SQP round keeps counting
+      hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, cs, w.cnt, nc);
     if (lean)
       hipLaunchKernelGGL((k_admm_persistent_lean<NX, NU, DI>), dim3(grid), dim3(threads), lds_bytes, cs, pb, w, L.S,
                          lds_floats);
@@ -1794,7 +1977,7 @@ constexpr int kWideChunk = 8;   // ADMM iterations per launch of the wide-mode g
 // once per launch).
 template <int NX, int NU, bool DI>
 tadmm_status run_wide(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layout &L, const tadmm_batch *b,
-                      const tadmm_out &out, void *ws, size_t bytes) {
+                      const tadmm_out &out, void *ws, size_t bytes, int variant = 0, const int *skip = nullptr) {
   char *w8 = (char *)ws;
   int *d_wide = (int *)(w8 + L.o_wide);
   long long max_n = 1, max_nt = 1, max_work = 1;
@@ -1817,7 +2000,8 @@ tadmm_status run_wide(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layout 
   GraphKey key;
   std::memset(&key, 0, sizeof(key));
   key.ws = ws; key.out = out; key.x0 = b->x0; key.xref = b->xref; key.qd = b->q_diag; key.rd = b->r_diag;
-  key.normals = b->normals; key.S = L.S; key.threads = gp; key.grid = gx; key.bytes = bytes; key.prm = ctx->prm;
+  key.normals = w.normals; key.S = L.S; key.threads = gp; key.grid = gx; key.bytes = bytes; key.prm = ctx->prm;
+  key.variant = variant;
   if (!(ctx->wexec[0] && key == ctx->wkey)) {
     for (int q = 0; q < 2; ++q) {
       if (ctx->wexec[q]) { (void)hipGraphExecDestroy(ctx->wexec[q]); ctx->wexec[q] = nullptr; }
@@ -1849,6 +2033,7 @@ tadmm_status run_wide(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layout 
   }
   HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
   for (int s = 0; s < L.S; ++s) {
+    if (skip && skip[s]) continue;
     ctx->h_flags[8] = s;
     HIPCHK(hipMemcpyAsync(d_wide + 1, ctx->h_flags + 8, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(hipGraphLaunch(ctx->wexec[0], ctx->stream));
@@ -1901,6 +2086,95 @@ tadmm_status solve_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *o
   ctx->solved_N.assign(b->n_agents, b->n_agents + L.S);
   ctx->solved_T.assign(b->horizon, b->horizon + L.S);
   return TADMM_OK;
+}
+
+// The SQP loop (k_sqp_*): rounds of frozen-normal solves in the given mode.
+// Round 0 takes the batch's normals (or the references'); each later round
+// re-linearizes about the previous solution and continues from the
+// workspace's state (iterate, duals, working sets, factors) for the
+// scenarios still in the loop.
+template <int NX, int NU, bool DI>
+tadmm_status sqp_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *out, void *ws, size_t bytes, int mode,
+                      int max_rounds, float rtol, float sep_tol, float *stats) {
+  if (max_rounds < 1) return fail(ctx, TADMM_ERR_INVALID_ARG, "max_rounds must be >= 1");
+  if (!(std::isfinite(rtol) && rtol >= 0.f && std::isfinite(sep_tol) && sep_tol >= 0.f))
+    return fail(ctx, TADMM_ERR_INVALID_ARG, "rtol and sep_tol must be finite and >= 0");
+  if (mode != TADMM_MODE_PLAIN && mode != TADMM_MODE_BATCHED && mode != TADMM_MODE_WIDE)
+    return fail(ctx, TADMM_ERR_INVALID_ARG, "unknown mode");
+  Layout L;
+  if (!make_layout(&ctx->prm, b->n_scen, b->n_agents, b->horizon, L, ctx->err)) return TADMM_ERR_SHAPE;
+  if (!ws || bytes < L.bytes) return fail(ctx, TADMM_ERR_WORKSPACE, "workspace missing or smaller than tadmm_workspace_size()");
+  if (((uintptr_t)ws) % kAlign) return fail(ctx, TADMM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  ctx->solved = false;   // the derivative is defined for tadmm_solve results only
+  ctx->polished = false;
+  if (L.S == 0) return TADMM_OK;
+  if (!b->x0 || !b->xref || !b->q_diag || !b->r_diag) return fail(ctx, TADMM_ERR_INVALID_ARG, "batch input pointer is NULL");
+  if (!out->status || !out->iters) return fail(ctx, TADMM_ERR_INVALID_ARG, "out.status and out.iters are required");
+  char *w8 = (char *)ws;
+  tadmm_status st = stage_tables(ctx, L, b->n_agents, b->horizon, w8);
+  if (st != TADMM_OK) return st;
+  Prob pb = to_prob(ctx->prm);
+  pb.normal_mode = TADMM_NORMAL_FROZEN;
+  const WS w = make_ws(L, w8, b);
+  int *d_flags = (int *)(w8 + L.o_flags);
+  if (ctx->prm.check_inputs) {
+    st = run_checks<NX, NU>(ctx, pb, w, L.S, d_flags);
+    if (st != TADMM_OK) return st;
+  }
+  double *jprev = (double *)(w8 + L.o_sqpj);
+  int *rounds = w.skip + L.S;
+  float *minsep = (float *)(w8 + L.o_sqpf);
+  float *nrm = (float *)(w8 + L.o_nrm);
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((2 * L.S + 255) / 256)), dim3(256), 0, ctx->stream, w.skip, 2 * L.S, 0);
+  HIPCHK(hipGetLastError());
+  std::vector<int> hskip(L.S, 0);
+  const int grid = std::min(L.S, 65535);
+  float total_ms = 0.f;
+  for (int r = 0; r < max_rounds; ++r) {
+    Prob pr = pb;
+    pr.cont = r > 0 ? 1 : 0;
+    WS wr = w;
+    if (r > 0) {
+      wr.normals = nrm;
+      hipLaunchKernelGGL((k_sqp_relin<NX, NU>), dim3(grid), dim3(256), 0, ctx->stream, wr, nrm, L.S);
+      HIPCHK(hipGetLastError());
+    }
+    const int variant = 2 + pr.cont;
+    if (mode == TADMM_MODE_PLAIN)
+      st = run_plain<NX, NU, DI>(ctx, pr, wr, L, b->n_agents, b->horizon, d_flags, *out, hskip.data());
+    else if (mode == TADMM_MODE_BATCHED)
+      st = run_batched<NX, NU, DI>(ctx, pr, wr, L, b, *out, ws, bytes, variant);
+    else
+      st = run_wide<NX, NU, DI>(ctx, pr, wr, L, b, *out, ws, bytes, variant, hskip.data());
+    if (st != TADMM_OK) return st;
+    total_ms += ctx->last_ms;
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, ctx->stream, d_flags + 3, 1, 0);
+    hipLaunchKernelGGL((k_sqp_eval<NX, NU>), dim3(grid), dim3(256), 0, ctx->stream, pr, wr, jprev, rounds, minsep, L.S,
+                       r, rtol, sep_tol, d_flags + 3);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(ctx->h_flags + 3, d_flags + 3, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(hskip.data(), w.skip, sizeof(int) * L.S, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (ctx->h_flags[3] == 0) break;
+  }
+  if (stats) {
+    hipLaunchKernelGGL(k_sqp_stats, dim3((unsigned)((L.S + 255) / 256)), dim3(256), 0, ctx->stream, w, jprev, rounds,
+                       minsep, L.S, stats);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  }
+  ctx->last_ms = total_ms;
+  return TADMM_OK;
+}
+
+tadmm_status sqp_dispatch(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *out, void *ws, size_t bytes, int mode,
+                          int max_rounds, float rtol, float sep_tol, float *stats) {
+  const bool di = is_double_integrator(ctx->prm);
+  if (ctx->prm.nx == 4)
+    return di ? sqp_impl<4, 2, true>(ctx, b, out, ws, bytes, mode, max_rounds, rtol, sep_tol, stats)
+              : sqp_impl<4, 2, false>(ctx, b, out, ws, bytes, mode, max_rounds, rtol, sep_tol, stats);
+  return di ? sqp_impl<6, 3, true>(ctx, b, out, ws, bytes, mode, max_rounds, rtol, sep_tol, stats)
+            : sqp_impl<6, 3, false>(ctx, b, out, ws, bytes, mode, max_rounds, rtol, sep_tol, stats);
 }
 
 EWS make_ews(const Layout &L, char *ws) {
@@ -2044,6 +2318,15 @@ tadmm_status tadmm_solve(tadmm_ctx *ctx, const tadmm_batch *batch, const tadmm_o
               : solve_impl<4, 2, false>(ctx, batch, out, workspace, workspace_bytes, mode);
   return di ? solve_impl<6, 3, true>(ctx, batch, out, workspace, workspace_bytes, mode)
             : solve_impl<6, 3, false>(ctx, batch, out, workspace, workspace_bytes, mode);
+}
+
+tadmm_status tadmm_sqp(tadmm_ctx *ctx, const tadmm_batch *batch, const tadmm_out *out, void *workspace,
+                       size_t workspace_bytes, int32_t mode, int32_t max_rounds, float rtol, float sep_tol,
+                       float *stats) {
+  if (!ctx) return TADMM_ERR_INVALID_ARG;
+  if (!batch || !out) return fail(ctx, TADMM_ERR_INVALID_ARG, "batch / out is NULL");
+  ctx->err.clear();
+  return sqp_dispatch(ctx, batch, out, workspace, workspace_bytes, mode, max_rounds, rtol, sep_tol, stats);
 }
 
 tadmm_status tadmm_autotune(tadmm_ctx *ctx, const tadmm_batch *batch, const tadmm_out *out, void *workspace,
