@@ -32,7 +32,13 @@ least-squares exponent of time against N.  The swaps are symmetric and run
 to the 200-iteration cap, so the iteration count is fixed and the per-solve
 times scale as the per-iteration ones.
 
-    python -m paper_2602_15838_amd.study [--ablation] [--sweep] [--seeds 20]
+SQP (the outer re-linearization loop, tadmm_sqp).  The benchmark's ragged
+batch (4096 scenarios) through the SQP loop in the batched mode, with the
+stopping rule of Sec. V-A (relative objective change 1e-4, every pair at
+least d_min - sep_tol apart): wall time, rounds, outcomes, and the same
+batch through one solve with the normals re-linearized every iteration.
+
+    python -m paper_2602_15838_amd.study [--ablation] [--sweep] [--sqp] [--seeds 20]
 
 prints one JSON object per line.
 """
@@ -157,14 +163,53 @@ def sweep(agents: Sequence[int] = SWEEP_AGENTS) -> List[Dict]:
     return recs
 
 
+def sqp_study(S: int = 4096, max_rounds: int = 10, rtol: float = 1e-4, sep_tol: float = 1e-2) -> List[Dict]:
+    import torch
+
+    import synth
+    import paper_2602_15838_amd as tadmm
+    problem, scs = synth.config2(S=S)
+    pk = synth.pack(problem, scs)
+    solver = tadmm.Solver(tadmm.make_params(problem))
+    prep = solver.prepare(pk.n_agents, pk.horizon, pk.x0, pk.xref, pk.q_diag, pk.r_diag)
+    prep.sqp(tadmm.MODE_BATCHED, max_rounds=max_rounds, rtol=rtol, sep_tol=sep_tol)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = prep.sqp(tadmm.MODE_BATCHED, max_rounds=max_rounds, rtol=rtol, sep_tol=sep_tol)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = st.cpu().numpy()
+    status = prep.o["status"].cpu().numpy()
+    rounds = st[:, 0].astype(int)
+    prep1 = solver.prepare(pk.n_agents, pk.horizon, pk.x0, pk.xref, pk.q_diag, pk.r_diag)
+    prep1.run(tadmm.MODE_BATCHED)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prep1.run(tadmm.MODE_BATCHED)
+    torch.cuda.synchronize()
+    d1 = time.perf_counter() - t1
+    s1 = prep1.o["status"].cpu().numpy()
+    solver.close()
+    return [dict(study="sqp", scenarios=S, max_rounds=max_rounds, rtol=rtol, sep_tol=sep_tol,
+                 ms=round(1e3 * dt, 2), scenario_sqp_solves_per_s=round(S / dt, 1),
+                 rounds_mean=round(float(rounds.mean()), 3),
+                 rounds_hist={str(r): int((rounds == r).sum()) for r in range(1, max_rounds + 1)},
+                 stopping_rule_met=round(float(st[:, 1].mean()), 4),
+                 last_round_admm_converged=round(float((status == tadmm.SCEN_CONVERGED).mean()), 4),
+                 min_separation_median=round(float(np.median(st[:, 3])), 4),
+                 per_iteration_normals=dict(ms=round(1e3 * d1, 2),
+                                            admm_converged=round(float((s1 == tadmm.SCEN_CONVERGED).mean()), 4)))]
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--ablation", action="store_true")
     ap.add_argument("--sweep", action="store_true")
+    ap.add_argument("--sqp", action="store_true")
     ap.add_argument("--seeds", type=int, default=20)
     args = ap.parse_args(argv)
-    if not (args.ablation or args.sweep):
-        args.ablation = args.sweep = True
+    if not (args.ablation or args.sweep or args.sqp):
+        args.ablation = args.sweep = args.sqp = True
     import torch
     torch.cuda.set_device(0)
     if args.ablation:
@@ -172,6 +217,9 @@ def main(argv=None):
             print(json.dumps(rec), flush=True)
     if args.sweep:
         for rec in sweep():
+            print(json.dumps(rec), flush=True)
+    if args.sqp:
+        for rec in sqp_study():
             print(json.dumps(rec), flush=True)
 
 
