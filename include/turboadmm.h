@@ -138,6 +138,15 @@ typedef struct {
                                 tadmm_adjoint: 1 FP64 (recommended), 0 FP32;
                                 their multipliers and reductions are FP64 either
                                 way                                                 */
+  int32_t adaptive_rho;      /* 1: per-scenario penalty by residual balancing
+                                (Boyd et al. 2011, Sec. 3.4.1; the paper names
+                                adaptive penalties as future work, Sec. VI):
+                                every rho_every iterations, rho <- rho_tau rho if
+                                r > rho_mu s, rho <- rho / rho_tau if s > rho_mu r
+                                (lambda unscaled, unchanged); a change refactors
+                                every stage.  0: rho fixed (default)              */
+  float rho_mu, rho_tau;     /* with adaptive_rho: rho_mu >= 1, rho_tau > 1      */
+  int32_t rho_every;         /* with adaptive_rho: >= 1                           */
 } tadmm_params;
 
 /* A ragged batch of S independent scenarios.  Scenario s has N_s agents and

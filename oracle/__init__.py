@@ -55,7 +55,8 @@ class _Params(C.Structure):
                 ("eps_abs", C.c_double), ("eps_rel", C.c_double), ("mu_tol", C.c_double),
                 ("max_iter", C.c_int), ("max_as_iter", C.c_int), ("normal_mode", C.c_int),
                 ("warm_start", C.c_int), ("hotstart", C.c_int), ("lu_reuse", C.c_int),
-                ("fixed_iters", C.c_int)]
+                ("fixed_iters", C.c_int), ("adaptive_rho", C.c_int), ("rho_mu", C.c_double),
+                ("rho_tau", C.c_double), ("rho_every", C.c_int)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -72,7 +73,7 @@ class _Result(C.Structure):
                 ("status", C.c_int), ("iters", C.c_int),
                 ("r_norm", C.c_double), ("s_norm", C.c_double),
                 ("eps_pri", C.c_double), ("eps_dual", C.c_double),
-                ("as_passes", C.c_long), ("lu_factorizations", C.c_long)]
+                ("as_passes", C.c_long), ("lu_factorizations", C.c_long), ("rho_hist", _dp)]
 
 
 def lib():
@@ -114,6 +115,10 @@ class OracleOptions:
     eps_abs: Optional[float] = None
     eps_rel: Optional[float] = None
     rho: Optional[float] = None
+    adaptive_rho: bool = False      # residual balancing (Boyd et al. 2011, Sec. 3.4.1)
+    rho_mu: float = 10.0
+    rho_tau: float = 2.0
+    rho_every: int = 1
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -148,6 +153,10 @@ def make_params(problem, opts: OracleOptions) -> _Params:
     p.hotstart = int(bool(opts.hotstart))
     p.lu_reuse = int(bool(opts.lu_reuse))
     p.fixed_iters = int(opts.fixed_iters)
+    p.adaptive_rho = int(bool(opts.adaptive_rho))
+    p.rho_mu = float(opts.rho_mu)
+    p.rho_tau = float(opts.rho_tau)
+    p.rho_every = max(int(opts.rho_every), 1)
     return p
 
 
@@ -171,19 +180,21 @@ class _Holder:
         self.mu = np.zeros((N, T, nu))
         self.pa = np.zeros((P, T), dtype=np.uint8)
         self.hist = np.zeros((max(maxit, 1), 4))
+        self.rho_hist = np.zeros(max(maxit, 1))
         self.z = np.zeros((N, N, T, dp)) if keep_zl else None
         self.lam = np.zeros((N, N, T, dp)) if keep_zl else None
         self.sc = _Scenario(N, T, _ptr(self.x0), _ptr(self.xref), _ptr(self.q), _ptr(self.r), _ptr(self.normals))
         self.res = _Result(_ptr(self.x), _ptr(self.u), self.w.ctypes.data_as(C.POINTER(C.c_byte)), _ptr(self.mu),
                            self.pa.ctypes.data_as(C.POINTER(C.c_ubyte)), _ptr(self.z), _ptr(self.lam),
-                           _ptr(self.hist), 0, 0, 0.0, 0.0, 0.0, 0.0, 0, 0)
+                           _ptr(self.hist), 0, 0, 0.0, 0.0, 0.0, 0.0, 0, 0, _ptr(self.rho_hist))
 
     def output(self) -> Dict[str, object]:
         r = self.res
         out = dict(x=self.x, u=self.u, w=self.w, mu=self.mu, pair_active=self.pa,
                    status=int(r.status), iters=int(r.iters), r_norm=float(r.r_norm), s_norm=float(r.s_norm),
                    eps_pri=float(r.eps_pri), eps_dual=float(r.eps_dual), as_passes=int(r.as_passes),
-                   lu_factorizations=int(r.lu_factorizations), hist=self.hist[:max(int(r.iters), 0)])
+                   lu_factorizations=int(r.lu_factorizations), hist=self.hist[:max(int(r.iters), 0)],
+                   rho_hist=self.rho_hist[:max(int(r.iters), 0)])
         if self.z is not None:
             out["z"] = self.z
             out["lam"] = self.lam

@@ -89,6 +89,7 @@ typedef struct {
   const orc_params *prm;
   int T, n_nbr, nx, nu, dp, nv, nd;
   const double *x0;
+  const double *qd;  /* diagonal of Q */
   double *Hd;      /* [nv] diagonal of H                       */
   double *cv;      /* [nv] linear term                          */
   /* KKT factor cache, valid for the working set stored in wkey */
@@ -198,6 +199,7 @@ static int qp_ws_init(qp_ws *q, const orc_params *prm, int T, int n_nbr, const d
   q->nv = T * (q->nu + q->nx);
   q->nd = T * q->nx;
   q->x0 = x0;
+  q->qd = qd;
   const int nkmax = q->nv + q->nd + T * q->nu;
   q->Hd = (double *)malloc(sizeof(double) * q->nv);
   q->cv = (double *)malloc(sizeof(double) * q->nv);
@@ -226,6 +228,17 @@ static void qp_ws_set_linear(qp_ws *q, const double *xref, const double *qd, con
       const double wq = (t == q->T ? q->prm->qT_scale : 1.0) * qd[r];
       q->cv[ix(q, t, r)] = -2.0 * wq * xref[t * q->nx + r] - (r < q->dp && ysum ? ysum[t * q->dp + r] : 0.0);
     }
+}
+
+/* A new penalty rho: the position entries of H change, so the cached KKT
+ * factors no longer hold. */
+static void qp_ws_set_rho(qp_ws *q, double rho) {
+  for (int t = 1; t <= q->T; ++t)
+    for (int r = 0; r < q->dp; ++r) {
+      const double wq = (t == q->T ? q->prm->qT_scale : 1.0) * q->qd[r];
+      q->Hd[ix(q, t, r)] = 2.0 * wq + rho * (double)q->n_nbr;
+    }
+  q->cache_valid = 0;
 }
 
 static void qp_ws_free(qp_ws *q) {
@@ -382,7 +395,7 @@ static int all_finite(const double *a, size_t n) {
 int orc_admm(const orc_params *prm, const orc_scenario *sc, orc_result *res, int threads) {
   const int N = sc->N, T = sc->T, nx = prm->nx, nu = prm->nu, dp = prm->dp;
   const int P = N * (N - 1) / 2;
-  const double rho = prm->rho;
+  double rho = prm->rho;
   const size_t zsz = (size_t)N * N * T * dp;
   if (threads < 1) threads = 1;
 
@@ -533,6 +546,7 @@ int orc_admm(const orc_params *prm, const orc_scenario *sc, orc_result *res, int
       res->hist[(k - 1) * 4 + 0] = rn; res->hist[(k - 1) * 4 + 1] = sn;
       res->hist[(k - 1) * 4 + 2] = eps_pri; res->hist[(k - 1) * 4 + 3] = eps_dual;
     }
+    if (res->rho_hist) res->rho_hist[k - 1] = rho;
     if (!isfinite(rn) || !isfinite(sn) || !all_finite(res->x, (size_t)N * (T + 1) * nx)) {
       res->status = ORC_NONFINITE;
       break;
@@ -540,9 +554,20 @@ int orc_admm(const orc_params *prm, const orc_scenario *sc, orc_result *res, int
     const int conv = (rn <= eps_pri) && (sn <= eps_dual);
     if (prm->fixed_iters > 0) {
       if (k == maxit) res->status = conv ? ORC_CONVERGED : ORC_MAX_ITER;
-      continue;
+    } else if (conv) {
+      res->status = ORC_CONVERGED;
+      break;
     }
-    if (conv) { res->status = ORC_CONVERGED; break; }
+    /* residual balancing: the next iteration's penalty (none after the last) */
+    if (prm->adaptive_rho && k < maxit && k % prm->rho_every == 0) {
+      double nr = rho;
+      if (rn > prm->rho_mu * sn) nr = rho * prm->rho_tau;
+      else if (sn > prm->rho_mu * rn) nr = rho / prm->rho_tau;
+      if (nr != rho) {
+        rho = nr;
+        for (int i = 0; i < N; ++i) qp_ws_set_rho(&qs[i], rho);
+      }
+    }
   }
 
   if (res->z || res->lam)

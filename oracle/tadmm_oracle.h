@@ -49,6 +49,12 @@ typedef struct {
   int hotstart;              /* 1: later ADMM iterations start from the previous (w, W) */
   int lu_reuse;              /* 1: keep the KKT factors while W is unchanged */
   int fixed_iters;           /* > 0: run exactly this many iterations (stop test ignored) */
+  /* Adaptive penalty by residual balancing (Boyd et al. 2011, Sec. 3.4.1):
+   * every rho_every iterations, rho <- rho_tau rho if r > rho_mu s,
+   * rho <- rho / rho_tau if s > rho_mu r (lambda unscaled, unchanged). */
+  int adaptive_rho;
+  double rho_mu, rho_tau;
+  int rho_every;
 } orc_params;
 
 typedef struct {
@@ -73,6 +79,7 @@ typedef struct {
   double r_norm, s_norm, eps_pri, eps_dual;
   long as_passes;            /* equality-QP solves over the whole run */
   long lu_factorizations;
+  double *rho_hist;          /* optional [max_iter]: the rho of iteration k */
 } orc_result;
 
 /* One agent's local QP (Eq. 3) with the consensus data folded into

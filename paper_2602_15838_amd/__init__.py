@@ -40,7 +40,8 @@ class Params(C.Structure):
                 ("max_iter", C.c_int32), ("max_as_iter", C.c_int32), ("normal_mode", C.c_int32),
                 ("cache_factors", C.c_int32), ("riccati_warmstart", C.c_int32), ("hotstart", C.c_int32),
                 ("check_inputs", C.c_int32), ("block_threads", C.c_int32), ("refine", C.c_int32),
-                ("refine_band", C.c_float), ("eqp_fp64", C.c_int32)]
+                ("refine_band", C.c_float), ("eqp_fp64", C.c_int32), ("adaptive_rho", C.c_int32),
+                ("rho_mu", C.c_float), ("rho_tau", C.c_float), ("rho_every", C.c_int32)]
 
 
 _fp = C.POINTER(C.c_float)
@@ -108,7 +109,8 @@ EXPORTED_SYMBOLS = ("tadmm_workspace_size", "tadmm_create", "tadmm_solve", "tadm
 def make_params(problem, *, normal_mode: int = NORMAL_PER_ITER, mu_tol: float = 1e-5, max_as_iter: int = 0,
                 cache_factors: bool = True, riccati_warmstart: bool = True, hotstart: bool = True,
                 check_inputs: bool = True, block_threads: int = 0, refine: bool = True,
-                refine_band: float = 10.0, eqp_fp64: bool = True, max_iter: Optional[int] = None,
+                refine_band: float = 10.0, eqp_fp64: bool = True, adaptive_rho: bool = False,
+                rho_mu: float = 10.0, rho_tau: float = 2.0, rho_every: int = 1, max_iter: Optional[int] = None,
                 eps_abs: Optional[float] = None, eps_rel: Optional[float] = None,
                 rho: Optional[float] = None) -> Params:
     """Fill the C parameter struct from a problem description (attributes
@@ -140,6 +142,10 @@ def make_params(problem, *, normal_mode: int = NORMAL_PER_ITER, mu_tol: float = 
     p.refine = int(bool(refine))
     p.refine_band = float(refine_band)
     p.eqp_fp64 = int(bool(eqp_fp64))
+    p.adaptive_rho = int(bool(adaptive_rho))
+    p.rho_mu = float(rho_mu)
+    p.rho_tau = float(rho_tau)
+    p.rho_every = int(rho_every)
     return p
 
 

@@ -35,6 +35,8 @@ struct Prob {
   float refine_band;             // refine when both residuals are within this factor of their tolerances (0: always)
   int max_iter, max_as, normal_mode, cache, warm, hot, refine;
   int cont;                      // continue from the workspace's state (a later SQP round)
+  int adapt, rho_every;          // residual balancing of the per-scenario penalty
+  float rho_mu, rho_tau;
 };
 
 // Per-scenario table columns (int64).
@@ -65,6 +67,7 @@ struct WS {
   float *snorm;                      // [S][SN_NCOL]
   unsigned long long *cnt;           // [S][CT_NCOL]
   int *skip;                         // [S] SQP: scenario converged, not solved again
+  float *rhos;                       // [S][2] penalty of the next / of the last iteration
   // inputs (caller layouts)
   const float *x0, *xref, *qd, *rd, *normals;
 };
@@ -251,10 +254,11 @@ struct Dyn<NX, NU, true> {
 // Stage weights (cost Eq. 1 without 1/2, penalty (rho/2)||.||^2 per partner):
 // H_x,t = 2 Q_t + rho n_nbr C'C with Q_T = qT Q; H_u = 2 R.
 template <int NX, int NU>
-__device__ __forceinline__ void stage_hx(const Prob &pb, const float *qd, int t, int T, int n_nbr, float hx[NX]) {
+__device__ __forceinline__ void stage_hx(const Prob &pb, const float *qd, int t, int T, int n_nbr, float rho,
+                                         float hx[NX]) {
   const float w = (t == T) ? pb.qT : 1.0f;
 #pragma unroll
-  for (int r = 0; r < NX; ++r) hx[r] = 2.0f * w * qd[r] + (r < NU ? pb.rho * (float)n_nbr : 0.0f);
+  for (int r = 0; r < NX; ++r) hx[r] = 2.0f * w * qd[r] + (r < NU ? rho * (float)n_nbr : 0.0f);
 }
 
 // ---------------------------------------------------------------------------

@@ -61,9 +61,11 @@ struct AgentView {
   const float *qd;            // diagonal of Q
   unsigned GS, N, i;
   float lo[NU], hi[NU], hu[NU];
+  float rho, rho_prev;        // penalty of this iteration, of the last one
   __device__ __forceinline__ AgentView(const Prob &pb, const WS &ws, const Scen &sc, int i_)
       : R(ws.fr + sc.fo), Wb(ws.wr + sc.bo), D(ws.dr + sc.dof), dirty(ws.adirty + (sc.ao + i_) * NU_),
-        qd(ws.qd + (long long)sc.s * NX), GS((unsigned)sc.GS), N((unsigned)sc.N), i((unsigned)i_) {
+        qd(ws.qd + (long long)sc.s * NX), GS((unsigned)sc.GS), N((unsigned)sc.N), i((unsigned)i_),
+        rho(ws.rhos[2 * sc.s]), rho_prev(ws.rhos[2 * sc.s + 1]) {
     const float *rd = ws.rd + (long long)sc.s * NU;
 #pragma unroll
     for (int a = 0; a < NU; ++a) { lo[a] = pb.ulo[a]; hi[a] = pb.uhi[a]; hu[a] = 2.0f * rd[a]; }
@@ -79,12 +81,13 @@ struct AgentView {
   __device__ __forceinline__ float &KV(int a, int t) const { return f(F::KV + a, t); }
   __device__ __forceinline__ float &UE(int a, int t) const { return f(F::UE + a, t); }
   __device__ __forceinline__ float &Q(int r, int t) const { return f(F::Q + r, t); }
+  __device__ __forceinline__ float &ZD(int c, int t) const { return f(F::ZD + c, t); }
   __device__ __forceinline__ float &X(int r, int t) const { return f(F::X + r, t); }
   __device__ __forceinline__ float &U(int a, int t) const { return f(F::U + a, t); }
   __device__ __forceinline__ int8_t &w(int a, int t) const { return Wb[g(t) * 4u + a]; }
   __device__ __forceinline__ double &d(int r, int t) const { return D[g(t) * (unsigned)NX + r]; }
   __device__ __forceinline__ void hx(const Prob &pb, int t, int T, int n_nbr, float h[NX]) const {
-    stage_hx<NX, NU>(pb, qd, t, T, n_nbr, h);
+    stage_hx<NX, NU>(pb, qd, t, T, n_nbr, rho, h);
   }
 };
 
@@ -108,10 +111,11 @@ struct AxisView {
   int *dirty;
   unsigned GS, N, i, c;
   float qd[2], lo[1], hi[1], hu[1];
+  float rho, rho_prev;        // penalty of this iteration, of the last one
   __device__ __forceinline__ AxisView(const Prob &pb, const WS &ws, const Scen &sc, int i_, int c_)
       : R(ws.fr + sc.fo), AX(ws.fr + sc.fo + (long long)Fld<NXF, NUF>::NF * sc.GS), Wb(ws.wr + sc.bo),
         D(ws.dr + sc.dof), dirty(ws.adirty + (sc.ao + i_) * NUF + c_), GS((unsigned)sc.GS), N((unsigned)sc.N),
-        i((unsigned)i_), c((unsigned)c_) {
+        i((unsigned)i_), c((unsigned)c_), rho(ws.rhos[2 * sc.s]), rho_prev(ws.rhos[2 * sc.s + 1]) {
     const float *q = ws.qd + (long long)sc.s * NXF;
     const float *rd = ws.rd + (long long)sc.s * NUF;
     qd[0] = q[c];
@@ -140,6 +144,7 @@ struct AxisView {
   __device__ __forceinline__ float &UE(int, int t) const { return ax(AXG_AFF, 1, t); }
   __device__ __forceinline__ float &PU(int k, int t) const { return ax(AXG_P, k, t); }
   __device__ __forceinline__ float &Q(int r, int t) const { return fref(R, GS, g(t), F::Q + (int)st(r)); }
+  __device__ __forceinline__ float &ZD(int, int t) const { return fref(R, GS, g(t), F::ZD + (int)c); }
   __device__ __forceinline__ float &X(int r, int t) const { return fref(R, GS, g(t), F::X + (int)st(r)); }
   __device__ __forceinline__ float &U(int, int t) const { return fref(R, GS, g(t), F::U + (int)c); }
   __device__ __forceinline__ int8_t &w(int, int t) const { return Wb[g(t) * 4u + c]; }
@@ -147,7 +152,7 @@ struct AxisView {
   // stage_hx of the axis: 2 w q_pos + rho n_nbr on the position, 2 w q_vel
   __device__ __forceinline__ void hx(const Prob &pb, int t, int T, int n_nbr, float h[2]) const {
     const float w = (t == T) ? pb.qT : 1.0f;
-    h[0] = 2.0f * w * qd[0] + pb.rho * (float)n_nbr;
+    h[0] = 2.0f * w * qd[0] + rho * (float)n_nbr;
     h[1] = 2.0f * w * qd[1];
   }
 };
@@ -680,6 +685,24 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, const
   // FP32 rounding of the local QP is far below what the iteration resolves)
   const bool refine = pb.refine && (pb.refine_band <= 0.f || uni(ws.sst[(long long)sc.s * ST_NCOL + ST_NEAR]) != 0);
 
+  if (m.rho != m.rho_prev) {
+    // The penalty changed after the last test (residual balancing).  The
+    // position part of the linear term, GQP - rho (n_nbr C x + ZD) +
+    // sum_j lambda_ij, moves by (rho_prev - rho)(n_nbr C x + ZD); the stage
+    // Hessians change, so every factor is stale, including P_T.
+    const float d = m.rho_prev - m.rho;
+    for (int t = 0; t <= T; ++t)
+#pragma unroll
+      for (int c = 0; c < NU; ++c) m.Q(c, t) = fmaf(d, fmaf((float)n_nbr, m.X(c, t), m.ZD(c, t)), m.Q(c, t));
+    float hT[NX];
+    m.hx(pb, T, T, n_nbr, hT);
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int c = r; c < NX; ++c) m.PU(sym_idx<NX>(r, c), T) = (r == c) ? hT[r] : 0.f;
+    td = T - 1;
+  }
+
   if ((k == 1 && !pb.cont) || !pb.hot) {
     // fresh start: empty working set ...
     for (int t = 0; t < T; ++t)
@@ -885,7 +908,7 @@ __device__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, i
   for (int c = 0; c < NX; ++c) bad |= !isfinite(Ri(F::X + c));
   float *gm = ws.gam + sc.lo;
   uint8_t *pa = ws.pact + sc.lb;
-  const float rho = pb.rho, irho = 1.0f / pb.rho;
+  const float rho = ws.rhos[2 * sc.s], irho = 1.0f / rho;
   const bool frozen = pb.normal_mode == NORMAL_FROZEN;
   float es[NU], zd[NU], ls[NU];   // sum (lam_old - 2 lam_new), sum (z - C x), sum lam_new
 #pragma unroll
@@ -1040,6 +1063,14 @@ __device__ int scenario_test(const Prob &pb, const WS &ws, const Scen &sc, int k
       sn_out[SN_R] = rn; sn_out[SN_S] = sn; sn_out[SN_EPRI] = epri; sn_out[SN_EDUAL] = edual;
     }
     st[ST_NEAR] = (rn <= pb.refine_band * epri && sn <= pb.refine_band * edual) ? 1 : 0;
+    // residual balancing (Boyd et al. 2011, Sec. 3.4.1): the next iteration's
+    // penalty; the last one is kept for the x-update's correction
+    float *rh = ws.rhos + 2 * sc.s;
+    rh[1] = rh[0];
+    if (!done && pb.adapt && k % pb.rho_every == 0) {
+      if (rn > pb.rho_mu * sn) rh[0] = rh[1] * pb.rho_tau;
+      else if (sn > pb.rho_mu * rn) rh[0] = rh[1] / pb.rho_tau;
+    }
     st[ST_STATUS] = status;
     st[ST_ITERS] = k;
     st[ST_DONE] = done;
@@ -1069,7 +1100,7 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
         auto Rg = [&](int f) -> float & { return R[fidx((unsigned)GS, (unsigned)idx, f)]; };
 #pragma unroll
         for (int c = 0; c < NU; ++c) {
-          Rg(F::Q + c) = fmaf(-pb.rho * (float)n_nbr, Rg(F::X + c), Rg(F::GQP + c));
+          Rg(F::Q + c) = fmaf(-ws.rhos[2 * sc.s] * (float)n_nbr, Rg(F::X + c), Rg(F::GQP + c));
           Rg(F::ZD + c) = 0.f;
         }
       }
@@ -1123,7 +1154,7 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
     }
     if (t == T) {
       float hx[NX];
-      stage_hx<NX, NU>(pb, qd, T, T, n_nbr, hx);
+      stage_hx<NX, NU>(pb, qd, T, T, n_nbr, pb.rho, hx);
 #pragma unroll
       for (int r2 = 0; r2 < NX; ++r2)
 #pragma unroll
@@ -1155,6 +1186,7 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
     st[ST_NEAR] = 0;
     float *sn = ws.snorm + (long long)sc.s * SN_NCOL;
     sn[SN_R] = sn[SN_S] = sn[SN_EPRI] = sn[SN_EDUAL] = 0.f;
+    ws.rhos[2 * sc.s] = ws.rhos[2 * sc.s + 1] = pb.rho;
   }
 }
 
@@ -1623,6 +1655,7 @@ struct Layout {
   size_t o_er = 0, o_nrm = 0, o_cidx = 0, o_clist = 0, o_cg = 0, o_m = 0;
   size_t o_wide = 0;   // wide mode: iteration number, scenario index
   size_t o_sqpj = 0, o_sqpi = 0, o_sqpf = 0;   // SQP: objective [S] (FP64); skip, rounds [2][S]; min distance [S]
+  size_t o_rho = 0;    // [S][2] penalty of the next / last iteration
   long long sumPT = 0;
   std::vector<long long> tab;
   std::vector<int> order;
@@ -1655,6 +1688,10 @@ bool params_ok(const tadmm_params *p, std::string &err) {
   }
   if (!(std::isfinite(p->mu_tol) && p->mu_tol >= 0.f)) { err = "mu_tol must be >= 0"; return false; }
   if (!(std::isfinite(p->refine_band) && p->refine_band >= 0.f)) { err = "refine_band must be >= 0"; return false; }
+  if (p->adaptive_rho && !(std::isfinite(p->rho_mu) && p->rho_mu >= 1.f && std::isfinite(p->rho_tau) &&
+                           p->rho_tau > 1.f && p->rho_every >= 1)) {
+    err = "adaptive_rho needs rho_mu >= 1, rho_tau > 1 and rho_every >= 1"; return false;
+  }
   if (p->max_iter < 1) { err = "max_iter must be >= 1"; return false; }
   if (p->normal_mode != TADMM_NORMAL_PER_ITER && p->normal_mode != TADMM_NORMAL_FROZEN) {
     err = "unknown normal_mode"; return false;
@@ -1725,6 +1762,7 @@ bool make_layout(const tadmm_params *p, int S, const int32_t *N, const int32_t *
   L.o_sqpj = take(sizeof(double) * S);
   L.o_sqpi = take(sizeof(int) * 2 * S);
   L.o_sqpf = take(sizeof(float) * S);
+  L.o_rho = take(sizeof(float) * 2 * S);
   L.bytes = off;
   // launch order for the persistent queue: largest N^2 T first (LPT)
   L.order.resize(S);
@@ -1772,6 +1810,10 @@ Prob to_prob(const tadmm_params &p) {
   pb.cache = p.cache_factors ? 1 : 0; pb.warm = p.riccati_warmstart ? 1 : 0; pb.hot = p.hotstart ? 1 : 0;
   pb.refine = p.refine ? 1 : 0;
   pb.refine_band = p.refine_band;
+  pb.adapt = p.adaptive_rho ? 1 : 0;
+  pb.rho_every = std::max(p.rho_every, 1);
+  pb.rho_mu = p.rho_mu;
+  pb.rho_tau = p.rho_tau;
   return pb;
 }
 
@@ -1867,6 +1909,7 @@ WS make_ws(const Layout &L, char *ws, const tadmm_batch *b) {
   w.x0 = b->x0; w.xref = b->xref; w.qd = b->q_diag; w.rd = b->r_diag;
   w.normals = (b->normals && true) ? b->normals : nullptr;
   w.skip = (int *)(ws + L.o_sqpi);
+  w.rhos = (float *)(ws + L.o_rho);
   return w;
 }
 

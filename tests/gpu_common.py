@@ -78,7 +78,8 @@ def self_sensitivity(problem, sc, opts, rel=1e-7, seed=0, threads=1) -> float:
 def oracle_opts(solver_kw=None, lockstep=None):
     kw = dict(solver_kw or {})
     o = oracle.OracleOptions()
-    for k in ("normal_mode", "mu_tol", "max_as_iter", "max_iter", "eps_abs", "eps_rel", "rho"):
+    for k in ("normal_mode", "mu_tol", "max_as_iter", "max_iter", "eps_abs", "eps_rel", "rho", "adaptive_rho",
+              "rho_mu", "rho_tau", "rho_every"):
         if k in kw:
             setattr(o, k, kw[k])
     if "riccati_warmstart" in kw:

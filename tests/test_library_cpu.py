@@ -78,6 +78,18 @@ def test_inverted_box_rejected():
     assert _ws(prm, [2], [20])[0] == 1
 
 
+@pytest.mark.parametrize("field, value", [("rho_mu", 0.5), ("rho_tau", 1.0), ("rho_every", 0),
+                                          ("rho_tau", float("nan"))])
+def test_bad_adaptive_rho_params_rejected(field, value):
+    prm = tadmm.make_params(synth.ProblemParams(), adaptive_rho=True)
+    assert _ws(prm, [2], [20])[0] == 0
+    setattr(prm, field, value)
+    rc, _ = _ws(prm, [2], [20])
+    assert rc == 1
+    prm.adaptive_rho = 0          # the fields are not read with a fixed penalty
+    assert _ws(prm, [2], [20])[0] == 0
+
+
 @pytest.mark.parametrize("N,T", [([0], [20]), ([2], [0]), ([5000], [10])])
 def test_bad_shapes_rejected(N, T):
     prm = tadmm.make_params(synth.ProblemParams())

@@ -34,6 +34,7 @@ MUTANTS = {
     "consensus_init_zero": ("z[ZI(i, j, t) + k] = sc->xref[((size_t)i * (T + 1) + t) * nx + k];",
                             "z[ZI(i, j, t) + k] = 0.0;"),
     "never_drops_negative_multiplier": ("if (drop >= 0 && mu_min < -prm->mu_tol) {", "if (0) {"),
+    "adaptive_rho_keeps_stale_hessian": ("for (int i = 0; i < N; ++i) qp_ws_set_rho(&qs[i], rho);", "(void)qs;"),
 }
 
 # The fast pins (each well under a second on the committed oracle).  Mistakes
@@ -51,7 +52,8 @@ PIN_FUNCS = [pins.test_agent_qp_unconstrained_matches_condensed_least_squares,
              pins.test_admm_residual_history_consistent_with_iterates,
              pins.test_admm_translation_invariance,
              pins.test_admm_single_agent_converges_first_iteration,
-             pins.test_admm_frozen_limit_is_centralized_qp_kkt_certificate]
+             pins.test_admm_frozen_limit_is_centralized_qp_kkt_certificate,
+             pins.test_admm_adaptive_rho_frozen_limit_is_the_same_kkt_point]
 
 
 def _call_pin(fn):

@@ -253,6 +253,37 @@ def test_admm_frozen_limit_is_centralized_qp_kkt_certificate():
     assert np.all(m >= -1e-7)
 
 
+def test_admm_adaptive_rho_frozen_limit_is_the_same_kkt_point():
+    """Residual balancing (Boyd et al. 2011, Sec. 3.4.1) changes the path,
+    not the fixed point: from a penalty 100x too large the run adapts rho,
+    and its limit passes the same centralized-QP certificate and equals the
+    fixed-penalty limit."""
+    p = synth.ProblemParams(dp=2, u_max=2.0)
+    sc, nrm = _side_pass()
+    tight = dict(normal_mode=oracle.NORMAL_FROZEN, max_iter=20000, eps_abs=1e-11, eps_rel=1e-11)
+    res = oracle.solve(p, sc, oracle.OracleOptions(rho=1000.0, adaptive_rho=True, **tight), normals=nrm)
+    assert res["status"] == oracle.CONVERGED
+    assert len(np.unique(res["rho_hist"])) >= 3 and res["rho_hist"][-1] < 1000.0
+    fixed = oracle.solve(p, sc, oracle.OracleOptions(rho=10.0, **tight), normals=nrm)
+    np.testing.assert_allclose(res["u"], fixed["u"], atol=1e-7)
+    J, b, G, h = _monolithic_pieces(p, sc, nrm)
+    U = res["u"].reshape(-1)
+    assert np.all(G @ U - h >= -1e-7)
+    grad = 2.0 * J.T @ (J @ U - b)
+    W = res["w"].reshape(-1)
+    cols = []
+    for k in np.nonzero(W)[0]:
+        e = np.zeros(U.size)
+        e[k] = 1.0 if W[k] == 1 else -1.0
+        cols.append(e)
+    for k in np.nonzero(np.abs(G @ U - h) < 1e-6)[0]:
+        cols.append(G[k])
+    M = np.array(cols).T
+    m, *_ = np.linalg.lstsq(M, grad, rcond=None)
+    assert np.linalg.norm(M @ m - grad) < 1e-6 * (1 + np.linalg.norm(grad))
+    assert np.all(m >= -1e-7)
+
+
 def test_admm_frozen_limit_matches_slsqp():
     p = synth.ProblemParams(dp=2, u_max=2.0)
     sc, nrm = _side_pass()
