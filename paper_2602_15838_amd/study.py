@@ -38,7 +38,10 @@ stopping rule of Sec. V-A (relative objective change 1e-4, every pair at
 least d_min - sep_tol apart): wall time, rounds, outcomes, and the same
 batch through one solve with the normals re-linearized every iteration.
 
-    python -m paper_2602_15838_amd.study [--ablation] [--sweep] [--sqp] [--seeds 20]
+Penalty (adaptive rho).  The benchmark's batch with rho fixed and adapted
+by residual balancing: converged fraction, iterations, refactors, time.
+
+    python -m paper_2602_15838_amd.study [--ablation] [--sweep] [--sqp] [--rho] [--seeds 20]
 
 prints one JSON object per line.
 """
@@ -201,15 +204,49 @@ def sqp_study(S: int = 4096, max_rounds: int = 10, rtol: float = 1e-4, sep_tol: 
                                             admm_converged=round(float((s1 == tadmm.SCEN_CONVERGED).mean()), 4)))]
 
 
+def rho_study(S: int = 4096) -> List[Dict]:
+    """The benchmark's batch with the penalty fixed (rho = 1) and adapted by
+    residual balancing (mu = 10, tau = 2, every iteration): converged
+    fraction, mean iterations, refactored stages and time."""
+    import torch
+
+    import synth
+    import paper_2602_15838_amd as tadmm
+    problem, scs = synth.config2(S=S)
+    pk = synth.pack(problem, scs)
+    recs = []
+    for name, kw in (("fixed", {}), ("adaptive", dict(adaptive_rho=True, rho_mu=10.0, rho_tau=2.0, rho_every=1))):
+        solver = tadmm.Solver(tadmm.make_params(problem, **kw))
+        prep = solver.prepare(pk.n_agents, pk.horizon, pk.x0, pk.xref, pk.q_diag, pk.r_diag)
+        prep.run(tadmm.MODE_BATCHED)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prep.run(tadmm.MODE_BATCHED)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = prep.o["status"].cpu().numpy()
+        it = prep.o["iters"].cpu().numpy()
+        cnt = prep.o["counters"].cpu().numpy()
+        recs.append(dict(study="rho", penalty=name, scenarios=S, ms=round(1e3 * dt, 2),
+                         scenario_solves_per_s=round(S / dt, 1),
+                         converged=round(float((st == tadmm.SCEN_CONVERGED).mean()), 4),
+                         mean_iters=round(float(it.mean()), 2),
+                         mean_iters_converged=round(float(it[st == tadmm.SCEN_CONVERGED].mean()), 2),
+                         refactored_axis_stages=int(cnt[:, 1].sum())))
+        solver.close()
+    return recs
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--ablation", action="store_true")
     ap.add_argument("--sweep", action="store_true")
     ap.add_argument("--sqp", action="store_true")
+    ap.add_argument("--rho", action="store_true")
     ap.add_argument("--seeds", type=int, default=20)
     args = ap.parse_args(argv)
-    if not (args.ablation or args.sweep or args.sqp):
-        args.ablation = args.sweep = args.sqp = True
+    if not (args.ablation or args.sweep or args.sqp or args.rho):
+        args.ablation = args.sweep = args.sqp = args.rho = True
     import torch
     torch.cuda.set_device(0)
     if args.ablation:
@@ -220,6 +257,9 @@ def main(argv=None):
             print(json.dumps(rec), flush=True)
     if args.sqp:
         for rec in sqp_study():
+            print(json.dumps(rec), flush=True)
+    if args.rho:
+        for rec in rho_study():
             print(json.dumps(rec), flush=True)
 
 
