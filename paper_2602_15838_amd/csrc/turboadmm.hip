@@ -91,12 +91,14 @@ struct AgentView {
   }
 };
 
-// Groups of an axis-stage: factor (K_0, K_1, S'^-1, kc), value terms
-// (c_0, c_1, p_0, p_1), affine terms (k, equality-QP input, -, -) and the
-// packed value Hessian (P_00, P_01, P_11, -).
-enum { AXG_FAC = 0, AXG_VAL, AXG_AFF, AXG_P, AXG_N };
+// Arrays of the axis-stage region, each [a][width] floats over the
+// axis-stages a, so that a pass writes whole contiguous spans: the factor
+// (K_0, K_1, S'^-1, kc), the value constant (c_0, c_1), the affine value
+// term (p_0, p_1; written where the input is fixed), the affine terms (k,
+// the equality-QP input) and the packed value Hessian (P_00, P_01, P_11, -).
+enum { AXA_FAC = 0, AXA_C = 4, AXA_PV = 6, AXA_AFF = 8, AXA_P = 10, AXA_W = 14 };   // offsets in units of GA floats
 // floats of a scenario's axis-stage region (GS agent-stages, dp axes)
-__host__ __device__ constexpr long long axis_region_floats(long long GS, int dp) { return 4ll * AXG_N * GS * dp; }
+__host__ __device__ constexpr long long axis_region_floats(long long GS, int dp) { return (long long)AXA_W * GS * dp; }
 
 template <int NXF, int NUF>
 struct AxisView {
@@ -131,18 +133,20 @@ struct AxisView {
   }
   __device__ __forceinline__ unsigned g(int t) const { return (unsigned)t * N + i; }
   __device__ __forceinline__ unsigned st(int r) const { return r ? NUF + c : c; }   // state index in the agent
-  __device__ __forceinline__ float &ax(int grp, int slot, int t) const {
-    float *base = AX + (size_t)((unsigned)grp * (GS * (unsigned)NUF * 4u));
-    return base[(g(t) * (unsigned)NUF + c) * 4u + (unsigned)slot];
+  // element `slot` of array `arr` (offset arr * GA floats, `width` floats per axis-stage)
+  template <int ARR, int WIDTH>
+  __device__ __forceinline__ float &ax(int slot, int t) const {
+    float *base = AX + (size_t)((unsigned)ARR * (GS * (unsigned)NUF));
+    return base[(g(t) * (unsigned)NUF + c) * (unsigned)WIDTH + (unsigned)slot];
   }
-  __device__ __forceinline__ float &K(int, int col, int t) const { return ax(AXG_FAC, col, t); }
-  __device__ __forceinline__ float &SV(int, int t) const { return ax(AXG_FAC, 2, t); }
-  __device__ __forceinline__ float &KC(int, int t) const { return ax(AXG_FAC, 3, t); }
-  __device__ __forceinline__ float &CC(int r, int t) const { return ax(AXG_VAL, r, t); }
-  __device__ __forceinline__ float &PV(int r, int t) const { return ax(AXG_VAL, 2 + r, t); }
-  __device__ __forceinline__ float &KV(int, int t) const { return ax(AXG_AFF, 0, t); }
-  __device__ __forceinline__ float &UE(int, int t) const { return ax(AXG_AFF, 1, t); }
-  __device__ __forceinline__ float &PU(int k, int t) const { return ax(AXG_P, k, t); }
+  __device__ __forceinline__ float &K(int, int col, int t) const { return ax<AXA_FAC, 4>(col, t); }
+  __device__ __forceinline__ float &SV(int, int t) const { return ax<AXA_FAC, 4>(2, t); }
+  __device__ __forceinline__ float &KC(int, int t) const { return ax<AXA_FAC, 4>(3, t); }
+  __device__ __forceinline__ float &CC(int r, int t) const { return ax<AXA_C, 2>(r, t); }
+  __device__ __forceinline__ float &PV(int r, int t) const { return ax<AXA_PV, 2>(r, t); }
+  __device__ __forceinline__ float &KV(int, int t) const { return ax<AXA_AFF, 2>(0, t); }
+  __device__ __forceinline__ float &UE(int, int t) const { return ax<AXA_AFF, 2>(1, t); }
+  __device__ __forceinline__ float &PU(int k, int t) const { return ax<AXA_P, 4>(k, t); }
   __device__ __forceinline__ float &Q(int r, int t) const { return fref(R, GS, g(t), F::Q + (int)st(r)); }
   __device__ __forceinline__ float &ZD(int, int t) const { return fref(R, GS, g(t), F::ZD + (int)c); }
   __device__ __forceinline__ float &X(int r, int t) const { return fref(R, GS, g(t), F::X + (int)st(r)); }
@@ -1160,7 +1164,7 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
 #pragma unroll
         for (int c = r2; c < NX; ++c) Rg(F::PU + sym_idx<NX>(r2, c)) = (r2 == c) ? hx[r2] : 0.f;
       // and of each axis problem (the axis-stage region follows the fields)
-      float *AP = R + (size_t)F::NF * GS + (size_t)AXG_P * GS * NU * 4;
+      float *AP = R + (size_t)F::NF * GS + (size_t)AXA_P * GS * NU;
 #pragma unroll
       for (int c = 0; c < NU; ++c) {
         float *e = AP + ((size_t)idx * NU + c) * 4;
