@@ -105,9 +105,7 @@ struct Fld {
   static constexpr int CC = KC + pad4(NU);      // value-gradient constant c_t    [NX]
   // linear term of the local QP at stage t:
   //   q_t = -2 Q_t r_t - C' sum_j (rho z_ij,t - lambda_ij,t);
-  // its position part is rewritten by every consensus step as
-  //   GQP - rho n_nbr C x^k_t - sum_j (lambda_ij^(k-1) - 2 lambda_ij^k)
-  // from the small dual part (no long sums of position-sized terms in FP32)
+  // its velocity part (constant) is here, its position part in QZ
   static constexpr int Q = CC + pad4(NX);       //                                [NX]
   static constexpr int PV = Q + pad4(NX);       // affine value term p_t          [NX]
   static constexpr int KV = PV + pad4(NX);      // affine feedforward k_t         [NU]
@@ -115,8 +113,12 @@ struct Fld {
   static constexpr int X = U + pad4(NU);        // current iterate x_t            [NX]
   static constexpr int UE = X + pad4(NX);       // equality-QP solution u_t       [NU]
   static constexpr int XP = UE + pad4(NU);      // C x^k (previous positions)     [DP]
-  static constexpr int ZD = XP + pad4(DP);      // sum_j z_ij - n_nbr C x^k       [DP]
-  static constexpr int GQP = ZD + pad4(DP);     // -2 Q_t r_t, positions          [DP]
+  // written together by every consensus step: the position part of q,
+  //   GQP - rho n_nbr C x^k_t - sum_j (lambda_ij^(k-1) - 2 lambda_ij^k)
+  // (from the small dual part: no long sums of position-sized terms in
+  // FP32), then ZD = sum_j z_ij - n_nbr C x^k                      [2 DP]
+  static constexpr int QZ = XP + pad4(DP);
+  static constexpr int GQP = QZ + pad4(2 * DP);  // -2 Q_t r_t, positions          [DP]
   static constexpr int PU = GQP + pad4(DP);     // value Hessian P_t (upper)      [NP]
   static constexpr int RED = PU + pad4(NP);     // residual partial sums          [5]
   static constexpr int NF = RED + pad4(5);

@@ -80,8 +80,8 @@ struct AgentView {
   __device__ __forceinline__ float &PV(int r, int t) const { return f(F::PV + r, t); }
   __device__ __forceinline__ float &KV(int a, int t) const { return f(F::KV + a, t); }
   __device__ __forceinline__ float &UE(int a, int t) const { return f(F::UE + a, t); }
-  __device__ __forceinline__ float &Q(int r, int t) const { return f(F::Q + r, t); }
-  __device__ __forceinline__ float &ZD(int c, int t) const { return f(F::ZD + c, t); }
+  __device__ __forceinline__ float &Q(int r, int t) const { return f(r < NU ? F::QZ + r : F::Q + r, t); }
+  __device__ __forceinline__ float &ZD(int c, int t) const { return f(F::QZ + NU + c, t); }
   __device__ __forceinline__ float &X(int r, int t) const { return f(F::X + r, t); }
   __device__ __forceinline__ float &U(int a, int t) const { return f(F::U + a, t); }
   __device__ __forceinline__ int8_t &w(int a, int t) const { return Wb[g(t) * 4u + a]; }
@@ -147,8 +147,10 @@ struct AxisView {
   __device__ __forceinline__ float &KV(int, int t) const { return ax<AXA_AFF, 2>(0, t); }
   __device__ __forceinline__ float &UE(int, int t) const { return ax<AXA_AFF, 2>(1, t); }
   __device__ __forceinline__ float &PU(int k, int t) const { return ax<AXA_P, 4>(k, t); }
-  __device__ __forceinline__ float &Q(int r, int t) const { return fref(R, GS, g(t), F::Q + (int)st(r)); }
-  __device__ __forceinline__ float &ZD(int, int t) const { return fref(R, GS, g(t), F::ZD + (int)c); }
+  __device__ __forceinline__ float &Q(int r, int t) const {
+    return fref(R, GS, g(t), r ? F::Q + NUF + (int)c : F::QZ + (int)c);
+  }
+  __device__ __forceinline__ float &ZD(int, int t) const { return fref(R, GS, g(t), F::QZ + NUF + (int)c); }
   __device__ __forceinline__ float &X(int r, int t) const { return fref(R, GS, g(t), F::X + (int)st(r)); }
   __device__ __forceinline__ float &U(int, int t) const { return fref(R, GS, g(t), F::U + (int)c); }
   __device__ __forceinline__ int8_t &w(int, int t) const { return Wb[g(t) * 4u + c]; }
@@ -1001,12 +1003,12 @@ __device__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, i
 #pragma unroll
   for (int c = 0; c < NU; ++c) {
     // rho sum_j (z_ij^(k+1) - z_ij^k) = rho (n_nbr (C x^(k+1) - C x^k) + ZD^(k+1) - ZD^k)
-    const float ds = rho * fmaf(nn, pi[c] - qi[c], zd[c] - Ri(F::ZD + c));
+    const float ds = rho * fmaf(nn, pi[c] - qi[c], zd[c] - Ri(F::QZ + NU + c));
     s2 = fmaf(ds, ds, s2);
     ax2 = fmaf(pi[c], pi[c], ax2);
     aty2 = fmaf(ls[c], ls[c], aty2);
-    Ri(F::Q + c) = fmaf(-rho * nn, pi[c], Ri(F::GQP + c)) - es[c];
-    Ri(F::ZD + c) = zd[c];
+    Ri(F::QZ + c) = fmaf(-rho * nn, pi[c], Ri(F::GQP + c)) - es[c];
+    Ri(F::QZ + NU + c) = zd[c];
   }
   ax2 *= nn;
   if (bad) r2 = NAN;
@@ -1104,8 +1106,8 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
         auto Rg = [&](int f) -> float & { return R[fidx((unsigned)GS, (unsigned)idx, f)]; };
 #pragma unroll
         for (int c = 0; c < NU; ++c) {
-          Rg(F::Q + c) = fmaf(-ws.rhos[2 * sc.s] * (float)n_nbr, Rg(F::X + c), Rg(F::GQP + c));
-          Rg(F::ZD + c) = 0.f;
+          Rg(F::QZ + c) = fmaf(-ws.rhos[2 * sc.s] * (float)n_nbr, Rg(F::X + c), Rg(F::GQP + c));
+          Rg(F::QZ + NU + c) = 0.f;
         }
       }
       float *gm = ws.gam + sc.lo;
@@ -1142,9 +1144,9 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
     for (int c = 0; c < NU; ++c) {
       // x^0 := r so that z^0 = C r, lambda^0 = 0
       Rg(F::GQP + c) = gq[c];
-      Rg(F::Q + c) = fmaf(-pb.rho * (float)n_nbr, r[c], gq[c]);
+      Rg(F::QZ + c) = fmaf(-pb.rho * (float)n_nbr, r[c], gq[c]);
       Rg(F::XP + c) = r[c];
-      Rg(F::ZD + c) = 0.f;
+      Rg(F::QZ + NU + c) = 0.f;
       Rg(F::U + c) = 0.f;
     }
 #pragma unroll
