@@ -48,6 +48,22 @@ namespace tadmm {
 // V::kBatch stages are loaded per batch in the sweeps: all their loads are
 // issued before the first one is used, so a batch costs about one memory
 // round trip instead of one per stage.
+// Arrays of the axis-stage region, each [a][width] floats over the
+// axis-stages a, so that a pass writes whole contiguous spans: the factor
+// (K_0, K_1, S'^-1, kc), the value constant (c_0, c_1), the affine value
+// term (p_0, p_1; written where the input is fixed), the affine terms (k,
+// the equality-QP input) and the packed value Hessian (P_00, P_01, P_11, -).
+enum { AXA_FAC = 0, AXA_C = 4, AXA_PV = 6, AXA_AFF = 8, AXA_P = 10, AXA_W = 14 };   // offsets in units of GA floats
+// floats of a scenario's axis-stage region (GS agent-stages, dp axes)
+__host__ __device__ constexpr long long axis_region_floats(long long GS, int dp) { return (long long)AXA_W * GS * dp; }
+// The inputs u are a dense [GS][NU] array after the axis-stage region (a pass
+// writes every input of a stage: whole contiguous spans).
+__host__ __device__ constexpr long long input_region_floats(long long GS, int nu) { return GS * nu; }
+template <int NX, int NU>
+__device__ __forceinline__ float &uref(float *R, unsigned GS, unsigned g, int c) {
+  return R[(size_t)Fld<NX, NU>::NF * GS + (size_t)axis_region_floats(GS, NU) + (size_t)g * NU + c];
+}
+
 template <int NX_, int NU_, bool DI_>
 struct AgentView {
   static constexpr int NX = NX_, NU = NU_, NS = NU_ * (NU_ + 1) / 2, NP = NX_ * (NX_ + 1) / 2;
@@ -83,22 +99,13 @@ struct AgentView {
   __device__ __forceinline__ float &Q(int r, int t) const { return f(r < NU ? F::QZ + r : F::Q + r, t); }
   __device__ __forceinline__ float &ZD(int c, int t) const { return f(F::QZ + NU + c, t); }
   __device__ __forceinline__ float &X(int r, int t) const { return f(F::X + r, t); }
-  __device__ __forceinline__ float &U(int a, int t) const { return f(F::U + a, t); }
+  __device__ __forceinline__ float &U(int a, int t) const { return uref<NX, NU>(R, GS, g(t), a); }
   __device__ __forceinline__ int8_t &w(int a, int t) const { return Wb[g(t) * 4u + a]; }
   __device__ __forceinline__ double &d(int r, int t) const { return D[g(t) * (unsigned)NX + r]; }
   __device__ __forceinline__ void hx(const Prob &pb, int t, int T, int n_nbr, float h[NX]) const {
     stage_hx<NX, NU>(pb, qd, t, T, n_nbr, rho, h);
   }
 };
-
-// Arrays of the axis-stage region, each [a][width] floats over the
-// axis-stages a, so that a pass writes whole contiguous spans: the factor
-// (K_0, K_1, S'^-1, kc), the value constant (c_0, c_1), the affine value
-// term (p_0, p_1; written where the input is fixed), the affine terms (k,
-// the equality-QP input) and the packed value Hessian (P_00, P_01, P_11, -).
-enum { AXA_FAC = 0, AXA_C = 4, AXA_PV = 6, AXA_AFF = 8, AXA_P = 10, AXA_W = 14 };   // offsets in units of GA floats
-// floats of a scenario's axis-stage region (GS agent-stages, dp axes)
-__host__ __device__ constexpr long long axis_region_floats(long long GS, int dp) { return (long long)AXA_W * GS * dp; }
 
 template <int NXF, int NUF>
 struct AxisView {
@@ -152,7 +159,7 @@ struct AxisView {
   }
   __device__ __forceinline__ float &ZD(int, int t) const { return fref(R, GS, g(t), F::QZ + NUF + (int)c); }
   __device__ __forceinline__ float &X(int r, int t) const { return fref(R, GS, g(t), F::X + (int)st(r)); }
-  __device__ __forceinline__ float &U(int, int t) const { return fref(R, GS, g(t), F::U + (int)c); }
+  __device__ __forceinline__ float &U(int, int t) const { return uref<NXF, NUF>(R, GS, g(t), (int)c); }
   __device__ __forceinline__ int8_t &w(int, int t) const { return Wb[g(t) * 4u + c]; }
   __device__ __forceinline__ double &d(int r, int t) const { return D[g(t) * (unsigned)NXF + st(r)]; }
   // stage_hx of the axis: 2 w q_pos + rho n_nbr on the position, 2 w q_vel
@@ -1147,7 +1154,7 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
       Rg(F::QZ + c) = fmaf(-pb.rho * (float)n_nbr, r[c], gq[c]);
       Rg(F::XP + c) = r[c];
       Rg(F::QZ + NU + c) = 0.f;
-      Rg(F::U + c) = 0.f;
+      uref<NX, NU>(R, (unsigned)GS, (unsigned)idx, c) = 0.f;
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) Wb[(unsigned)idx * 4u + c] = 0;
@@ -1549,7 +1556,7 @@ __global__ __launch_bounds__(256) void k_sqp_eval(Prob pb, WS ws, double *jprev,
       } else {
 #pragma unroll
         for (int a = 0; a < NU; ++a) {
-          const double u = (double)R[fidx(GS, (unsigned)e, F::U + a)];
+          const double u = (double)uref<NX, NU>(const_cast<float *>(R), GS, (unsigned)e, a);
           v = fma((double)rd[a] * u, u, v);
         }
       }
@@ -1616,7 +1623,7 @@ __global__ void k_writeback(WS ws, int S, tadmm_out out) {
     if (out.u || out.w)
       for (int e = threadIdx.x; e < N * T * NU; e += blockDim.x) {
         const int c = e % NU, it = e / NU, t = it % T, i = it / T;
-        if (out.u) out.u[sc.uo * NU + e] = R[fidx((unsigned)sc.GS, (unsigned)(t * N + i), F::U + c)];
+        if (out.u) out.u[sc.uo * NU + e] = uref<NX, NU>(const_cast<float *>(R), (unsigned)sc.GS, (unsigned)(t * N + i), c);
         if (out.w) out.w[sc.uo * NU + e] = Wb[(unsigned)(t * N + i) * 4u + c];
       }
     if (out.pair_active)
@@ -1720,7 +1727,7 @@ bool make_layout(const tadmm_params *p, int S, const int32_t *N, const int32_t *
     if (n < 1 || t < 1) { err = "every scenario needs N >= 1 and T >= 1"; return false; }
     if (n > 4096 || t > 65536) { err = "scenario too large (N <= 4096, T <= 65536)"; return false; }
     const long long GS = n * (t + 1);
-    if ((long long)L.NF * GS + axis_region_floats(GS, p->nu) >= (1ll << 31) ||
+    if ((long long)L.NF * GS + axis_region_floats(GS, p->nu) + input_region_floats(GS, p->nu) >= (1ll << 31) ||
         (long long)p->nu * t * n * n >= (1ll << 31) ||
         (long long)p->nx * GS >= (1ll << 31)) {
       err = "scenario too large for 32-bit in-scenario offsets"; return false;
@@ -1728,7 +1735,7 @@ bool make_layout(const tadmm_params *p, int S, const int32_t *N, const int32_t *
     long long *tb = &L.tab[(size_t)s * TB_NCOL];
     tb[TB_F] = fo; tb[TB_B] = bo; tb[TB_L] = lo; tb[TB_A] = ao; tb[TB_XO] = xo; tb[TB_UO] = uo; tb[TB_PO] = po; tb[TB_LB] = lb;
     tb[TB_D] = dof;
-    fo += (long long)L.NF * GS + axis_region_floats(GS, p->nu);
+    fo += (long long)L.NF * GS + axis_region_floats(GS, p->nu) + input_region_floats(GS, p->nu);
     dof += (long long)p->nx * GS;
     bo += 4ll * GS;
     lo += t * n * n;
