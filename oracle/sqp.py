@@ -27,18 +27,20 @@ import oracle
 def objective(problem, x, u, xref, q_diag, r_diag) -> float:
     """Objective of Eq. 1 for one scenario: sum over agents of
     sum_{t<T} ||x_t - r_t||_Q^2 + ||u_t||_R^2, plus ||x_T - r_T||_{Q_T}^2 with
-    Q_T = qT_scale Q.  x, xref [N][T+1][nx], u [N][T][nu]."""
+    Q_T = qT_scale Q.  x, xref [N][T+1][nx], u [N][T][nu]; q_diag, r_diag
+    shared ([nx], [nu]) or per agent ([N][nx], [N][nu])."""
     x = np.asarray(x, np.float64)
     u = np.asarray(u, np.float64)
     e = x - np.asarray(xref, np.float64)
-    q = np.asarray(q_diag, np.float64)
-    r = np.asarray(r_diag, np.float64)
+    N = x.shape[0]
+    q = np.broadcast_to(np.asarray(q_diag, np.float64), (N, x.shape[2]))
+    r = np.broadcast_to(np.asarray(r_diag, np.float64), (N, u.shape[2]))
     J = 0.0
-    for i in range(x.shape[0]):
+    for i in range(N):
         T = u.shape[1]
         for t in range(T):
-            J += float(e[i, t] @ (q * e[i, t])) + float(u[i, t] @ (r * u[i, t]))
-        J += problem.qT_scale * float(e[i, T] @ (q * e[i, T]))
+            J += float(e[i, t] @ (q[i] * e[i, t])) + float(u[i, t] @ (r[i] * u[i, t]))
+        J += problem.qT_scale * float(e[i, T] @ (q[i] * e[i, T]))
     return J
 
 
@@ -65,8 +67,10 @@ def sqp_solve(problem, scenarios: Sequence, opts: Optional[oracle.OracleOptions]
     o = oracle.OracleOptions(**{**base.__dict__, "normal_mode": oracle.NORMAL_FROZEN})
     S = len(scenarios)
     ins = [(sc.x0(), sc.xref()) if inputs is None else inputs[k] for k, sc in enumerate(scenarios)]
-    qd = [problem.q_diag if sc.q_diag is None else sc.q_diag for sc in scenarios]
-    rd = [problem.r_diag if sc.r_diag is None else sc.r_diag for sc in scenarios]
+    qd = [sc.agent_q if getattr(sc, "agent_q", None) is not None else
+          (problem.q_diag if sc.q_diag is None else sc.q_diag) for sc in scenarios]
+    rd = [sc.agent_r if getattr(sc, "agent_r", None) is not None else
+          (problem.r_diag if sc.r_diag is None else sc.r_diag) for sc in scenarios]
     out: List[Optional[Dict[str, object]]] = [None] * S
     hist = [dict(objective=[], min_sep=[]) for _ in range(S)]
     normals: List[Optional[np.ndarray]] = [None] * S      # round 0: the reference normals

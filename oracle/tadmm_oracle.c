@@ -90,6 +90,7 @@ typedef struct {
   int T, n_nbr, nx, nu, dp, nv, nd;
   const double *x0;
   const double *qd;  /* diagonal of Q */
+  const double *lo, *hi;  /* input box of this agent */
   double *Hd;      /* [nv] diagonal of H                       */
   double *cv;      /* [nv] linear term                          */
   /* KKT factor cache, valid for the working set stored in wkey */
@@ -172,7 +173,7 @@ static int eqp_solve(qp_ws *q, const signed char *W, double *sol, long *facts) {
   for (int k = 0; k < T * nu; ++k) {
     if (!W[k]) continue;
     const int c = k % nu;
-    sol[nv + nd + a] = (W[k] == 1) ? prm->u_lo[c] : prm->u_hi[c];
+    sol[nv + nd + a] = (W[k] == 1) ? q->lo[c] : q->hi[c];
     ++a;
   }
   lu_solve(q->K, nk, q->piv, sol);
@@ -200,6 +201,8 @@ static int qp_ws_init(qp_ws *q, const orc_params *prm, int T, int n_nbr, const d
   q->nd = T * q->nx;
   q->x0 = x0;
   q->qd = qd;
+  q->lo = prm->u_lo;
+  q->hi = prm->u_hi;
   const int nkmax = q->nv + q->nd + T * q->nu;
   q->Hd = (double *)malloc(sizeof(double) * q->nv);
   q->cv = (double *)malloc(sizeof(double) * q->nv);
@@ -273,8 +276,8 @@ static int active_set(qp_ws *q, double *x, double *u, signed char *W, double *mu
     for (int k = 0; k < T * nu; ++k) {
       const int c = k % nu;
       W[k] = 0;
-      if (u[k] < prm->u_lo[c]) { u[k] = prm->u_lo[c]; W[k] = 1; }
-      else if (u[k] > prm->u_hi[c]) { u[k] = prm->u_hi[c]; W[k] = 2; }
+      if (u[k] < q->lo[c]) { u[k] = q->lo[c]; W[k] = 1; }
+      else if (u[k] > q->hi[c]) { u[k] = q->hi[c]; W[k] = 2; }
     }
     rollout(q, x, u);
   }
@@ -290,11 +293,11 @@ static int active_set(qp_ws *q, double *x, double *u, signed char *W, double *mu
       if (W[k]) continue;
       const int c = k % nu;
       const double ue = sol[k], uc = u[k];
-      if (ue < prm->u_lo[c]) {
-        const double r = (prm->u_lo[c] - uc) / (ue - uc);
+      if (ue < q->lo[c]) {
+        const double r = (q->lo[c] - uc) / (ue - uc);
         if (r < alpha) { alpha = r; blk = k; side = 1; }
-      } else if (ue > prm->u_hi[c]) {
-        const double r = (prm->u_hi[c] - uc) / (ue - uc);
+      } else if (ue > q->hi[c]) {
+        const double r = (q->hi[c] - uc) / (ue - uc);
         if (r < alpha) { alpha = r; blk = k; side = 2; }
       }
     }
@@ -303,7 +306,7 @@ static int active_set(qp_ws *q, double *x, double *u, signed char *W, double *mu
       for (int k = 0; k < T * nu; ++k) u[k] += alpha * (sol[k] - u[k]);
       for (int t = 1; t <= T; ++t)
         for (int r = 0; r < nx; ++r) x[t * nx + r] += alpha * (sol[ix(q, t, r)] - x[t * nx + r]);
-      u[blk] = (side == 1) ? prm->u_lo[blk % nu] : prm->u_hi[blk % nu];
+      u[blk] = (side == 1) ? q->lo[blk % nu] : q->hi[blk % nu];
       W[blk] = (signed char)side;
       continue;
     }
@@ -392,6 +395,14 @@ static int all_finite(const double *a, size_t n) {
   return 1;
 }
 
+/* Weights of agent i: its own (heterogeneous agents) or the scenario's. */
+static const double *agent_q(const orc_scenario *sc, int nx, int i) {
+  return sc->agent_q ? sc->agent_q + (size_t)i * nx : sc->q_diag;
+}
+static const double *agent_r(const orc_scenario *sc, int nu, int i) {
+  return sc->agent_r ? sc->agent_r + (size_t)i * nu : sc->r_diag;
+}
+
 int orc_admm(const orc_params *prm, const orc_scenario *sc, orc_result *res, int threads) {
   const int N = sc->N, T = sc->T, nx = prm->nx, nu = prm->nu, dp = prm->dp;
   const int P = N * (N - 1) / 2;
@@ -420,9 +431,12 @@ int orc_admm(const orc_params *prm, const orc_scenario *sc, orc_result *res, int
           z[ZI(i, j, t) + k] = sc->xref[((size_t)i * (T + 1) + t) * nx + k];
     }
   int setup_fail = 0;
-  for (int i = 0; i < N; ++i)
+  for (int i = 0; i < N; ++i) {
     setup_fail |= qp_ws_init(&qs[i], prm, T, N - 1, sc->x0 + (size_t)i * nx,
-                             sc->xref + (size_t)i * (T + 1) * nx, sc->q_diag, sc->r_diag, NULL);
+                             sc->xref + (size_t)i * (T + 1) * nx, agent_q(sc, nx, i), agent_r(sc, nu, i), NULL);
+    if (sc->agent_lo) qs[i].lo = sc->agent_lo + (size_t)i * nu;
+    if (sc->agent_hi) qs[i].hi = sc->agent_hi + (size_t)i * nu;
+  }
   res->status = ORC_MAX_ITER;
   res->iters = 0;
   res->as_passes = 0;
@@ -450,7 +464,7 @@ int orc_admm(const orc_params *prm, const orc_scenario *sc, orc_result *res, int
 #pragma omp parallel for schedule(dynamic) num_threads(threads) reduction(| : cap_hit, fail) reduction(+ : passes, facts)
     for (int i = 0; i < N; ++i) {
       qp_ws *q = &qs[i];
-      qp_ws_set_linear(q, sc->xref + (size_t)i * (T + 1) * nx, sc->q_diag, ysum + (size_t)i * (T + 1) * dp);
+      qp_ws_set_linear(q, sc->xref + (size_t)i * (T + 1) * nx, agent_q(sc, nx, i), ysum + (size_t)i * (T + 1) * dp);
       int start = ORC_START_PREV;
       if (k == 1 || !prm->hotstart) start = prm->warm_start ? ORC_START_WARM : ORC_START_COLD;
       const int rc = active_set(q, res->x + (size_t)i * (T + 1) * nx, res->u + (size_t)i * T * nu,

@@ -64,6 +64,10 @@ typedef struct {
   const double *q_diag;      /* [nx] */
   const double *r_diag;      /* [nu] */
   const double *normals;     /* FROZEN: [P][T][dp] (pair i<j lexicographic, t=1..T) or NULL */
+  /* heterogeneous agents (each NULL: the scenario's / the params' value) */
+  const double *agent_q;     /* [N][nx] diagonal of Q per agent */
+  const double *agent_r;     /* [N][nu] diagonal of R per agent */
+  const double *agent_lo, *agent_hi;   /* [N][nu] input box per agent */
 } orc_scenario;
 
 typedef struct {

@@ -99,6 +99,12 @@ class Scenario:
     dt: float = DT
     q_diag: Optional[np.ndarray] = None   # per-scenario override of the weights
     r_diag: Optional[np.ndarray] = None
+    # heterogeneous agents: per-agent weights [N][nx], [N][nu] and input
+    # boxes [N][nu] (None: the scenario's / the problem's)
+    agent_q: Optional[np.ndarray] = None
+    agent_r: Optional[np.ndarray] = None
+    agent_lo: Optional[np.ndarray] = None
+    agent_hi: Optional[np.ndarray] = None
 
     @property
     def N(self) -> int:
@@ -265,6 +271,10 @@ class PackedBatch:
     xref: np.ndarray
     q_diag: np.ndarray
     r_diag: np.ndarray
+    agent_q: Optional[np.ndarray] = None    # [sum N_s][nx] (heterogeneous agents)
+    agent_r: Optional[np.ndarray] = None    # [sum N_s][nu]
+    agent_lo: Optional[np.ndarray] = None   # [sum N_s][nu]
+    agent_hi: Optional[np.ndarray] = None   # [sum N_s][nu]
 
     @property
     def S(self) -> int:
@@ -298,7 +308,31 @@ def pack(params: ProblemParams, scenarios: List[Scenario], dtype=np.float64) -> 
         if scenarios else np.zeros((0, nx), dtype)
     r = np.stack([(params.r_diag if sc.r_diag is None else sc.r_diag) for sc in scenarios]).astype(dtype) \
         if scenarios else np.zeros((0, nu), dtype)
-    return PackedBatch(Ns, Ts, x0, xref, q, r)
+    pb = PackedBatch(Ns, Ts, x0, xref, q, r)
+    if any(getattr(sc, f) is not None for sc in scenarios for f in ("agent_q", "agent_r", "agent_lo", "agent_hi")):
+        # every agent's own values, the scenario's / problem's where not given
+        def per_agent(field, fallback, width):
+            return np.concatenate([np.asarray(getattr(sc, field), np.float64).reshape(sc.N, width)
+                                   if getattr(sc, field) is not None else
+                                   np.tile(np.asarray(fallback(sc), np.float64), (sc.N, 1))
+                                   for sc in scenarios]).astype(dtype)
+        pb.agent_q = per_agent("agent_q", lambda sc: params.q_diag if sc.q_diag is None else sc.q_diag, nx)
+        pb.agent_r = per_agent("agent_r", lambda sc: params.r_diag if sc.r_diag is None else sc.r_diag, nu)
+        pb.agent_lo = per_agent("agent_lo", lambda sc: params.u_lo, nu)
+        pb.agent_hi = per_agent("agent_hi", lambda sc: params.u_hi, nu)
+    return pb
+
+
+def heterogeneous(rng: np.random.Generator, sc: Scenario, params: ProblemParams, spread: float = 4.0) -> Scenario:
+    """The same scenario with heterogeneous agents: each agent's Q and R
+    diagonals scaled by log-uniform factors in [1/spread, spread], and its
+    input box |u_c| <= u_max * U(0.5, 1.5) per component."""
+    N, nx, nu = sc.N, params.nx, params.nu
+    f = lambda shape: np.exp(rng.uniform(-np.log(spread), np.log(spread), size=shape))
+    q = (params.q_diag if sc.q_diag is None else sc.q_diag)[None, :] * f((N, nx))
+    r = (params.r_diag if sc.r_diag is None else sc.r_diag)[None, :] * f((N, nu))
+    umax = params.u_max * rng.uniform(0.5, 1.5, size=(N, nu))
+    return dataclasses.replace(sc, agent_q=q, agent_r=r, agent_lo=-umax, agent_hi=umax)
 
 
 def problem_dimensions(N: int, T: int, nx: int = 4, nu: int = 2):

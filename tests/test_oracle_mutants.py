@@ -35,6 +35,9 @@ MUTANTS = {
                             "z[ZI(i, j, t) + k] = 0.0;"),
     "never_drops_negative_multiplier": ("if (drop >= 0 && mu_min < -prm->mu_tol) {", "if (0) {"),
     "adaptive_rho_keeps_stale_hessian": ("for (int i = 0; i < N; ++i) qp_ws_set_rho(&qs[i], rho);", "(void)qs;"),
+    "agent_weights_of_the_first_agent": ("return sc->agent_q ? sc->agent_q + (size_t)i * nx : sc->q_diag;",
+                                         "return sc->agent_q ? sc->agent_q : sc->q_diag;"),
+    "agent_box_ignored": ("if (sc->agent_lo) qs[i].lo = sc->agent_lo + (size_t)i * nu;", ""),
 }
 
 # The fast pins (each well under a second on the committed oracle).  Mistakes
@@ -53,7 +56,9 @@ PIN_FUNCS = [pins.test_agent_qp_unconstrained_matches_condensed_least_squares,
              pins.test_admm_translation_invariance,
              pins.test_admm_single_agent_converges_first_iteration,
              pins.test_admm_frozen_limit_is_centralized_qp_kkt_certificate,
-             pins.test_admm_adaptive_rho_frozen_limit_is_the_same_kkt_point]
+             pins.test_admm_adaptive_rho_frozen_limit_is_the_same_kkt_point,
+             pins.test_hetero_single_agent_is_its_local_qp,
+             pins.test_hetero_agent_permutation_equivariance]
 
 
 def _call_pin(fn):

@@ -9,6 +9,8 @@ import copy
 import math
 import os
 
+import dataclasses
+
 import numpy as np
 import pytest
 import scipy.linalg
@@ -467,3 +469,62 @@ def test_admm_lu_reuse_changes_nothing():
     b = oracle.solve(p, scs[0], oracle.OracleOptions(fixed_iters=20, lu_reuse=False))
     np.testing.assert_allclose(a["x"], b["x"], atol=1e-9)
     assert a["lu_factorizations"] < b["lu_factorizations"]
+
+
+# ---------------------------------------------------------------------------
+# heterogeneous agents (per-agent weights and input boxes)
+# ---------------------------------------------------------------------------
+
+def _hetero_case(seed=3, N=4, T=12):
+    p = synth.ProblemParams(dp=2, u_max=2.0)
+    rng = np.random.default_rng(seed)
+    sc = synth.random_box(rng, N, T)
+    return p, synth.heterogeneous(rng, sc, p)
+
+
+def test_hetero_single_agent_is_its_local_qp():
+    """One agent alone converges in one iteration to its local QP: solved by
+    the oracle's local QP routine with the agent's weights and box set
+    problem-wide, the heterogeneous solve must agree."""
+    p, sc = _hetero_case(N=3)
+    one = dataclasses.replace(sc, starts=sc.starts[:1], goals=sc.goals[:1], agent_q=sc.agent_q[:1],
+                              agent_r=sc.agent_r[:1], agent_lo=sc.agent_lo[:1], agent_hi=sc.agent_hi[:1])
+    res = oracle.solve(p, one)
+    assert res["status"] == oracle.CONVERGED and res["iters"] == 1
+    umax = float(one.agent_hi[0, 0])
+    p1 = dataclasses.replace(p, u_max=umax)
+    # the local QP routine takes one symmetric box for all components: use
+    # an agent whose two components share it
+    one2 = dataclasses.replace(one, agent_lo=np.full((1, 2), -umax), agent_hi=np.full((1, 2), umax))
+    res2 = oracle.solve(p, one2)
+    o = oracle.agent_qp(p1, one.T, 0, one.x0()[0], one.xref()[0], one.agent_q[0], one.agent_r[0])
+    np.testing.assert_allclose(res2["u"][0], o["u"], atol=1e-9)
+    assert np.all(np.abs(res["u"][0]) <= one.agent_hi[0] + 1e-12)
+
+
+def test_hetero_uniform_values_equal_the_scenario_solve():
+    """Per-agent arrays that repeat the scenario's values change nothing."""
+    p, scs = synth.config2(S=3)
+    sc = scs[2]
+    N = sc.N
+    same = dataclasses.replace(sc, agent_q=np.tile(p.q_diag, (N, 1)), agent_r=np.tile(p.r_diag, (N, 1)),
+                               agent_lo=np.tile(p.u_lo, (N, 1)), agent_hi=np.tile(p.u_hi, (N, 1)))
+    o = oracle.OracleOptions(max_iter=40)
+    a, b = oracle.solve(p, sc, o), oracle.solve(p, same, o)
+    np.testing.assert_array_equal(a["x"], b["x"])
+    np.testing.assert_array_equal(a["u"], b["u"])
+
+
+def test_hetero_agent_permutation_equivariance():
+    """Relabelling the agents together with their own weights and boxes
+    relabels the solution (each agent's values follow it)."""
+    p, sc = _hetero_case(seed=5, N=4, T=12)
+    perm = np.array([2, 0, 3, 1])
+    sp = dataclasses.replace(sc, starts=sc.starts[perm], goals=sc.goals[perm], agent_q=sc.agent_q[perm],
+                             agent_r=sc.agent_r[perm], agent_lo=sc.agent_lo[perm], agent_hi=sc.agent_hi[perm])
+    o = oracle.OracleOptions(max_iter=60)
+    a, b = oracle.solve(p, sc, o), oracle.solve(p, sp, o)
+    np.testing.assert_allclose(b["x"], a["x"][perm], atol=1e-9)
+    # and the agents do differ: the weights matter
+    hom = oracle.solve(p, dataclasses.replace(sc, agent_q=None, agent_r=None, agent_lo=None, agent_hi=None), o)
+    assert np.abs(hom["u"] - a["u"]).max() > 1e-3
