@@ -157,6 +157,13 @@ typedef struct {
  *   r_diag  DEVICE float [S][nu]   diagonal of R, > 0
  *   normals DEVICE float [sum_s P_s T_s][nu] or NULL; FROZEN mode only;
  *           (s, pair i<j in lexicographic order, t = 1..T_s), unit vectors.
+ * Heterogeneous agents (each optional, NULL: the scenario's or the params'
+ * value for every agent; not supported by tadmm_polish / tadmm_adjoint,
+ * whose gradients are per scenario):
+ *   agent_q   DEVICE float [sum_s N_s][nx]  each agent's diagonal of Q, > 0
+ *   agent_r   DEVICE float [sum_s N_s][nu]  each agent's diagonal of R, > 0
+ *   agent_lo, agent_hi  DEVICE float [sum_s N_s][nu]  each agent's input
+ *             box (both or neither), finite, lo < hi
  * P_s = N_s (N_s - 1) / 2. */
 typedef struct {
   int32_t n_scen;
@@ -167,6 +174,7 @@ typedef struct {
   const float *q_diag;
   const float *r_diag;
   const float *normals;
+  const float *agent_q, *agent_r, *agent_lo, *agent_hi;
 } tadmm_batch;
 
 /* Outputs, caller-allocated DEVICE buffers (any may be NULL except status

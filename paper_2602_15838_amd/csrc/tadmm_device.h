@@ -70,6 +70,7 @@ struct WS {
   float *rhos;                       // [S][2] penalty of the next / of the last iteration
   // inputs (caller layouts)
   const float *x0, *xref, *qd, *rd, *normals;
+  const float *aq, *ar, *alo, *ahi;  // heterogeneous agents (each NULL: the shared value)
 };
 
 // Layout of a scenario's float region: structure of arrays of 4-float groups

@@ -80,11 +80,15 @@ struct AgentView {
   float rho, rho_prev;        // penalty of this iteration, of the last one
   __device__ __forceinline__ AgentView(const Prob &pb, const WS &ws, const Scen &sc, int i_)
       : R(ws.fr + sc.fo), Wb(ws.wr + sc.bo), D(ws.dr + sc.dof), dirty(ws.adirty + (sc.ao + i_) * NU_),
-        qd(ws.qd + (long long)sc.s * NX), GS((unsigned)sc.GS), N((unsigned)sc.N), i((unsigned)i_),
-        rho(ws.rhos[2 * sc.s]), rho_prev(ws.rhos[2 * sc.s + 1]) {
-    const float *rd = ws.rd + (long long)sc.s * NU;
+        qd(ws.aq ? ws.aq + (sc.ao + i_) * NX : ws.qd + (long long)sc.s * NX), GS((unsigned)sc.GS),
+        N((unsigned)sc.N), i((unsigned)i_), rho(ws.rhos[2 * sc.s]), rho_prev(ws.rhos[2 * sc.s + 1]) {
+    const float *rd = ws.ar ? ws.ar + (sc.ao + i_) * NU : ws.rd + (long long)sc.s * NU;
 #pragma unroll
-    for (int a = 0; a < NU; ++a) { lo[a] = pb.ulo[a]; hi[a] = pb.uhi[a]; hu[a] = 2.0f * rd[a]; }
+    for (int a = 0; a < NU; ++a) {
+      lo[a] = ws.alo ? ws.alo[(sc.ao + i_) * NU + a] : pb.ulo[a];
+      hi[a] = ws.ahi ? ws.ahi[(sc.ao + i_) * NU + a] : pb.uhi[a];
+      hu[a] = 2.0f * rd[a];
+    }
   }
   __device__ __forceinline__ unsigned g(int t) const { return (unsigned)t * N + i; }
   __device__ __forceinline__ float &f(int field, int t) const { return fref(R, GS, g(t), field); }
@@ -125,18 +129,22 @@ struct AxisView {
       : R(ws.fr + sc.fo), AX(ws.fr + sc.fo + (long long)Fld<NXF, NUF>::NF * sc.GS), Wb(ws.wr + sc.bo),
         D(ws.dr + sc.dof), dirty(ws.adirty + (sc.ao + i_) * NUF + c_), GS((unsigned)sc.GS), N((unsigned)sc.N),
         i((unsigned)i_), c((unsigned)c_), rho(ws.rhos[2 * sc.s]), rho_prev(ws.rhos[2 * sc.s + 1]) {
-    const float *q = ws.qd + (long long)sc.s * NXF;
-    const float *rd = ws.rd + (long long)sc.s * NUF;
+    const float *q = ws.aq ? ws.aq + (sc.ao + i_) * NXF : ws.qd + (long long)sc.s * NXF;
+    const float *rd = ws.ar ? ws.ar + (sc.ao + i_) * NUF : ws.rd + (long long)sc.s * NUF;
     qd[0] = q[c];
     qd[1] = q[NUF + c];
     hu[0] = 2.0f * rd[c];
-    // the bounds of this axis, selected without indexing the argument arrays
-    float l = pb.ulo[0], h = pb.uhi[0];
+    if (ws.alo) {   // this agent's own box
+      lo[0] = ws.alo[(sc.ao + i_) * NUF + c_];
+      hi[0] = ws.ahi[(sc.ao + i_) * NUF + c_];
+    } else {        // the bounds of this axis, selected without indexing the argument arrays
+      float l = pb.ulo[0], h = pb.uhi[0];
 #pragma unroll
-    for (int a = 1; a < NUF; ++a)
-      if (c_ == a) { l = pb.ulo[a]; h = pb.uhi[a]; }
-    lo[0] = l;
-    hi[0] = h;
+      for (int a = 1; a < NUF; ++a)
+        if (c_ == a) { l = pb.ulo[a]; h = pb.uhi[a]; }
+      lo[0] = l;
+      hi[0] = h;
+    }
   }
   __device__ __forceinline__ unsigned g(int t) const { return (unsigned)t * N + i; }
   __device__ __forceinline__ unsigned st(int r) const { return r ? NUF + c : c; }   // state index in the agent
@@ -1141,10 +1149,11 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
     auto Rg = [&](int f) -> float & { return R[fidx((unsigned)GS, (unsigned)idx, f)]; };
     const float *r = ws.xref + (sc.xo + (long long)i * (T + 1) + t) * NX;
     const float w = (t == T) ? pb.qT : 1.0f;
+    const float *qi = ws.aq ? ws.aq + (sc.ao + i) * NX : qd;   // this agent's weights
     float gq[NX];
 #pragma unroll
     for (int c = 0; c < NX; ++c) {
-      gq[c] = (t >= 1) ? -2.0f * w * qd[c] * r[c] : 0.f;
+      gq[c] = (t >= 1) ? -2.0f * w * qi[c] * r[c] : 0.f;
       if (c >= NU) Rg(F::Q + c) = gq[c];
     }
 #pragma unroll
@@ -1167,7 +1176,7 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
     }
     if (t == T) {
       float hx[NX];
-      stage_hx<NX, NU>(pb, qd, T, T, n_nbr, pb.rho, hx);
+      stage_hx<NX, NU>(pb, qi, T, T, n_nbr, pb.rho, hx);
 #pragma unroll
       for (int r2 = 0; r2 < NX; ++r2)
 #pragma unroll
@@ -1451,6 +1460,21 @@ __global__ void k_check(Prob pb, WS ws, int S, int *flags) {
     for (long long e = threadIdx.x; e < (long long)N * (T + 1) * NX; e += blockDim.x) bad |= !isfinite(ws.xref[sc.xo * NX + e]);
     if (threadIdx.x < NX) { const float q = ws.qd[(long long)s * NX + threadIdx.x]; bad |= !(isfinite(q) && q > 0.f); }
     if (threadIdx.x < NU) { const float r = ws.rd[(long long)s * NU + threadIdx.x]; bad |= !(isfinite(r) && r > 0.f); }
+    if (ws.aq)
+      for (int e = threadIdx.x; e < N * NX; e += blockDim.x) {
+        const float q = ws.aq[sc.ao * NX + e];
+        bad |= !(isfinite(q) && q > 0.f);
+      }
+    if (ws.ar)
+      for (int e = threadIdx.x; e < N * NU; e += blockDim.x) {
+        const float r = ws.ar[sc.ao * NU + e];
+        bad |= !(isfinite(r) && r > 0.f);
+      }
+    if (ws.alo)
+      for (int e = threadIdx.x; e < N * NU; e += blockDim.x) {
+        const float l = ws.alo[sc.ao * NU + e], h = ws.ahi[sc.ao * NU + e];
+        bad |= !(isfinite(l) && isfinite(h) && l < h);
+      }
     if (ws.normals && pb.normal_mode == NORMAL_FROZEN)
       for (long long e = threadIdx.x; e < (long long)N * (N - 1) / 2 * T * NU; e += blockDim.x)
         bad |= !isfinite(ws.normals[sc.po * NU + e]);
@@ -1540,11 +1564,12 @@ __global__ __launch_bounds__(256) void k_sqp_eval(Prob pb, WS ws, double *jprev,
     const int N = sc.N, T = sc.T;
     const unsigned GS = (unsigned)sc.GS;
     const float *R = ws.fr + sc.fo;
-    const float *qd = ws.qd + (long long)s * NX, *rd = ws.rd + (long long)s * NU;
     double J = 0.0;
     for (int e = threadIdx.x; e < sc.GS; e += blockDim.x) {
       const int t = e / N, i = e % N;
       const float *r = ws.xref + (sc.xo + (long long)i * (T + 1) + t) * NX;
+      const float *qd = ws.aq ? ws.aq + (sc.ao + i) * NX : ws.qd + (long long)s * NX;
+      const float *rd = ws.ar ? ws.ar + (sc.ao + i) * NU : ws.rd + (long long)s * NU;
       double v = 0.0;
 #pragma unroll
       for (int c = 0; c < NX; ++c) {
@@ -1834,6 +1859,7 @@ struct GraphKey {
   const void *ws = nullptr;
   tadmm_out out{};
   const float *x0 = nullptr, *xref = nullptr, *qd = nullptr, *rd = nullptr, *normals = nullptr;
+  const float *aq = nullptr, *ar = nullptr, *alo = nullptr, *ahi = nullptr;
   int S = 0, threads = 0, grid = 0;
   int variant = 0;   // 0: a solve; SQP rounds: 2 (first) or 3 (later, continuing)
   size_t bytes = 0;
@@ -1921,6 +1947,7 @@ WS make_ws(const Layout &L, char *ws, const tadmm_batch *b) {
   w.cnt = (unsigned long long *)(ws + L.o_cnt);
   w.x0 = b->x0; w.xref = b->xref; w.qd = b->q_diag; w.rd = b->r_diag;
   w.normals = (b->normals && true) ? b->normals : nullptr;
+  w.aq = b->agent_q; w.ar = b->agent_r; w.alo = b->agent_lo; w.ahi = b->agent_hi;
   w.skip = (int *)(ws + L.o_sqpi);
   w.rhos = (float *)(ws + L.o_rho);
   return w;
@@ -1987,6 +2014,7 @@ tadmm_status run_batched(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layo
   std::memset(&key, 0, sizeof(key));
   key.ws = ws; key.out = out; key.x0 = b->x0; key.xref = b->xref; key.qd = b->q_diag; key.rd = b->r_diag;
   key.normals = w.normals; key.S = L.S; key.threads = threads; key.grid = grid; key.bytes = bytes; key.prm = ctx->prm;
+  key.aq = w.aq; key.ar = w.ar; key.alo = w.alo; key.ahi = w.ahi;
   key.variant = variant;
   if (!(ctx->gexec && key == ctx->key)) {
     if (ctx->gexec) { (void)hipGraphExecDestroy(ctx->gexec); ctx->gexec = nullptr; }
@@ -2057,6 +2085,7 @@ tadmm_status run_wide(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layout 
   std::memset(&key, 0, sizeof(key));
   key.ws = ws; key.out = out; key.x0 = b->x0; key.xref = b->xref; key.qd = b->q_diag; key.rd = b->r_diag;
   key.normals = w.normals; key.S = L.S; key.threads = gp; key.grid = gx; key.bytes = bytes; key.prm = ctx->prm;
+  key.aq = w.aq; key.ar = w.ar; key.alo = w.alo; key.ahi = w.ahi;
   key.variant = variant;
   if (!(ctx->wexec[0] && key == ctx->wkey)) {
     for (int q = 0; q < 2; ++q) {
@@ -2120,6 +2149,7 @@ tadmm_status solve_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *o
   if (L.S == 0) return TADMM_OK;
   if (!b->x0 || !b->xref || !b->q_diag || !b->r_diag) return fail(ctx, TADMM_ERR_INVALID_ARG, "batch input pointer is NULL");
   if (!out->status || !out->iters) return fail(ctx, TADMM_ERR_INVALID_ARG, "out.status and out.iters are required");
+  if (!b->agent_lo != !b->agent_hi) return fail(ctx, TADMM_ERR_INVALID_ARG, "agent_lo and agent_hi: both or neither");
   char *w8 = (char *)ws;
   tadmm_status st = stage_tables(ctx, L, b->n_agents, b->horizon, w8);
   if (st != TADMM_OK) return st;
@@ -2166,6 +2196,7 @@ tadmm_status sqp_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *out
   if (L.S == 0) return TADMM_OK;
   if (!b->x0 || !b->xref || !b->q_diag || !b->r_diag) return fail(ctx, TADMM_ERR_INVALID_ARG, "batch input pointer is NULL");
   if (!out->status || !out->iters) return fail(ctx, TADMM_ERR_INVALID_ARG, "out.status and out.iters are required");
+  if (!b->agent_lo != !b->agent_hi) return fail(ctx, TADMM_ERR_INVALID_ARG, "agent_lo and agent_hi: both or neither");
   char *w8 = (char *)ws;
   tadmm_status st = stage_tables(ctx, L, b->n_agents, b->horizon, w8);
   if (st != TADMM_OK) return st;
@@ -2251,6 +2282,8 @@ tadmm_status eqp_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *out
   if (!ctx->solved || ctx->solved_ws != ws || ctx->solved_bytes != bytes)
     return fail(ctx, TADMM_ERR_STATE, "needs a successful tadmm_solve with this workspace first");
   const tadmm_batch &sb = ctx->solved_batch;
+  if (b->agent_q || b->agent_r || b->agent_lo || b->agent_hi)
+    return fail(ctx, TADMM_ERR_INVALID_ARG, "the derivative takes per-scenario weights (no agent_* arrays)");
   if (b->n_scen != sb.n_scen || b->x0 != sb.x0 || b->xref != sb.xref || b->q_diag != sb.q_diag ||
       b->r_diag != sb.r_diag || b->normals != sb.normals)
     return fail(ctx, TADMM_ERR_STATE, "batch differs from the one of the last tadmm_solve");
