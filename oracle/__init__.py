@@ -56,7 +56,8 @@ class _Params(C.Structure):
                 ("max_iter", C.c_int), ("max_as_iter", C.c_int), ("normal_mode", C.c_int),
                 ("warm_start", C.c_int), ("hotstart", C.c_int), ("lu_reuse", C.c_int),
                 ("fixed_iters", C.c_int), ("adaptive_rho", C.c_int), ("rho_mu", C.c_double),
-                ("rho_tau", C.c_double), ("rho_every", C.c_int)]
+                ("rho_tau", C.c_double), ("rho_every", C.c_int), ("state_box", C.c_int),
+                ("s_lo", C.c_double * 3), ("s_hi", C.c_double * 3)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -120,6 +121,9 @@ class OracleOptions:
     rho_mu: float = 10.0
     rho_tau: float = 2.0
     rho_every: int = 1
+    state_box: bool = False         # box on the non-position states (a further ADMM split)
+    s_lo: tuple = (-np.inf, -np.inf, -np.inf)
+    s_hi: tuple = (np.inf, np.inf, np.inf)
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -158,6 +162,10 @@ def make_params(problem, opts: OracleOptions) -> _Params:
     p.rho_mu = float(opts.rho_mu)
     p.rho_tau = float(opts.rho_tau)
     p.rho_every = max(int(opts.rho_every), 1)
+    p.state_box = int(bool(opts.state_box))
+    for c in range(3):
+        p.s_lo[c] = float(opts.s_lo[c])
+        p.s_hi[c] = float(opts.s_hi[c])
     return p
 
 

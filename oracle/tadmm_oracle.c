@@ -219,17 +219,24 @@ static int qp_ws_init(qp_ws *q, const orc_params *prm, int T, int n_nbr, const d
     for (int r = 0; r < q->nx; ++r) {
       const double wq = (t == T ? prm->qT_scale : 1.0) * qd[r];
       const int k = ix(q, t, r);
-      q->Hd[k] = 2.0 * wq + (r < q->dp ? prm->rho * (double)n_nbr : 0.0);
+      q->Hd[k] = 2.0 * wq + (r < q->dp ? prm->rho * (double)n_nbr : (prm->state_box ? prm->rho : 0.0));
       q->cv[k] = -2.0 * wq * xref[t * q->nx + r] - (r < q->dp && ysum ? ysum[t * q->dp + r] : 0.0);
     }
   return 0;
 }
 
-static void qp_ws_set_linear(qp_ws *q, const double *xref, const double *qd, const double *ysum) {
+/* ysum [T+1][dp]: sum_j (rho z - lambda) on the positions; vsum [T+1][dp]
+ * (or NULL): sigma y - mu on the boxed states. */
+static void qp_ws_set_linear(qp_ws *q, const double *xref, const double *qd, const double *ysum,
+                             const double *vsum) {
+  const int dp = q->dp;
   for (int t = 1; t <= q->T; ++t)
     for (int r = 0; r < q->nx; ++r) {
       const double wq = (t == q->T ? q->prm->qT_scale : 1.0) * qd[r];
-      q->cv[ix(q, t, r)] = -2.0 * wq * xref[t * q->nx + r] - (r < q->dp && ysum ? ysum[t * q->dp + r] : 0.0);
+      double v = -2.0 * wq * xref[t * q->nx + r];
+      if (r < dp && ysum) v -= ysum[t * dp + r];
+      if (r >= dp && vsum) v -= vsum[t * dp + (r - dp)];
+      q->cv[ix(q, t, r)] = v;
     }
 }
 
@@ -414,9 +421,15 @@ int orc_admm(const orc_params *prm, const orc_scenario *sc, orc_result *res, int
   double *lam = (double *)calloc(zsz, sizeof(double));
   double *zsum_old = (double *)calloc((size_t)N * T * dp, sizeof(double));
   double *ysum = (double *)calloc((size_t)N * (T + 1) * dp, sizeof(double));
+  /* state box split: yb in the box, its dual mb, vsum = sigma yb - mb */
+  const int box = prm->state_box;
+  const double sigma = prm->rho;
+  double *yb = (double *)calloc((size_t)N * (T + 1) * dp, sizeof(double));
+  double *mb = (double *)calloc((size_t)N * (T + 1) * dp, sizeof(double));
+  double *vsum = (double *)calloc((size_t)N * (T + 1) * dp, sizeof(double));
   qp_ws *qs = (qp_ws *)calloc((size_t)N, sizeof(qp_ws));
-  if (!z || !lam || !zsum_old || !ysum || !qs) {
-    free(z); free(lam); free(zsum_old); free(ysum); free(qs);
+  if (!z || !lam || !zsum_old || !ysum || !qs || !yb || !mb || !vsum) {
+    free(z); free(lam); free(zsum_old); free(ysum); free(qs); free(yb); free(mb); free(vsum);
     return -1;
   }
 #define ZI(i, j, t) (((size_t)(i) * N + (j)) * T + ((t) - 1)) * dp
@@ -430,6 +443,14 @@ int orc_admm(const orc_params *prm, const orc_scenario *sc, orc_result *res, int
         for (int k = 0; k < dp; ++k)
           z[ZI(i, j, t) + k] = sc->xref[((size_t)i * (T + 1) + t) * nx + k];
     }
+  /* y^(0): the references' boxed states, clipped; mu^(0) = 0 */
+  if (box)
+    for (int i = 0; i < N; ++i)
+      for (int t = 1; t <= T; ++t)
+        for (int c = 0; c < dp; ++c) {
+          const double r = sc->xref[((size_t)i * (T + 1) + t) * nx + dp + c];
+          yb[((size_t)i * (T + 1) + t) * dp + c] = fmin(fmax(r, prm->s_lo[c]), prm->s_hi[c]);
+        }
   int setup_fail = 0;
   for (int i = 0; i < N; ++i) {
     setup_fail |= qp_ws_init(&qs[i], prm, T, N - 1, sc->x0 + (size_t)i * nx,
@@ -464,7 +485,13 @@ int orc_admm(const orc_params *prm, const orc_scenario *sc, orc_result *res, int
 #pragma omp parallel for schedule(dynamic) num_threads(threads) reduction(| : cap_hit, fail) reduction(+ : passes, facts)
     for (int i = 0; i < N; ++i) {
       qp_ws *q = &qs[i];
-      qp_ws_set_linear(q, sc->xref + (size_t)i * (T + 1) * nx, agent_q(sc, nx, i), ysum + (size_t)i * (T + 1) * dp);
+      if (box)
+        for (int e = 0; e < (T + 1) * dp; ++e) {
+          const size_t o = (size_t)i * (T + 1) * dp + e;
+          vsum[o] = sigma * yb[o] - mb[o];
+        }
+      qp_ws_set_linear(q, sc->xref + (size_t)i * (T + 1) * nx, agent_q(sc, nx, i), ysum + (size_t)i * (T + 1) * dp,
+                       box ? vsum + (size_t)i * (T + 1) * dp : NULL);
       int start = ORC_START_PREV;
       if (k == 1 || !prm->hotstart) start = prm->warm_start ? ORC_START_WARM : ORC_START_COLD;
       const int rc = active_set(q, res->x + (size_t)i * (T + 1) * nx, res->u + (size_t)i * T * nu,
@@ -531,6 +558,23 @@ int orc_admm(const orc_params *prm, const orc_scenario *sc, orc_result *res, int
 
     /* ---- residuals and stopping test (Boyd et al. 2011, Sec. 3.3.1) ---- */
     double r2 = 0.0, s2 = 0.0, ax2 = 0.0, z2 = 0.0, aty2 = 0.0;
+    /* the state box block: y = clip(x + mu / sigma), mu += sigma (x - y) */
+    if (box)
+      for (int i = 0; i < N; ++i)
+        for (int t = 1; t <= T; ++t)
+          for (int c = 0; c < dp; ++c) {
+            const size_t o = ((size_t)i * (T + 1) + t) * dp + c;
+            const double xv = res->x[((size_t)i * (T + 1) + t) * nx + dp + c];
+            const double yn = fmin(fmax(xv + mb[o] / sigma, prm->s_lo[c]), prm->s_hi[c]);
+            const double ds = sigma * (yn - yb[o]);
+            mb[o] += sigma * (xv - yn);
+            yb[o] = yn;
+            r2 += (xv - yn) * (xv - yn);
+            s2 += ds * ds;
+            ax2 += xv * xv;
+            z2 += yn * yn;
+            aty2 += mb[o] * mb[o];
+          }
     for (int i = 0; i < N; ++i)
       for (int t = 1; t <= T; ++t) {
         const double *pi = res->x + ((size_t)i * (T + 1) + t) * nx;
@@ -553,8 +597,9 @@ int orc_admm(const orc_params *prm, const orc_scenario *sc, orc_result *res, int
         }
       }
     const double rn = sqrt(r2), sn = sqrt(s2);
-    const double eps_pri = sqrt((double)2 * P * T * dp) * prm->eps_abs + prm->eps_rel * fmax(sqrt(ax2), sqrt(z2));
-    const double eps_dual = sqrt((double)N * T * dp) * prm->eps_abs + prm->eps_rel * sqrt(aty2);
+    const double nbox = box ? (double)N * T * dp : 0.0;   /* rows and coupled states of the box block */
+    const double eps_pri = sqrt((double)2 * P * T * dp + nbox) * prm->eps_abs + prm->eps_rel * fmax(sqrt(ax2), sqrt(z2));
+    const double eps_dual = sqrt((double)N * T * dp + nbox) * prm->eps_abs + prm->eps_rel * sqrt(aty2);
     res->r_norm = rn; res->s_norm = sn; res->eps_pri = eps_pri; res->eps_dual = eps_dual;
     if (res->hist) {
       res->hist[(k - 1) * 4 + 0] = rn; res->hist[(k - 1) * 4 + 1] = sn;
@@ -594,12 +639,12 @@ int orc_admm(const orc_params *prm, const orc_scenario *sc, orc_result *res, int
             if (res->lam) res->lam[o] = (i == j) ? 0.0 : lam[o];
           }
   for (int i = 0; i < N; ++i) qp_ws_free(&qs[i]);
-  free(z); free(lam); free(zsum_old); free(ysum); free(qs);
+  free(z); free(lam); free(zsum_old); free(ysum); free(qs); free(yb); free(mb); free(vsum);
   return 0;
 
 done_fail:
   for (int i = 0; i < N; ++i) qp_ws_free(&qs[i]);
-  free(z); free(lam); free(zsum_old); free(ysum); free(qs);
+  free(z); free(lam); free(zsum_old); free(ysum); free(qs); free(yb); free(mb); free(vsum);
   return -1;
 #undef ZI
 }

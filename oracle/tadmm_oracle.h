@@ -55,6 +55,11 @@ typedef struct {
   int adaptive_rho;
   double rho_mu, rho_tau;
   int rho_every;
+  /* State box on the non-position states (x_t components dp..nx-1, t >= 1),
+   * by a further ADMM split: a copy y of those states held in the box, its
+   * dual mu, penalty sigma = the initial rho; +-inf: unbounded. */
+  int state_box;
+  double s_lo[3], s_hi[3];
 } orc_params;
 
 typedef struct {

@@ -38,6 +38,8 @@ MUTANTS = {
     "agent_weights_of_the_first_agent": ("return sc->agent_q ? sc->agent_q + (size_t)i * nx : sc->q_diag;",
                                          "return sc->agent_q ? sc->agent_q : sc->q_diag;"),
     "agent_box_ignored": ("if (sc->agent_lo) qs[i].lo = sc->agent_lo + (size_t)i * nu;", ""),
+    "state_box_dual_not_updated": ("mb[o] += sigma * (xv - yn);", "(void)0;"),
+    "state_box_missing_hessian_term": ("(prm->state_box ? prm->rho : 0.0)", "0.0"),
 }
 
 # The fast pins (each well under a second on the committed oracle).  Mistakes
@@ -58,7 +60,8 @@ PIN_FUNCS = [pins.test_agent_qp_unconstrained_matches_condensed_least_squares,
              pins.test_admm_frozen_limit_is_centralized_qp_kkt_certificate,
              pins.test_admm_adaptive_rho_frozen_limit_is_the_same_kkt_point,
              pins.test_hetero_single_agent_is_its_local_qp,
-             pins.test_hetero_agent_permutation_equivariance]
+             pins.test_hetero_agent_permutation_equivariance,
+             pins.test_admm_state_box_frozen_limit_is_centralized_qp_kkt_certificate]
 
 
 def _call_pin(fn):

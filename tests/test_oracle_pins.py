@@ -286,6 +286,55 @@ def test_admm_adaptive_rho_frozen_limit_is_the_same_kkt_point():
     assert np.all(m >= -1e-7)
 
 
+def test_admm_state_box_frozen_limit_is_centralized_qp_kkt_certificate():
+    """The state box (a further ADMM split on the velocities): with fixed
+    normals the limit solves the centralized QP with the velocity box added.
+    Certificate as above (gradient = a nonnegative combination of the
+    binding rows), with the velocity rows v_t = (Phi_t x0 + Gam_t u) in
+    [-vmax, vmax] among the constraints; the box must bind."""
+    p = synth.ProblemParams(dp=2, u_max=2.0)
+    sc, nrm = _side_pass()
+    T, dp, vmax = sc.T, p.dp, 2.8
+    res = oracle.solve(p, sc, oracle.OracleOptions(normal_mode=oracle.NORMAL_FROZEN, rho=10.0, max_iter=3000,
+                                                   eps_abs=1e-11, eps_rel=1e-11, state_box=True,
+                                                   s_lo=(-vmax,) * 3, s_hi=(vmax,) * 3), normals=nrm)
+    assert res["status"] == oracle.CONVERGED
+    J, b, G, h = _monolithic_pieces(p, sc, nrm)
+    Phi, Gam = condensed.state_maps(p.A, p.B, T)
+    n = T * p.nu
+    x0 = sc.x0()
+    rows, rhs = [], []
+    for i in range(sc.N):
+        for t in range(1, T + 1):
+            for c in range(dp):
+                g = np.zeros(sc.N * n)
+                g[i * n:(i + 1) * n] = Gam[t][dp + c]
+                v0 = (Phi[t] @ x0[i])[dp + c]
+                rows += [g, -g]
+                rhs += [-vmax - v0, -vmax + v0]
+    G = np.vstack([G, np.array(rows)])
+    h = np.concatenate([h, np.array(rhs)])
+    U = res["u"].reshape(-1)
+    slack = G @ U - h
+    assert np.all(slack >= -1e-7)
+    nbox = len(rows)
+    assert np.sum(np.abs(slack[-nbox:]) < 1e-6) >= 1, "the velocity box should bind"
+    grad = 2.0 * J.T @ (J @ U - b)
+    W = res["w"].reshape(-1)
+    cols = []
+    for k in np.nonzero(W)[0]:
+        e = np.zeros(U.size)
+        e[k] = 1.0 if W[k] == 1 else -1.0
+        cols.append(e)
+    for k in np.nonzero(np.abs(slack) < 1e-6)[0]:
+        cols.append(G[k])
+    # the active rows are dependent here (a bound input and the velocity
+    # rows it drives): certify with nonnegative least squares
+    M = np.array(cols).T
+    m, resid = scipy.optimize.nnls(M, grad)
+    assert resid < 1e-6 * (1 + np.linalg.norm(grad))
+
+
 def test_admm_frozen_limit_matches_slsqp():
     p = synth.ProblemParams(dp=2, u_max=2.0)
     sc, nrm = _side_pass()
