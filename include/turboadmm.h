@@ -147,6 +147,13 @@ typedef struct {
                                 every stage.  0: rho fixed (default)              */
   float rho_mu, rho_tau;     /* with adaptive_rho: rho_mu >= 1, rho_tau > 1      */
   int32_t rho_every;         /* with adaptive_rho: >= 1                           */
+  int32_t state_box;         /* 1: box s_lo <= x_t,k <= s_hi on the non-position
+                                states (k = nu..nx-1, the velocities of the
+                                double integrator; t = 1..T), the state sets of
+                                Eq. 1, by a further ADMM split: a copy y of those
+                                states held in the box, its dual, penalty = the
+                                initial rho.  Not with tadmm_polish/adjoint.     */
+  float s_lo[3], s_hi[3];    /* with state_box: s_lo < s_hi (+-inf: unbounded)   */
 } tadmm_params;
 
 /* A ragged batch of S independent scenarios.  Scenario s has N_s agents and

@@ -37,6 +37,8 @@ struct Prob {
   int cont;                      // continue from the workspace's state (a later SQP round)
   int adapt, rho_every;          // residual balancing of the per-scenario penalty
   float rho_mu, rho_tau;
+  int sbox;                      // box on the non-position states (ADMM split, penalty sigma)
+  float sigma, slo[3], shi[3];
 };
 
 // Per-scenario table columns (int64).
@@ -120,7 +122,11 @@ struct Fld {
   // FP32), then ZD = sum_j z_ij - n_nbr C x^k                      [2 DP]
   static constexpr int QZ = XP + pad4(DP);
   static constexpr int GQP = QZ + pad4(2 * DP);  // -2 Q_t r_t, positions          [DP]
-  static constexpr int PU = GQP + pad4(DP);     // value Hessian P_t (upper)      [NP]
+  // state box on the non-position states: the copy y and its dual mu
+  // [2 DP], and the constant velocity tracking term -2 Q_t r_t     [DP]
+  static constexpr int YM = GQP + pad4(DP);
+  static constexpr int GQV = YM + pad4(2 * DP);
+  static constexpr int PU = GQV + pad4(DP);     // value Hessian P_t (upper)      [NP]
   static constexpr int RED = PU + pad4(NP);     // residual partial sums          [5]
   static constexpr int NF = RED + pad4(5);
 };
@@ -255,13 +261,15 @@ struct Dyn<NX, NU, true> {
 };
 
 // Stage weights (cost Eq. 1 without 1/2, penalty (rho/2)||.||^2 per partner):
-// H_x,t = 2 Q_t + rho n_nbr C'C with Q_T = qT Q; H_u = 2 R.
+// H_x,t = 2 Q_t + rho n_nbr C'C with Q_T = qT Q, plus sigma on the non-position
+// states with the state box; H_u = 2 R.
 template <int NX, int NU>
 __device__ __forceinline__ void stage_hx(const Prob &pb, const float *qd, int t, int T, int n_nbr, float rho,
                                          float hx[NX]) {
   const float w = (t == T) ? pb.qT : 1.0f;
 #pragma unroll
-  for (int r = 0; r < NX; ++r) hx[r] = 2.0f * w * qd[r] + (r < NU ? rho * (float)n_nbr : 0.0f);
+  for (int r = 0; r < NX; ++r)
+    hx[r] = 2.0f * w * qd[r] + (r < NU ? rho * (float)n_nbr : (pb.sbox ? pb.sigma : 0.0f));
 }
 
 // ---------------------------------------------------------------------------

@@ -174,7 +174,7 @@ struct AxisView {
   __device__ __forceinline__ void hx(const Prob &pb, int t, int T, int n_nbr, float h[2]) const {
     const float w = (t == T) ? pb.qT : 1.0f;
     h[0] = 2.0f * w * qd[0] + rho * (float)n_nbr;
-    h[1] = 2.0f * w * qd[1];
+    h[1] = 2.0f * w * qd[1] + (pb.sbox ? pb.sigma : 0.0f);
   }
 };
 
@@ -1026,6 +1026,26 @@ __device__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, i
     Ri(F::QZ + NU + c) = zd[c];
   }
   ax2 *= nn;
+  if (pb.sbox) {
+    // the state box block: y = clip(x + mu / sigma), mu += sigma (x - y), and
+    // the next linear term -2 Q r - (sigma y - mu) on those states
+    const float sg = pb.sigma;
+#pragma unroll
+    for (int c = 0; c < NX - NU; ++c) {
+      const float xv = Ri(F::X + NU + c), yo = Ri(F::YM + c), mo = Ri(F::YM + NU + c);
+      const float yn = fminf(fmaxf(xv + mo / sg, pb.slo[c]), pb.shi[c]);
+      const float mn = fmaf(sg, xv - yn, mo);
+      const float ds = sg * (yn - yo);
+      Ri(F::YM + c) = yn;
+      Ri(F::YM + NU + c) = mn;
+      Ri(F::Q + NU + c) = Ri(F::GQV + c) - fmaf(sg, yn, -mn);
+      r2 = fmaf(xv - yn, xv - yn, r2);
+      s2 = fmaf(ds, ds, s2);
+      ax2 = fmaf(xv, xv, ax2);
+      z2 = fmaf(yn, yn, z2);
+      aty2 = fmaf(mn, mn, aty2);
+    }
+  }
   if (bad) r2 = NAN;
   Ri(F::RED + 0) = r2;
   Ri(F::RED + 1) = s2;
@@ -1068,9 +1088,12 @@ __device__ int scenario_test(const Prob &pb, const WS &ws, const Scen &sc, int k
   if (lane == 0) {
     const float P = 0.5f * (float)sc.N * (float)(sc.N - 1);
     const float rn = sqrtf(a[0]), sn = sqrtf(a[1]);
-    const float epri = sqrtf(2.0f * P * (float)sc.T * (float)NU) * pb.eps_abs +
+    // the state box block adds N T (NX - NU) rows and coupled states
+    const float nbox = pb.sbox ? (float)sc.N * (float)sc.T * (float)(NX - NU) : 0.0f;
+    const float epri = sqrtf(fmaf(2.0f * P, (float)sc.T * (float)NU, nbox)) * pb.eps_abs +
                        pb.eps_rel * fmaxf(sqrtf(a[2]), sqrtf(a[3]));
-    const float edual = sqrtf((float)sc.N * (float)sc.T * (float)NU) * pb.eps_abs + pb.eps_rel * sqrtf(a[4]);
+    const float edual = sqrtf(fmaf((float)sc.N, (float)sc.T * (float)NU, nbox)) * pb.eps_abs +
+                        pb.eps_rel * sqrtf(a[4]);
     int *st = ws.sst + (long long)sc.s * ST_NCOL;
     float *sn_out = ws.snorm + (long long)sc.s * SN_NCOL;
     int status = SCEN_MAX_ITER;
@@ -1124,6 +1147,16 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
           Rg(F::QZ + c) = fmaf(-ws.rhos[2 * sc.s] * (float)n_nbr, Rg(F::X + c), Rg(F::GQP + c));
           Rg(F::QZ + NU + c) = 0.f;
         }
+        // and the state box block restarts at y = clip(x), mu = 0
+        if (pb.sbox && idx >= N) {
+#pragma unroll
+          for (int c = 0; c < NX - NU; ++c) {
+            const float y0 = fminf(fmaxf(Rg(F::X + NU + c), pb.slo[c]), pb.shi[c]);
+            Rg(F::YM + c) = y0;
+            Rg(F::YM + NU + c) = 0.f;
+            Rg(F::Q + NU + c) = fmaf(-pb.sigma, y0, Rg(F::GQV + c));
+          }
+        }
       }
       float *gm = ws.gam + sc.lo;
       uint8_t *pa = ws.pact + sc.lb;
@@ -1154,7 +1187,15 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
 #pragma unroll
     for (int c = 0; c < NX; ++c) {
       gq[c] = (t >= 1) ? -2.0f * w * qi[c] * r[c] : 0.f;
-      if (c >= NU) Rg(F::Q + c) = gq[c];
+      if (c >= NU) {
+        // the state box: y^0 = the reference's states clipped, mu^0 = 0, and
+        // the linear term -2 Q r - (sigma y - mu)
+        const float y0 = fminf(fmaxf(r[c], pb.slo[c - NU]), pb.shi[c - NU]);
+        Rg(F::GQV + c - NU) = gq[c];
+        Rg(F::YM + c - NU) = y0;
+        Rg(F::YM + NU + c - NU) = 0.f;
+        Rg(F::Q + c) = (pb.sbox && t >= 1) ? fmaf(-pb.sigma, y0, gq[c]) : gq[c];
+      }
     }
 #pragma unroll
     for (int c = 0; c < NU; ++c) {
@@ -1730,6 +1771,11 @@ bool params_ok(const tadmm_params *p, std::string &err) {
                            p->rho_tau > 1.f && p->rho_every >= 1)) {
     err = "adaptive_rho needs rho_mu >= 1, rho_tau > 1 and rho_every >= 1"; return false;
   }
+  if (p->state_box)
+    for (int c = 0; c < p->nx - p->nu; ++c)
+      if (std::isnan(p->s_lo[c]) || std::isnan(p->s_hi[c]) || !(p->s_lo[c] < p->s_hi[c])) {
+        err = "state_box needs s_lo < s_hi (infinite ends allowed)"; return false;
+      }
   if (p->max_iter < 1) { err = "max_iter must be >= 1"; return false; }
   if (p->normal_mode != TADMM_NORMAL_PER_ITER && p->normal_mode != TADMM_NORMAL_FROZEN) {
     err = "unknown normal_mode"; return false;
@@ -1852,6 +1898,9 @@ Prob to_prob(const tadmm_params &p) {
   pb.rho_every = std::max(p.rho_every, 1);
   pb.rho_mu = p.rho_mu;
   pb.rho_tau = p.rho_tau;
+  pb.sbox = p.state_box ? 1 : 0;
+  pb.sigma = p.rho;
+  for (int c = 0; c < 3; ++c) { pb.slo[c] = p.s_lo[c]; pb.shi[c] = p.s_hi[c]; }
   return pb;
 }
 
@@ -2284,6 +2333,8 @@ tadmm_status eqp_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *out
   const tadmm_batch &sb = ctx->solved_batch;
   if (b->agent_q || b->agent_r || b->agent_lo || b->agent_hi)
     return fail(ctx, TADMM_ERR_INVALID_ARG, "the derivative takes per-scenario weights (no agent_* arrays)");
+  if (ctx->prm.state_box)
+    return fail(ctx, TADMM_ERR_INVALID_ARG, "the derivative covers input bounds only (no state_box)");
   if (b->n_scen != sb.n_scen || b->x0 != sb.x0 || b->xref != sb.xref || b->q_diag != sb.q_diag ||
       b->r_diag != sb.r_diag || b->normals != sb.normals)
     return fail(ctx, TADMM_ERR_STATE, "batch differs from the one of the last tadmm_solve");

@@ -80,13 +80,16 @@ def oracle_opts(solver_kw=None, lockstep=None):
     kw = dict(solver_kw or {})
     o = oracle.OracleOptions()
     for k in ("normal_mode", "mu_tol", "max_as_iter", "max_iter", "eps_abs", "eps_rel", "rho", "adaptive_rho",
-              "rho_mu", "rho_tau", "rho_every"):
+              "rho_mu", "rho_tau", "rho_every", "state_box"):
         if k in kw:
             setattr(o, k, kw[k])
     if "riccati_warmstart" in kw:
         o.warm_start = bool(kw["riccati_warmstart"])
     if "hotstart" in kw:
         o.hotstart = bool(kw["hotstart"])
+    for k in ("s_lo", "s_hi"):
+        if k in kw:
+            setattr(o, k, tuple(float(np.float32(v)) for v in kw[k]) + (0.0,) * (3 - len(kw[k])))
     if lockstep:
         o.fixed_iters = lockstep
     return o

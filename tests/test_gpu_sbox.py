@@ -1,0 +1,123 @@
+"""The state box (bounds on the non-position states, here the velocities, by
+a further ADMM split: y = clip(x + mu / sigma), mu += sigma (x - y), with
+sigma the penalty) on the device against the oracle's, through the C ABI.
+Lockstep runs follow the oracle's iterates to the parity bar; with frozen
+normals the converged device solution is the oracle's solution of the same
+strictly convex QP, and its velocities respect the box; the three modes agree
+bitwise; the derivative rejects the box."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import gpu_common as gc
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2602_15838_amd as tadmm  # noqa: E402
+
+VMAX = 2.0
+BOX = dict(state_box=True, s_lo=(-VMAX, -VMAX), s_hi=(VMAX, VMAX))
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _vel(r, dp):
+    return np.abs(r["x"][:, 1:, dp:])
+
+
+def test_state_box_lockstep_matches_oracle():
+    p, scs = synth.config2(S=12)
+    K = 40
+    _say(f"state-box lockstep K={K}, vmax {VMAX}, N = {[s.N for s in scs]}")
+    kw = dict(BOX, max_iter=K, eps_abs=0.0, eps_rel=0.0)
+    g = gc.gpu_solve(p, scs, solver_kw=kw)
+    o = gc.oracle_same_instance(p, scs, gc.oracle_opts(kw, lockstep=K), threads=4)
+    free = gc.gpu_solve(p, scs, solver_kw=dict(max_iter=K, eps_abs=0.0, eps_rel=0.0))
+    worst, differs = 0.0, 0
+    for sc, gr, orr, fr in zip(scs, g, o, free):
+        assert orr["iters"] == K and (gr["iters"] == K or (gr["status"] == tadmm.SCEN_CONVERGED and
+                                                            gr["r_norm"] == 0.0 and gr["s_norm"] == 0.0))
+        rel = gc.rel_traj_err(gr, orr)
+        worst = max(worst, rel)
+        assert rel <= gc.REL_TOL, (sc.N, sc.T, rel)
+        differs += not np.array_equal(gr["x"], fr["x"])
+    _say(f"  worst rel {worst:.2e}; {differs} of {len(scs)} differ from the unboxed run")
+    assert differs >= len(scs) // 2        # the box binds (it changes the iterates)
+
+
+def _side_pass(T=20):
+    sc = synth.Scenario(starts=np.array([[-3.0, 0.6], [3.0, -0.6]]), goals=np.array([[3.0, 0.1], [-3.0, -0.1]]), T=T)
+    nrm = np.zeros((1, T, 2))
+    nrm[..., 1] = 1.0
+    return sc, nrm
+
+
+@pytest.mark.parametrize("vmax", [2.5, 1.5])
+def test_state_box_frozen_limit_matches_oracle(vmax):
+    """Two agents passing side by side with a fixed normal: the device's
+    converged solution equals the oracle's tight solution of the same QP,
+    and the velocities stay within the box (to the ADMM tolerance).  The
+    bounds are off the grid of velocities that inputs at their bounds reach
+    (multiples of u_max dt = 0.2): on that grid the binding box and the
+    binding input bounds are degenerate, and ADMM's convergence there slows
+    to a crawl once FP32 rounding leaves the box a hair out of reach."""
+    p = synth.ProblemParams(dp=2, u_max=2.0)
+    sc, nrm = _side_pass()
+    box = dict(state_box=True, s_lo=(-vmax, -vmax), s_hi=(vmax, vmax))
+    base = dict(box, normal_mode=tadmm.NORMAL_FROZEN, rho=10.0)
+    g = gc.gpu_solve(p, [sc], normals=[nrm], solver_kw=dict(base, max_iter=20000, eps_abs=1e-6, eps_rel=1e-6))[0]
+    o = gc.oracle_same_instance(p, [sc], gc.oracle_opts(dict(base, max_iter=20000, eps_abs=1e-11, eps_rel=1e-11)),
+                                normals=[nrm])[0]
+    free = gc.oracle_same_instance(p, [sc], gc.oracle_opts(dict(base, state_box=False, max_iter=20000,
+                                                                eps_abs=1e-11, eps_rel=1e-11)), normals=[nrm])[0]
+    rel = gc.rel_traj_err(g, o)
+    _say(f"  vmax {vmax}: device {g['iters']} iterations, status {g['status']}; rel {rel:.2e}; "
+         f"max |v| {_vel(g, p.dp).max():.4f} (unboxed {_vel(free, p.dp).max():.4f})")
+    assert o["status"] == oracle.CONVERGED and g["status"] == tadmm.SCEN_CONVERGED
+    assert _vel(free, p.dp).max() > vmax + 0.05            # the box binds
+    assert rel <= gc.REL_TOL
+    assert _vel(g, p.dp).max() <= vmax + 1e-3
+
+
+def test_state_box_modes_bitwise_equal():
+    p, scs = synth.config2(S=10)
+    kw = dict(BOX, max_iter=100)
+    a = gc.gpu_solve(p, scs, mode=tadmm.MODE_PLAIN, solver_kw=kw)
+    for mode in (tadmm.MODE_BATCHED, tadmm.MODE_WIDE):
+        b = gc.gpu_solve(p, scs, mode=mode, solver_kw=kw)
+        for ga, gb in zip(a, b):
+            assert ga["iters"] == gb["iters"] and ga["status"] == gb["status"]
+            np.testing.assert_array_equal(ga["x"], gb["x"])
+
+
+def test_state_box_with_adaptive_rho_lockstep():
+    """Both options together: the box keeps its sigma (the initial penalty)
+    while the consensus penalty adapts."""
+    p, scs = synth.config2(S=6)
+    K = 40
+    kw = dict(BOX, adaptive_rho=True, rho_mu=10.0, rho_tau=2.0, rho_every=1, max_iter=K, eps_abs=0.0, eps_rel=0.0)
+    g = gc.gpu_solve(p, scs, solver_kw=kw)
+    o = gc.oracle_same_instance(p, scs, gc.oracle_opts(kw, lockstep=K), threads=4)
+    for sc, gr, orr in zip(scs, g, o):
+        rel = gc.rel_traj_err(gr, orr)
+        _say(f"  N={sc.N} T={sc.T}: rel {rel:.2e}, rho values {np.unique(orr['rho_hist']).tolist()}")
+        assert rel <= gc.REL_TOL
+
+
+def test_state_box_derivative_rejected():
+    p, scs = synth.config0()
+    res, prep, solver = gc.gpu_solve(p, scs, solver_kw=dict(BOX, max_iter=50), return_prep=True)
+    with pytest.raises(tadmm.TadmmError) as e:
+        prep.polish()
+    assert "error 1" in str(e.value)
+    solver.close()

@@ -90,6 +90,20 @@ def test_bad_adaptive_rho_params_rejected(field, value):
     assert _ws(prm, [2], [20])[0] == 0
 
 
+@pytest.mark.parametrize("lo, hi", [(1.0, 1.0), (2.0, -2.0), (float("nan"), 1.0), (float("inf"), float("inf"))])
+def test_bad_state_box_rejected(lo, hi):
+    prm = tadmm.make_params(synth.ProblemParams(), state_box=True, s_lo=(-1.0, -1.0), s_hi=(1.0, 1.0))
+    assert _ws(prm, [2], [20])[0] == 0
+    prm.s_lo[1], prm.s_hi[1] = lo, hi
+    assert _ws(prm, [2], [20])[0] == 1
+    prm.state_box = 0             # the bounds are not read without the box
+    assert _ws(prm, [2], [20])[0] == 0
+    # a one-sided box (an infinite end) is allowed; the unused third slot is not read in 2-D
+    prm = tadmm.make_params(synth.ProblemParams(), state_box=True, s_lo=(-1.0, -np.inf), s_hi=(np.inf, 1.0))
+    prm.s_lo[2] = prm.s_hi[2] = float("nan")
+    assert _ws(prm, [2], [20])[0] == 0
+
+
 @pytest.mark.parametrize("N,T", [([0], [20]), ([2], [0]), ([5000], [10])])
 def test_bad_shapes_rejected(N, T):
     prm = tadmm.make_params(synth.ProblemParams())

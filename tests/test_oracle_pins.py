@@ -294,7 +294,7 @@ def test_admm_state_box_frozen_limit_is_centralized_qp_kkt_certificate():
     [-vmax, vmax] among the constraints; the box must bind."""
     p = synth.ProblemParams(dp=2, u_max=2.0)
     sc, nrm = _side_pass()
-    T, dp, vmax = sc.T, p.dp, 2.8
+    T, dp, vmax = sc.T, p.dp, 2.5    # off the grid of multiples of u_max dt (degenerate there)
     res = oracle.solve(p, sc, oracle.OracleOptions(normal_mode=oracle.NORMAL_FROZEN, rho=10.0, max_iter=3000,
                                                    eps_abs=1e-11, eps_rel=1e-11, state_box=True,
                                                    s_lo=(-vmax,) * 3, s_hi=(vmax,) * 3), normals=nrm)
