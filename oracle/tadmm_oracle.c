@@ -423,6 +423,7 @@ int orc_admm(const orc_params *prm, const orc_scenario *sc, orc_result *res, int
   double *ysum = (double *)calloc((size_t)N * (T + 1) * dp, sizeof(double));
   /* state box split: yb in the box, its dual mb, vsum = sigma yb - mb */
   const int box = prm->state_box;
+  const int relax = prm->alpha != 1.0;
   const double sigma = prm->rho;
   double *yb = (double *)calloc((size_t)N * (T + 1) * dp, sizeof(double));
   double *mb = (double *)calloc((size_t)N * (T + 1) * dp, sizeof(double));
@@ -533,11 +534,19 @@ int orc_admm(const orc_params *prm, const orc_scenario *sc, orc_result *res, int
             if (dd >= 1e-6) for (int c = 0; c < dp; ++c) n[c] = (pi[c] - pj[c]) / dd;
             else reference_normal(prm, sc, i, j, t, n);
           }
+          /* over-relaxation (Boyd et al. 2011, Sec. 3.4.3): the z- and dual
+           * updates take xh = alpha C x^(k+1) + (1 - alpha) z^k in place of
+           * C x^(k+1); alpha = 1 is plain ADMM */
+          double xi[3], xj[3];
+          for (int c = 0; c < dp; ++c) {
+            xi[c] = relax ? prm->alpha * pi[c] + (1.0 - prm->alpha) * z[ZI(i, j, t) + c] : pi[c];
+            xj[c] = relax ? prm->alpha * pj[c] + (1.0 - prm->alpha) * z[ZI(j, i, t) + c] : pj[c];
+          }
           /* the two agents' copies shifted by their scaled duals */
           double a[3], b[3];
           for (int c = 0; c < dp; ++c) {
-            a[c] = pi[c] + lam[ZI(i, j, t) + c] / rho;
-            b[c] = pj[c] + lam[ZI(j, i, t) + c] / rho;
+            a[c] = xi[c] + lam[ZI(i, j, t) + c] / rho;
+            b[c] = xj[c] + lam[ZI(j, i, t) + c] / rho;
           }
           /* Euclidean projection of (a, b) onto {n'(a - b) >= d_min}: the
            * half-space normal in R^{2dp} is (n, -n) with squared norm 2 */
@@ -551,8 +560,8 @@ int orc_admm(const orc_params *prm, const orc_scenario *sc, orc_result *res, int
           for (int c = 0; c < dp; ++c) {
             z[ZI(i, j, t) + c] = a[c];
             z[ZI(j, i, t) + c] = b[c];
-            lam[ZI(i, j, t) + c] += rho * (pi[c] - a[c]);
-            lam[ZI(j, i, t) + c] += rho * (pj[c] - b[c]);
+            lam[ZI(i, j, t) + c] += rho * (xi[c] - a[c]);
+            lam[ZI(j, i, t) + c] += rho * (xj[c] - b[c]);
           }
         }
 

@@ -60,6 +60,9 @@ typedef struct {
    * dual mu, penalty sigma = the initial rho; +-inf: unbounded. */
   int state_box;
   double s_lo[3], s_hi[3];
+  /* Over-relaxation (Boyd et al. 2011, Sec. 3.4.3): the z- and dual updates
+   * use alpha C x^(k+1) + (1 - alpha) z^k; 1 is plain ADMM, (0, 2) valid. */
+  double alpha;
 } orc_params;
 
 typedef struct {

@@ -24,8 +24,8 @@ MUTANTS = {
     "terminal_weight_index": ("(t == T ? prm->qT_scale : 1.0)", "(t == T - 1 ? prm->qT_scale : 1.0)"),
     "projection_half_step": ("a[c] += 0.5 * v * n[c]; b[c] -= 0.5 * v * n[c];",
                              "a[c] += v * n[c]; b[c] -= v * n[c];"),
-    "dual_update_sign": ("lam[ZI(i, j, t) + c] += rho * (pi[c] - a[c]);",
-                         "lam[ZI(i, j, t) + c] -= rho * (pi[c] - a[c]);"),
+    "dual_update_sign": ("lam[ZI(i, j, t) + c] += rho * (xi[c] - a[c]);",
+                         "lam[ZI(i, j, t) + c] -= rho * (xi[c] - a[c]);"),
     "multiplier_sign": ("m = (W[k] == 1) ? -y : y;", "m = (W[k] == 1) ? y : -y;"),
     "normal_orientation": ("n[c] = (pi[c] - pj[c]) / dd;", "n[c] = (pj[c] - pi[c]) / dd;"),
     "dynamics_A_transposed": ("const double a = prm->A[r * nx + c];", "const double a = prm->A[c * nx + r];"),
@@ -40,6 +40,10 @@ MUTANTS = {
     "agent_box_ignored": ("if (sc->agent_lo) qs[i].lo = sc->agent_lo + (size_t)i * nu;", ""),
     "state_box_dual_not_updated": ("mb[o] += sigma * (xv - yn);", "(void)0;"),
     "state_box_missing_hessian_term": ("(prm->state_box ? prm->rho : 0.0)", "0.0"),
+    "relaxation_dual_update_unrelaxed": ("lam[ZI(i, j, t) + c] += rho * (xi[c] - a[c]);",
+                                         "lam[ZI(i, j, t) + c] += rho * (pi[c] - a[c]);"),
+    "relaxation_weights_swapped": ("prm->alpha * pi[c] + (1.0 - prm->alpha) * z[ZI(i, j, t) + c]",
+                                   "(1.0 - prm->alpha) * pi[c] + prm->alpha * z[ZI(i, j, t) + c]"),
 }
 
 # The fast pins (each well under a second on the committed oracle).  Mistakes
@@ -61,7 +65,9 @@ PIN_FUNCS = [pins.test_agent_qp_unconstrained_matches_condensed_least_squares,
              pins.test_admm_adaptive_rho_frozen_limit_is_the_same_kkt_point,
              pins.test_hetero_single_agent_is_its_local_qp,
              pins.test_hetero_agent_permutation_equivariance,
-             pins.test_admm_state_box_frozen_limit_is_centralized_qp_kkt_certificate]
+             pins.test_admm_state_box_frozen_limit_is_centralized_qp_kkt_certificate,
+             pins.test_admm_relaxation_closed_form_far_apart,
+             pins.test_admm_relaxation_frozen_limit_is_the_same_kkt_point]
 
 
 def _call_pin(fn):
@@ -78,6 +84,8 @@ def _call_pin(fn):
             kw[name] = 3
         elif name == "start":
             kw[name] = oracle.START_COLD
+        elif name == "alpha":
+            kw[name] = 1.5
     try:
         fn(**kw)
         return True

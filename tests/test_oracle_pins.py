@@ -577,3 +577,59 @@ def test_hetero_agent_permutation_equivariance():
     # and the agents do differ: the weights matter
     hom = oracle.solve(p, dataclasses.replace(sc, agent_q=None, agent_r=None, agent_lo=None, agent_hi=None), o)
     assert np.abs(hom["u"] - a["u"]).max() > 1e-3
+
+
+@pytest.mark.parametrize("alpha", [0.6, 1.0, 1.5, 1.9])
+def test_admm_relaxation_closed_form_far_apart(alpha):
+    """Over-relaxation (Boyd et al. 2011, Sec. 3.4.3) on two agents that
+    never come near each other, with T = 1 and inactive input bounds.  Every
+    projection is then the identity, so lambda stays 0 and z^(k+1) =
+    alpha p^(k+1) + (1 - alpha) z^k, and each agent-axis local QP is a
+    scalar quadratic in u_0 whose minimiser makes p_1 affine in z:
+    p_1 = l z + beta with l = rho h^2 / H (h = B's position entry, H the
+    second derivative).  After K iterations the oracle's p_1 and z must be
+    those of this scalar recursion, started from z^0 = the reference."""
+    p = synth.ProblemParams(dp=2, u_max=1e4)
+    sc = synth.Scenario(starts=np.array([[-50.0, 3.0], [60.0, -40.0]]),
+                        goals=np.array([[-48.0, 4.5], [58.0, -41.0]]), T=1)
+    K, rho = 7, p.rho
+    res = oracle.solve(p, sc, oracle.OracleOptions(alpha=alpha, fixed_iters=K), keep_zl=True)
+    assert res["iters"] == K
+    np.testing.assert_array_equal(res["lam"], 0.0)
+    A, B = p.A, p.B
+    dt, dp = p.dt, p.dp
+    qT = p.qT_scale
+    xr = sc.xref()
+    for i in range(2):
+        for c in range(dp):
+            h, b = B[c, c], B[dp + c, c]           # position and velocity entries of B
+            P = A[c] @ sc.x0()[i]                  # position after one step with u = 0
+            V = A[dp + c] @ sc.x0()[i]
+            rp, rv = xr[i, 1, c], xr[i, 1, dp + c]
+            qp, qv, r = p.q_diag[c], p.q_diag[dp + c], p.r_diag[c]
+            # d/du of qT qp (P + h u - rp)^2 + qT qv (V + b u - rv)^2 + r u^2 + rho/2 (P + h u - z)^2
+            H = 2 * qT * qp * h * h + 2 * qT * qv * b * b + 2 * r + rho * h * h
+            z = rp
+            for _ in range(K):
+                u = -(2 * qT * qp * h * (P - rp) + 2 * qT * qv * b * (V - rv) + rho * h * (P - z)) / H
+                p1 = P + h * u
+                z = alpha * p1 + (1 - alpha) * z
+            assert res["x"][i, 1, c] == pytest.approx(p1, rel=1e-12, abs=1e-12)
+            assert res["u"][i, 0, c] == pytest.approx(u, rel=1e-10, abs=1e-12)
+            np.testing.assert_allclose(res["z"][i, 1 - i, 0, c], z, rtol=1e-12, atol=1e-12)
+
+
+def test_admm_relaxation_frozen_limit_is_the_same_kkt_point():
+    """Relaxation changes the path, not the fixed point: with alpha = 1.6 the
+    frozen side pass converges to the same point as plain ADMM, which passes
+    the centralized-QP certificate (test above), and does so in fewer
+    iterations (the speed-up Boyd et al. report for alpha in [1.5, 1.8])."""
+    p = synth.ProblemParams(dp=2, u_max=2.0)
+    sc, nrm = _side_pass()
+    tight = dict(normal_mode=oracle.NORMAL_FROZEN, rho=10.0, max_iter=20000, eps_abs=1e-10, eps_rel=1e-10)
+    plain = oracle.solve(p, sc, oracle.OracleOptions(**tight), normals=nrm)
+    relax = oracle.solve(p, sc, oracle.OracleOptions(alpha=1.6, **tight), normals=nrm)
+    assert plain["status"] == oracle.CONVERGED and relax["status"] == oracle.CONVERGED
+    np.testing.assert_allclose(relax["u"], plain["u"], atol=1e-7)
+    np.testing.assert_allclose(relax["x"], plain["x"], atol=1e-7)
+    assert relax["iters"] < plain["iters"]
