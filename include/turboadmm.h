@@ -154,6 +154,15 @@ typedef struct {
                                 states held in the box, its dual, penalty = the
                                 initial rho.  Not with tadmm_polish/adjoint.     */
   float s_lo[3], s_hi[3];    /* with state_box: s_lo < s_hi (+-inf: unbounded)   */
+  float alpha;               /* over-relaxation (Boyd et al. 2011, Sec. 3.4.3;
+                                the paper names ADMM variants as future work,
+                                Sec. VI): the consensus and dual updates use
+                                alpha C x^(k+1) + (1 - alpha) z^k, 0 < alpha
+                                < 2.  1 (or 0, for zero-initialized structs):
+                                plain ADMM.  Otherwise the workspace holds 2 nu
+                                floats more per ordered pair copy and step (the
+                                copies' z), and tadmm_polish/adjoint reject the
+                                solve.                                           */
 } tadmm_params;
 
 /* A ragged batch of S independent scenarios.  Scenario s has N_s agents and

@@ -39,6 +39,8 @@ struct Prob {
   float rho_mu, rho_tau;
   int sbox;                      // box on the non-position states (ADMM split, penalty sigma)
   float sigma, slo[3], shi[3];
+  int relax;                     // over-relaxation with factor alpha (alpha != 1)
+  float alpha;
 };
 
 // Per-scenario table columns (int64).
@@ -70,6 +72,9 @@ struct WS {
   unsigned long long *cnt;           // [S][CT_NCOL]
   int *skip;                         // [S] SQP: scenario converged, not solved again
   float *rhos;                       // [S][2] penalty of the next / of the last iteration
+  // over-relaxation only: per scenario 2 NU planes shaped like gam, the
+  // copies' z: D = z_ij - z_ji (NU planes), then e = z_ij - C x_i (NU planes)
+  float *orx;
   // inputs (caller layouts)
   const float *x0, *xref, *qd, *rd, *normals;
   const float *aq, *ar, *alo, *ahi;  // heterogeneous agents (each NULL: the shared value)

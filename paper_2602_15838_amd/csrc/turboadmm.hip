@@ -913,9 +913,16 @@ __device__ __forceinline__ void pair_normal(const Prob &pb, const WS &ws, const 
   }
 }
 
-template <int NX, int NU>
-__device__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, int i, int t,
-                                 const float *__restrict__ lpos, const float *__restrict__ lprev, int lofs = 0) {
+// One agent-stage's consensus step over its partners.  REL: over-relaxation
+// (Boyd et al. 2011, Sec. 3.4.3).  The z- and dual updates take
+// xh = alpha C x^(k+1) + (1 - alpha) z^k for C x^(k+1), so the copies' z is
+// kept: D = z_ij - z_ji (both orientations store exact negatives, as with
+// gamma) and e = z_ij - C x_i (offsets stay small).  The duals keep their
+// collapsed form lambda_ij = -gamma n, since the projection still moves the
+// pair symmetrically about its midpoint.
+template <int NX, int NU, bool REL>
+__device__ void pair_agent_stage_impl(const Prob &pb, const WS &ws, const Scen &sc, int i, int t,
+                                      const float *__restrict__ lpos, const float *__restrict__ lprev, int lofs) {
   using F = Fld<NX, NU>;
   const int N = sc.N;
   float *R = ws.fr + sc.fo;
@@ -956,16 +963,27 @@ __device__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, i
   // The partner loop skips j == i and runs in batches of kPB partners: the
   // duals and positions of a batch are all read before the first is used
   // (each dual is read before this loop stores its own word).
-  constexpr int kPB = 8;
+  constexpr int kPB = REL ? 4 : 8;
   const int np = N - 1;
   auto jof = [&](int jj) { return jj + (jj >= i); };
+  const long long LS = (long long)sc.T * N * N;
+  float *ob = REL ? ws.orx + 2LL * NU * sc.lo : nullptr;   // plane c at ob + c LS
+  const float al = pb.alpha, bl = 1.0f - pb.alpha;
   for (int j0 = 0; j0 < np; j0 += kPB) {
     float gb[kPB], pjb[kPB][NU], qjb[kPB][NU];
+    float Db[REL ? kPB : 1][NU], eb[REL ? kPB : 1][NU];
 #pragma unroll
     for (int q = 0; q < kPB; ++q)
       if (j0 + q < np) {
         gb[q] = gm[gbase + jof(j0 + q) * N];
         partner(jof(j0 + q), pjb[q], qjb[q]);
+        if constexpr (REL) {
+#pragma unroll
+          for (int c = 0; c < NU; ++c) {
+            Db[q][c] = ob[c * LS + gbase + jof(j0 + q) * N];
+            eb[q][c] = ob[(NU + c) * LS + gbase + jof(j0 + q) * N];
+          }
+        }
       }
 #pragma unroll
     for (int q = 0; q < kPB; ++q) {
@@ -990,23 +1008,41 @@ __device__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, i
       }
       const int li = gbase + j * N;  // this lane's ordered copy (i, j)
       float g = 0.f;
+      float abv[NU];
 #pragma unroll
       for (int c = 0; c < NU; ++c) {
-        const float ab = (pi[c] - pj[c]) + 2.0f * irho * lown[c];  // a - b
-        g = fmaf(n[c], ab, g);
+        // a - b; relaxed: xh_i - xh_j = alpha (p_i - p_j) + (1 - alpha) D
+        float dx;
+        if constexpr (REL) dx = fmaf(al, pi[c] - pj[c], bl * Db[q][c]);
+        else dx = pi[c] - pj[c];
+        abv[c] = dx + 2.0f * irho * lown[c];
+        g = fmaf(n[c], abv[c], g);
       }
       const float v = pb.dmin - g;
       const float gam = 0.5f * rho * fmaxf(v, 0.f);
 #pragma unroll
       for (int c = 0; c < NU; ++c) {
         const float lo = -gam * n[c];                  // lambda_ij after Eq. 5
-        const float dl = (lown[c] - lo) * irho;        // z_ij - C x_i
-        const float zo = pi[c] + dl;
-        es[c] += lown[c] - 2.0f * lo;                  // rho z_ij - lam_new - rho C x_i
-        zd[c] += dl;
-        ls[c] += lo;
-        r2 = fmaf(dl, dl, r2);
-        z2 = fmaf(zo, zo, z2);
+        const float dl = (lown[c] - lo) * irho;        // z_ij - xh_i
+        if constexpr (REL) {
+          // e' = z_ij - C x_i = (1 - alpha)(z^k_ij - C x_i) + dl, z^k_ij = C x^k_i + e
+          const float en = fmaf(bl, (qi[c] + eb[q][c]) - pi[c], dl);
+          const float zo = pi[c] + en;
+          ob[c * LS + li] = fmaf(fmaxf(v, 0.f), n[c], abv[c]);   // z_ij - z_ji after the projection
+          ob[(NU + c) * LS + li] = en;
+          es[c] += fmaf(rho, en, -lo);                 // rho (z_ij - C x_i) - lam_new
+          zd[c] += en;
+          ls[c] += lo;
+          r2 = fmaf(en, en, r2);
+          z2 = fmaf(zo, zo, z2);
+        } else {
+          const float zo = pi[c] + dl;
+          es[c] += lown[c] - 2.0f * lo;                // rho z_ij - lam_new - rho C x_i
+          zd[c] += dl;
+          ls[c] += lo;
+          r2 = fmaf(dl, dl, r2);
+          z2 = fmaf(zo, zo, z2);
+        }
       }
       const bool first = i < j;
       gm[li] = gam;
@@ -1052,6 +1088,14 @@ __device__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, i
   Ri(F::RED + 2) = ax2;
   Ri(F::RED + 3) = z2;
   Ri(F::RED + 4) = aty2;
+}
+
+template <int NX, int NU>
+__device__ __forceinline__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, int i, int t,
+                                                 const float *__restrict__ lpos, const float *__restrict__ lprev,
+                                                 int lofs = 0) {
+  if (pb.relax) pair_agent_stage_impl<NX, NU, true>(pb, ws, sc, i, t, lpos, lprev, lofs);
+  else pair_agent_stage_impl<NX, NU, false>(pb, ws, sc, i, t, lpos, lprev, lofs);
 }
 
 // After a consensus step: the positions of this step become the previous
@@ -1164,6 +1208,20 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
         gm[idx] = 0.f;
         pa[idx] = 0;
       }
+      if (pb.relax) {
+        // the copies restart at z = C x: D = C x_i - C x_j, e = 0
+        const long long LS = (long long)T * N * N;
+        float *ob = ws.orx + 2LL * NU * sc.lo;
+        for (int idx = tid; idx < T * N * N; idx += nthreads) {
+          const int i = idx % N, j = (idx / N) % N, t = idx / (N * N) + 1;
+#pragma unroll
+          for (int c = 0; c < NU; ++c) {
+            ob[c * LS + idx] = R[fidx((unsigned)GS, (unsigned)(t * N + i), F::X + c)] -
+                               R[fidx((unsigned)GS, (unsigned)(t * N + j), F::X + c)];
+            ob[(NU + c) * LS + idx] = 0.f;
+          }
+        }
+      }
     }
     if (tid == 0) {
       int *st = ws.sst + (long long)sc.s * ST_NCOL;
@@ -1240,6 +1298,20 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
     gm[idx] = 0.f;
     pa[idx] = 0;
   }
+  if (pb.relax) {
+    // the copies' z^0 = C r: D = r_i - r_j, e = 0 (copy (i, j) at [t][j][i])
+    float *ob = ws.orx + 2LL * NU * sc.lo;
+    for (int idx = tid; idx < LS; idx += nthreads) {
+      const int i = idx % N, j = (idx / N) % N, t = idx / (N * N) + 1;
+      const float *ri = ws.xref + (sc.xo + (long long)i * (T + 1) + t) * NX;
+      const float *rj = ws.xref + (sc.xo + (long long)j * (T + 1) + t) * NX;
+#pragma unroll
+      for (int c = 0; c < NU; ++c) {
+        ob[(long long)c * LS + idx] = ri[c] - rj[c];
+        ob[(long long)(NU + c) * LS + idx] = 0.f;
+      }
+    }
+  }
   if (tid == 0) {
     int *st = ws.sst + (long long)sc.s * ST_NCOL;
     st[ST_STATUS] = SCEN_MAX_ITER;
@@ -1310,7 +1382,7 @@ __global__ __launch_bounds__(64) void k_resid(Prob pb, WS ws, int s, int k, int 
 // scenario's own stopping test passes; the three phases are separated by
 // workgroup barriers.  Every wave reaches the queue read, so the grid drains
 // once the counter passes S.
-template <int NX, int NU, bool DI>
+template <int NX, int NU, bool DI, bool REL>
 __device__ __forceinline__ void persistent_body(Prob pb, WS ws, int S, int lds_floats) {
   extern __shared__ float lds_pos[];  // positions of the scenario and the previous ones, [t][i][c] each
   __shared__ int s_item;
@@ -1354,8 +1426,8 @@ __device__ __forceinline__ void persistent_body(Prob pb, WS ws, int S, int lds_f
           __syncthreads();
         }
         for (int idx = tid; idx < sc.N * sc.T; idx += nt)
-          pair_agent_stage<NX, NU>(pb, ws, sc, idx % sc.N, idx / sc.N + 1, staged ? lds_pos : nullptr,
-                                   staged ? lds_prev : nullptr);
+          pair_agent_stage_impl<NX, NU, REL>(pb, ws, sc, idx % sc.N, idx / sc.N + 1, staged ? lds_pos : nullptr,
+                                             staged ? lds_prev : nullptr, 0);
         if (tid == 0) cnt[CT_PAIRS] += (long long)sc.N * (sc.N - 1) / 2 * sc.T;
         __syncthreads();
         commit_positions<NX, NU>(ws, sc, tid, nt);
@@ -1382,16 +1454,25 @@ __device__ __forceinline__ void persistent_body(Prob pb, WS ws, int S, int lds_f
 // Two launch shapes of the same persistent loop: workgroups of 128-256
 // threads (several waves share a scenario's consensus step), and one-wave
 // workgroups held to at most 128 VGPRs so that four waves fit per SIMD and a
-// whole batch of a few thousand scenarios is resident at once.
-template <int NX, int NU, bool DI>
+// whole batch of a few thousand scenarios is resident at once.  REL:
+// over-relaxation, a kernel of its own so that the plain kernel's code and
+// register allocation stay as they are.
+template <int NX, int NU, bool DI, bool REL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_admm_persistent(Prob pb, WS ws, int S, int lds_floats) {
-  persistent_body<NX, NU, DI>(pb, ws, S, lds_floats);
+  persistent_body<NX, NU, DI, REL>(pb, ws, S, lds_floats);
+}
+
+template <int NX, int NU, bool DI, bool REL>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_admm_persistent_lean(
+    Prob pb, WS ws, int S, int lds_floats) {
+  persistent_body<NX, NU, DI, REL>(pb, ws, S, lds_floats);
 }
 
 template <int NX, int NU, bool DI>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_admm_persistent_lean(
-    Prob pb, WS ws, int S, int lds_floats) {
-  persistent_body<NX, NU, DI>(pb, ws, S, lds_floats);
+const void *persistent_kernel(bool lean, bool rel) {
+  if (lean) return rel ? (const void *)k_admm_persistent_lean<NX, NU, DI, true>
+                       : (const void *)k_admm_persistent_lean<NX, NU, DI, false>;
+  return rel ? (const void *)k_admm_persistent<NX, NU, DI, true> : (const void *)k_admm_persistent<NX, NU, DI, false>;
 }
 
 __global__ void k_fill_i32(int *p, int n, int v) {
@@ -1735,10 +1816,14 @@ struct Layout {
   size_t o_wide = 0;   // wide mode: iteration number, scenario index
   size_t o_sqpj = 0, o_sqpi = 0, o_sqpf = 0;   // SQP: objective [S] (FP64); skip, rounds [2][S]; min distance [S]
   size_t o_rho = 0;    // [S][2] penalty of the next / last iteration
+  size_t o_orx = 0;    // over-relaxation: [2 nu] planes shaped like the gamma region
   long long sumPT = 0;
   std::vector<long long> tab;
   std::vector<int> order;
 };
+
+// over-relaxation requested (alpha = 0 reads as 1: plain ADMM)
+bool relaxed(const tadmm_params &p) { return p.alpha != 0.f && p.alpha != 1.f; }
 
 int fields_per_stage(int nx, int nu) {
   return (nx == 4) ? Fld<4, 2>::NF : Fld<6, 3>::NF;
@@ -1776,6 +1861,7 @@ bool params_ok(const tadmm_params *p, std::string &err) {
       if (std::isnan(p->s_lo[c]) || std::isnan(p->s_hi[c]) || !(p->s_lo[c] < p->s_hi[c])) {
         err = "state_box needs s_lo < s_hi (infinite ends allowed)"; return false;
       }
+  if (!(p->alpha >= 0.f && p->alpha < 2.f)) { err = "alpha must be in (0, 2) (0: plain ADMM)"; return false; }
   if (p->max_iter < 1) { err = "max_iter must be >= 1"; return false; }
   if (p->normal_mode != TADMM_NORMAL_PER_ITER && p->normal_mode != TADMM_NORMAL_FROZEN) {
     err = "unknown normal_mode"; return false;
@@ -1847,6 +1933,7 @@ bool make_layout(const tadmm_params *p, int S, const int32_t *N, const int32_t *
   L.o_sqpi = take(sizeof(int) * 2 * S);
   L.o_sqpf = take(sizeof(float) * S);
   L.o_rho = take(sizeof(float) * 2 * S);
+  if (relaxed(*p)) L.o_orx = take(sizeof(float) * 2 * (size_t)p->nu * (size_t)lo);
   L.bytes = off;
   // launch order for the persistent queue: largest N^2 T first (LPT)
   L.order.resize(S);
@@ -1898,6 +1985,8 @@ Prob to_prob(const tadmm_params &p) {
   pb.rho_every = std::max(p.rho_every, 1);
   pb.rho_mu = p.rho_mu;
   pb.rho_tau = p.rho_tau;
+  pb.relax = relaxed(p) ? 1 : 0;
+  pb.alpha = pb.relax ? p.alpha : 1.0f;
   pb.sbox = p.state_box ? 1 : 0;
   pb.sigma = p.rho;
   for (int c = 0; c < 3; ++c) { pb.slo[c] = p.s_lo[c]; pb.shi[c] = p.s_hi[c]; }
@@ -1999,6 +2088,7 @@ WS make_ws(const Layout &L, char *ws, const tadmm_batch *b) {
   w.aq = b->agent_q; w.ar = b->agent_r; w.alo = b->agent_lo; w.ahi = b->agent_hi;
   w.skip = (int *)(ws + L.o_sqpi);
   w.rhos = (float *)(ws + L.o_rho);
+  w.orx = L.o_orx ? (float *)(ws + L.o_orx) : nullptr;
   return w;
 }
 
@@ -2054,7 +2144,7 @@ tadmm_status run_batched(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layo
   const bool lean = (threads == 64);
   const int lds_floats = (int)std::min<long long>(2 * max_gs * NU, lean ? 4096 : 8192);
   const size_t lds_bytes = sizeof(float) * (size_t)lds_floats;
-  const void *kfn = lean ? (const void *)k_admm_persistent_lean<NX, NU, DI> : (const void *)k_admm_persistent<NX, NU, DI>;
+  const void *kfn = persistent_kernel<NX, NU, DI>(lean, pb.relax != 0);
   int per_cu = 0;
   HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, threads, lds_bytes));
   if (per_cu < 1) return fail(ctx, TADMM_ERR_HIP, "persistent kernel does not fit on a compute unit");
@@ -2078,14 +2168,14 @@ tadmm_status run_batched(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layo
     const long long nc = (long long)L.S * CT_NCOL;
     if (!pb.cont)   // a continuing SQP round keeps counting
       hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, cs, w.cnt, nc);
-    if (lean)
-      hipLaunchKernelGGL((k_admm_persistent_lean<NX, NU, DI>), dim3(grid), dim3(threads), lds_bytes, cs, pb, w, L.S,
-                         lds_floats);
-    else
-      hipLaunchKernelGGL((k_admm_persistent<NX, NU, DI>), dim3(grid), dim3(threads), lds_bytes, cs, pb, w, L.S,
-                         lds_floats);
+    Prob kpb = pb;
+    WS kw = w;
+    int kS = L.S, klds = lds_floats;
+    void *args[] = {&kpb, &kw, &kS, &klds};
+    const hipError_t lk = hipLaunchKernel(kfn, dim3(grid), dim3(threads), args, lds_bytes, cs);
     hipLaunchKernelGGL((k_writeback<NX, NU>), dim3(std::min(L.S, 4096)), dim3(256), 0, cs, w, L.S, out);
     hipError_t le = hipGetLastError();
+    if (le == hipSuccess) le = lk;
     hipError_t ce = hipStreamEndCapture(cs, &ctx->graph);
     if (le != hipSuccess || ce != hipSuccess) {
       ctx->err = std::string("graph capture failed: ") + hipGetErrorString(le != hipSuccess ? le : ce);
@@ -2335,6 +2425,8 @@ tadmm_status eqp_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *out
     return fail(ctx, TADMM_ERR_INVALID_ARG, "the derivative takes per-scenario weights (no agent_* arrays)");
   if (ctx->prm.state_box)
     return fail(ctx, TADMM_ERR_INVALID_ARG, "the derivative covers input bounds only (no state_box)");
+  if (relaxed(ctx->prm))
+    return fail(ctx, TADMM_ERR_INVALID_ARG, "the derivative follows plain ADMM (alpha = 1)");
   if (b->n_scen != sb.n_scen || b->x0 != sb.x0 || b->xref != sb.xref || b->q_diag != sb.q_diag ||
       b->r_diag != sb.r_diag || b->normals != sb.normals)
     return fail(ctx, TADMM_ERR_STATE, "batch differs from the one of the last tadmm_solve");

@@ -104,6 +104,27 @@ def test_bad_state_box_rejected(lo, hi):
     assert _ws(prm, [2], [20])[0] == 0
 
 
+@pytest.mark.parametrize("alpha", [-0.5, 2.0, float("nan"), float("inf")])
+def test_bad_relaxation_rejected(alpha):
+    prm = tadmm.make_params(synth.ProblemParams(), alpha=1.5)
+    assert _ws(prm, [2], [20])[0] == 0
+    prm.alpha = alpha
+    assert _ws(prm, [2], [20])[0] == 1
+
+
+def test_relaxation_workspace_holds_the_copies():
+    """alpha != 1 adds 2 nu floats per ordered pair copy and step (rounded
+    up to the region alignment); alpha = 0 reads as plain ADMM."""
+    sizes = {}
+    for a in (1.0, 0.0, 1.5):
+        rc, b = _ws(tadmm.make_params(synth.ProblemParams(), alpha=a), [5, 3], [20, 11])
+        assert rc == 0
+        sizes[a] = b
+    assert sizes[0.0] == sizes[1.0]
+    extra = 4 * 2 * 2 * (20 * 5 * 5 + 11 * 3 * 3)
+    assert extra <= sizes[1.5] - sizes[1.0] <= extra + 512
+
+
 @pytest.mark.parametrize("N,T", [([0], [20]), ([2], [0]), ([5000], [10])])
 def test_bad_shapes_rejected(N, T):
     prm = tadmm.make_params(synth.ProblemParams())
