@@ -57,7 +57,8 @@ class _Params(C.Structure):
                 ("warm_start", C.c_int), ("hotstart", C.c_int), ("lu_reuse", C.c_int),
                 ("fixed_iters", C.c_int), ("adaptive_rho", C.c_int), ("rho_mu", C.c_double),
                 ("rho_tau", C.c_double), ("rho_every", C.c_int), ("state_box", C.c_int),
-                ("s_lo", C.c_double * 3), ("s_hi", C.c_double * 3), ("alpha", C.c_double)]
+                ("s_lo", C.c_double * 3), ("s_hi", C.c_double * 3), ("p_lo", C.c_double * 3),
+                ("p_hi", C.c_double * 3), ("alpha", C.c_double)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -124,6 +125,8 @@ class OracleOptions:
     state_box: bool = False         # box on the non-position states (a further ADMM split)
     s_lo: tuple = (-np.inf, -np.inf, -np.inf)
     s_hi: tuple = (np.inf, np.inf, np.inf)
+    p_lo: tuple = (-np.inf, -np.inf, -np.inf)   # with state_box: the position box
+    p_hi: tuple = (np.inf, np.inf, np.inf)
     alpha: float = 1.0              # over-relaxation (Boyd et al. 2011, Sec. 3.4.3)
 
 
@@ -167,6 +170,8 @@ def make_params(problem, opts: OracleOptions) -> _Params:
     for c in range(3):
         p.s_lo[c] = float(opts.s_lo[c])
         p.s_hi[c] = float(opts.s_hi[c])
+        p.p_lo[c] = float(opts.p_lo[c])
+        p.p_hi[c] = float(opts.p_hi[c])
     p.alpha = float(opts.alpha)
     return p
 

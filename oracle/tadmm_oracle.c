@@ -104,6 +104,19 @@ typedef struct {
 static int iu(const qp_ws *q, int t, int c) { return t * q->nu + c; }
 static int ix(const qp_ws *q, int t, int r) { return q->T * q->nu + (t - 1) * q->nx + r; } /* t >= 1 */
 
+/* The state box covers two groups of states, each only where one of its
+ * bounds is finite: the positions (state r < dp; p_lo, p_hi) and the other
+ * states (r >= dp; s_lo, s_hi). */
+static int state_boxed(const orc_params *prm, int r) {
+  if (!prm->state_box) return 0;
+  const double *lo = r < prm->dp ? prm->p_lo : prm->s_lo, *hi = r < prm->dp ? prm->p_hi : prm->s_hi;
+  for (int c = 0; c < prm->dp; ++c)
+    if (isfinite(lo[c]) || isfinite(hi[c])) return 1;
+  return 0;
+}
+static double state_lo(const orc_params *prm, int r) { return r < prm->dp ? prm->p_lo[r] : prm->s_lo[r - prm->dp]; }
+static double state_hi(const orc_params *prm, int r) { return r < prm->dp ? prm->p_hi[r] : prm->s_hi[r - prm->dp]; }
+
 /* Equality-constrained QP for working set W: dynamics plus u_tc fixed at its
  * bound for every (t,c) in W.  KKT system
  *     [H  E'] [w]   [-c]
@@ -219,14 +232,14 @@ static int qp_ws_init(qp_ws *q, const orc_params *prm, int T, int n_nbr, const d
     for (int r = 0; r < q->nx; ++r) {
       const double wq = (t == T ? prm->qT_scale : 1.0) * qd[r];
       const int k = ix(q, t, r);
-      q->Hd[k] = 2.0 * wq + (r < q->dp ? prm->rho * (double)n_nbr : (prm->state_box ? prm->rho : 0.0));
+      q->Hd[k] = 2.0 * wq + (r < q->dp ? prm->rho * (double)n_nbr : 0.0) + (state_boxed(prm, r) ? prm->rho : 0.0);
       q->cv[k] = -2.0 * wq * xref[t * q->nx + r] - (r < q->dp && ysum ? ysum[t * q->dp + r] : 0.0);
     }
   return 0;
 }
 
-/* ysum [T+1][dp]: sum_j (rho z - lambda) on the positions; vsum [T+1][dp]
- * (or NULL): sigma y - mu on the boxed states. */
+/* ysum [T+1][dp]: sum_j (rho z - lambda) on the positions; vsum [T+1][nx]
+ * (or NULL): sigma y - mu on the boxed states (0 elsewhere). */
 static void qp_ws_set_linear(qp_ws *q, const double *xref, const double *qd, const double *ysum,
                              const double *vsum) {
   const int dp = q->dp;
@@ -235,7 +248,7 @@ static void qp_ws_set_linear(qp_ws *q, const double *xref, const double *qd, con
       const double wq = (t == q->T ? q->prm->qT_scale : 1.0) * qd[r];
       double v = -2.0 * wq * xref[t * q->nx + r];
       if (r < dp && ysum) v -= ysum[t * dp + r];
-      if (r >= dp && vsum) v -= vsum[t * dp + (r - dp)];
+      if (vsum) v -= vsum[t * q->nx + r];
       q->cv[ix(q, t, r)] = v;
     }
 }
@@ -246,7 +259,7 @@ static void qp_ws_set_rho(qp_ws *q, double rho) {
   for (int t = 1; t <= q->T; ++t)
     for (int r = 0; r < q->dp; ++r) {
       const double wq = (t == q->T ? q->prm->qT_scale : 1.0) * q->qd[r];
-      q->Hd[ix(q, t, r)] = 2.0 * wq + rho * (double)q->n_nbr;
+      q->Hd[ix(q, t, r)] = 2.0 * wq + rho * (double)q->n_nbr + (state_boxed(q->prm, r) ? q->prm->rho : 0.0);
     }
   q->cache_valid = 0;
 }
@@ -421,13 +434,14 @@ int orc_admm(const orc_params *prm, const orc_scenario *sc, orc_result *res, int
   double *lam = (double *)calloc(zsz, sizeof(double));
   double *zsum_old = (double *)calloc((size_t)N * T * dp, sizeof(double));
   double *ysum = (double *)calloc((size_t)N * (T + 1) * dp, sizeof(double));
-  /* state box split: yb in the box, its dual mb, vsum = sigma yb - mb */
-  const int box = prm->state_box;
+  /* state box split: yb in the box, its dual mb, vsum = sigma yb - mb, per
+   * agent, step and state ([N][T+1][nx]; entries of unboxed states stay 0) */
+  const int box = state_boxed(prm, 0) || state_boxed(prm, dp);
   const int relax = prm->alpha != 1.0;
   const double sigma = prm->rho;
-  double *yb = (double *)calloc((size_t)N * (T + 1) * dp, sizeof(double));
-  double *mb = (double *)calloc((size_t)N * (T + 1) * dp, sizeof(double));
-  double *vsum = (double *)calloc((size_t)N * (T + 1) * dp, sizeof(double));
+  double *yb = (double *)calloc((size_t)N * (T + 1) * nx, sizeof(double));
+  double *mb = (double *)calloc((size_t)N * (T + 1) * nx, sizeof(double));
+  double *vsum = (double *)calloc((size_t)N * (T + 1) * nx, sizeof(double));
   qp_ws *qs = (qp_ws *)calloc((size_t)N, sizeof(qp_ws));
   if (!z || !lam || !zsum_old || !ysum || !qs || !yb || !mb || !vsum) {
     free(z); free(lam); free(zsum_old); free(ysum); free(qs); free(yb); free(mb); free(vsum);
@@ -448,9 +462,10 @@ int orc_admm(const orc_params *prm, const orc_scenario *sc, orc_result *res, int
   if (box)
     for (int i = 0; i < N; ++i)
       for (int t = 1; t <= T; ++t)
-        for (int c = 0; c < dp; ++c) {
-          const double r = sc->xref[((size_t)i * (T + 1) + t) * nx + dp + c];
-          yb[((size_t)i * (T + 1) + t) * dp + c] = fmin(fmax(r, prm->s_lo[c]), prm->s_hi[c]);
+        for (int r = 0; r < nx; ++r) {
+          if (!state_boxed(prm, r)) continue;
+          const size_t o = ((size_t)i * (T + 1) + t) * nx + r;
+          yb[o] = fmin(fmax(sc->xref[o], state_lo(prm, r)), state_hi(prm, r));
         }
   int setup_fail = 0;
   for (int i = 0; i < N; ++i) {
@@ -487,12 +502,12 @@ int orc_admm(const orc_params *prm, const orc_scenario *sc, orc_result *res, int
     for (int i = 0; i < N; ++i) {
       qp_ws *q = &qs[i];
       if (box)
-        for (int e = 0; e < (T + 1) * dp; ++e) {
-          const size_t o = (size_t)i * (T + 1) * dp + e;
+        for (int e = 0; e < (T + 1) * nx; ++e) {
+          const size_t o = (size_t)i * (T + 1) * nx + e;
           vsum[o] = sigma * yb[o] - mb[o];
         }
       qp_ws_set_linear(q, sc->xref + (size_t)i * (T + 1) * nx, agent_q(sc, nx, i), ysum + (size_t)i * (T + 1) * dp,
-                       box ? vsum + (size_t)i * (T + 1) * dp : NULL);
+                       box ? vsum + (size_t)i * (T + 1) * nx : NULL);
       int start = ORC_START_PREV;
       if (k == 1 || !prm->hotstart) start = prm->warm_start ? ORC_START_WARM : ORC_START_COLD;
       const int rc = active_set(q, res->x + (size_t)i * (T + 1) * nx, res->u + (size_t)i * T * nu,
@@ -571,10 +586,11 @@ int orc_admm(const orc_params *prm, const orc_scenario *sc, orc_result *res, int
     if (box)
       for (int i = 0; i < N; ++i)
         for (int t = 1; t <= T; ++t)
-          for (int c = 0; c < dp; ++c) {
-            const size_t o = ((size_t)i * (T + 1) + t) * dp + c;
-            const double xv = res->x[((size_t)i * (T + 1) + t) * nx + dp + c];
-            const double yn = fmin(fmax(xv + mb[o] / sigma, prm->s_lo[c]), prm->s_hi[c]);
+          for (int r = 0; r < nx; ++r) {
+            if (!state_boxed(prm, r)) continue;
+            const size_t o = ((size_t)i * (T + 1) + t) * nx + r;
+            const double xv = res->x[o];
+            const double yn = fmin(fmax(xv + mb[o] / sigma, state_lo(prm, r)), state_hi(prm, r));
             const double ds = sigma * (yn - yb[o]);
             mb[o] += sigma * (xv - yn);
             yb[o] = yn;
@@ -606,7 +622,8 @@ int orc_admm(const orc_params *prm, const orc_scenario *sc, orc_result *res, int
         }
       }
     const double rn = sqrt(r2), sn = sqrt(s2);
-    const double nbox = box ? (double)N * T * dp : 0.0;   /* rows and coupled states of the box block */
+    /* rows and coupled states of the box block */
+    const double nbox = (double)N * T * dp * (state_boxed(prm, 0) + state_boxed(prm, dp));
     const double eps_pri = sqrt((double)2 * P * T * dp + nbox) * prm->eps_abs + prm->eps_rel * fmax(sqrt(ax2), sqrt(z2));
     const double eps_dual = sqrt((double)N * T * dp + nbox) * prm->eps_abs + prm->eps_rel * sqrt(aty2);
     res->r_norm = rn; res->s_norm = sn; res->eps_pri = eps_pri; res->eps_dual = eps_dual;

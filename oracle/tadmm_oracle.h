@@ -55,11 +55,14 @@ typedef struct {
   int adaptive_rho;
   double rho_mu, rho_tau;
   int rho_every;
-  /* State box on the non-position states (x_t components dp..nx-1, t >= 1),
-   * by a further ADMM split: a copy y of those states held in the box, its
-   * dual mu, penalty sigma = the initial rho; +-inf: unbounded. */
+  /* State box (x_t, t >= 1) by a further ADMM split: a copy y of the boxed
+   * states held in the box, its dual mu, penalty sigma = the initial rho.
+   * Two groups, each split only where one of its bounds is finite: the
+   * non-position states (components dp..nx-1) in [s_lo, s_hi], the
+   * positions in [p_lo, p_hi]; +-inf: unbounded. */
   int state_box;
   double s_lo[3], s_hi[3];
+  double p_lo[3], p_hi[3];
   /* Over-relaxation (Boyd et al. 2011, Sec. 3.4.3): the z- and dual updates
    * use alpha C x^(k+1) + (1 - alpha) z^k; 1 is plain ADMM, (0, 2) valid. */
   double alpha;

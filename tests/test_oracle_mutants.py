@@ -39,7 +39,10 @@ MUTANTS = {
                                          "return sc->agent_q ? sc->agent_q : sc->q_diag;"),
     "agent_box_ignored": ("if (sc->agent_lo) qs[i].lo = sc->agent_lo + (size_t)i * nu;", ""),
     "state_box_dual_not_updated": ("mb[o] += sigma * (xv - yn);", "(void)0;"),
-    "state_box_missing_hessian_term": ("(prm->state_box ? prm->rho : 0.0)", "0.0"),
+    "state_box_missing_hessian_term": ("(state_boxed(prm, r) ? prm->rho : 0.0)", "0.0"),
+    "position_box_bounds_of_the_velocities": ("return r < prm->dp ? prm->p_hi[r] : prm->s_hi[r - prm->dp];",
+                                              "return prm->s_hi[r % prm->dp];"),
+    "adaptive_rho_drops_box_hessian_term": ("+ (state_boxed(q->prm, r) ? q->prm->rho : 0.0);", ";"),
     "relaxation_dual_update_unrelaxed": ("lam[ZI(i, j, t) + c] += rho * (xi[c] - a[c]);",
                                          "lam[ZI(i, j, t) + c] += rho * (pi[c] - a[c]);"),
     "relaxation_weights_swapped": ("prm->alpha * pi[c] + (1.0 - prm->alpha) * z[ZI(i, j, t) + c]",
@@ -66,6 +69,8 @@ PIN_FUNCS = [pins.test_agent_qp_unconstrained_matches_condensed_least_squares,
              pins.test_hetero_single_agent_is_its_local_qp,
              pins.test_hetero_agent_permutation_equivariance,
              pins.test_admm_state_box_frozen_limit_is_centralized_qp_kkt_certificate,
+             pins.test_admm_position_box_frozen_limit_is_centralized_qp_kkt_certificate,
+             pins.test_admm_position_box_with_adaptive_rho_same_certified_limit,
              pins.test_admm_relaxation_closed_form_far_apart,
              pins.test_admm_relaxation_frozen_limit_is_the_same_kkt_point]
 

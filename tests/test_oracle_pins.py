@@ -286,19 +286,14 @@ def test_admm_adaptive_rho_frozen_limit_is_the_same_kkt_point():
     assert np.all(m >= -1e-7)
 
 
-def test_admm_state_box_frozen_limit_is_centralized_qp_kkt_certificate():
-    """The state box (a further ADMM split on the velocities): with fixed
-    normals the limit solves the centralized QP with the velocity box added.
-    Certificate as above (gradient = a nonnegative combination of the
-    binding rows), with the velocity rows v_t = (Phi_t x0 + Gam_t u) in
-    [-vmax, vmax] among the constraints; the box must bind."""
-    p = synth.ProblemParams(dp=2, u_max=2.0)
-    sc, nrm = _side_pass()
-    T, dp, vmax = sc.T, p.dp, 2.5    # off the grid of multiples of u_max dt (degenerate there)
-    res = oracle.solve(p, sc, oracle.OracleOptions(normal_mode=oracle.NORMAL_FROZEN, rho=10.0, max_iter=3000,
-                                                   eps_abs=1e-11, eps_rel=1e-11, state_box=True,
-                                                   s_lo=(-vmax,) * 3, s_hi=(vmax,) * 3), normals=nrm)
-    assert res["status"] == oracle.CONVERGED
+def _box_certificate(p, sc, nrm, res, k0, lo, hi, what):
+    """Centralized-QP certificate with state rows x_t[k0 + c] = (Phi_t x0 +
+    Gam_t u)[k0 + c] in [lo_c, hi_c] (t = 1..T) among the constraints: the
+    solution is feasible, the box binds, and the objective's gradient is a
+    nonnegative combination of the binding rows (nonnegative least squares:
+    the active rows can be dependent, e.g. a bound input and the state rows
+    it drives)."""
+    T, dp = sc.T, p.dp
     J, b, G, h = _monolithic_pieces(p, sc, nrm)
     Phi, Gam = condensed.state_maps(p.A, p.B, T)
     n = T * p.nu
@@ -308,17 +303,17 @@ def test_admm_state_box_frozen_limit_is_centralized_qp_kkt_certificate():
         for t in range(1, T + 1):
             for c in range(dp):
                 g = np.zeros(sc.N * n)
-                g[i * n:(i + 1) * n] = Gam[t][dp + c]
-                v0 = (Phi[t] @ x0[i])[dp + c]
+                g[i * n:(i + 1) * n] = Gam[t][k0 + c]
+                s0 = (Phi[t] @ x0[i])[k0 + c]
                 rows += [g, -g]
-                rhs += [-vmax - v0, -vmax + v0]
+                rhs += [lo[c] - s0, -(hi[c] - s0)]
     G = np.vstack([G, np.array(rows)])
     h = np.concatenate([h, np.array(rhs)])
     U = res["u"].reshape(-1)
     slack = G @ U - h
     assert np.all(slack >= -1e-7)
     nbox = len(rows)
-    assert np.sum(np.abs(slack[-nbox:]) < 1e-6) >= 1, "the velocity box should bind"
+    assert np.sum(np.abs(slack[-nbox:]) < 1e-6) >= 1, f"the {what} box should bind"
     grad = 2.0 * J.T @ (J @ U - b)
     W = res["w"].reshape(-1)
     cols = []
@@ -328,11 +323,82 @@ def test_admm_state_box_frozen_limit_is_centralized_qp_kkt_certificate():
         cols.append(e)
     for k in np.nonzero(np.abs(slack) < 1e-6)[0]:
         cols.append(G[k])
-    # the active rows are dependent here (a bound input and the velocity
-    # rows it drives): certify with nonnegative least squares
     M = np.array(cols).T
     m, resid = scipy.optimize.nnls(M, grad)
     assert resid < 1e-6 * (1 + np.linalg.norm(grad))
+
+
+def test_admm_state_box_frozen_limit_is_centralized_qp_kkt_certificate():
+    """The state box (a further ADMM split on the velocities): with fixed
+    normals the limit solves the centralized QP with the velocity box added
+    (certificate above, with the velocity rows v_t in [-vmax, vmax])."""
+    p = synth.ProblemParams(dp=2, u_max=2.0)
+    sc, nrm = _side_pass()
+    vmax = 2.5    # off the grid of multiples of u_max dt (degenerate there)
+    res = oracle.solve(p, sc, oracle.OracleOptions(normal_mode=oracle.NORMAL_FROZEN, rho=10.0, max_iter=3000,
+                                                   eps_abs=1e-11, eps_rel=1e-11, state_box=True,
+                                                   s_lo=(-vmax,) * 3, s_hi=(vmax,) * 3), normals=nrm)
+    assert res["status"] == oracle.CONVERGED
+    _box_certificate(p, sc, nrm, res, p.dp, (-vmax,) * 2, (vmax,) * 2, "velocity")
+
+
+def _box_pass(T=30):
+    """Two agents passing side by side towards goals beyond x = +-3."""
+    sc = synth.Scenario(starts=np.array([[-2.0, 0.6], [2.0, -0.6]]),
+                        goals=np.array([[3.5, 0.1], [-3.5, -0.1]]), T=T)
+    nrm = np.zeros((1, T, 2))
+    nrm[..., 1] = 1.0
+    return sc, nrm
+
+
+def test_admm_position_box_frozen_limit_is_centralized_qp_kkt_certificate():
+    """The position box (the same split on the positions, whose rows then
+    carry both the consensus and the box penalty): the limit solves the
+    centralized QP with the position rows p_t in [-3, 3] x [-1, 1]; the
+    x bound binds (the goals lie beyond it)."""
+    p = synth.ProblemParams(dp=2, u_max=2.0)
+    sc, nrm = _box_pass()
+    lo, hi = (-3.0, -1.0), (3.0, 1.0)
+    res = oracle.solve(p, sc, oracle.OracleOptions(normal_mode=oracle.NORMAL_FROZEN, rho=10.0, max_iter=3000,
+                                                   eps_abs=1e-11, eps_rel=1e-11, state_box=True,
+                                                   p_lo=lo + (0.0,), p_hi=hi + (0.0,)), normals=nrm)
+    assert res["status"] == oracle.CONVERGED
+    _box_certificate(p, sc, nrm, res, 0, lo, hi, "position")
+
+
+def test_admm_position_box_with_adaptive_rho_same_certified_limit():
+    """Residual balancing keeps the box's sigma (the initial penalty) on the
+    position rows while rho moves (here from 3 up to 24 and down to 1.5):
+    the adaptive run's limit passes the same certificate.  A shorter pass
+    (T = 20, |x| <= 2.2) keeps the pin fast."""
+    p = synth.ProblemParams(dp=2, u_max=2.0)
+    T = 20
+    sc = synth.Scenario(starts=np.array([[-1.5, 0.6], [1.5, -0.6]]), goals=np.array([[3.5, 0.1], [-3.5, -0.1]]), T=T)
+    nrm = np.zeros((1, T, 2))
+    nrm[..., 1] = 1.0
+    lo, hi = (-2.2, -1.0), (2.2, 1.0)
+    res = oracle.solve(p, sc, oracle.OracleOptions(normal_mode=oracle.NORMAL_FROZEN, rho=3.0, adaptive_rho=True,
+                                                   rho_mu=5.0, max_iter=1000, eps_abs=1e-11, eps_rel=1e-11,
+                                                   state_box=True, p_lo=lo + (0.0,), p_hi=hi + (0.0,)), normals=nrm)
+    assert res["status"] == oracle.CONVERGED and len(np.unique(res["rho_hist"][:res["iters"]])) >= 3
+    _box_certificate(p, sc, nrm, res, 0, lo, hi, "position")
+
+
+def test_admm_state_box_groups_split_only_where_bounded():
+    """A group of states with no finite bound is not split: infinite bounds
+    reproduce the unboxed run bitwise, and a velocity box leaves the
+    iterates of an infinite position box unchanged."""
+    p, scs = synth.config2(S=3)
+    sc = scs[2]
+    base = dict(max_iter=30, fixed_iters=30)
+    plain = oracle.solve(p, sc, oracle.OracleOptions(**base))
+    inf = oracle.solve(p, sc, oracle.OracleOptions(state_box=True, **base))
+    np.testing.assert_array_equal(plain["x"], inf["x"])
+    vel = oracle.solve(p, sc, oracle.OracleOptions(state_box=True, s_lo=(-2.0,) * 3, s_hi=(2.0,) * 3, **base))
+    both = oracle.solve(p, sc, oracle.OracleOptions(state_box=True, s_lo=(-2.0,) * 3, s_hi=(2.0,) * 3,
+                                                    p_lo=(-np.inf,) * 3, p_hi=(np.inf,) * 3, **base))
+    np.testing.assert_array_equal(vel["x"], both["x"])
+    assert not np.array_equal(vel["x"], plain["x"])
 
 
 def test_admm_frozen_limit_matches_slsqp():
@@ -626,7 +692,7 @@ def test_admm_relaxation_frozen_limit_is_the_same_kkt_point():
     iterations (the speed-up Boyd et al. report for alpha in [1.5, 1.8])."""
     p = synth.ProblemParams(dp=2, u_max=2.0)
     sc, nrm = _side_pass()
-    tight = dict(normal_mode=oracle.NORMAL_FROZEN, rho=10.0, max_iter=20000, eps_abs=1e-10, eps_rel=1e-10)
+    tight = dict(normal_mode=oracle.NORMAL_FROZEN, rho=10.0, max_iter=1000, eps_abs=1e-10, eps_rel=1e-10)
     plain = oracle.solve(p, sc, oracle.OracleOptions(**tight), normals=nrm)
     relax = oracle.solve(p, sc, oracle.OracleOptions(alpha=1.6, **tight), normals=nrm)
     assert plain["status"] == oracle.CONVERGED and relax["status"] == oracle.CONVERGED
