@@ -163,6 +163,11 @@ typedef struct {
                                 floats more per ordered pair copy and step (the
                                 copies' z), and tadmm_polish/adjoint reject the
                                 solve.                                           */
+  float p_lo[3], p_hi[3];    /* with state_box: a box p_lo <= x_t,c <= p_hi on the
+                                positions (c < nu, t = 1..T), by the same split;
+                                p_lo < p_hi (+-inf: unbounded).  Each group
+                                (positions, other states) is split only where
+                                one of its bounds is finite.                     */
 } tadmm_params;
 
 /* A ragged batch of S independent scenarios.  Scenario s has N_s agents and

@@ -43,7 +43,7 @@ class Params(C.Structure):
                 ("refine_band", C.c_float), ("eqp_fp64", C.c_int32), ("adaptive_rho", C.c_int32),
                 ("rho_mu", C.c_float), ("rho_tau", C.c_float), ("rho_every", C.c_int32),
                 ("state_box", C.c_int32), ("s_lo", C.c_float * 3), ("s_hi", C.c_float * 3),
-                ("alpha", C.c_float)]
+                ("alpha", C.c_float), ("p_lo", C.c_float * 3), ("p_hi", C.c_float * 3)]
 
 
 _fp = C.POINTER(C.c_float)
@@ -115,7 +115,8 @@ def make_params(problem, *, normal_mode: int = NORMAL_PER_ITER, mu_tol: float = 
                 refine_band: float = 10.0, eqp_fp64: bool = True, adaptive_rho: bool = False,
                 rho_mu: float = 10.0, rho_tau: float = 2.0, rho_every: int = 1, state_box: bool = False,
                 s_lo: Optional[Sequence[float]] = None, s_hi: Optional[Sequence[float]] = None,
-                alpha: float = 1.0, max_iter: Optional[int] = None,
+                alpha: float = 1.0, p_lo: Optional[Sequence[float]] = None,
+                p_hi: Optional[Sequence[float]] = None, max_iter: Optional[int] = None,
                 eps_abs: Optional[float] = None, eps_rel: Optional[float] = None,
                 rho: Optional[float] = None) -> Params:
     """Fill the C parameter struct from a problem description (attributes
@@ -156,6 +157,9 @@ def make_params(problem, *, normal_mode: int = NORMAL_PER_ITER, mu_tol: float = 
         p.s_lo[c] = float(-np.inf if s_lo is None or c >= len(s_lo) else s_lo[c])
         p.s_hi[c] = float(np.inf if s_hi is None or c >= len(s_hi) else s_hi[c])
     p.alpha = float(alpha)
+    for c in range(3):
+        p.p_lo[c] = float(-np.inf if p_lo is None or c >= len(p_lo) else p_lo[c])
+        p.p_hi[c] = float(np.inf if p_hi is None or c >= len(p_hi) else p_hi[c])
     return p
 
 

@@ -39,6 +39,8 @@ struct Prob {
   float rho_mu, rho_tau;
   int sbox;                      // box on the non-position states (ADMM split, penalty sigma)
   float sigma, slo[3], shi[3];
+  int pbox;                      // box on the positions (the same split)
+  float plo[3], phi[3];
   int relax;                     // over-relaxation with factor alpha (alpha != 1)
   float alpha;
 };
@@ -131,7 +133,8 @@ struct Fld {
   // [2 DP], and the constant velocity tracking term -2 Q_t r_t     [DP]
   static constexpr int YM = GQP + pad4(DP);
   static constexpr int GQV = YM + pad4(2 * DP);
-  static constexpr int PU = GQV + pad4(DP);     // value Hessian P_t (upper)      [NP]
+  static constexpr int YP = GQV + pad4(DP);     // position box: copy y and dual mu [2 DP]
+  static constexpr int PU = YP + pad4(2 * DP);  // value Hessian P_t (upper)      [NP]
   static constexpr int RED = PU + pad4(NP);     // residual partial sums          [5]
   static constexpr int NF = RED + pad4(5);
 };
@@ -274,7 +277,8 @@ __device__ __forceinline__ void stage_hx(const Prob &pb, const float *qd, int t,
   const float w = (t == T) ? pb.qT : 1.0f;
 #pragma unroll
   for (int r = 0; r < NX; ++r)
-    hx[r] = 2.0f * w * qd[r] + (r < NU ? rho * (float)n_nbr : (pb.sbox ? pb.sigma : 0.0f));
+    hx[r] = 2.0f * w * qd[r] + (r < NU ? rho * (float)n_nbr + (pb.pbox ? pb.sigma : 0.0f)
+                                       : (pb.sbox ? pb.sigma : 0.0f));
 }
 
 // ---------------------------------------------------------------------------

@@ -173,7 +173,7 @@ struct AxisView {
   // stage_hx of the axis: 2 w q_pos + rho n_nbr on the position, 2 w q_vel
   __device__ __forceinline__ void hx(const Prob &pb, int t, int T, int n_nbr, float h[2]) const {
     const float w = (t == T) ? pb.qT : 1.0f;
-    h[0] = 2.0f * w * qd[0] + rho * (float)n_nbr;
+    h[0] = 2.0f * w * qd[0] + rho * (float)n_nbr + (pb.pbox ? pb.sigma : 0.0f);
     h[1] = 2.0f * w * qd[1] + (pb.sbox ? pb.sigma : 0.0f);
   }
 };
@@ -1062,6 +1062,26 @@ __device__ void pair_agent_stage_impl(const Prob &pb, const WS &ws, const Scen &
     Ri(F::QZ + NU + c) = zd[c];
   }
   ax2 *= nn;
+  if (pb.pbox) {
+    // the position box block, as below; its linear term joins the consensus
+    // part of q written above
+    const float sg = pb.sigma;
+#pragma unroll
+    for (int c = 0; c < NU; ++c) {
+      const float yo = Ri(F::YP + c), mo = Ri(F::YP + NU + c);
+      const float yn = fminf(fmaxf(pi[c] + mo / sg, pb.plo[c]), pb.phi[c]);
+      const float mn = fmaf(sg, pi[c] - yn, mo);
+      const float ds = sg * (yn - yo);
+      Ri(F::YP + c) = yn;
+      Ri(F::YP + NU + c) = mn;
+      Ri(F::QZ + c) -= fmaf(sg, yn, -mn);
+      r2 = fmaf(pi[c] - yn, pi[c] - yn, r2);
+      s2 = fmaf(ds, ds, s2);
+      ax2 = fmaf(pi[c], pi[c], ax2);
+      z2 = fmaf(yn, yn, z2);
+      aty2 = fmaf(mn, mn, aty2);
+    }
+  }
   if (pb.sbox) {
     // the state box block: y = clip(x + mu / sigma), mu += sigma (x - y), and
     // the next linear term -2 Q r - (sigma y - mu) on those states
@@ -1133,7 +1153,7 @@ __device__ int scenario_test(const Prob &pb, const WS &ws, const Scen &sc, int k
     const float P = 0.5f * (float)sc.N * (float)(sc.N - 1);
     const float rn = sqrtf(a[0]), sn = sqrtf(a[1]);
     // the state box block adds N T (NX - NU) rows and coupled states
-    const float nbox = pb.sbox ? (float)sc.N * (float)sc.T * (float)(NX - NU) : 0.0f;
+    const float nbox = (float)sc.N * (float)sc.T * (float)NU * (float)(pb.sbox + pb.pbox);
     const float epri = sqrtf(fmaf(2.0f * P, (float)sc.T * (float)NU, nbox)) * pb.eps_abs +
                        pb.eps_rel * fmaxf(sqrtf(a[2]), sqrtf(a[3]));
     const float edual = sqrtf(fmaf((float)sc.N, (float)sc.T * (float)NU, nbox)) * pb.eps_abs +
@@ -1190,6 +1210,12 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
         for (int c = 0; c < NU; ++c) {
           Rg(F::QZ + c) = fmaf(-ws.rhos[2 * sc.s] * (float)n_nbr, Rg(F::X + c), Rg(F::GQP + c));
           Rg(F::QZ + NU + c) = 0.f;
+          if (pb.pbox && idx >= N) {
+            const float y0 = fminf(fmaxf(Rg(F::X + c), pb.plo[c]), pb.phi[c]);
+            Rg(F::YP + c) = y0;
+            Rg(F::YP + NU + c) = 0.f;
+            Rg(F::QZ + c) -= pb.sigma * y0;
+          }
         }
         // and the state box block restarts at y = clip(x), mu = 0
         if (pb.sbox && idx >= N) {
@@ -1259,7 +1285,13 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
     for (int c = 0; c < NU; ++c) {
       // x^0 := r so that z^0 = C r, lambda^0 = 0
       Rg(F::GQP + c) = gq[c];
-      Rg(F::QZ + c) = fmaf(-pb.rho * (float)n_nbr, r[c], gq[c]);
+      float qz = fmaf(-pb.rho * (float)n_nbr, r[c], gq[c]);
+      // the position box: y^0 = the reference clipped, mu^0 = 0
+      const float y0 = fminf(fmaxf(r[c], pb.plo[c]), pb.phi[c]);
+      Rg(F::YP + c) = y0;
+      Rg(F::YP + NU + c) = 0.f;
+      if (pb.pbox && t >= 1) qz -= pb.sigma * y0;
+      Rg(F::QZ + c) = qz;
       Rg(F::XP + c) = r[c];
       Rg(F::QZ + NU + c) = 0.f;
       uref<NX, NU>(R, (unsigned)GS, (unsigned)idx, c) = 0.f;
@@ -1857,10 +1889,14 @@ bool params_ok(const tadmm_params *p, std::string &err) {
     err = "adaptive_rho needs rho_mu >= 1, rho_tau > 1 and rho_every >= 1"; return false;
   }
   if (p->state_box)
-    for (int c = 0; c < p->nx - p->nu; ++c)
+    for (int c = 0; c < p->nu; ++c) {
       if (std::isnan(p->s_lo[c]) || std::isnan(p->s_hi[c]) || !(p->s_lo[c] < p->s_hi[c])) {
         err = "state_box needs s_lo < s_hi (infinite ends allowed)"; return false;
       }
+      if (std::isnan(p->p_lo[c]) || std::isnan(p->p_hi[c]) || !(p->p_lo[c] < p->p_hi[c])) {
+        err = "state_box needs p_lo < p_hi (infinite ends allowed)"; return false;
+      }
+    }
   if (!(p->alpha >= 0.f && p->alpha < 2.f)) { err = "alpha must be in (0, 2) (0: plain ADMM)"; return false; }
   if (p->max_iter < 1) { err = "max_iter must be >= 1"; return false; }
   if (p->normal_mode != TADMM_NORMAL_PER_ITER && p->normal_mode != TADMM_NORMAL_FROZEN) {
@@ -1987,7 +2023,15 @@ Prob to_prob(const tadmm_params &p) {
   pb.rho_tau = p.rho_tau;
   pb.relax = relaxed(p) ? 1 : 0;
   pb.alpha = pb.relax ? p.alpha : 1.0f;
-  pb.sbox = p.state_box ? 1 : 0;
+  // each group of states is split only where one of its bounds is finite
+  auto bounded = [&](const float *lo, const float *hi) {
+    for (int c = 0; c < p.nu; ++c)
+      if (std::isfinite(lo[c]) || std::isfinite(hi[c])) return true;
+    return false;
+  };
+  pb.sbox = (p.state_box && bounded(p.s_lo, p.s_hi)) ? 1 : 0;
+  pb.pbox = (p.state_box && bounded(p.p_lo, p.p_hi)) ? 1 : 0;
+  for (int c = 0; c < 3; ++c) { pb.plo[c] = p.p_lo[c]; pb.phi[c] = p.p_hi[c]; }
   pb.sigma = p.rho;
   for (int c = 0; c < 3; ++c) { pb.slo[c] = p.s_lo[c]; pb.shi[c] = p.s_hi[c]; }
   return pb;

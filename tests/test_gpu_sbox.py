@@ -1,9 +1,9 @@
-"""The state box (bounds on the non-position states, here the velocities, by
-a further ADMM split: y = clip(x + mu / sigma), mu += sigma (x - y), with
+"""The state box (bounds on the velocities and on the positions, each group
+by a further ADMM split: y = clip(x + mu / sigma), mu += sigma (x - y), with
 sigma the penalty) on the device against the oracle's, through the C ABI.
 Lockstep runs follow the oracle's iterates to the parity bar; with frozen
 normals the converged device solution is the oracle's solution of the same
-strictly convex QP, and its velocities respect the box; the three modes agree
+strictly convex QP, and its states respect the box; the three modes agree
 bitwise; the derivative rejects the box."""
 import sys
 
@@ -121,3 +121,78 @@ def test_state_box_derivative_rejected():
         prep.polish()
     assert "error 1" in str(e.value)
     solver.close()
+
+
+PBOX = dict(state_box=True, p_lo=(-4.6, -4.6), p_hi=(4.6, 4.6))
+
+
+@pytest.mark.parametrize("both", [False, True])
+def test_position_box_lockstep_matches_oracle(both):
+    """Config-2 crossings (starts and goals in [-5, 5]^2) with the positions
+    held in [-4.6, 4.6]^2, alone and with the velocity box."""
+    p, scs = synth.config2(S=12)
+    K = 40
+    kw = dict(PBOX, max_iter=K, eps_abs=0.0, eps_rel=0.0)
+    if both:
+        kw.update(s_lo=BOX["s_lo"], s_hi=BOX["s_hi"])
+    g = gc.gpu_solve(p, scs, solver_kw=kw)
+    o = gc.oracle_same_instance(p, scs, gc.oracle_opts(kw, lockstep=K), threads=4)
+    free = gc.gpu_solve(p, scs, solver_kw=dict(max_iter=K, eps_abs=0.0, eps_rel=0.0))
+    worst, differs = 0.0, 0
+    for sc, gr, orr, fr in zip(scs, g, o, free):
+        rel = gc.rel_traj_err(gr, orr)
+        worst = max(worst, rel)
+        assert rel <= gc.REL_TOL, (sc.N, sc.T, rel)
+        differs += not np.array_equal(gr["x"], fr["x"])
+    _say(f"  position box{' + velocity box' if both else ''}: worst rel {worst:.2e}; {differs} of {len(scs)} "
+         f"differ from the unboxed run")
+    assert differs >= len(scs) // 2
+
+
+def test_position_box_frozen_limit_matches_oracle():
+    """Two agents passing side by side towards goals beyond x = +-3, with the
+    positions held in [-3, 3] x [-1, 1]: the converged device solution is the
+    oracle's tight one, and the positions respect the box."""
+    p = synth.ProblemParams(dp=2, u_max=2.0)
+    T = 30
+    sc = synth.Scenario(starts=np.array([[-2.0, 0.6], [2.0, -0.6]]), goals=np.array([[3.5, 0.1], [-3.5, -0.1]]), T=T)
+    nrm = np.zeros((1, T, 2))
+    nrm[..., 1] = 1.0
+    base = dict(state_box=True, p_lo=(-3.0, -1.0), p_hi=(3.0, 1.0), normal_mode=tadmm.NORMAL_FROZEN, rho=10.0)
+    run = dict(base, max_iter=20000, eps_abs=1e-6, eps_rel=1e-6)
+    g = gc.gpu_solve(p, [sc], normals=[nrm], solver_kw=run)[0]
+    o = gc.oracle_same_instance(p, [sc], gc.oracle_opts(run), normals=[nrm])[0]
+    tight = gc.oracle_same_instance(p, [sc], gc.oracle_opts(dict(base, max_iter=20000, eps_abs=1e-11,
+                                                                 eps_rel=1e-11)), normals=[nrm])[0]
+    rel, rel_t = gc.rel_traj_err(g, o), gc.rel_traj_err(g, tight)
+    # ADMM converges slowly here: at tolerance 1e-6 both sides stop about
+    # 1e-4 short of the limit, so the tight comparison takes 10 times the
+    # oracle's own distance (the bar of runs limited by their tolerance)
+    own = gc.rel_traj_err(dict(x=o["x"], u=o["u"]), tight)
+    px = np.abs(g["x"][:, 1:, 0]).max()
+    _say(f"  device {g['iters']} / oracle {o['iters']} iterations; rel {rel:.2e} (same tolerance), {rel_t:.2e} "
+         f"(tight; the oracle's own {own:.2e}); max |x| {px:.5f}")
+    assert o["status"] == oracle.CONVERGED and tight["status"] == oracle.CONVERGED
+    assert g["status"] == tadmm.SCEN_CONVERGED
+    assert rel <= gc.REL_TOL and rel_t <= max(gc.REL_TOL, 10.0 * own)
+    assert px <= 3.0 + 1e-3 and px >= 3.0 - 1e-3     # the bound binds and holds
+
+
+def test_position_box_modes_bitwise_equal():
+    p, scs = synth.config2(S=10)
+    kw = dict(PBOX, s_lo=BOX["s_lo"], s_hi=BOX["s_hi"], max_iter=100)
+    a = gc.gpu_solve(p, scs, mode=tadmm.MODE_PLAIN, solver_kw=kw)
+    for mode in (tadmm.MODE_BATCHED, tadmm.MODE_WIDE):
+        b = gc.gpu_solve(p, scs, mode=mode, solver_kw=kw)
+        for ga, gb in zip(a, b):
+            assert ga["iters"] == gb["iters"] and ga["status"] == gb["status"]
+            np.testing.assert_array_equal(ga["x"], gb["x"])
+
+
+def test_infinite_box_is_no_box():
+    """state_box with every bound infinite splits nothing: bitwise the plain solve."""
+    p, scs = synth.config2(S=6)
+    a = gc.gpu_solve(p, scs, solver_kw=dict(max_iter=60))
+    b = gc.gpu_solve(p, scs, solver_kw=dict(state_box=True, max_iter=60))
+    for ga, gb in zip(a, b):
+        np.testing.assert_array_equal(ga["x"], gb["x"])

@@ -98,6 +98,10 @@ def test_bad_state_box_rejected(lo, hi):
     assert _ws(prm, [2], [20])[0] == 1
     prm.state_box = 0             # the bounds are not read without the box
     assert _ws(prm, [2], [20])[0] == 0
+    prm = tadmm.make_params(synth.ProblemParams(), state_box=True, p_lo=(-1.0, -1.0), p_hi=(1.0, 1.0))
+    assert _ws(prm, [2], [20])[0] == 0
+    prm.p_lo[0], prm.p_hi[0] = lo, hi
+    assert _ws(prm, [2], [20])[0] == 1
     # a one-sided box (an infinite end) is allowed; the unused third slot is not read in 2-D
     prm = tadmm.make_params(synth.ProblemParams(), state_box=True, s_lo=(-1.0, -np.inf), s_hi=(np.inf, 1.0))
     prm.s_lo[2] = prm.s_hi[2] = float("nan")
