@@ -161,8 +161,8 @@ typedef struct {
                                 < 2.  1 (or 0, for zero-initialized structs):
                                 plain ADMM.  Otherwise the workspace holds 2 nu
                                 floats more per ordered pair copy and step (the
-                                copies' z), and tadmm_polish/adjoint reject the
-                                solve.                                           */
+                                copies' z).  The derivative of a relaxed solve is
+                                that of its converged point, as without.         */
   float p_lo[3], p_hi[3];    /* with state_box: a box p_lo <= x_t,c <= p_hi on the
                                 positions (c < nu, t = 1..T), by the same split;
                                 p_lo < p_hi (+-inf: unbounded).  Each group

@@ -4,7 +4,8 @@ oracle's, through the C ABI.  Lockstep runs follow the oracle's iterates to
 the parity bar; with frozen normals the relaxed run converges to the oracle's
 solution of the same QP in fewer iterations than plain ADMM; the three modes
 agree bitwise; SQP rounds (whose restarts reset the copies' z) match the
-oracle's."""
+oracle's.  The derivative of a relaxed solve is tested with the others
+(tests/test_gpu_adjoint.py)."""
 import sys
 
 import numpy as np
@@ -111,7 +112,7 @@ def test_relaxed_sqp_matches_oracle():
     st = prep.sqp(tadmm.MODE_BATCHED, max_rounds=10).cpu().numpy()
     res = tadmm.split_outputs(prep.result(), pk.n_agents, pk.horizon, p.nx, p.nu)
     with pytest.raises(tadmm.TadmmError):
-        prep.polish()
+        prep.polish()             # the derivative is defined for tadmm_solve results
     solver.close()
     o = oracle.OracleOptions(alpha=float(np.float32(ALPHA)), **KW)
     ref = osqp.sqp_solve(gc.Fp32Problem(p), scs, o, inputs=[gc.fp32_inputs(sc) for sc in scs], max_rounds=10)
@@ -124,10 +125,3 @@ def test_relaxed_sqp_matches_oracle():
         assert abs(J - r["objective"][-1]) <= 1e-5 * abs(r["objective"][-1])
 
 
-def test_relaxed_derivative_rejected():
-    p, scs = synth.config0()
-    res, prep, solver = gc.gpu_solve(p, scs, solver_kw=dict(alpha=ALPHA, max_iter=50), return_prep=True)
-    with pytest.raises(tadmm.TadmmError) as e:
-        prep.polish()
-    assert "error" in str(e.value)
-    solver.close()
