@@ -67,7 +67,8 @@ _dp = C.POINTER(C.c_double)
 class _Scenario(C.Structure):
     _fields_ = [("N", C.c_int), ("T", C.c_int), ("x0", _dp), ("xref", _dp),
                 ("q_diag", _dp), ("r_diag", _dp), ("normals", _dp),
-                ("agent_q", _dp), ("agent_r", _dp), ("agent_lo", _dp), ("agent_hi", _dp)]
+                ("agent_q", _dp), ("agent_r", _dp), ("agent_lo", _dp), ("agent_hi", _dp),
+                ("agent_A", _dp), ("agent_B", _dp)]
 
 
 class _Result(C.Structure):
@@ -199,13 +200,15 @@ class _Holder:
         self.rho_hist = np.zeros(max(maxit, 1))
         self.z = np.zeros((N, N, T, dp)) if keep_zl else None
         self.lam = np.zeros((N, N, T, dp)) if keep_zl else None
-        # heterogeneous agents: per-agent weights and input boxes (optional)
+        # heterogeneous agents: per-agent weights, input boxes, dynamics (optional)
         per = lambda f, w: (None if getattr(sc, f, None) is None else
                             np.ascontiguousarray(np.asarray(getattr(sc, f), dtype=np.float64).reshape(N, w)))
         self.aq, self.ar = per("agent_q", nx), per("agent_r", nu)
         self.alo, self.ahi = per("agent_lo", nu), per("agent_hi", nu)
+        self.aA, self.aB = per("agent_A", nx * nx), per("agent_B", nx * nu)
         self.sc = _Scenario(N, T, _ptr(self.x0), _ptr(self.xref), _ptr(self.q), _ptr(self.r), _ptr(self.normals),
-                            _ptr(self.aq), _ptr(self.ar), _ptr(self.alo), _ptr(self.ahi))
+                            _ptr(self.aq), _ptr(self.ar), _ptr(self.alo), _ptr(self.ahi), _ptr(self.aA),
+                            _ptr(self.aB))
         self.res = _Result(_ptr(self.x), _ptr(self.u), self.w.ctypes.data_as(C.POINTER(C.c_byte)), _ptr(self.mu),
                            self.pa.ctypes.data_as(C.POINTER(C.c_ubyte)), _ptr(self.z), _ptr(self.lam),
                            _ptr(self.hist), 0, 0, 0.0, 0.0, 0.0, 0.0, 0, 0, _ptr(self.rho_hist))

@@ -91,6 +91,7 @@ typedef struct {
   const double *x0;
   const double *qd;  /* diagonal of Q */
   const double *lo, *hi;  /* input box of this agent */
+  const double *A, *B;    /* dynamics of this agent, row-major nx*nx and nx*nu */
   double *Hd;      /* [nv] diagonal of H                       */
   double *cv;      /* [nv] linear term                          */
   /* KKT factor cache, valid for the working set stored in wkey */
@@ -144,7 +145,7 @@ static int eqp_solve(qp_ws *q, const signed char *W, double *sol, long *facts) {
         K[(size_t)cx1 * nk + R] = 1.0;
         if (t >= 1) {
           for (int c = 0; c < nx; ++c) {
-            const double a = prm->A[r * nx + c];
+            const double a = q->A[r * nx + c];
             if (a == 0.0) continue;
             const int col = ix(q, t, c);
             K[(size_t)R * nk + col] = -a;
@@ -152,7 +153,7 @@ static int eqp_solve(qp_ws *q, const signed char *W, double *sol, long *facts) {
           }
         }
         for (int c = 0; c < nu; ++c) {
-          const double b = prm->B[r * nu + c];
+          const double b = q->B[r * nu + c];
           if (b == 0.0) continue;
           const int col = iu(q, t, c);
           K[(size_t)R * nk + col] = -b;
@@ -179,7 +180,7 @@ static int eqp_solve(qp_ws *q, const signed char *W, double *sol, long *facts) {
     for (int r = 0; r < nx; ++r) {
       double e = 0.0;
       if (t == 0)
-        for (int c = 0; c < nx; ++c) e += prm->A[r * nx + c] * q->x0[c];
+        for (int c = 0; c < nx; ++c) e += q->A[r * nx + c] * q->x0[c];
       sol[nv + t * nx + r] = e;
     }
   int a = 0;
@@ -199,8 +200,8 @@ static void rollout(const qp_ws *q, double *x, const double *u) {
   for (int t = 0; t < q->T; ++t) {
     for (int r = 0; r < nx; ++r) {
       double v = 0.0;
-      for (int c = 0; c < nx; ++c) v += q->prm->A[r * nx + c] * x[t * nx + c];
-      for (int c = 0; c < nu; ++c) v += q->prm->B[r * nu + c] * u[t * nu + c];
+      for (int c = 0; c < nx; ++c) v += q->A[r * nx + c] * x[t * nx + c];
+      for (int c = 0; c < nu; ++c) v += q->B[r * nu + c] * u[t * nu + c];
       x[(t + 1) * nx + r] = v;
     }
   }
@@ -216,6 +217,8 @@ static int qp_ws_init(qp_ws *q, const orc_params *prm, int T, int n_nbr, const d
   q->qd = qd;
   q->lo = prm->u_lo;
   q->hi = prm->u_hi;
+  q->A = prm->A;
+  q->B = prm->B;
   const int nkmax = q->nv + q->nd + T * q->nu;
   q->Hd = (double *)malloc(sizeof(double) * q->nv);
   q->cv = (double *)malloc(sizeof(double) * q->nv);
@@ -473,6 +476,8 @@ int orc_admm(const orc_params *prm, const orc_scenario *sc, orc_result *res, int
                              sc->xref + (size_t)i * (T + 1) * nx, agent_q(sc, nx, i), agent_r(sc, nu, i), NULL);
     if (sc->agent_lo) qs[i].lo = sc->agent_lo + (size_t)i * nu;
     if (sc->agent_hi) qs[i].hi = sc->agent_hi + (size_t)i * nu;
+    if (sc->agent_A) qs[i].A = sc->agent_A + (size_t)i * nx * nx;
+    if (sc->agent_B) qs[i].B = sc->agent_B + (size_t)i * nx * nu;
   }
   res->status = ORC_MAX_ITER;
   res->iters = 0;

@@ -79,6 +79,7 @@ typedef struct {
   const double *agent_q;     /* [N][nx] diagonal of Q per agent */
   const double *agent_r;     /* [N][nu] diagonal of R per agent */
   const double *agent_lo, *agent_hi;   /* [N][nu] input box per agent */
+  const double *agent_A, *agent_B;     /* [N][nx*nx], [N][nx*nu] dynamics per agent (row-major) */
 } orc_scenario;
 
 typedef struct {

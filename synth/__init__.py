@@ -105,6 +105,9 @@ class Scenario:
     agent_r: Optional[np.ndarray] = None
     agent_lo: Optional[np.ndarray] = None
     agent_hi: Optional[np.ndarray] = None
+    # per-agent dynamics [N][nx][nx], [N][nx][nu] (None: the problem's)
+    agent_A: Optional[np.ndarray] = None
+    agent_B: Optional[np.ndarray] = None
 
     @property
     def N(self) -> int:
@@ -275,6 +278,8 @@ class PackedBatch:
     agent_r: Optional[np.ndarray] = None    # [sum N_s][nu]
     agent_lo: Optional[np.ndarray] = None   # [sum N_s][nu]
     agent_hi: Optional[np.ndarray] = None   # [sum N_s][nu]
+    agent_A: Optional[np.ndarray] = None    # [sum N_s][nx*nx] (per-agent dynamics)
+    agent_B: Optional[np.ndarray] = None    # [sum N_s][nx*nu]
 
     @property
     def S(self) -> int:
@@ -320,6 +325,14 @@ def pack(params: ProblemParams, scenarios: List[Scenario], dtype=np.float64) -> 
         pb.agent_r = per_agent("agent_r", lambda sc: params.r_diag if sc.r_diag is None else sc.r_diag, nu)
         pb.agent_lo = per_agent("agent_lo", lambda sc: params.u_lo, nu)
         pb.agent_hi = per_agent("agent_hi", lambda sc: params.u_hi, nu)
+    if any(getattr(sc, f) is not None for sc in scenarios for f in ("agent_A", "agent_B")):
+        def per_agent_dyn(field, fallback, width):
+            return np.concatenate([np.asarray(getattr(sc, field), np.float64).reshape(sc.N, width)
+                                   if getattr(sc, field) is not None else
+                                   np.tile(np.asarray(fallback, np.float64).reshape(1, width), (sc.N, 1))
+                                   for sc in scenarios]).astype(dtype)
+        pb.agent_A = per_agent_dyn("agent_A", params.A, nx * nx)
+        pb.agent_B = per_agent_dyn("agent_B", params.B, nx * nu)
     return pb
 
 
@@ -333,6 +346,32 @@ def heterogeneous(rng: np.random.Generator, sc: Scenario, params: ProblemParams,
     r = (params.r_diag if sc.r_diag is None else sc.r_diag)[None, :] * f((N, nu))
     umax = params.u_max * rng.uniform(0.5, 1.5, size=(N, nu))
     return dataclasses.replace(sc, agent_q=q, agent_r=r, agent_lo=-umax, agent_hi=umax)
+
+
+def damped_point_mass(dp: int, dt: float, drag: float, mass: float):
+    """Exact zero-order-hold discretization of p' = v, v' = -drag v + u / mass
+    in `dp` dimensions (positions first), by the matrix exponential of the
+    augmented continuous system [[Ac, Bc], [0, 0]] dt."""
+    import scipy.linalg
+    n, m = 2 * dp, dp
+    M = np.zeros((n + m, n + m))
+    M[:dp, dp:n] = np.eye(dp)
+    M[dp:n, dp:n] = -drag * np.eye(dp)
+    M[dp:n, n:] = np.eye(dp) / mass
+    E = scipy.linalg.expm(M * dt)
+    return E[:n, :n], E[:n, n:]
+
+
+def mixed_dynamics(rng: np.random.Generator, sc: Scenario, params: ProblemParams, drag=(0.0, 1.5),
+                   mass=(0.5, 2.0)) -> Scenario:
+    """The same scenario with per-agent dynamics: each agent a damped point
+    mass with drag ~ U(drag) and mass ~ U(mass), exactly discretized."""
+    As, Bs = [], []
+    for _ in range(sc.N):
+        A, B = damped_point_mass(params.dp, sc.dt, rng.uniform(*drag), rng.uniform(*mass))
+        As.append(A)
+        Bs.append(B)
+    return dataclasses.replace(sc, agent_A=np.stack(As), agent_B=np.stack(Bs))
 
 
 def problem_dimensions(N: int, T: int, nx: int = 4, nu: int = 2):

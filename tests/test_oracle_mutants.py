@@ -43,6 +43,9 @@ MUTANTS = {
     "position_box_bounds_of_the_velocities": ("return r < prm->dp ? prm->p_hi[r] : prm->s_hi[r - prm->dp];",
                                               "return prm->s_hi[r % prm->dp];"),
     "adaptive_rho_drops_box_hessian_term": ("+ (state_boxed(q->prm, r) ? q->prm->rho : 0.0);", ";"),
+    "agent_dynamics_of_the_first_agent": ("if (sc->agent_A) qs[i].A = sc->agent_A + (size_t)i * nx * nx;",
+                                          "if (sc->agent_A) qs[i].A = sc->agent_A;"),
+    "agent_input_matrix_ignored_in_kkt": ("const double b = q->B[r * nu + c];", "const double b = prm->B[r * nu + c];"),
     "relaxation_dual_update_unrelaxed": ("lam[ZI(i, j, t) + c] += rho * (xi[c] - a[c]);",
                                          "lam[ZI(i, j, t) + c] += rho * (pi[c] - a[c]);"),
     "relaxation_weights_swapped": ("prm->alpha * pi[c] + (1.0 - prm->alpha) * z[ZI(i, j, t) + c]",
@@ -71,6 +74,9 @@ PIN_FUNCS = [pins.test_agent_qp_unconstrained_matches_condensed_least_squares,
              pins.test_admm_state_box_frozen_limit_is_centralized_qp_kkt_certificate,
              pins.test_admm_position_box_frozen_limit_is_centralized_qp_kkt_certificate,
              pins.test_admm_position_box_with_adaptive_rho_same_certified_limit,
+             pins.test_agent_dynamics_satisfied_per_agent,
+             pins.test_agent_dynamics_single_agent_is_its_local_qp,
+             pins.test_agent_input_gain_is_a_reparametrization,
              pins.test_admm_relaxation_closed_form_far_apart,
              pins.test_admm_relaxation_frozen_limit_is_the_same_kkt_point]
 

@@ -699,3 +699,87 @@ def test_admm_relaxation_frozen_limit_is_the_same_kkt_point():
     np.testing.assert_allclose(relax["u"], plain["u"], atol=1e-7)
     np.testing.assert_allclose(relax["x"], plain["x"], atol=1e-7)
     assert relax["iters"] < plain["iters"]
+
+
+class _WithDynamics:
+    """A problem's constants with its dynamics replaced by (A, B)."""
+
+    def __init__(self, p, A, B):
+        for k in ("dp", "nx", "nu", "dt", "max_iter", "u_lo", "u_hi", "u_max", "q_diag", "r_diag", "qT_scale",
+                  "d_min", "rho", "eps_abs", "eps_rel"):
+            setattr(self, k, getattr(p, k))
+        self.A, self.B = np.asarray(A, np.float64), np.asarray(B, np.float64)
+
+
+def _mixed_case(seed=3, N=4, T=14):
+    p, scs = synth.config2(S=40)
+    sc = [s for s in scs if s.N >= N][0]
+    sc = dataclasses.replace(sc, starts=sc.starts[:N], goals=sc.goals[:N], T=T)
+    return p, synth.mixed_dynamics(np.random.default_rng(seed), sc, p)
+
+
+def test_agent_dynamics_satisfied_per_agent():
+    """Each agent's trajectory obeys its own dynamics x_{t+1} = A_i x_t +
+    B_i u_t from its start, and its own are not its neighbours'."""
+    p, sc = _mixed_case()
+    res = oracle.solve(p, sc, oracle.OracleOptions(max_iter=60))
+    for i in range(sc.N):
+        x, u = res["x"][i], res["u"][i]
+        np.testing.assert_allclose(x[0], sc.x0()[i], atol=0)
+        pred = x[:-1] @ sc.agent_A[i].T + u @ sc.agent_B[i].T
+        np.testing.assert_allclose(x[1:], pred, atol=1e-10)
+        j = (i + 1) % sc.N
+        other = x[:-1] @ sc.agent_A[j].T + u @ sc.agent_B[j].T
+        assert np.abs(other - x[1:]).max() > 1e-6
+
+
+def test_agent_dynamics_single_agent_is_its_local_qp():
+    """One agent alone with its own dynamics converges in one iteration to
+    the local QP solved with those dynamics set problem-wide."""
+    p, sc = _mixed_case(N=3)
+    one = dataclasses.replace(sc, starts=sc.starts[:1], goals=sc.goals[:1], agent_A=sc.agent_A[:1],
+                              agent_B=sc.agent_B[:1])
+    res = oracle.solve(p, one)
+    assert res["status"] == oracle.CONVERGED and res["iters"] == 1
+    o = oracle.agent_qp(_WithDynamics(p, one.agent_A[0], one.agent_B[0]), one.T, 0, one.x0()[0], one.xref()[0],
+                        p.q_diag, p.r_diag)
+    np.testing.assert_allclose(res["u"][0], o["u"], atol=1e-9)
+    shared = oracle.solve(p, dataclasses.replace(one, agent_A=None, agent_B=None))
+    assert np.abs(shared["u"][0] - o["u"]).max() > 1e-3
+
+
+def test_agent_dynamics_uniform_equal_the_shared():
+    """Per-agent dynamics that repeat the problem's change nothing."""
+    p, scs = synth.config2(S=3)
+    sc = scs[2]
+    same = dataclasses.replace(sc, agent_A=np.tile(p.A, (sc.N, 1, 1)), agent_B=np.tile(p.B, (sc.N, 1, 1)))
+    o = oracle.OracleOptions(max_iter=40)
+    a, b = oracle.solve(p, sc, o), oracle.solve(p, same, o)
+    np.testing.assert_array_equal(a["x"], b["x"])
+    np.testing.assert_array_equal(a["u"], b["u"])
+
+
+def test_agent_input_gain_is_a_reparametrization():
+    """An agent whose input enters with gain g (B_i = g B) is the same agent
+    with input v = g u: its R scaled by 1/g^2 and its box by g.  Through
+    ADMM (4 crossing agents, 30 iterations in lockstep) the two give the
+    same states, and the inputs differ by the gain."""
+    p, sc = _mixed_case(N=4)
+    g = np.array([0.5, 1.7, 1.0, 2.3])
+    gained = dataclasses.replace(sc, agent_A=np.tile(p.A, (4, 1, 1)), agent_B=g[:, None, None] * p.B[None])
+    scaled = dataclasses.replace(sc, agent_A=None, agent_B=None, agent_r=p.r_diag[None, :] / g[:, None] ** 2,
+                                 agent_lo=p.u_lo[None, :] * g[:, None], agent_hi=p.u_hi[None, :] * g[:, None])
+    o = oracle.OracleOptions(fixed_iters=30)
+    a, b = oracle.solve(p, gained, o), oracle.solve(p, scaled, o)
+    np.testing.assert_allclose(a["x"], b["x"], atol=1e-8)
+    np.testing.assert_allclose(a["u"] * g[:, None, None], b["u"], atol=1e-8)
+
+
+def test_agent_dynamics_permutation_equivariance():
+    p, sc = _mixed_case(seed=5, N=4, T=12)
+    perm = np.array([2, 0, 3, 1])
+    sp = dataclasses.replace(sc, starts=sc.starts[perm], goals=sc.goals[perm], agent_A=sc.agent_A[perm],
+                             agent_B=sc.agent_B[perm])
+    o = oracle.OracleOptions(max_iter=60)
+    a, b = oracle.solve(p, sc, o), oracle.solve(p, sp, o)
+    np.testing.assert_allclose(b["x"], a["x"][perm], atol=1e-9)
