@@ -185,6 +185,10 @@ typedef struct {
  *   agent_r   DEVICE float [sum_s N_s][nu]  each agent's diagonal of R, > 0
  *   agent_lo, agent_hi  DEVICE float [sum_s N_s][nu]  each agent's input
  *             box (both or neither), finite, lo < hi
+ *   agent_A, agent_B  DEVICE float [sum_s N_s][nx*nx], [sum_s N_s][nx*nu]
+ *             each agent's dynamics x_{t+1} = A x_t + B u_t, row-major
+ *             (both or neither), finite; the solve then takes the
+ *             one-lane-per-agent path for every agent
  * P_s = N_s (N_s - 1) / 2. */
 typedef struct {
   int32_t n_scen;
@@ -196,6 +200,7 @@ typedef struct {
   const float *r_diag;
   const float *normals;
   const float *agent_q, *agent_r, *agent_lo, *agent_hi;
+  const float *agent_A, *agent_B;
 } tadmm_batch;
 
 /* Outputs, caller-allocated DEVICE buffers (any may be NULL except status

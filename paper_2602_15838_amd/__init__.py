@@ -54,7 +54,7 @@ class Batch(C.Structure):
     _fields_ = [("n_scen", C.c_int32), ("n_agents", _ip), ("horizon", _ip),
                 ("x0", C.c_void_p), ("xref", C.c_void_p), ("q_diag", C.c_void_p), ("r_diag", C.c_void_p),
                 ("normals", C.c_void_p), ("agent_q", C.c_void_p), ("agent_r", C.c_void_p),
-                ("agent_lo", C.c_void_p), ("agent_hi", C.c_void_p)]
+                ("agent_lo", C.c_void_p), ("agent_hi", C.c_void_p), ("agent_A", C.c_void_p), ("agent_B", C.c_void_p)]
 
 
 class Out(C.Structure):
@@ -210,10 +210,11 @@ class Solver:
         return int(nb.value)
 
     def prepare(self, n_agents, horizon, x0, xref, q_diag, r_diag, normals=None, agent_q=None, agent_r=None,
-                agent_lo=None, agent_hi=None):
+                agent_lo=None, agent_hi=None, agent_A=None, agent_B=None):
         """Allocate device inputs, outputs and the workspace for a batch.
-        agent_q [A][nx], agent_r [A][nu], agent_lo / agent_hi [A][nu]:
-        heterogeneous agents (each optional)."""
+        agent_q [A][nx], agent_r [A][nu], agent_lo / agent_hi [A][nu],
+        agent_A [A][nx*nx], agent_B [A][nx*nu]: heterogeneous agents (each
+        optional)."""
         torch = self.torch
         N = np.ascontiguousarray(n_agents, dtype=np.int32)
         T = np.ascontiguousarray(horizon, dtype=np.int32)
@@ -236,7 +237,9 @@ class Solver:
                  agent_q=None if agent_q is None else dt(agent_q, (A, nx)),
                  agent_r=None if agent_r is None else dt(agent_r, (A, nu)),
                  agent_lo=None if agent_lo is None else dt(agent_lo, (A, nu)),
-                 agent_hi=None if agent_hi is None else dt(agent_hi, (A, nu)))
+                 agent_hi=None if agent_hi is None else dt(agent_hi, (A, nu)),
+                 agent_A=None if agent_A is None else dt(agent_A, (A, nx * nx)),
+                 agent_B=None if agent_B is None else dt(agent_B, (A, nx * nu)))
         o = dict(x=torch.zeros(GS, nx, device=dev), u=torch.zeros(GU, nu, device=dev),
                  w=torch.zeros(GU, nu, dtype=torch.int8, device=dev),
                  pair_active=torch.zeros(PT, dtype=torch.uint8, device=dev),
@@ -262,7 +265,8 @@ class Prepared:
         self.solver, self.b, self.o, self.ws, self.nbytes = solver, b, o, ws, nbytes
         self.batch = Batch(int(b["N"].size), b["N"].ctypes.data_as(_ip), b["T"].ctypes.data_as(_ip),
                            _ptr(b["x0"]), _ptr(b["xref"]), _ptr(b["q_diag"]), _ptr(b["r_diag"]), _ptr(b["normals"]),
-                           _ptr(b["agent_q"]), _ptr(b["agent_r"]), _ptr(b["agent_lo"]), _ptr(b["agent_hi"]))
+                           _ptr(b["agent_q"]), _ptr(b["agent_r"]), _ptr(b["agent_lo"]), _ptr(b["agent_hi"]),
+                           _ptr(b["agent_A"]), _ptr(b["agent_B"]))
         self.out = Out(*[_ptr(o[k]) for k in ("x", "u", "w", "pair_active", "status", "iters", "r_norm", "s_norm",
                                               "eps_pri", "eps_dual", "counters")])
 

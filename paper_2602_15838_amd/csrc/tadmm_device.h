@@ -43,6 +43,9 @@ struct Prob {
   float plo[3], phi[3];
   int relax;                     // over-relaxation with factor alpha (alpha != 1)
   float alpha;
+  // the shared dynamics, in the form the dynamics products read
+  __host__ __device__ __forceinline__ float a(int k) const { return A[k]; }
+  __host__ __device__ __forceinline__ float b(int k) const { return B[k]; }
 };
 
 // Per-scenario table columns (int64).
@@ -80,6 +83,7 @@ struct WS {
   // inputs (caller layouts)
   const float *x0, *xref, *qd, *rd, *normals;
   const float *aq, *ar, *alo, *ahi;  // heterogeneous agents (each NULL: the shared value)
+  const float *aA, *aB;              // per-agent dynamics [agents][NX*NX], [agents][NX*NU] (NULL: shared)
 };
 
 // Layout of a scenario's float region: structure of arrays of 4-float groups
@@ -184,7 +188,8 @@ __device__ __forceinline__ Scen load_scen(const WS &ws, int s) {
 
 // ---------------------------------------------------------------------------
 // Dynamics x_{t+1} = A x_t + B u_t: products with A, A', B, B'.  The general
-// form reads A and B from the kernel arguments; the double-integrator form
+// form reads A and B through pb.a() / pb.b() (the kernel arguments, or an
+// agent's own matrices); the double-integrator form
 // (A = [[I, dt I], [0, I]], B = [[dt^2/2 I], [dt I]], positions first) uses
 // only dt and h = dt^2/2 and is selected by the host when A and B have it.
 // ---------------------------------------------------------------------------
@@ -193,43 +198,43 @@ struct Dyn;
 
 template <int NX, int NU>
 struct Dyn<NX, NU, false> {
-  template <class R>
-  __device__ static __forceinline__ void ax(const Prob &pb, const R *x, R *y) {
+  template <class M, class R>
+  __device__ static __forceinline__ void ax(const M &pb, const R *x, R *y) {
 #pragma unroll
     for (int r = 0; r < NX; ++r) {
       R v = R(0);
 #pragma unroll
-      for (int c = 0; c < NX; ++c) v = fma((R)pb.A[r * NX + c], x[c], v);
+      for (int c = 0; c < NX; ++c) v = fma((R)pb.a(r * NX + c), x[c], v);
       y[r] = v;
     }
   }
-  template <class R>
-  __device__ static __forceinline__ void atx(const Prob &pb, const R *x, R *y) {
+  template <class M, class R>
+  __device__ static __forceinline__ void atx(const M &pb, const R *x, R *y) {
 #pragma unroll
     for (int c = 0; c < NX; ++c) {
       R v = R(0);
 #pragma unroll
-      for (int r = 0; r < NX; ++r) v = fma((R)pb.A[r * NX + c], x[r], v);
+      for (int r = 0; r < NX; ++r) v = fma((R)pb.a(r * NX + c), x[r], v);
       y[c] = v;
     }
   }
-  template <class R>
-  __device__ static __forceinline__ void add_bu(const Prob &pb, const R *u, R *y) {
+  template <class M, class R>
+  __device__ static __forceinline__ void add_bu(const M &pb, const R *u, R *y) {
 #pragma unroll
     for (int r = 0; r < NX; ++r) {
       R v = y[r];
 #pragma unroll
-      for (int a = 0; a < NU; ++a) v = fma((R)pb.B[r * NU + a], u[a], v);
+      for (int a = 0; a < NU; ++a) v = fma((R)pb.b(r * NU + a), u[a], v);
       y[r] = v;
     }
   }
-  template <class R>
-  __device__ static __forceinline__ void btx(const Prob &pb, const R *x, R *y) {
+  template <class M, class R>
+  __device__ static __forceinline__ void btx(const M &pb, const R *x, R *y) {
 #pragma unroll
     for (int a = 0; a < NU; ++a) {
       R v = R(0);
 #pragma unroll
-      for (int r = 0; r < NX; ++r) v = fma((R)pb.B[r * NU + a], x[r], v);
+      for (int r = 0; r < NX; ++r) v = fma((R)pb.b(r * NU + a), x[r], v);
       y[a] = v;
     }
   }
@@ -237,32 +242,32 @@ struct Dyn<NX, NU, false> {
 
 template <int NX, int NU>
 struct Dyn<NX, NU, true> {
-  template <class R>
-  __device__ static __forceinline__ void ax(const Prob &pb, const R *x, R *y) {
+  template <class M, class R>
+  __device__ static __forceinline__ void ax(const M &pb, const R *x, R *y) {
 #pragma unroll
     for (int c = 0; c < NU; ++c) {
       y[c] = fma((R)pb.dt, x[NU + c], x[c]);
       y[NU + c] = x[NU + c];
     }
   }
-  template <class R>
-  __device__ static __forceinline__ void atx(const Prob &pb, const R *x, R *y) {
+  template <class M, class R>
+  __device__ static __forceinline__ void atx(const M &pb, const R *x, R *y) {
 #pragma unroll
     for (int c = 0; c < NU; ++c) {
       y[c] = x[c];
       y[NU + c] = fma((R)pb.dt, x[c], x[NU + c]);
     }
   }
-  template <class R>
-  __device__ static __forceinline__ void add_bu(const Prob &pb, const R *u, R *y) {
+  template <class M, class R>
+  __device__ static __forceinline__ void add_bu(const M &pb, const R *u, R *y) {
 #pragma unroll
     for (int c = 0; c < NU; ++c) {
       y[c] = fma((R)pb.h, u[c], y[c]);
       y[NU + c] = fma((R)pb.dt, u[c], y[NU + c]);
     }
   }
-  template <class R>
-  __device__ static __forceinline__ void btx(const Prob &pb, const R *x, R *y) {
+  template <class M, class R>
+  __device__ static __forceinline__ void btx(const M &pb, const R *x, R *y) {
 #pragma unroll
     for (int a = 0; a < NU; ++a) y[a] = fma((R)pb.dt, x[NU + a], (R)pb.h * x[a]);
   }
@@ -297,8 +302,8 @@ __device__ __forceinline__ void stage_hx(const Prob &pb, const float *qd, int t,
 // With these, the affine terms of the sweep are
 //   k_t = kc - Sv B'p_{t+1},   p_t = q_t + c + A'p_{t+1} + K' B'p_{t+1},
 // since A + B K is the closed loop and -Sv B' the gain of k_t on p_{t+1}.
-template <int NX, int NU, bool DI, class R>
-__device__ __forceinline__ void factor_stage(const Prob &pb, const R hx[NX], const R hu[NU], const R Pn[NX][NX],
+template <int NX, int NU, bool DI, class R, class DM>
+__device__ __forceinline__ void factor_stage(const DM &pb, const R hx[NX], const R hu[NU], const R Pn[NX][NX],
                                              const int8_t wt[NU], const float *lo, const float *hi, bool want_P,
                                              R Pt[NX][NX], R K[NU][NX], R Sv[NU][NU], R kc[NU], R cc[NX]) {
   using D = Dyn<NX, NU, DI>;

@@ -64,6 +64,15 @@ __device__ __forceinline__ float &uref(float *R, unsigned GS, unsigned g, int c)
   return R[(size_t)Fld<NX, NU>::NF * GS + (size_t)axis_region_floats(GS, NU) + (size_t)g * NU + c];
 }
 
+// An agent's dynamics for the dynamics products: its own matrices when the
+// batch gives them, else the shared ones of the kernel arguments.
+struct DynSel {
+  const Prob &pb;
+  const float *A, *B;
+  __device__ __forceinline__ float a(int k) const { return A ? A[k] : pb.A[k]; }
+  __device__ __forceinline__ float b(int k) const { return B ? B[k] : pb.B[k]; }
+};
+
 template <int NX_, int NU_, bool DI_>
 struct AgentView {
   static constexpr int NX = NX_, NU = NU_, NS = NU_ * (NU_ + 1) / 2, NP = NX_ * (NX_ + 1) / 2;
@@ -78,10 +87,13 @@ struct AgentView {
   unsigned GS, N, i;
   float lo[NU], hi[NU], hu[NU];
   float rho, rho_prev;        // penalty of this iteration, of the last one
+  const float *Ad, *Bd;       // this agent's own dynamics (NULL: the shared ones)
   __device__ __forceinline__ AgentView(const Prob &pb, const WS &ws, const Scen &sc, int i_)
       : R(ws.fr + sc.fo), Wb(ws.wr + sc.bo), D(ws.dr + sc.dof), dirty(ws.adirty + (sc.ao + i_) * NU_),
         qd(ws.aq ? ws.aq + (sc.ao + i_) * NX : ws.qd + (long long)sc.s * NX), GS((unsigned)sc.GS),
-        N((unsigned)sc.N), i((unsigned)i_), rho(ws.rhos[2 * sc.s]), rho_prev(ws.rhos[2 * sc.s + 1]) {
+        N((unsigned)sc.N), i((unsigned)i_), rho(ws.rhos[2 * sc.s]), rho_prev(ws.rhos[2 * sc.s + 1]),
+        Ad(ws.aA ? ws.aA + (sc.ao + i_) * (NX * NX) : nullptr),
+        Bd(ws.aB ? ws.aB + (sc.ao + i_) * (NX * NU) : nullptr) {
     const float *rd = ws.ar ? ws.ar + (sc.ao + i_) * NU : ws.rd + (long long)sc.s * NU;
 #pragma unroll
     for (int a = 0; a < NU; ++a) {
@@ -109,6 +121,7 @@ struct AgentView {
   __device__ __forceinline__ void hx(const Prob &pb, int t, int T, int n_nbr, float h[NX]) const {
     stage_hx<NX, NU>(pb, qd, t, T, n_nbr, rho, h);
   }
+  __device__ __forceinline__ DynSel dyn(const Prob &pb) const { return DynSel{pb, Ad, Bd}; }
 };
 
 template <int NXF, int NUF>
@@ -176,6 +189,7 @@ struct AxisView {
     h[0] = 2.0f * w * qd[0] + rho * (float)n_nbr + (pb.pbox ? pb.sigma : 0.0f);
     h[1] = 2.0f * w * qd[1] + (pb.sbox ? pb.sigma : 0.0f);
   }
+  __device__ __forceinline__ const Prob &dyn(const Prob &pb) const { return pb; }
 };
 
 template <class V>
@@ -211,7 +225,7 @@ __device__ void refactor(const Prob &pb, const V &m, int T, int n_nbr, int thi) 
       float hx[NX];
       m.hx(pb, t, T, n_nbr, hx);
       float Pt[NX][NX], K[NU][NX], Sv[NU][NU], kc[NU], cc[NX];
-      factor_stage<NX, NU, V::DI>(pb, hx, m.hu, Pn, wb[q], m.lo, m.hi, t >= 1, Pt, K, Sv, kc, cc);
+      factor_stage<NX, NU, V::DI>(m.dyn(pb), hx, m.hu, Pn, wb[q], m.lo, m.hi, t >= 1, Pt, K, Sv, kc, cc);
 #pragma unroll
       for (int a = 0; a < NU; ++a) {
 #pragma unroll
@@ -288,7 +302,7 @@ __device__ __forceinline__ void affine_sweep(const Prob &pb, const V &m, int T) 
         for (int r = 0; r < NX; ++r) m.PV(r, t + 1) = p[r];
       }
       float bp[NU];
-      D::btx(pb, p, bp);
+      D::btx(m.dyn(pb), p, bp);
 #pragma unroll
       for (int a = 0; a < NU; ++a) {
         float v = cur.kc[a];
@@ -298,7 +312,7 @@ __device__ __forceinline__ void affine_sweep(const Prob &pb, const V &m, int T) 
       }
       if (t >= 1) {
         float np[NX];
-        D::atx(pb, p, np);
+        D::atx(m.dyn(pb), p, np);
 #pragma unroll
         for (int c = 0; c < NX; ++c) {
           float v = (cur.q[c] + cur.cc[c]) + np[c];
@@ -413,8 +427,8 @@ __device__ void settle_iterate(const Prob &pb, const V &m, int T, const PendingS
         }
       }
       float xn[NX];
-      D::ax(pb, x, xn);
-      D::add_bu(pb, u, xn);
+      D::ax(m.dyn(pb), x, xn);
+      D::add_bu(m.dyn(pb), u, xn);
 #pragma unroll
       for (int r = 0; r < NX; ++r) { x[r] = xn[r]; m.X(r, t + 1) = xn[r]; }
     }
@@ -474,16 +488,16 @@ __device__ __forceinline__ StepInfo forward_rollout(const Prob &pb, const V &m, 
         m.UE(a, t) = v;
       }
       float xn[NX];
-      D::ax(pb, x, xn);
-      D::add_bu(pb, ue, xn);
+      D::ax(m.dyn(pb), x, xn);
+      D::add_bu(m.dyn(pb), ue, xn);
 #pragma unroll
       for (int r = 0; r < NX; ++r) m.X(r, t + 1) = xn[r];   // the states are read only at the loop's end
       if (fp64_states) {
         double ud[NU], xdn[NX];
 #pragma unroll
         for (int a = 0; a < NU; ++a) ud[a] = (double)ue[a];
-        D::ax(pb, xd, xdn);
-        D::add_bu(pb, ud, xdn);
+        D::ax(m.dyn(pb), xd, xdn);
+        D::add_bu(m.dyn(pb), ud, xdn);
 #pragma unroll
         for (int r = 0; r < NX; ++r) { xd[r] = xdn[r]; m.d(r, t + 1) = xdn[r]; }
       }
@@ -509,10 +523,10 @@ __device__ __forceinline__ StepInfo forward_rollout(const Prob &pb, const V &m, 
           nu[r] = v;
         }
         float bn[NU], an[NX], bs[NU];
-        D::btx(pb, nu, bn);
+        D::btx(m.dyn(pb), nu, bn);
 #pragma unroll
         for (int r = 0; r < NX; ++r) an[r] = fabsf(nu[r]);
-        D::btx(pb, an, bs);   // |B|'|nu| for the general form with nonnegative B
+        D::btx(m.dyn(pb), an, bs);   // |B|'|nu| for the general form with nonnegative B
 #pragma unroll
         for (int a = 0; a < NU; ++a) {
           if (cur.wt[a] == 0) continue;
@@ -563,8 +577,8 @@ __device__ void refine_solution(const Prob &pb, const V &m, int T, int n_nbr, bo
 #pragma unroll
         for (int a = 0; a < NU; ++a) un[a] = uin(a, t + 1);
       }
-      D::ax(pb, x, xn);
-      D::add_bu(pb, u, xn);
+      D::ax(m.dyn(pb), x, xn);
+      D::add_bu(m.dyn(pb), u, xn);
 #pragma unroll
       for (int r = 0; r < NX; ++r) { x[r] = xn[r]; m.d(r, t + 1) = xn[r]; }
     }
@@ -608,8 +622,8 @@ __device__ void refine_solution(const Prob &pb, const V &m, int T, int n_nbr, bo
     if (t >= 1) bload(nxt, t - 1);
     double bnu[NU];
     float bpc[NU], sg[NU];
-    D::btx(pb, nu, bnu);
-    D::btx(pb, pc, bpc);
+    D::btx(m.dyn(pb), nu, bnu);
+    D::btx(m.dyn(pb), pc, bpc);
 #pragma unroll
     for (int a = 0; a < NU; ++a) {
       const double g = fma((double)m.hu[a], (double)cur.u[a], bnu[a]);
@@ -627,8 +641,8 @@ __device__ void refine_solution(const Prob &pb, const V &m, int T, int n_nbr, bo
       m.hx(pb, t, T, n_nbr, hx);
       float np[NX];
       double nn[NX];
-      D::atx(pb, pc, np);
-      D::atx(pb, nu, nn);
+      D::atx(m.dyn(pb), pc, np);
+      D::atx(m.dyn(pb), nu, nn);
 #pragma unroll
       for (int c = 0; c < NX; ++c) {
         float v = np[c];
@@ -676,10 +690,10 @@ __device__ void refine_solution(const Prob &pb, const V &m, int T, int n_nbr, bo
     }
     float dxn[NX];
     double xn[NX];
-    D::ax(pb, dx, dxn);
-    D::add_bu(pb, du, dxn);
-    D::ax(pb, x, xn);
-    D::add_bu(pb, ud, xn);
+    D::ax(m.dyn(pb), dx, dxn);
+    D::add_bu(m.dyn(pb), du, dxn);
+    D::ax(m.dyn(pb), x, xn);
+    D::add_bu(m.dyn(pb), ud, xn);
 #pragma unroll
     for (int r = 0; r < NX; ++r) {
       dx[r] = dxn[r];
@@ -765,8 +779,8 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, const
           m.U(a, t) = u;
         }
         float xn[NX];
-        D::ax(pb, x, xn);
-        D::add_bu(pb, ust, xn);
+        D::ax(m.dyn(pb), x, xn);
+        D::add_bu(m.dyn(pb), ust, xn);
 #pragma unroll
         for (int r = 0; r < NX; ++r) { x[r] = xn[r]; m.X(r, t + 1) = xn[r]; }
       }
@@ -1629,6 +1643,10 @@ __global__ void k_check(Prob pb, WS ws, int S, int *flags) {
         const float l = ws.alo[sc.ao * NU + e], h = ws.ahi[sc.ao * NU + e];
         bad |= !(isfinite(l) && isfinite(h) && l < h);
       }
+    if (ws.aA) {
+      for (int e = threadIdx.x; e < N * NX * NX; e += blockDim.x) bad |= !isfinite(ws.aA[sc.ao * NX * NX + e]);
+      for (int e = threadIdx.x; e < N * NX * NU; e += blockDim.x) bad |= !isfinite(ws.aB[sc.ao * NX * NU + e]);
+    }
     if (ws.normals && pb.normal_mode == NORMAL_FROZEN)
       for (long long e = threadIdx.x; e < (long long)N * (N - 1) / 2 * T * NU; e += blockDim.x)
         bad |= !isfinite(ws.normals[sc.po * NU + e]);
@@ -1984,6 +2002,13 @@ bool make_layout(const tadmm_params *p, int S, const int32_t *N, const int32_t *
 // the caller's value, dt^2/2 for the exact zero-order hold): the dynamics of
 // every workload here; it selects the structured products (two FMAs per
 // position instead of dense 4x4 / 6x6 products).
+bool is_double_integrator(const tadmm_params &p);
+
+bool is_double_integrator(const tadmm_params &p, const tadmm_batch *b) {
+  if (b && (b->agent_A || b->agent_B)) return false;   // per-agent dynamics: the general path
+  return is_double_integrator(p);
+}
+
 bool is_double_integrator(const tadmm_params &p) {
   const int nx = p.nx, nu = p.nu;
   const float dt = p.A[0 * nx + nu];
@@ -2041,7 +2066,7 @@ struct GraphKey {
   const void *ws = nullptr;
   tadmm_out out{};
   const float *x0 = nullptr, *xref = nullptr, *qd = nullptr, *rd = nullptr, *normals = nullptr;
-  const float *aq = nullptr, *ar = nullptr, *alo = nullptr, *ahi = nullptr;
+  const float *aq = nullptr, *ar = nullptr, *alo = nullptr, *ahi = nullptr, *aA = nullptr, *aB = nullptr;
   int S = 0, threads = 0, grid = 0;
   int variant = 0;   // 0: a solve; SQP rounds: 2 (first) or 3 (later, continuing)
   size_t bytes = 0;
@@ -2130,6 +2155,7 @@ WS make_ws(const Layout &L, char *ws, const tadmm_batch *b) {
   w.x0 = b->x0; w.xref = b->xref; w.qd = b->q_diag; w.rd = b->r_diag;
   w.normals = (b->normals && true) ? b->normals : nullptr;
   w.aq = b->agent_q; w.ar = b->agent_r; w.alo = b->agent_lo; w.ahi = b->agent_hi;
+  w.aA = b->agent_A; w.aB = b->agent_B;
   w.skip = (int *)(ws + L.o_sqpi);
   w.rhos = (float *)(ws + L.o_rho);
   w.orx = L.o_orx ? (float *)(ws + L.o_orx) : nullptr;
@@ -2197,7 +2223,7 @@ tadmm_status run_batched(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layo
   std::memset(&key, 0, sizeof(key));
   key.ws = ws; key.out = out; key.x0 = b->x0; key.xref = b->xref; key.qd = b->q_diag; key.rd = b->r_diag;
   key.normals = w.normals; key.S = L.S; key.threads = threads; key.grid = grid; key.bytes = bytes; key.prm = ctx->prm;
-  key.aq = w.aq; key.ar = w.ar; key.alo = w.alo; key.ahi = w.ahi;
+  key.aq = w.aq; key.ar = w.ar; key.alo = w.alo; key.ahi = w.ahi; key.aA = w.aA; key.aB = w.aB;
   key.variant = variant;
   if (!(ctx->gexec && key == ctx->key)) {
     if (ctx->gexec) { (void)hipGraphExecDestroy(ctx->gexec); ctx->gexec = nullptr; }
@@ -2268,7 +2294,7 @@ tadmm_status run_wide(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layout 
   std::memset(&key, 0, sizeof(key));
   key.ws = ws; key.out = out; key.x0 = b->x0; key.xref = b->xref; key.qd = b->q_diag; key.rd = b->r_diag;
   key.normals = w.normals; key.S = L.S; key.threads = gp; key.grid = gx; key.bytes = bytes; key.prm = ctx->prm;
-  key.aq = w.aq; key.ar = w.ar; key.alo = w.alo; key.ahi = w.ahi;
+  key.aq = w.aq; key.ar = w.ar; key.alo = w.alo; key.ahi = w.ahi; key.aA = w.aA; key.aB = w.aB;
   key.variant = variant;
   if (!(ctx->wexec[0] && key == ctx->wkey)) {
     for (int q = 0; q < 2; ++q) {
@@ -2333,6 +2359,7 @@ tadmm_status solve_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *o
   if (!b->x0 || !b->xref || !b->q_diag || !b->r_diag) return fail(ctx, TADMM_ERR_INVALID_ARG, "batch input pointer is NULL");
   if (!out->status || !out->iters) return fail(ctx, TADMM_ERR_INVALID_ARG, "out.status and out.iters are required");
   if (!b->agent_lo != !b->agent_hi) return fail(ctx, TADMM_ERR_INVALID_ARG, "agent_lo and agent_hi: both or neither");
+  if (!b->agent_A != !b->agent_B) return fail(ctx, TADMM_ERR_INVALID_ARG, "agent_A and agent_B: both or neither");
   char *w8 = (char *)ws;
   tadmm_status st = stage_tables(ctx, L, b->n_agents, b->horizon, w8);
   if (st != TADMM_OK) return st;
@@ -2380,6 +2407,7 @@ tadmm_status sqp_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *out
   if (!b->x0 || !b->xref || !b->q_diag || !b->r_diag) return fail(ctx, TADMM_ERR_INVALID_ARG, "batch input pointer is NULL");
   if (!out->status || !out->iters) return fail(ctx, TADMM_ERR_INVALID_ARG, "out.status and out.iters are required");
   if (!b->agent_lo != !b->agent_hi) return fail(ctx, TADMM_ERR_INVALID_ARG, "agent_lo and agent_hi: both or neither");
+  if (!b->agent_A != !b->agent_B) return fail(ctx, TADMM_ERR_INVALID_ARG, "agent_A and agent_B: both or neither");
   char *w8 = (char *)ws;
   tadmm_status st = stage_tables(ctx, L, b->n_agents, b->horizon, w8);
   if (st != TADMM_OK) return st;
@@ -2439,7 +2467,7 @@ tadmm_status sqp_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *out
 
 tadmm_status sqp_dispatch(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *out, void *ws, size_t bytes, int mode,
                           int max_rounds, float rtol, float sep_tol, float *stats) {
-  const bool di = is_double_integrator(ctx->prm);
+  const bool di = is_double_integrator(ctx->prm, b);
   if (ctx->prm.nx == 4)
     return di ? sqp_impl<4, 2, true>(ctx, b, out, ws, bytes, mode, max_rounds, rtol, sep_tol, stats)
               : sqp_impl<4, 2, false>(ctx, b, out, ws, bytes, mode, max_rounds, rtol, sep_tol, stats);
@@ -2465,7 +2493,7 @@ tadmm_status eqp_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *out
   if (!ctx->solved || ctx->solved_ws != ws || ctx->solved_bytes != bytes)
     return fail(ctx, TADMM_ERR_STATE, "needs a successful tadmm_solve with this workspace first");
   const tadmm_batch &sb = ctx->solved_batch;
-  if (b->agent_q || b->agent_r || b->agent_lo || b->agent_hi)
+  if (b->agent_q || b->agent_r || b->agent_lo || b->agent_hi || b->agent_A || b->agent_B)
     return fail(ctx, TADMM_ERR_INVALID_ARG, "the derivative takes per-scenario weights (no agent_* arrays)");
   if (ctx->prm.state_box)
     return fail(ctx, TADMM_ERR_INVALID_ARG, "the derivative covers input bounds only (no state_box)");
@@ -2507,7 +2535,7 @@ tadmm_status eqp_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *out
 
 tadmm_status eqp_dispatch(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *out, void *ws, size_t bytes, int mode,
                           const EqpIO &io) {
-  const bool di = is_double_integrator(ctx->prm);
+  const bool di = is_double_integrator(ctx->prm, b);
   if (ctx->prm.nx == 4)
     return di ? eqp_impl<4, 2, true>(ctx, b, out, ws, bytes, mode, io) : eqp_impl<4, 2, false>(ctx, b, out, ws, bytes, mode, io);
   return di ? eqp_impl<6, 3, true>(ctx, b, out, ws, bytes, mode, io) : eqp_impl<6, 3, false>(ctx, b, out, ws, bytes, mode, io);
@@ -2586,7 +2614,7 @@ tadmm_status tadmm_solve(tadmm_ctx *ctx, const tadmm_batch *batch, const tadmm_o
   if (!ctx) return TADMM_ERR_INVALID_ARG;
   if (!batch || !out) return fail(ctx, TADMM_ERR_INVALID_ARG, "batch / out is NULL");
   ctx->err.clear();
-  const bool di = is_double_integrator(ctx->prm);
+  const bool di = is_double_integrator(ctx->prm, batch);
   if (ctx->prm.nx == 4)
     return di ? solve_impl<4, 2, true>(ctx, batch, out, workspace, workspace_bytes, mode)
               : solve_impl<4, 2, false>(ctx, batch, out, workspace, workspace_bytes, mode);

@@ -22,7 +22,8 @@ def gpu_solve(problem, scs, mode=None, normals=None, solver_kw=None, return_prep
     solver = tadmm.Solver(tadmm.make_params(problem, **(solver_kw or {})))
     nrm = None if normals is None else np.concatenate([np.asarray(n).reshape(-1, problem.nu) for n in normals])
     prep = solver.prepare(pk.n_agents, pk.horizon, pk.x0, pk.xref, pk.q_diag, pk.r_diag, nrm, agent_q=pk.agent_q,
-                          agent_r=pk.agent_r, agent_lo=pk.agent_lo, agent_hi=pk.agent_hi)
+                          agent_r=pk.agent_r, agent_lo=pk.agent_lo, agent_hi=pk.agent_hi, agent_A=pk.agent_A,
+                          agent_B=pk.agent_B)
     prep.run(mode)
     res = tadmm.split_outputs(prep.result(), pk.n_agents, pk.horizon, problem.nx, problem.nu)
     if return_prep:
