@@ -58,7 +58,8 @@ class _Params(C.Structure):
                 ("fixed_iters", C.c_int), ("adaptive_rho", C.c_int), ("rho_mu", C.c_double),
                 ("rho_tau", C.c_double), ("rho_every", C.c_int), ("state_box", C.c_int),
                 ("s_lo", C.c_double * 3), ("s_hi", C.c_double * 3), ("p_lo", C.c_double * 3),
-                ("p_hi", C.c_double * 3), ("alpha", C.c_double)]
+                ("p_hi", C.c_double * 3), ("alpha", C.c_double),
+                ("momentum", C.c_int), ("mom_eta", C.c_double)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -129,6 +130,8 @@ class OracleOptions:
     p_lo: tuple = (-np.inf, -np.inf, -np.inf)   # with state_box: the position box
     p_hi: tuple = (np.inf, np.inf, np.inf)
     alpha: float = 1.0              # over-relaxation (Boyd et al. 2011, Sec. 3.4.3)
+    momentum: bool = False          # fast ADMM with restart (Goldstein et al. 2014, Alg. 8)
+    mom_eta: float = 0.999
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -174,6 +177,8 @@ def make_params(problem, opts: OracleOptions) -> _Params:
         p.p_lo[c] = float(opts.p_lo[c])
         p.p_hi[c] = float(opts.p_hi[c])
     p.alpha = float(opts.alpha)
+    p.momentum = int(bool(opts.momentum))
+    p.mom_eta = float(opts.mom_eta)
     return p
 
 

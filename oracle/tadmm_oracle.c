@@ -445,9 +445,21 @@ int orc_admm(const orc_params *prm, const orc_scenario *sc, orc_result *res, int
   double *yb = (double *)calloc((size_t)N * (T + 1) * nx, sizeof(double));
   double *mb = (double *)calloc((size_t)N * (T + 1) * nx, sizeof(double));
   double *vsum = (double *)calloc((size_t)N * (T + 1) * nx, sizeof(double));
+  /* momentum (fast ADMM with restart, Goldstein et al. 2014, Alg. 8): the
+   * extrapolated copies zh and duals lh that the next iteration uses, and
+   * the previous iterates zp, lp; plain ADMM otherwise, and not combined
+   * with the other variants */
+  const int mom = prm->momentum;
+  if (mom && (box || relax || prm->adaptive_rho)) return -1;
+  double *zh = (double *)calloc(zsz, sizeof(double));
+  double *lh = (double *)calloc(zsz, sizeof(double));
+  double *zp = (double *)calloc(zsz, sizeof(double));
+  double *lp = (double *)calloc(zsz, sizeof(double));
+  double mom_a = 1.0, mom_c = INFINITY;
   qp_ws *qs = (qp_ws *)calloc((size_t)N, sizeof(qp_ws));
-  if (!z || !lam || !zsum_old || !ysum || !qs || !yb || !mb || !vsum) {
+  if (!z || !lam || !zsum_old || !ysum || !qs || !yb || !mb || !vsum || !zh || !lh || !zp || !lp) {
     free(z); free(lam); free(zsum_old); free(ysum); free(qs); free(yb); free(mb); free(vsum);
+    free(zh); free(lh); free(zp); free(lp);
     return -1;
   }
 #define ZI(i, j, t) (((size_t)(i) * N + (j)) * T + ((t) - 1)) * dp
@@ -461,6 +473,8 @@ int orc_admm(const orc_params *prm, const orc_scenario *sc, orc_result *res, int
         for (int k = 0; k < dp; ++k)
           z[ZI(i, j, t) + k] = sc->xref[((size_t)i * (T + 1) + t) * nx + k];
     }
+  /* momentum: zh^(1) = z^(0), lh^(1) = lambda^(0) = 0, alpha_1 = 1, c_0 = inf */
+  if (mom) { memcpy(zh, z, zsz * sizeof(double)); memcpy(zp, z, zsz * sizeof(double)); }
   /* y^(0): the references' boxed states, clipped; mu^(0) = 0 */
   if (box)
     for (int i = 0; i < N; ++i)
@@ -496,7 +510,7 @@ int orc_admm(const orc_params *prm, const orc_scenario *sc, orc_result *res, int
           double s = 0.0;
           for (int j = 0; j < N; ++j) {
             if (j == i) continue;
-            s += rho * z[ZI(i, j, t) + c] - lam[ZI(i, j, t) + c];
+            s += mom ? rho * zh[ZI(i, j, t) + c] - lh[ZI(i, j, t) + c] : rho * z[ZI(i, j, t) + c] - lam[ZI(i, j, t) + c];
           }
           ys[t * dp + c] = s;
         }
@@ -532,9 +546,16 @@ int orc_admm(const orc_params *prm, const orc_scenario *sc, orc_result *res, int
       for (int t = 1; t <= T; ++t)
         for (int c = 0; c < dp; ++c) {
           double s = 0.0;
-          for (int j = 0; j < N; ++j) if (j != i) s += z[ZI(i, j, t) + c];
+          for (int j = 0; j < N; ++j) if (j != i) s += mom ? zh[ZI(i, j, t) + c] : z[ZI(i, j, t) + c];
           zsum_old[((size_t)i * T + (t - 1)) * dp + c] = s;
         }
+    /* momentum: the consensus and dual updates start from the extrapolated
+     * duals; keep the previous iterates for the next extrapolation */
+    if (mom) {
+      memcpy(zp, z, zsz * sizeof(double));
+      memcpy(lp, lam, zsz * sizeof(double));
+      memcpy(lam, lh, zsz * sizeof(double));
+    }
 
     /* ---- z-update (Eq. 4) and dual update (Eq. 5) for every pair and step ---- */
     int p = 0;
@@ -648,6 +669,29 @@ int orc_admm(const orc_params *prm, const orc_scenario *sc, orc_result *res, int
       res->status = ORC_CONVERGED;
       break;
     }
+    /* momentum: the combined residual decides between extrapolation and restart */
+    if (mom && k < maxit) {
+      double ck = 0.0;
+      for (size_t o = 0; o < zsz; ++o) {
+        const double dl = lam[o] - lh[o], dz = z[o] - zh[o];
+        ck += dl * dl / rho + rho * dz * dz;
+      }
+      if (ck < prm->mom_eta * mom_c) {
+        const double an = 0.5 * (1.0 + sqrt(1.0 + 4.0 * mom_a * mom_a));
+        const double beta = (mom_a - 1.0) / an;
+        for (size_t o = 0; o < zsz; ++o) {
+          zh[o] = z[o] + beta * (z[o] - zp[o]);
+          lh[o] = lam[o] + beta * (lam[o] - lp[o]);
+        }
+        mom_a = an;
+        mom_c = ck;
+      } else {
+        memcpy(zh, zp, zsz * sizeof(double));
+        memcpy(lh, lp, zsz * sizeof(double));
+        mom_a = 1.0;
+        mom_c = mom_c / prm->mom_eta;
+      }
+    }
     /* residual balancing: the next iteration's penalty (none after the last) */
     if (prm->adaptive_rho && k < maxit && k % prm->rho_every == 0) {
       double nr = rho;
@@ -671,11 +715,13 @@ int orc_admm(const orc_params *prm, const orc_scenario *sc, orc_result *res, int
           }
   for (int i = 0; i < N; ++i) qp_ws_free(&qs[i]);
   free(z); free(lam); free(zsum_old); free(ysum); free(qs); free(yb); free(mb); free(vsum);
+  free(zh); free(lh); free(zp); free(lp);
   return 0;
 
 done_fail:
   for (int i = 0; i < N; ++i) qp_ws_free(&qs[i]);
   free(z); free(lam); free(zsum_old); free(ysum); free(qs); free(yb); free(mb); free(vsum);
+  free(zh); free(lh); free(zp); free(lp);
   return -1;
 #undef ZI
 }

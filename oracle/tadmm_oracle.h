@@ -66,6 +66,12 @@ typedef struct {
   /* Over-relaxation (Boyd et al. 2011, Sec. 3.4.3): the z- and dual updates
    * use alpha C x^(k+1) + (1 - alpha) z^k; 1 is plain ADMM, (0, 2) valid. */
   double alpha;
+  /* Momentum: fast ADMM with restart (Goldstein et al. 2014, Alg. 8) on the
+   * consensus block: the next iteration takes extrapolated copies and duals,
+   * restarting when the combined residual fails to fall by mom_eta.  Not
+   * combined with adaptive_rho, alpha != 1 or the state box. */
+  int momentum;
+  double mom_eta;
 } orc_params;
 
 typedef struct {

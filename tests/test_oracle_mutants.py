@@ -46,6 +46,9 @@ MUTANTS = {
     "agent_dynamics_of_the_first_agent": ("if (sc->agent_A) qs[i].A = sc->agent_A + (size_t)i * nx * nx;",
                                           "if (sc->agent_A) qs[i].A = sc->agent_A;"),
     "agent_input_matrix_ignored_in_kkt": ("const double b = q->B[r * nu + c];", "const double b = prm->B[r * nu + c];"),
+    "momentum_weight_without_minus_one": ("const double beta = (mom_a - 1.0) / an;", "const double beta = mom_a / an;"),
+    "momentum_restart_to_the_current_iterate": ("memcpy(zh, zp, zsz * sizeof(double));",
+                                                "memcpy(zh, z, zsz * sizeof(double));"),
     "relaxation_dual_update_unrelaxed": ("lam[ZI(i, j, t) + c] += rho * (xi[c] - a[c]);",
                                          "lam[ZI(i, j, t) + c] += rho * (pi[c] - a[c]);"),
     "relaxation_weights_swapped": ("prm->alpha * pi[c] + (1.0 - prm->alpha) * z[ZI(i, j, t) + c]",
@@ -78,6 +81,8 @@ PIN_FUNCS = [pins.test_agent_qp_unconstrained_matches_condensed_least_squares,
              pins.test_agent_dynamics_single_agent_is_its_local_qp,
              pins.test_agent_input_gain_is_a_reparametrization,
              pins.test_admm_relaxation_closed_form_far_apart,
+             pins.test_admm_momentum_closed_form_far_apart,
+             pins.test_admm_momentum_frozen_limit_is_the_same_kkt_point,
              pins.test_admm_relaxation_frozen_limit_is_the_same_kkt_point]
 
 

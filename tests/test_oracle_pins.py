@@ -783,3 +783,77 @@ def test_agent_dynamics_permutation_equivariance():
     o = oracle.OracleOptions(max_iter=60)
     a, b = oracle.solve(p, sc, o), oracle.solve(p, sp, o)
     np.testing.assert_allclose(b["x"], a["x"][perm], atol=1e-9)
+
+
+def _momentum_far_apart_model(p, sc, K, eta=0.999):
+    """The fast ADMM with restart (Goldstein et al. 2014, Alg. 8) on two
+    agents that never come near each other (T = 1, inactive input bounds):
+    every projection is the identity, so the duals stay 0, z_k = p_1(zh_k)
+    with p_1 affine in zh per agent and axis (as in the relaxation pin), the
+    combined residual is c_k = rho sum (z_k - zh_k)^2 over the ordered
+    copies, and zh follows the extrapolation / restart rule."""
+    rho, dt, dp, qT = p.rho, p.dt, p.dp, p.qT_scale
+    A, B, xr = p.A, p.B, sc.xref()
+    ell, beta0 = [], []
+    for i in range(2):
+        for c in range(dp):
+            h, b = B[c, c], B[dp + c, c]
+            P, V = A[c] @ sc.x0()[i], A[dp + c] @ sc.x0()[i]
+            rp, rv = xr[i, 1, c], xr[i, 1, dp + c]
+            qp, qv, r = p.q_diag[c], p.q_diag[dp + c], p.r_diag[c]
+            H = 2 * qT * qp * h * h + 2 * qT * qv * b * b + 2 * r + rho * h * h
+            # p_1 = P + h u, u = -(g0 + rho h (P - zh)) / H
+            g0 = 2 * qT * qp * h * (P - rp) + 2 * qT * qv * b * (V - rv)
+            ell.append(rho * h * h / H)
+            beta0.append(P - h * (g0 + rho * h * P) / H)
+    ell, beta0 = np.array(ell), np.array(beta0)
+    z0 = np.array([xr[i, 1, c] for i in range(2) for c in range(dp)])
+    zh, zprev, a, cprev, restarts = z0.copy(), z0.copy(), 1.0, np.inf, 0
+    for k in range(1, K + 1):
+        z = ell * zh + beta0                  # z_k = p_1 (the projection is the identity)
+        ck = rho * np.sum((z - zh) ** 2)      # one ordered copy per agent and axis
+        if k == K:
+            break
+        if ck < eta * cprev:
+            an = 0.5 * (1 + np.sqrt(1 + 4 * a * a))
+            zh = z + (a - 1) / an * (z - zprev)
+            a, cprev = an, ck
+        else:
+            zh, a, cprev = zprev.copy(), 1.0, cprev / eta
+            restarts += 1
+        zprev = z
+    return z.reshape(2, dp), restarts
+
+
+def test_admm_momentum_closed_form_far_apart():
+    """The oracle's momentum run against the scalar model above after K
+    iterations; the model restarts at least once on the way, so both the
+    extrapolation and the restart rule are pinned.  A large penalty makes
+    plain ADMM slow here (p_1's slope in zh near 1), so the iterates are
+    still far from the limit and differ from plain ADMM's."""
+    p = synth.ProblemParams(dp=2, u_max=1e4, rho=1e4)
+    sc = synth.Scenario(starts=np.array([[-50.0, 3.0], [60.0, -40.0]]),
+                        goals=np.array([[-48.0, 4.5], [58.0, -41.0]]), T=1)
+    K = 25
+    want, restarts = _momentum_far_apart_model(p, sc, K)
+    assert restarts >= 1
+    res = oracle.solve(p, sc, oracle.OracleOptions(momentum=True, fixed_iters=K), keep_zl=True)
+    plain = oracle.solve(p, sc, oracle.OracleOptions(fixed_iters=K))
+    assert np.abs(plain["x"][:, 1, :2] - want).max() > 1e-3
+    np.testing.assert_array_equal(res["lam"], 0.0)
+    for i in range(2):
+        np.testing.assert_allclose(res["x"][i, 1, :2], want[i], rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(res["z"][i, 1 - i, 0], want[i], rtol=1e-12, atol=1e-12)
+
+
+def test_admm_momentum_frozen_limit_is_the_same_kkt_point():
+    """Momentum changes the path, not the fixed point: the frozen side pass
+    converges to the plain-ADMM limit (certified above)."""
+    p = synth.ProblemParams(dp=2, u_max=2.0)
+    sc, nrm = _side_pass()
+    tight = dict(normal_mode=oracle.NORMAL_FROZEN, rho=10.0, max_iter=2000, eps_abs=1e-10, eps_rel=1e-10)
+    plain = oracle.solve(p, sc, oracle.OracleOptions(**tight), normals=nrm)
+    fast = oracle.solve(p, sc, oracle.OracleOptions(momentum=True, **tight), normals=nrm)
+    assert plain["status"] == oracle.CONVERGED and fast["status"] == oracle.CONVERGED
+    np.testing.assert_allclose(fast["u"], plain["u"], atol=1e-7)
+    np.testing.assert_allclose(fast["x"], plain["x"], atol=1e-7)
