@@ -28,7 +28,7 @@ MUTANTS = {
                          "lam[ZI(i, j, t) + c] -= rho * (xi[c] - a[c]);"),
     "multiplier_sign": ("m = (W[k] == 1) ? -y : y;", "m = (W[k] == 1) ? y : -y;"),
     "normal_orientation": ("n[c] = (pi[c] - pj[c]) / dd;", "n[c] = (pj[c] - pi[c]) / dd;"),
-    "dynamics_A_transposed": ("const double a = prm->A[r * nx + c];", "const double a = prm->A[c * nx + r];"),
+    "dynamics_A_transposed": ("const double a = q->A[r * nx + c];", "const double a = q->A[c * nx + r];"),
     "dual_residual_no_previous": ("rho * (zs[c] - zsum_old[((size_t)i * T + (t - 1)) * dp + c]);", "rho * zs[c];"),
     "primal_residual_term": ("r2 += (pi[c] - zc) * (pi[c] - zc);", "r2 += zc * zc;"),
     "consensus_init_zero": ("z[ZI(i, j, t) + k] = sc->xref[((size_t)i * (T + 1) + t) * nx + k];",
