@@ -168,6 +168,16 @@ typedef struct {
                                 p_lo < p_hi (+-inf: unbounded).  Each group
                                 (positions, other states) is split only where
                                 one of its bounds is finite.                     */
+  int32_t momentum;          /* 1: momentum ADMM, the fast ADMM with restart of
+                                Goldstein et al. (2014, Alg. 8) on the consensus
+                                block: each iteration takes extrapolated copies
+                                and duals, restarting when the combined residual
+                                fails to fall by the factor mom_eta.  Batched
+                                mode only; not with adaptive_rho, alpha != 1,
+                                state_box, tadmm_sqp or tadmm_polish/adjoint.
+                                The workspace holds 6 nu floats more per
+                                ordered pair copy and step.  0: off (default)    */
+  float mom_eta;             /* with momentum: 0 < mom_eta < 1 (0.999)            */
 } tadmm_params;
 
 /* A ragged batch of S independent scenarios.  Scenario s has N_s agents and

@@ -43,7 +43,8 @@ class Params(C.Structure):
                 ("refine_band", C.c_float), ("eqp_fp64", C.c_int32), ("adaptive_rho", C.c_int32),
                 ("rho_mu", C.c_float), ("rho_tau", C.c_float), ("rho_every", C.c_int32),
                 ("state_box", C.c_int32), ("s_lo", C.c_float * 3), ("s_hi", C.c_float * 3),
-                ("alpha", C.c_float), ("p_lo", C.c_float * 3), ("p_hi", C.c_float * 3)]
+                ("alpha", C.c_float), ("p_lo", C.c_float * 3), ("p_hi", C.c_float * 3),
+                ("momentum", C.c_int32), ("mom_eta", C.c_float)]
 
 
 _fp = C.POINTER(C.c_float)
@@ -116,7 +117,8 @@ def make_params(problem, *, normal_mode: int = NORMAL_PER_ITER, mu_tol: float = 
                 rho_mu: float = 10.0, rho_tau: float = 2.0, rho_every: int = 1, state_box: bool = False,
                 s_lo: Optional[Sequence[float]] = None, s_hi: Optional[Sequence[float]] = None,
                 alpha: float = 1.0, p_lo: Optional[Sequence[float]] = None,
-                p_hi: Optional[Sequence[float]] = None, max_iter: Optional[int] = None,
+                p_hi: Optional[Sequence[float]] = None, momentum: bool = False, mom_eta: float = 0.999,
+                max_iter: Optional[int] = None,
                 eps_abs: Optional[float] = None, eps_rel: Optional[float] = None,
                 rho: Optional[float] = None) -> Params:
     """Fill the C parameter struct from a problem description (attributes
@@ -160,6 +162,8 @@ def make_params(problem, *, normal_mode: int = NORMAL_PER_ITER, mu_tol: float = 
     for c in range(3):
         p.p_lo[c] = float(-np.inf if p_lo is None or c >= len(p_lo) else p_lo[c])
         p.p_hi[c] = float(np.inf if p_hi is None or c >= len(p_hi) else p_hi[c])
+    p.momentum = int(bool(momentum))
+    p.mom_eta = float(mom_eta)
     return p
 
 

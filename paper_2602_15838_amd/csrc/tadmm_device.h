@@ -43,6 +43,8 @@ struct Prob {
   float plo[3], phi[3];
   int relax;                     // over-relaxation with factor alpha (alpha != 1)
   float alpha;
+  int mom;                       // momentum (fast ADMM with restart), restart factor mom_eta
+  float mom_eta;
   // the shared dynamics, in the form the dynamics products read
   __host__ __device__ __forceinline__ float a(int k) const { return A[k]; }
   __host__ __device__ __forceinline__ float b(int k) const { return B[k]; }
@@ -80,6 +82,11 @@ struct WS {
   // over-relaxation only: per scenario 2 NU planes shaped like gam, the
   // copies' z: D = z_ij - z_ji (NU planes), then e = z_ij - C x_i (NU planes)
   float *orx;
+  // momentum only: per scenario 6 NU planes shaped like gam (the copies'
+  // extrapolated dual and copy, z_k, z_(k-1), lambda_k, lambda_(k-1)), and
+  // per scenario [a_k, c_(k-1), beta, restart]
+  float *mom;
+  float *momst;
   // inputs (caller layouts)
   const float *x0, *xref, *qd, *rd, *normals;
   const float *aq, *ar, *alo, *ahi;  // heterogeneous agents (each NULL: the shared value)

@@ -1124,6 +1124,140 @@ __device__ void pair_agent_stage_impl(const Prob &pb, const WS &ws, const Scen &
   Ri(F::RED + 4) = aty2;
 }
 
+// Momentum ADMM (the fast ADMM with restart of Goldstein et al. 2014, Alg. 8)
+// on the consensus block.  Iteration k's x-update took the extrapolated
+// copies zh and duals lh; its consensus step projects C x_i + lh_ij / rho
+// (the pair still moves symmetrically about its midpoint, so lambda_ij =
+// -gamma n again) and keeps z_k, lambda_k and the previous ones per ordered
+// copy.  Planes (each shaped like the gamma region, copy (i, j) at
+// [t][j][i]): MP_LH lh, MP_ZH zh, MP_ZK z_k, MP_ZK1 z_(k-1), MP_LK lambda_k,
+// MP_LK1 lambda_(k-1), NU planes each.  Both orientations of a pair store
+// exact negatives of each other's differences, as with gamma.
+enum { MP_LH = 0, MP_ZH, MP_ZK, MP_ZK1, MP_LK, MP_LK1, MP_N };
+
+template <int NX, int NU>
+__device__ void pair_agent_stage_mom(const Prob &pb, const WS &ws, const Scen &sc, int i, int t,
+                                     const float *__restrict__ lpos) {
+  using F = Fld<NX, NU>;
+  const int N = sc.N;
+  float *R = ws.fr + sc.fo;
+  const unsigned GS = (unsigned)sc.GS, gi = (unsigned)(t * N + i);
+  auto Ri = [&](int f) -> float & { return fref(R, GS, gi, f); };
+  float pi[NU];
+  bool bad = false;
+#pragma unroll
+  for (int c = 0; c < NU; ++c) pi[c] = Ri(F::X + c);
+#pragma unroll
+  for (int c = 0; c < NX; ++c) bad |= !isfinite(Ri(F::X + c));
+  float *gm = ws.gam + sc.lo;
+  uint8_t *pa = ws.pact + sc.lb;
+  const long long LS = (long long)sc.T * N * N;
+  float *mp = ws.mom + (long long)MP_N * NU * sc.lo;
+  auto plane = [&](int which, int c) { return mp + (long long)(which * NU + c) * LS; };
+  const float rho = pb.rho, irho = 1.0f / rho;
+  float szk[NU], szh[NU], ls[NU];
+#pragma unroll
+  for (int c = 0; c < NU; ++c) { szk[c] = 0.f; szh[c] = 0.f; ls[c] = 0.f; }
+  float r2 = 0.f, z2 = 0.f, c2 = 0.f;
+  const int gbase = (t - 1) * N * N + i;
+  for (int jj = 0; jj < N - 1; ++jj) {
+    const int j = jj + (jj >= i);
+    const int li = gbase + j * N;
+    float pj[NU], lh[NU], zh[NU], zk[NU], lk[NU];
+#pragma unroll
+    for (int c = 0; c < NU; ++c) {
+      pj[c] = lpos ? lpos[(t * N + j) * NU + c] : R[fidx(GS, (unsigned)(t * N + j), F::X + c)];
+      lh[c] = plane(MP_LH, c)[li];
+      zh[c] = plane(MP_ZH, c)[li];
+      zk[c] = plane(MP_ZK, c)[li];
+      lk[c] = plane(MP_LK, c)[li];
+    }
+    float n[NU];
+    pair_normal<NX, NU>(pb, ws, sc, i, j, t, pi, pj, n);
+    float ab[NU], g = 0.f;
+#pragma unroll
+    for (int c = 0; c < NU; ++c) {
+      ab[c] = (pi[c] - pj[c]) + 2.0f * irho * lh[c];   // a - b with the extrapolated duals
+      g = fmaf(n[c], ab[c], g);
+    }
+    const float v = pb.dmin - g;
+    const float gam = 0.5f * rho * fmaxf(v, 0.f);
+#pragma unroll
+    for (int c = 0; c < NU; ++c) {
+      const float lo = -gam * n[c];                     // lambda_k
+      const float z = pi[c] + (lh[c] - lo) * irho;      // z_k
+      plane(MP_ZK1, c)[li] = zk[c];
+      plane(MP_ZK, c)[li] = z;
+      plane(MP_LK1, c)[li] = lk[c];
+      plane(MP_LK, c)[li] = lo;
+      const float dl = lo - lh[c], dz = z - zh[c];
+      c2 = fmaf(dl * dl, irho, fmaf(rho * dz, dz, c2));
+      r2 = fmaf(pi[c] - z, pi[c] - z, r2);
+      z2 = fmaf(z, z, z2);
+      szk[c] += z;
+      szh[c] += zh[c];
+      ls[c] += lo;
+    }
+    gm[li] = gam;
+    if (i < j) pa[li] = (uint8_t)(v > 0.f);
+  }
+  float s2 = 0.f, ax2 = 0.f, aty2 = 0.f;
+#pragma unroll
+  for (int c = 0; c < NU; ++c) {
+    // rho sum_j (z_k - zh_k): the x-update took zh
+    const float ds = rho * (szk[c] - szh[c]);
+    s2 = fmaf(ds, ds, s2);
+    ax2 = fmaf(pi[c], pi[c], ax2);
+    aty2 = fmaf(ls[c], ls[c], aty2);
+  }
+  ax2 *= (float)(N - 1);
+  if (bad) r2 = NAN;
+  Ri(F::RED + 0) = r2;
+  Ri(F::RED + 1) = s2;
+  Ri(F::RED + 2) = ax2;
+  Ri(F::RED + 3) = z2;
+  Ri(F::RED + 4) = aty2;
+  Ri(F::RED + 5) = c2;
+}
+
+// After the stopping test of an unfinished iteration: the next iteration's
+// extrapolated duals and copies (or the previous ones, after a restart), and
+// the position part of the next linear term, GQP - sum_j (rho zh - lh).
+template <int NX, int NU>
+__device__ void mom_extrapolate(const Prob &pb, const WS &ws, const Scen &sc, int i, int t) {
+  using F = Fld<NX, NU>;
+  const int N = sc.N;
+  float *R = ws.fr + sc.fo;
+  const unsigned GS = (unsigned)sc.GS, gi = (unsigned)(t * N + i);
+  auto Ri = [&](int f) -> float & { return fref(R, GS, gi, f); };
+  const long long LS = (long long)sc.T * N * N;
+  float *mp = ws.mom + (long long)MP_N * NU * sc.lo;
+  auto plane = [&](int which, int c) { return mp + (long long)(which * NU + c) * LS; };
+  const float *st = ws.momst + 4LL * sc.s;
+  const float beta = st[2];
+  const bool restart = st[3] != 0.f;
+  float szh[NU], slh[NU];
+#pragma unroll
+  for (int c = 0; c < NU; ++c) { szh[c] = 0.f; slh[c] = 0.f; }
+  const int gbase = (t - 1) * N * N + i;
+  for (int jj = 0; jj < N - 1; ++jj) {
+    const int li = gbase + (jj + (jj >= i)) * N;
+#pragma unroll
+    for (int c = 0; c < NU; ++c) {
+      const float zk = plane(MP_ZK, c)[li], zk1 = plane(MP_ZK1, c)[li];
+      const float lk = plane(MP_LK, c)[li], lk1 = plane(MP_LK1, c)[li];
+      const float zh = restart ? zk1 : fmaf(beta, zk - zk1, zk);
+      const float lh = restart ? lk1 : fmaf(beta, lk - lk1, lk);
+      plane(MP_ZH, c)[li] = zh;
+      plane(MP_LH, c)[li] = lh;
+      szh[c] += zh;
+      slh[c] += lh;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NU; ++c) Ri(F::QZ + c) = fmaf(-pb.rho, szh[c], Ri(F::GQP + c)) + slh[c];
+}
+
 template <int NX, int NU>
 __device__ __forceinline__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, int i, int t,
                                                  const float *__restrict__ lpos, const float *__restrict__ lprev,
@@ -1149,7 +1283,8 @@ __device__ __forceinline__ void commit_positions(const WS &ws, const Scen &sc, i
 // 3.3.1): p = 2 P T dp consensus rows, n = N T dp position variables.
 // Executed by one full wavefront; the sum over agent-stages has a fixed order
 // (lane l takes stages l, l+64, ...; then a fixed butterfly).
-template <int NX, int NU>
+// MOM: the momentum variant's combined residual and extrapolation decision.
+template <int NX, int NU, bool MOM = false>
 __device__ int scenario_test(const Prob &pb, const WS &ws, const Scen &sc, int k, int lane, int cap_hit) {
   using F = Fld<NX, NU>;
   const float *R = ws.fr + sc.fo;
@@ -1162,6 +1297,11 @@ __device__ int scenario_test(const Prob &pb, const WS &ws, const Scen &sc, int k
   }
 #pragma unroll
   for (int q = 0; q < 5; ++q) a[q] = wave_sum(a[q]);
+  float cmom = 0.f;   // momentum: the combined residual of the iteration
+  if constexpr (MOM) {
+    for (int idx = lane; idx < NT; idx += 64) cmom += R[fidx((unsigned)sc.GS, (unsigned)(sc.N + idx), F::RED + 5)];
+    cmom = wave_sum(cmom);
+  }
   int done = 0;
   if (lane == 0) {
     const float P = 0.5f * (float)sc.N * (float)(sc.N - 1);
@@ -1193,6 +1333,24 @@ __device__ int scenario_test(const Prob &pb, const WS &ws, const Scen &sc, int k
       if (rn > pb.rho_mu * sn) rh[0] = rh[1] * pb.rho_tau;
       else if (sn > pb.rho_mu * rn) rh[0] = rh[1] / pb.rho_tau;
     }
+    // momentum (Goldstein et al. 2014, Alg. 8): extrapolate if the combined
+    // residual fell by mom_eta, else restart from the previous iterates
+    if (MOM && !done) {
+      float *ms = ws.momst + 4LL * sc.s;
+      const float a0 = ms[0], cp = ms[1];
+      if (cmom < pb.mom_eta * cp) {
+        const float an = 0.5f * (1.0f + sqrtf(fmaf(4.0f * a0, a0, 1.0f)));
+        ms[2] = (a0 - 1.0f) / an;
+        ms[3] = 0.f;
+        ms[0] = an;
+        ms[1] = cmom;
+      } else {
+        ms[2] = 0.f;
+        ms[3] = 1.f;
+        ms[0] = 1.f;
+        ms[1] = cp / pb.mom_eta;
+      }
+    }
     st[ST_STATUS] = status;
     st[ST_ITERS] = k;
     st[ST_DONE] = done;
@@ -1203,7 +1361,7 @@ __device__ int scenario_test(const Prob &pb, const WS &ws, const Scen &sc, int k
 // Per-scenario initial state: z^(0) = C r, lambda^(0) = 0 (the position
 // linear term starts at -2 Q r - rho n_nbr C r), P_T = H_T, empty working
 // sets, every factor stale.
-template <int NX, int NU>
+template <int NX, int NU, bool MOM = false>
 __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int tid, int nthreads) {
   using F = Fld<NX, NU>;
   const int N = sc.N, T = sc.T, GS = sc.GS;
@@ -1344,6 +1502,31 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
     gm[idx] = 0.f;
     pa[idx] = 0;
   }
+  if constexpr (MOM) {
+    // momentum: zh = z_0 = z_(-1) = C r, lh = lambda_0 = lambda_(-1) = 0;
+    // alpha_1 = 1, c_0 = inf
+    float *mp = ws.mom + (long long)MP_N * NU * sc.lo;
+    for (int idx = tid; idx < LS; idx += nthreads) {
+      const int i = idx % N, t = idx / (N * N) + 1;
+      const float *ri = ws.xref + (sc.xo + (long long)i * (T + 1) + t) * NX;
+#pragma unroll
+      for (int c = 0; c < NU; ++c) {
+        mp[(long long)(MP_LH * NU + c) * LS + idx] = 0.f;
+        mp[(long long)(MP_ZH * NU + c) * LS + idx] = ri[c];
+        mp[(long long)(MP_ZK * NU + c) * LS + idx] = ri[c];
+        mp[(long long)(MP_ZK1 * NU + c) * LS + idx] = ri[c];
+        mp[(long long)(MP_LK * NU + c) * LS + idx] = 0.f;
+        mp[(long long)(MP_LK1 * NU + c) * LS + idx] = 0.f;
+      }
+    }
+    if (tid == 0) {
+      float *ms = ws.momst + 4LL * sc.s;
+      ms[0] = 1.f;
+      ms[1] = INFINITY;
+      ms[2] = 0.f;
+      ms[3] = 0.f;
+    }
+  }
   if (pb.relax) {
     // the copies' z^0 = C r: D = r_i - r_j, e = 0 (copy (i, j) at [t][j][i])
     float *ob = ws.orx + 2LL * NU * sc.lo;
@@ -1428,7 +1611,8 @@ __global__ __launch_bounds__(64) void k_resid(Prob pb, WS ws, int s, int k, int 
 // scenario's own stopping test passes; the three phases are separated by
 // workgroup barriers.  Every wave reaches the queue read, so the grid drains
 // once the counter passes S.
-template <int NX, int NU, bool DI, bool REL>
+// VAR: 0 plain ADMM, 1 over-relaxed, 2 momentum (each a kernel of its own).
+template <int NX, int NU, bool DI, int VAR>
 __device__ __forceinline__ void persistent_body(Prob pb, WS ws, int S, int lds_floats) {
   extern __shared__ float lds_pos[];  // positions of the scenario and the previous ones, [t][i][c] each
   __shared__ int s_item;
@@ -1444,7 +1628,7 @@ __device__ __forceinline__ void persistent_body(Prob pb, WS ws, int S, int lds_f
     const int s = __builtin_amdgcn_readfirstlane(ws.order[item]);
     if (pb.cont && uni(ws.skip[s])) continue;   // converged in an earlier SQP round
     const Scen sc = load_scen(ws, s);
-    scenario_setup<NX, NU>(pb, ws, sc, tid, nt);
+    scenario_setup<NX, NU, VAR == 2>(pb, ws, sc, tid, nt);
     if (tid == 0) { s_cap = 0; s_done = 0; }
     long long cnt[CT_NCOL] = {};
     __syncthreads();
@@ -1471,9 +1655,13 @@ __device__ __forceinline__ void persistent_body(Prob pb, WS ws, int S, int lds_f
             }
           __syncthreads();
         }
-        for (int idx = tid; idx < sc.N * sc.T; idx += nt)
-          pair_agent_stage_impl<NX, NU, REL>(pb, ws, sc, idx % sc.N, idx / sc.N + 1, staged ? lds_pos : nullptr,
-                                             staged ? lds_prev : nullptr, 0);
+        for (int idx = tid; idx < sc.N * sc.T; idx += nt) {
+          if constexpr (VAR == 2)
+            pair_agent_stage_mom<NX, NU>(pb, ws, sc, idx % sc.N, idx / sc.N + 1, staged ? lds_pos : nullptr);
+          else
+            pair_agent_stage_impl<NX, NU, VAR == 1>(pb, ws, sc, idx % sc.N, idx / sc.N + 1,
+                                                    staged ? lds_pos : nullptr, staged ? lds_prev : nullptr, 0);
+        }
         if (tid == 0) cnt[CT_PAIRS] += (long long)sc.N * (sc.N - 1) / 2 * sc.T;
         __syncthreads();
         commit_positions<NX, NU>(ws, sc, tid, nt);
@@ -1481,10 +1669,18 @@ __device__ __forceinline__ void persistent_body(Prob pb, WS ws, int S, int lds_f
       __syncthreads();
       const unsigned long long c2 = wall_clock64();
       if (tid < 64) {
-        const int d = scenario_test<NX, NU>(pb, ws, sc, k, tid, cap);
+        const int d = scenario_test<NX, NU, VAR == 2>(pb, ws, sc, k, tid, cap);
         if (tid == 0) s_done = d;
       }
       __syncthreads();
+      if constexpr (VAR == 2) {
+        // momentum: the next iteration's extrapolated duals and copies
+        if (!s_done) {
+          for (int idx = tid; idx < sc.N * sc.T; idx += nt)
+            mom_extrapolate<NX, NU>(pb, ws, sc, idx % sc.N, idx / sc.N + 1);
+          __syncthreads();
+        }
+      }
       if (tid == 0) {
         cnt[CT_T_X] += (long long)(c1 - c0);
         cnt[CT_T_PAIR] += (long long)(c2 - c1);
@@ -1503,22 +1699,25 @@ __device__ __forceinline__ void persistent_body(Prob pb, WS ws, int S, int lds_f
 // whole batch of a few thousand scenarios is resident at once.  REL:
 // over-relaxation, a kernel of its own so that the plain kernel's code and
 // register allocation stay as they are.
-template <int NX, int NU, bool DI, bool REL>
+template <int NX, int NU, bool DI, int VAR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_admm_persistent(Prob pb, WS ws, int S, int lds_floats) {
-  persistent_body<NX, NU, DI, REL>(pb, ws, S, lds_floats);
+  persistent_body<NX, NU, DI, VAR>(pb, ws, S, lds_floats);
 }
 
-template <int NX, int NU, bool DI, bool REL>
+template <int NX, int NU, bool DI, int VAR>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_admm_persistent_lean(
     Prob pb, WS ws, int S, int lds_floats) {
-  persistent_body<NX, NU, DI, REL>(pb, ws, S, lds_floats);
+  persistent_body<NX, NU, DI, VAR>(pb, ws, S, lds_floats);
 }
 
 template <int NX, int NU, bool DI>
-const void *persistent_kernel(bool lean, bool rel) {
-  if (lean) return rel ? (const void *)k_admm_persistent_lean<NX, NU, DI, true>
-                       : (const void *)k_admm_persistent_lean<NX, NU, DI, false>;
-  return rel ? (const void *)k_admm_persistent<NX, NU, DI, true> : (const void *)k_admm_persistent<NX, NU, DI, false>;
+const void *persistent_kernel(bool lean, int var) {
+  if (lean) return var == 2 ? (const void *)k_admm_persistent_lean<NX, NU, DI, 2>
+                 : var == 1 ? (const void *)k_admm_persistent_lean<NX, NU, DI, 1>
+                            : (const void *)k_admm_persistent_lean<NX, NU, DI, 0>;
+  return var == 2 ? (const void *)k_admm_persistent<NX, NU, DI, 2>
+         : var == 1 ? (const void *)k_admm_persistent<NX, NU, DI, 1>
+                    : (const void *)k_admm_persistent<NX, NU, DI, 0>;
 }
 
 __global__ void k_fill_i32(int *p, int n, int v) {
@@ -1867,6 +2066,7 @@ struct Layout {
   size_t o_sqpj = 0, o_sqpi = 0, o_sqpf = 0;   // SQP: objective [S] (FP64); skip, rounds [2][S]; min distance [S]
   size_t o_rho = 0;    // [S][2] penalty of the next / last iteration
   size_t o_orx = 0;    // over-relaxation: [2 nu] planes shaped like the gamma region
+  size_t o_mom = 0, o_momst = 0;   // momentum: [6 nu] planes shaped like the gamma region; [S][4]
   long long sumPT = 0;
   std::vector<long long> tab;
   std::vector<int> order;
@@ -1916,6 +2116,12 @@ bool params_ok(const tadmm_params *p, std::string &err) {
       }
     }
   if (!(p->alpha >= 0.f && p->alpha < 2.f)) { err = "alpha must be in (0, 2) (0: plain ADMM)"; return false; }
+  if (p->momentum) {
+    if (!(p->mom_eta > 0.f && p->mom_eta < 1.f)) { err = "momentum needs 0 < mom_eta < 1"; return false; }
+    if (p->adaptive_rho || relaxed(*p) || p->state_box) {
+      err = "momentum is not combined with adaptive_rho, alpha != 1 or state_box"; return false;
+    }
+  }
   if (p->max_iter < 1) { err = "max_iter must be >= 1"; return false; }
   if (p->normal_mode != TADMM_NORMAL_PER_ITER && p->normal_mode != TADMM_NORMAL_FROZEN) {
     err = "unknown normal_mode"; return false;
@@ -1988,6 +2194,10 @@ bool make_layout(const tadmm_params *p, int S, const int32_t *N, const int32_t *
   L.o_sqpf = take(sizeof(float) * S);
   L.o_rho = take(sizeof(float) * 2 * S);
   if (relaxed(*p)) L.o_orx = take(sizeof(float) * 2 * (size_t)p->nu * (size_t)lo);
+  if (p->momentum) {
+    L.o_mom = take(sizeof(float) * 6 * (size_t)p->nu * (size_t)lo);
+    L.o_momst = take(sizeof(float) * 4 * (size_t)S);
+  }
   L.bytes = off;
   // launch order for the persistent queue: largest N^2 T first (LPT)
   L.order.resize(S);
@@ -2046,6 +2256,8 @@ Prob to_prob(const tadmm_params &p) {
   pb.rho_every = std::max(p.rho_every, 1);
   pb.rho_mu = p.rho_mu;
   pb.rho_tau = p.rho_tau;
+  pb.mom = p.momentum ? 1 : 0;
+  pb.mom_eta = p.mom_eta;
   pb.relax = relaxed(p) ? 1 : 0;
   pb.alpha = pb.relax ? p.alpha : 1.0f;
   // each group of states is split only where one of its bounds is finite
@@ -2159,6 +2371,8 @@ WS make_ws(const Layout &L, char *ws, const tadmm_batch *b) {
   w.skip = (int *)(ws + L.o_sqpi);
   w.rhos = (float *)(ws + L.o_rho);
   w.orx = L.o_orx ? (float *)(ws + L.o_orx) : nullptr;
+  w.mom = L.o_mom ? (float *)(ws + L.o_mom) : nullptr;
+  w.momst = L.o_momst ? (float *)(ws + L.o_momst) : nullptr;
   return w;
 }
 
@@ -2214,7 +2428,7 @@ tadmm_status run_batched(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layo
   const bool lean = (threads == 64);
   const int lds_floats = (int)std::min<long long>(2 * max_gs * NU, lean ? 4096 : 8192);
   const size_t lds_bytes = sizeof(float) * (size_t)lds_floats;
-  const void *kfn = persistent_kernel<NX, NU, DI>(lean, pb.relax != 0);
+  const void *kfn = persistent_kernel<NX, NU, DI>(lean, pb.mom ? 2 : (pb.relax ? 1 : 0));
   int per_cu = 0;
   HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, threads, lds_bytes));
   if (per_cu < 1) return fail(ctx, TADMM_ERR_HIP, "persistent kernel does not fit on a compute unit");
@@ -2349,6 +2563,8 @@ tadmm_status run_wide(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layout 
 
 template <int NX, int NU, bool DI>
 tadmm_status solve_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *out, void *ws, size_t bytes, int mode) {
+  if (ctx->prm.momentum && mode != TADMM_MODE_BATCHED)
+    return fail(ctx, TADMM_ERR_INVALID_ARG, "momentum runs in the batched mode");
   Layout L;
   if (!make_layout(&ctx->prm, b->n_scen, b->n_agents, b->horizon, L, ctx->err)) return TADMM_ERR_SHAPE;
   if (!ws || bytes < L.bytes) return fail(ctx, TADMM_ERR_WORKSPACE, "workspace missing or smaller than tadmm_workspace_size()");
@@ -2392,6 +2608,7 @@ tadmm_status solve_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *o
 template <int NX, int NU, bool DI>
 tadmm_status sqp_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *out, void *ws, size_t bytes, int mode,
                       int max_rounds, float rtol, float sep_tol, float *stats) {
+  if (ctx->prm.momentum) return fail(ctx, TADMM_ERR_INVALID_ARG, "tadmm_sqp takes solves without momentum");
   if (max_rounds < 1) return fail(ctx, TADMM_ERR_INVALID_ARG, "max_rounds must be >= 1");
   if (!(std::isfinite(rtol) && rtol >= 0.f && std::isfinite(sep_tol) && sep_tol >= 0.f))
     return fail(ctx, TADMM_ERR_INVALID_ARG, "rtol and sep_tol must be finite and >= 0");
@@ -2497,6 +2714,8 @@ tadmm_status eqp_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *out
     return fail(ctx, TADMM_ERR_INVALID_ARG, "the derivative takes per-scenario weights (no agent_* arrays)");
   if (ctx->prm.state_box)
     return fail(ctx, TADMM_ERR_INVALID_ARG, "the derivative covers input bounds only (no state_box)");
+  if (ctx->prm.momentum)
+    return fail(ctx, TADMM_ERR_INVALID_ARG, "the derivative follows solves without momentum");
   if (b->n_scen != sb.n_scen || b->x0 != sb.x0 || b->xref != sb.xref || b->q_diag != sb.q_diag ||
       b->r_diag != sb.r_diag || b->normals != sb.normals)
     return fail(ctx, TADMM_ERR_STATE, "batch differs from the one of the last tadmm_solve");

@@ -90,6 +90,9 @@ def oracle_opts(solver_kw=None, lockstep=None):
         o.hotstart = bool(kw["hotstart"])
     if "alpha" in kw:
         o.alpha = float(np.float32(kw["alpha"]))
+    if kw.get("momentum"):
+        o.momentum = True
+        o.mom_eta = float(np.float32(kw.get("mom_eta", 0.999)))
     for k in ("s_lo", "s_hi", "p_lo", "p_hi"):
         if k in kw:
             setattr(o, k, tuple(float(np.float32(v)) for v in kw[k]) + (0.0,) * (3 - len(kw[k])))

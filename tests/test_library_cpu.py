@@ -108,6 +108,15 @@ def test_bad_state_box_rejected(lo, hi):
     assert _ws(prm, [2], [20])[0] == 0
 
 
+@pytest.mark.parametrize("extra", [dict(mom_eta=1.0), dict(mom_eta=0.0), dict(adaptive_rho=True), dict(alpha=1.5),
+                                   dict(state_box=True, s_lo=(-1.0, -1.0), s_hi=(1.0, 1.0))])
+def test_bad_momentum_params_rejected(extra):
+    prm = tadmm.make_params(synth.ProblemParams(), momentum=True)
+    assert _ws(prm, [2], [20])[0] == 0
+    assert _ws(tadmm.make_params(synth.ProblemParams(), momentum=True, **extra), [2], [20])[0] == 1
+    assert _ws(tadmm.make_params(synth.ProblemParams(), **extra), [2], [20])[0] == 0   # valid without momentum
+
+
 @pytest.mark.parametrize("alpha", [-0.5, 2.0, float("nan"), float("inf")])
 def test_bad_relaxation_rejected(alpha):
     prm = tadmm.make_params(synth.ProblemParams(), alpha=1.5)
