@@ -207,8 +207,9 @@ def sqp_study(S: int = 4096, max_rounds: int = 10, rtol: float = 1e-4, sep_tol: 
 def rho_study(S: int = 4096) -> List[Dict]:
     """The benchmark's batch with the penalty fixed (rho = 1) and adapted by
     residual balancing (mu = 10, tau = 2, every iteration), each without and
-    with over-relaxation (alpha = 1.6): converged fraction, mean iterations,
-    refactored stages and time."""
+    with over-relaxation (alpha = 1.6), and with momentum (fast ADMM with
+    restart, eta = 0.999): converged fraction, mean iterations, refactored
+    stages and time."""
     import torch
 
     import synth
@@ -218,7 +219,7 @@ def rho_study(S: int = 4096) -> List[Dict]:
     recs = []
     adapt = dict(adaptive_rho=True, rho_mu=10.0, rho_tau=2.0, rho_every=1)
     for name, kw in (("fixed", {}), ("adaptive", adapt), ("fixed, alpha 1.6", dict(alpha=1.6)),
-                     ("adaptive, alpha 1.6", dict(adapt, alpha=1.6))):
+                     ("adaptive, alpha 1.6", dict(adapt, alpha=1.6)), ("momentum", dict(momentum=True))):
         solver = tadmm.Solver(tadmm.make_params(problem, **kw))
         prep = solver.prepare(pk.n_agents, pk.horizon, pk.x0, pk.xref, pk.q_diag, pk.r_diag)
         prep.run(tadmm.MODE_BATCHED)
