@@ -1160,18 +1160,32 @@ __device__ void pair_agent_stage_mom(const Prob &pb, const WS &ws, const Scen &s
   for (int c = 0; c < NU; ++c) { szk[c] = 0.f; szh[c] = 0.f; ls[c] = 0.f; }
   float r2 = 0.f, z2 = 0.f, c2 = 0.f;
   const int gbase = (t - 1) * N * N + i;
-  for (int jj = 0; jj < N - 1; ++jj) {
-    const int j = jj + (jj >= i);
-    const int li = gbase + j * N;
-    float pj[NU], lh[NU], zh[NU], zk[NU], lk[NU];
+  // partners in batches of kPB: a batch's loads are all issued before the
+  // first is used
+  constexpr int kPB = 4;
+  const int np = N - 1;
+  for (int j0 = 0; j0 < np; j0 += kPB) {
+   float pjb[kPB][NU], lhb[kPB][NU], zhb[kPB][NU], zkb[kPB][NU], lkb[kPB][NU];
 #pragma unroll
-    for (int c = 0; c < NU; ++c) {
-      pj[c] = lpos ? lpos[(t * N + j) * NU + c] : R[fidx(GS, (unsigned)(t * N + j), F::X + c)];
-      lh[c] = plane(MP_LH, c)[li];
-      zh[c] = plane(MP_ZH, c)[li];
-      zk[c] = plane(MP_ZK, c)[li];
-      lk[c] = plane(MP_LK, c)[li];
+   for (int q = 0; q < kPB; ++q)
+    if (j0 + q < np) {
+      const int j = (j0 + q) + ((j0 + q) >= i);
+      const int li = gbase + j * N;
+#pragma unroll
+      for (int c = 0; c < NU; ++c) {
+        pjb[q][c] = lpos ? lpos[(t * N + j) * NU + c] : R[fidx(GS, (unsigned)(t * N + j), F::X + c)];
+        lhb[q][c] = plane(MP_LH, c)[li];
+        zhb[q][c] = plane(MP_ZH, c)[li];
+        zkb[q][c] = plane(MP_ZK, c)[li];
+        lkb[q][c] = plane(MP_LK, c)[li];
+      }
     }
+#pragma unroll
+   for (int q = 0; q < kPB; ++q) {
+    if (j0 + q >= np) break;
+    const int j = (j0 + q) + ((j0 + q) >= i);
+    const int li = gbase + j * N;
+    const float *pj = pjb[q], *lh = lhb[q], *zh = zhb[q], *zk = zkb[q], *lk = lkb[q];
     float n[NU];
     pair_normal<NX, NU>(pb, ws, sc, i, j, t, pi, pj, n);
     float ab[NU], g = 0.f;
@@ -1200,6 +1214,7 @@ __device__ void pair_agent_stage_mom(const Prob &pb, const WS &ws, const Scen &s
     }
     gm[li] = gam;
     if (i < j) pa[li] = (uint8_t)(v > 0.f);
+   }
   }
   float s2 = 0.f, ax2 = 0.f, aty2 = 0.f;
 #pragma unroll

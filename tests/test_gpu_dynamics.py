@@ -136,3 +136,24 @@ def test_agent_dynamics_bad_inputs_and_derivative_rejected():
         prep.polish()
     assert "error 1" in str(e.value)
     solver.close()
+
+
+def test_agent_dynamics_with_box_relaxation_and_hetero_weights_lockstep():
+    """Per-agent dynamics together with per-agent weights and boxes, the
+    velocity box and over-relaxation, in lockstep with the oracle (the
+    general path with every option that composes with it)."""
+    p, scs = synth.config2(S=6)
+    rng = np.random.default_rng(21)
+    mixed = []
+    for sc in _mixed(p, scs, seed=17):
+        h = synth.heterogeneous(rng, sc, p)
+        mixed.append(dataclasses.replace(h, agent_q=_f32(h.agent_q), agent_r=_f32(h.agent_r),
+                                         agent_lo=_f32(h.agent_lo), agent_hi=_f32(h.agent_hi)))
+    K = 40
+    kw = dict(alpha=1.6, state_box=True, s_lo=(-2.0, -2.0), s_hi=(2.0, 2.0), max_iter=K, eps_abs=0.0, eps_rel=0.0)
+    g = gc.gpu_solve(p, mixed, solver_kw=kw)
+    o = gc.oracle_same_instance(p, mixed, gc.oracle_opts(kw, lockstep=K), threads=4)
+    for sc, gr, orr in zip(mixed, g, o):
+        rel = gc.rel_traj_err(gr, orr)
+        _say(f"  N={sc.N} T={sc.T}: rel {rel:.2e}")
+        assert rel <= gc.REL_TOL
