@@ -220,6 +220,12 @@ def main():
         ro = oracle.solve_batch(problem, sub, threads=th)
         dtc = time.perf_counter() - tc
         oit = np.array([r["iters"] for r in ro], dtype=np.int64)
+        # the converged fraction at 1e-4 on this sample, beside the device's
+        # on the same scenarios (the oracle solves the FP64 instance)
+        ost = np.array([r["status"] for r in ro])
+        out["converged_fraction_sample"] = {"scenarios": len(ids),
+                                            "device": round(float((status[ids] == 0).mean()), 4),
+                                            "oracle": round(float((ost == oracle.CONVERGED).mean()), 4)}
         out["cpu_baseline"] = {"value": round(len(ids) / dtc, 3), "unit": "scenario solves/s", "cores": int(th),
                                "kind": "oracle",
                                "sample": f"scenarios 0..{len(ids) - 1} of the batch, FP64 dense-KKT oracle, OpenMP "
