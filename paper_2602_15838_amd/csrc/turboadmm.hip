@@ -1305,10 +1305,24 @@ __device__ int scenario_test(const Prob &pb, const WS &ws, const Scen &sc, int k
   const float *R = ws.fr + sc.fo;
   const int NT = sc.N * sc.T;
   float a[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-  for (int idx = lane; idx < NT; idx += 64) {
-    const int g = sc.N + idx;  // stages 1..T
+  // lane l adds stages l, l + 64, ... in that order; the loads of two of
+  // them are issued before the first is added
+  for (int idx0 = lane; idx0 < NT; idx0 += 2 * 64) {
+    float v[2][5];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) a[q] += R[fidx((unsigned)sc.GS, (unsigned)g, F::RED + q)];
+    for (int u = 0; u < 2; ++u) {
+      const int idx = idx0 + 64 * u;
+      if (idx < NT) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) v[u][q] = R[fidx((unsigned)sc.GS, (unsigned)(sc.N + idx), F::RED + q)];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+      if (idx0 + 64 * u < NT) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) a[q] += v[u][q];
+      }
   }
 #pragma unroll
   for (int q = 0; q < 5; ++q) a[q] = wave_sum(a[q]);
