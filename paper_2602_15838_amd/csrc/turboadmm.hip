@@ -1693,7 +1693,16 @@ __device__ __forceinline__ void persistent_body(Prob pb, WS ws, int S, int lds_f
         }
         if (tid == 0) cnt[CT_PAIRS] += (long long)sc.N * (sc.N - 1) / 2 * sc.T;
         __syncthreads();
-        commit_positions<NX, NU>(ws, sc, tid, nt);
+        if (staged) {
+          // the positions of this step are in LDS already
+          float *R = ws.fr + sc.fo;
+          const unsigned GS = (unsigned)sc.GS;
+          for (int idx = sc.N + tid; idx < sc.GS; idx += nt)
+#pragma unroll
+            for (int c = 0; c < NU; ++c) fref(R, GS, (unsigned)idx, Fld<NX, NU>::XP + c) = lds_pos[idx * NU + c];
+        } else {
+          commit_positions<NX, NU>(ws, sc, tid, nt);
+        }
       }
       __syncthreads();
       const unsigned long long c2 = wall_clock64();
