@@ -1,6 +1,6 @@
-"""The SQP outer loop (tadmm_sqp) with the extensions: a velocity box, and
+"""The SQP outer loop (tadmm_sqp) with the extensions: a velocity box,
 heterogeneous agents (per-agent weights in the objective of the stopping
-rule), against the oracle's loop (oracle/sqp.py) on the FP32 instance the
+rule), adaptive penalties and per-agent dynamics, against the oracle's loop (oracle/sqp.py) on the FP32 instance the
 device receives.  The bars are those of the plain loop's test: the same
 rounds and outcome, the objective within 1e-5 relative, the trajectories
 within the parity bar, or within 10 times the oracle's own distance between
@@ -36,7 +36,8 @@ def _compare(p, scs, extra):
     pk = synth.pack(p, scs)
     solver = tadmm.Solver(tadmm.make_params(p, **KW, **extra))
     prep = solver.prepare(pk.n_agents, pk.horizon, pk.x0, pk.xref, pk.q_diag, pk.r_diag, agent_q=pk.agent_q,
-                          agent_r=pk.agent_r, agent_lo=pk.agent_lo, agent_hi=pk.agent_hi)
+                          agent_r=pk.agent_r, agent_lo=pk.agent_lo, agent_hi=pk.agent_hi, agent_A=pk.agent_A,
+                          agent_B=pk.agent_B)
     st = prep.sqp(tadmm.MODE_BATCHED, max_rounds=10).cpu().numpy()
     res = tadmm.split_outputs(prep.result(), pk.n_agents, pk.horizon, p.nx, p.nu)
     solver.close()
@@ -80,4 +81,21 @@ def test_sqp_with_heterogeneous_agents_matches_oracle():
         h = synth.heterogeneous(rng, sc, p)
         scs.append(dataclasses.replace(h, agent_q=f32(h.agent_q), agent_r=f32(h.agent_r), agent_lo=f32(h.agent_lo),
                                        agent_hi=f32(h.agent_hi)))
+    _compare(p, scs, {})
+
+
+def test_sqp_with_adaptive_rho_matches_oracle():
+    """Residual balancing inside the rounds: the device's rounds continue with
+    the adapted penalty, the oracle's restart from the initial one; each
+    round's QP has one minimiser, so the bars are the same."""
+    p, scs = synth.config0()
+    _compare(p, scs, dict(adaptive_rho=True, rho_mu=10.0, rho_tau=2.0, rho_every=1))
+
+
+def test_sqp_with_agent_dynamics_matches_oracle():
+    p, s2 = synth.config2(S=40)
+    rng = np.random.default_rng(17)
+    f32 = lambda a: np.asarray(a, np.float32).astype(np.float64)
+    scs = [dataclasses.replace(m, agent_A=f32(m.agent_A), agent_B=f32(m.agent_B))
+           for m in (synth.mixed_dynamics(rng, sc, p) for sc in [s for s in s2 if s.N <= 8][:3])]
     _compare(p, scs, {})
