@@ -174,8 +174,9 @@ typedef struct {
                                 and duals, restarting when the combined residual
                                 fails to fall by the factor mom_eta.  Batched
                                 mode only; not with adaptive_rho, alpha != 1,
-                                state_box, tadmm_sqp or tadmm_polish/adjoint.
-                                The workspace holds 6 nu floats more per
+                                state_box or tadmm_sqp (the derivative of the
+                                solve is that of its converged point, as
+                                without).  The workspace holds 6 nu floats more per
                                 ordered pair copy and step.  0: off (default)    */
   float mom_eta;             /* with momentum: 0 < mom_eta < 1 (0.999)            */
 } tadmm_params;

@@ -2752,8 +2752,6 @@ tadmm_status eqp_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *out
     return fail(ctx, TADMM_ERR_INVALID_ARG, "the derivative takes per-scenario weights (no agent_* arrays)");
   if (ctx->prm.state_box)
     return fail(ctx, TADMM_ERR_INVALID_ARG, "the derivative covers input bounds only (no state_box)");
-  if (ctx->prm.momentum)
-    return fail(ctx, TADMM_ERR_INVALID_ARG, "the derivative follows solves without momentum");
   if (b->n_scen != sb.n_scen || b->x0 != sb.x0 || b->xref != sb.xref || b->q_diag != sb.q_diag ||
       b->r_diag != sb.r_diag || b->normals != sb.normals)
     return fail(ctx, TADMM_ERR_STATE, "batch differs from the one of the last tadmm_solve");

@@ -43,14 +43,14 @@ def _pack(problem, cases):
     return pk, nrm
 
 
-@functools.lru_cache(maxsize=3)
-def _gpu_run(fp64: bool, alpha: float = 1.0):
+@functools.lru_cache(maxsize=4)
+def _gpu_run(fp64: bool, alpha: float = 1.0, momentum: bool = False):
     """Frozen-normal solve of the cases on the device (over-relaxed when
-    alpha != 1), then the polish."""
+    alpha != 1, with momentum when asked), then the polish."""
     import paper_2602_15838_amd as tadmm
     p, cases = _cases()
     pk, nrm = _pack(p, cases)
-    solver = tadmm.Solver(tadmm.make_params(p, eqp_fp64=fp64, alpha=alpha, **FROZEN_KW))
+    solver = tadmm.Solver(tadmm.make_params(p, eqp_fp64=fp64, alpha=alpha, momentum=momentum, **FROZEN_KW))
     prep = solver.prepare(pk.n_agents, pk.horizon, pk.x0, pk.xref, pk.q_diag, pk.r_diag, nrm)
     prep.run(tadmm.MODE_BATCHED)
     pre = tadmm.split_outputs(prep.result(), pk.n_agents, pk.horizon, p.nx, p.nu)
@@ -157,13 +157,15 @@ def test_adjoint_matches_dense_kkt_gradient(fp64):
     print(f"eqp_fp64={fp64}: worst relative gradient error {worst}")
 
 
-def test_relaxed_solve_polish_and_adjoint_match_dense_kkt():
-    """The derivative of an over-relaxed solve (alpha = 1.6): relaxation
-    changes the path, not the converged point or its active sets, so the
-    polish and the gradients meet the same bars as after plain ADMM."""
+@pytest.mark.parametrize("variant", ["relaxed", "momentum"])
+def test_variant_solve_polish_and_adjoint_match_dense_kkt(variant):
+    """The derivative of an over-relaxed (alpha = 1.6) or momentum solve:
+    the variant changes the path, not the converged point or its active
+    sets, so the polish and the gradients meet the same bars as after plain
+    ADMM."""
     import torch
     p, cases = _cases()
-    solver, prep, pk, pre, post, st = _gpu_run(True, 1.6)
+    solver, prep, pk, pre, post, st = _gpu_run(True, 1.6, False) if variant == "relaxed" else _gpu_run(True, 1.0, True)
     m = _matching(pre, cases)
     assert len(m) >= WANT // 2
     sols = _oracle_solutions()
@@ -182,7 +184,7 @@ def test_relaxed_solve_polish_and_adjoint_match_dense_kkt():
             rel = GC.rel_err(gg[k][n], og[k][2][n])
             worst = max(worst, rel)
             assert rel <= GRAD_TOL, (cases[k].sid, n, rel)
-    print(f"alpha 1.6: {len(m)}/{len(cases)} active sets identical; worst relative gradient error {worst:.2e}")
+    print(f"{variant}: {len(m)}/{len(cases)} active sets identical; worst relative gradient error {worst:.2e}")
 
 
 def test_adjoint_matches_finite_differences():
