@@ -172,8 +172,8 @@ typedef struct {
                                 Goldstein et al. (2014, Alg. 8) on the consensus
                                 block: each iteration takes extrapolated copies
                                 and duals, restarting when the combined residual
-                                fails to fall by the factor mom_eta.  Batched
-                                mode only; not with adaptive_rho, alpha != 1,
+                                fails to fall by the factor mom_eta.  Not with
+                                adaptive_rho, alpha != 1,
                                 state_box or tadmm_sqp (the derivative of the
                                 solve is that of its converged point, as
                                 without).  The workspace holds 6 nu floats more per

@@ -1137,7 +1137,7 @@ enum { MP_LH = 0, MP_ZH, MP_ZK, MP_ZK1, MP_LK, MP_LK1, MP_N };
 
 template <int NX, int NU>
 __device__ void pair_agent_stage_mom(const Prob &pb, const WS &ws, const Scen &sc, int i, int t,
-                                     const float *__restrict__ lpos) {
+                                     const float *__restrict__ lpos, int lofs = 0) {
   using F = Fld<NX, NU>;
   const int N = sc.N;
   float *R = ws.fr + sc.fo;
@@ -1173,7 +1173,7 @@ __device__ void pair_agent_stage_mom(const Prob &pb, const WS &ws, const Scen &s
       const int li = gbase + j * N;
 #pragma unroll
       for (int c = 0; c < NU; ++c) {
-        pjb[q][c] = lpos ? lpos[(t * N + j) * NU + c] : R[fidx(GS, (unsigned)(t * N + j), F::X + c)];
+        pjb[q][c] = lpos ? lpos[(t * N + j - lofs) * NU + c] : R[fidx(GS, (unsigned)(t * N + j), F::X + c)];
         lhb[q][c] = plane(MP_LH, c)[li];
         zhb[q][c] = plane(MP_ZH, c)[li];
         zkb[q][c] = plane(MP_ZK, c)[li];
@@ -1277,7 +1277,8 @@ template <int NX, int NU>
 __device__ __forceinline__ void pair_agent_stage(const Prob &pb, const WS &ws, const Scen &sc, int i, int t,
                                                  const float *__restrict__ lpos, const float *__restrict__ lprev,
                                                  int lofs = 0) {
-  if (pb.relax) pair_agent_stage_impl<NX, NU, true>(pb, ws, sc, i, t, lpos, lprev, lofs);
+  if (pb.mom) pair_agent_stage_mom<NX, NU>(pb, ws, sc, i, t, lpos, lofs);
+  else if (pb.relax) pair_agent_stage_impl<NX, NU, true>(pb, ws, sc, i, t, lpos, lprev, lofs);
   else pair_agent_stage_impl<NX, NU, false>(pb, ws, sc, i, t, lpos, lprev, lofs);
 }
 
@@ -1595,7 +1596,8 @@ __device__ __forceinline__ void add_counters(const WS &ws, int s, const long lon
 template <int NX, int NU>
 __global__ __launch_bounds__(256) void k_setup(Prob pb, WS ws, int s) {
   const Scen sc = load_scen(ws, s);
-  scenario_setup<NX, NU>(pb, ws, sc, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+  if (pb.mom) scenario_setup<NX, NU, true>(pb, ws, sc, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+  else scenario_setup<NX, NU>(pb, ws, sc, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
   if (!pb.cont && blockIdx.x == 0 && threadIdx.x < CT_NCOL) ws.cnt[(long long)s * CT_NCOL + threadIdx.x] = 0ull;
 }
 
@@ -1627,9 +1629,20 @@ template <int NX, int NU>
 __global__ __launch_bounds__(64) void k_resid(Prob pb, WS ws, int s, int k, int *done_out) {
   const Scen sc = load_scen(ws, s);
   const int cap = ws.sst[(long long)s * ST_NCOL + ST_CAP];
-  const int done = scenario_test<NX, NU>(pb, ws, sc, k, threadIdx.x, cap);
+  const int done = pb.mom ? scenario_test<NX, NU, true>(pb, ws, sc, k, threadIdx.x, cap)
+                          : scenario_test<NX, NU>(pb, ws, sc, k, threadIdx.x, cap);
   if (threadIdx.x == 0) *done_out = done;
   if (!cap) commit_positions<NX, NU>(ws, sc, threadIdx.x, blockDim.x);
+}
+
+// Momentum: the next iteration's extrapolated duals and copies of a scenario
+// whose stopping test did not end it (one lane per agent-stage).
+template <int NX, int NU>
+__global__ __launch_bounds__(256) void k_extrap(Prob pb, WS ws, int s) {
+  if (uni(ws.sst[(long long)s * ST_NCOL + ST_DONE])) return;
+  const Scen sc = load_scen(ws, s);
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < sc.N * sc.T) mom_extrapolate<NX, NU>(pb, ws, sc, idx % sc.N, idx / sc.N + 1);
 }
 
 // ===========================================================================
@@ -1779,7 +1792,8 @@ __global__ void k_fill_u64(unsigned long long *p, long long n) {
 template <int NX, int NU>
 __global__ __launch_bounds__(256) void k_wide_setup(Prob pb, WS ws, int *wide) {
   const Scen sc = load_scen(ws, uni(wide[1]));
-  scenario_setup<NX, NU>(pb, ws, sc, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+  if (pb.mom) scenario_setup<NX, NU, true>(pb, ws, sc, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+  else scenario_setup<NX, NU>(pb, ws, sc, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
   if (!pb.cont && blockIdx.x == 0 && threadIdx.x < CT_NCOL) ws.cnt[(long long)sc.s * CT_NCOL + threadIdx.x] = 0ull;
   if (blockIdx.x == 0 && threadIdx.x == 0) wide[0] = 1;
 }
@@ -1844,8 +1858,19 @@ __global__ __launch_bounds__(64) void k_wide_test(Prob pb, WS ws, const int *wid
   if (uni(st[ST_DONE])) return;
   const Scen sc = load_scen(ws, s);
   const int cap = uni(st[ST_CAP]);
-  (void)scenario_test<NX, NU>(pb, ws, sc, uni(wide[0]), threadIdx.x, cap);
+  if (pb.mom) (void)scenario_test<NX, NU, true>(pb, ws, sc, uni(wide[0]), threadIdx.x, cap);
+  else (void)scenario_test<NX, NU>(pb, ws, sc, uni(wide[0]), threadIdx.x, cap);
   if (!cap) commit_positions<NX, NU>(ws, sc, threadIdx.x, blockDim.x);
+}
+
+// Momentum in the many-workgroup mode: the extrapolation after the test.
+template <int NX, int NU>
+__global__ __launch_bounds__(256) void k_wide_extrap(Prob pb, WS ws, const int *wide) {
+  const int s = uni(wide[1]);
+  if (uni(ws.sst[(long long)s * ST_NCOL + ST_DONE])) return;
+  const Scen sc = load_scen(ws, s);
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < sc.N * sc.T) mom_extrapolate<NX, NU>(pb, ws, sc, idx % sc.N, idx / sc.N + 1);
 }
 
 __global__ void k_wide_next(int *wide) {
@@ -2441,6 +2466,8 @@ tadmm_status run_plain(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layout
                          ctx->stream, pb, w, s, k);
       hipLaunchKernelGGL((k_pair<NX, NU>), dim3((n * t + 255) / 256), dim3(256), 0, ctx->stream, pb, w, s);
       hipLaunchKernelGGL((k_resid<NX, NU>), dim3(1), dim3(64), 0, ctx->stream, pb, w, s, k, d_flags + 2);
+      if (pb.mom)
+        hipLaunchKernelGGL((k_extrap<NX, NU>), dim3((n * t + 255) / 256), dim3(256), 0, ctx->stream, pb, w, s);
       HIPCHK(hipGetLastError());
       HIPCHK(hipMemcpyAsync(ctx->h_flags + 2, d_flags + 2, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
       HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -2564,6 +2591,8 @@ tadmm_status run_wide(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layout 
           hipLaunchKernelGGL((k_wide_pair<NX, NU>), dim3(gp), dim3(256), lds_bytes, cs, pb, w, (const int *)d_wide,
                              lds_floats);
           hipLaunchKernelGGL((k_wide_test<NX, NU>), dim3(1), dim3(64), 0, cs, pb, w, (const int *)d_wide);
+          if (pb.mom)
+            hipLaunchKernelGGL((k_wide_extrap<NX, NU>), dim3(gp), dim3(256), 0, cs, pb, w, (const int *)d_wide);
           hipLaunchKernelGGL(k_wide_next, dim3(1), dim3(64), 0, cs, d_wide);
         }
       }
@@ -2601,8 +2630,6 @@ tadmm_status run_wide(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layout 
 
 template <int NX, int NU, bool DI>
 tadmm_status solve_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *out, void *ws, size_t bytes, int mode) {
-  if (ctx->prm.momentum && mode != TADMM_MODE_BATCHED)
-    return fail(ctx, TADMM_ERR_INVALID_ARG, "momentum runs in the batched mode");
   Layout L;
   if (!make_layout(&ctx->prm, b->n_scen, b->n_agents, b->horizon, L, ctx->err)) return TADMM_ERR_SHAPE;
   if (!ws || bytes < L.bytes) return fail(ctx, TADMM_ERR_WORKSPACE, "workspace missing or smaller than tadmm_workspace_size()");

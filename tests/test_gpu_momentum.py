@@ -2,7 +2,8 @@
 8, on the consensus block) on the device against the oracle's, through the
 C ABI.  Lockstep runs follow the oracle's iterates (including its restart
 decisions) to the parity bar; with frozen normals the momentum run converges
-to the oracle's solution of the same QP; the option's limits are errors.
+to the oracle's solution of the same QP; the three modes agree bitwise; the
+option's limits are errors.
 The derivative of a momentum solve is tested with the others
 (tests/test_gpu_adjoint.py)."""
 import sys
@@ -69,15 +70,25 @@ def test_momentum_frozen_limit_matches_oracle():
     assert rel <= gc.REL_TOL
 
 
+def test_momentum_modes_bitwise_equal():
+    """Plain (host loop, an extrapolation kernel after each test), batched
+    (the persistent kernel's momentum variant) and many-workgroup (an
+    extrapolation kernel in each captured iteration) agree bitwise."""
+    p, scs = synth.config2(S=10)
+    kw = dict(MOM, max_iter=100)
+    a = gc.gpu_solve(p, scs, mode=tadmm.MODE_PLAIN, solver_kw=kw)
+    for mode in (tadmm.MODE_BATCHED, tadmm.MODE_WIDE):
+        b = gc.gpu_solve(p, scs, mode=mode, solver_kw=kw)
+        for ga, gb in zip(a, b):
+            assert ga["iters"] == gb["iters"] and ga["status"] == gb["status"]
+            np.testing.assert_array_equal(ga["x"], gb["x"])
+
+
 def test_momentum_limits_are_errors():
     p, scs = synth.config0()
     pk = synth.pack(p, scs)
     solver = tadmm.Solver(tadmm.make_params(p, max_iter=50, **MOM))
     prep = solver.prepare(pk.n_agents, pk.horizon, pk.x0, pk.xref, pk.q_diag, pk.r_diag)
-    for mode in (tadmm.MODE_PLAIN, tadmm.MODE_WIDE):
-        with pytest.raises(tadmm.TadmmError) as e:
-            prep.run(mode)
-        assert "error 1" in str(e.value)
     with pytest.raises(tadmm.TadmmError) as e:
         prep.sqp(tadmm.MODE_BATCHED)
     assert "error 1" in str(e.value)
