@@ -101,7 +101,7 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 (the multi-GPU sharding is a design, not a run)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
