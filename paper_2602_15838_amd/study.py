@@ -207,9 +207,10 @@ def sqp_study(S: int = 4096, max_rounds: int = 10, rtol: float = 1e-4, sep_tol: 
 def rho_study(S: int = 4096) -> List[Dict]:
     """The benchmark's batch with the penalty fixed (rho = 1) and adapted by
     residual balancing (mu = 10, tau = 2, every iteration), each without and
-    with over-relaxation (alpha = 1.6), and with momentum (fast ADMM with
-    restart, eta = 0.999): converged fraction, mean iterations, refactored
-    stages and time."""
+    with over-relaxation (alpha = 1.6), with momentum (fast ADMM with
+    restart, eta = 0.999), with a velocity box, and with the shared dynamics
+    given per agent (the one-lane-per-agent local QP instead of the per-axis
+    split): converged fraction, mean iterations, refactored stages and time."""
     import torch
 
     import synth
@@ -218,10 +219,16 @@ def rho_study(S: int = 4096) -> List[Dict]:
     pk = synth.pack(problem, scs)
     recs = []
     adapt = dict(adaptive_rho=True, rho_mu=10.0, rho_tau=2.0, rho_every=1)
+    dyn = dict(agent_A=np.tile(problem.A.reshape(1, -1), (int(pk.n_agents.sum()), 1)),
+               agent_B=np.tile(problem.B.reshape(1, -1), (int(pk.n_agents.sum()), 1)))
     for name, kw in (("fixed", {}), ("adaptive", adapt), ("fixed, alpha 1.6", dict(alpha=1.6)),
-                     ("adaptive, alpha 1.6", dict(adapt, alpha=1.6)), ("momentum", dict(momentum=True))):
+                     ("adaptive, alpha 1.6", dict(adapt, alpha=1.6)), ("momentum", dict(momentum=True)),
+                     ("velocity box |v| <= 2", dict(state_box=True, s_lo=(-2.0, -2.0), s_hi=(2.0, 2.0))),
+                     ("shared dynamics given per agent (one lane per agent)", dict(per_agent=True))):
+        per_agent = kw.pop("per_agent", False)
         solver = tadmm.Solver(tadmm.make_params(problem, **kw))
-        prep = solver.prepare(pk.n_agents, pk.horizon, pk.x0, pk.xref, pk.q_diag, pk.r_diag)
+        prep = solver.prepare(pk.n_agents, pk.horizon, pk.x0, pk.xref, pk.q_diag, pk.r_diag,
+                              **(dyn if per_agent else {}))
         prep.run(tadmm.MODE_BATCHED)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
