@@ -152,3 +152,33 @@ def test_null_arguments():
     assert L.tadmm_solve(None, None, None, None, 0, 0) == 1
     assert L.tadmm_destroy(None) == 1
     assert L.tadmm_last_kernel_ms(None) == -1.0
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes structs have the header's sizes and field
+    offsets (a C program compiled against include/turboadmm.h prints them)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None or not os.path.isdir("/opt/rocm/include"):
+        pytest.skip("no C compiler or HIP headers")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    fields = {"tadmm_params": [n for n, _ in tadmm.Params._fields_],
+              "tadmm_batch": [n for n, _ in tadmm.Batch._fields_],
+              "tadmm_out": [n for n, _ in tadmm.Out._fields_]}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "turboadmm.h"', 'int main(void) {']
+    for st, names in fields.items():
+        lines.append(f'  printf("{st} %zu\\n", sizeof({st}));')
+        for n in names:
+            lines.append(f'  printf("{st}.{n} %zu\\n", offsetof({st}, {n}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", inc, "-I/opt/rocm/include", "-D__HIP_PLATFORM_AMD__", str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    got = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                              text=True).stdout.split("\n") if line)
+    for st, cls in (("tadmm_params", tadmm.Params), ("tadmm_batch", tadmm.Batch), ("tadmm_out", tadmm.Out)):
+        assert int(got[st]) == C.sizeof(cls), st
+        for n in fields[st]:
+            assert int(got[f"{st}.{n}"]) == getattr(cls, n).offset, (st, n)
