@@ -91,6 +91,7 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--block-threads", type=int, default=0)
+    ap.add_argument("--cpu-variant-sample", type=int, default=24)
     ap.add_argument("--profile-steps", action="store_true", help="print one line per step (for profiler runs)")
     ap.add_argument("--no-scale", action="store_true", help="skip the 3-D single-scenario (128 agents) line")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -232,6 +233,20 @@ def main():
                                          f"over scenarios, {dtc:.1f}s",
                                "agent_qp_solves_per_s": round(float((np.array([s.N for s in sub]) * oit).sum()) / dtc, 1)}
         print(f"# cpu oracle sample {len(ids)} scenarios in {dtc:.1f}s on {th} threads", file=sys.stderr, flush=True)
+        # the oracle on one core, and without its factor reuse (the CPU
+        # mirror of the hotstart), on a smaller sample of the same batch
+        vids = ids[:min(len(ids), args.cpu_variant_sample)]
+        vsub = [scs[i] for i in vids]
+        var = {"sample": f"scenarios 0..{len(vids) - 1} of the batch", "unit": "scenario solves/s"}
+        for name, thr, opts in (("threads_all_lu_reuse", th, oracle.OracleOptions()),
+                                ("threads_1_lu_reuse", 1, oracle.OracleOptions()),
+                                ("threads_all_no_lu_reuse", th, oracle.OracleOptions(lu_reuse=False))):
+            tv = time.perf_counter()
+            oracle.solve_batch(problem, vsub, opts, threads=thr)
+            var[name] = round(len(vids) / (time.perf_counter() - tv), 3)
+        var["threads_all"] = int(th)
+        out["cpu_oracle_variants"] = var
+        print(f"# cpu oracle variants on {len(vids)} scenarios: {var}", file=sys.stderr, flush=True)
 
     if not args.no_scale:
         # the 3-D scale workload: one scenario of 128 agents, T = 50 (8128 pairs
