@@ -1014,8 +1014,12 @@ __device__ void pair_agent_stage_impl(const Prob &pb, const WS &ws, const Scen &
         if (frozen) {
 #pragma unroll
           for (int c = 0; c < NU; ++c) np_[c] = n[c];
-        } else {
+        } else if (gold != 0.f) {
           pair_normal<NX, NU>(pb, ws, sc, i, j, t, qi, qj, np_);
+        } else {
+          // an inactive pair's dual is zero whatever its normal
+#pragma unroll
+          for (int c = 0; c < NU; ++c) np_[c] = 0.f;
         }
 #pragma unroll
         for (int c = 0; c < NU; ++c) lown[c] = -gold * np_[c];
