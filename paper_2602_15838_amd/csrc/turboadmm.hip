@@ -983,6 +983,9 @@ __device__ void pair_agent_stage_impl(const Prob &pb, const WS &ws, const Scen &
   const long long LS = (long long)sc.T * N * N;
   float *ob = REL ? ws.orx + 2LL * NU * sc.lo : nullptr;   // plane c at ob + c LS
   const float al = pb.alpha, bl = 1.0f - pb.alpha;
+  // squared distance beyond which an inactive pair cannot become active
+  // (a margin of 0.1% over d_min covers the rounding of the normal)
+  const float far2 = (1.001f * pb.dmin) * (1.001f * pb.dmin);
   for (int j0 = 0; j0 < np; j0 += kPB) {
     float gb[kPB], pjb[kPB][NU], qjb[kPB][NU];
     float Db[REL ? kPB : 1][NU], eb[REL ? kPB : 1][NU];
@@ -1005,6 +1008,25 @@ __device__ void pair_agent_stage_impl(const Prob &pb, const WS &ws, const Scen &
       const int j = jof(j0 + q);
       const float gold = gb[q];
       const float *pj = pjb[q], *qj = qjb[q];
+      if constexpr (!REL) {
+        // A pair that was inactive and is now clearly apart (the half-plane
+        // about the separation direction holds with room to spare) stays
+        // inactive: z_ij = C x_i and every dual term is zero, so only the
+        // copies' norm and the zero dual are recorded.
+        if (!frozen && gold == 0.f) {
+          float d2 = 0.f;
+#pragma unroll
+          for (int c = 0; c < NU; ++c) d2 = fmaf(pi[c] - pj[c], pi[c] - pj[c], d2);
+          if (d2 > far2) {
+#pragma unroll
+            for (int c = 0; c < NU; ++c) z2 = fmaf(pi[c], pi[c], z2);
+            const int li = gbase + j * N;
+            gm[li] = 0.f;
+            if (i < j) pa[li] = 0;
+            continue;
+          }
+        }
+      }
       float n[NU];
       pair_normal<NX, NU>(pb, ws, sc, i, j, t, pi, pj, n);
       // lambda_ij of the previous step, -gamma_prev n_prev
