@@ -231,6 +231,12 @@ typedef struct {
                                 step updates; batched mode also the time spent
                                 in the x-update, pair and test phases (ticks of
                                 the 100 MHz device clock, one workgroup), 0     */
+  float *hist;               /* [S][max_iter][2] or NULL: for every iteration k
+                                = 1..iters the primal and dual residual norms
+                                ||r||, ||s|| of its stopping test (Sec. V-A) at
+                                [s][k-1][0..1]; entries beyond the scenario's
+                                last iteration are left untouched.  With
+                                tadmm_sqp: the last round of each scenario      */
 } tadmm_out;
 
 typedef struct tadmm_ctx tadmm_ctx;

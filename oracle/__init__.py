@@ -247,11 +247,13 @@ def solve(problem, scenario, opts: Optional[OracleOptions] = None, normals=None,
 
 
 def solve_batch(problem, scenarios: Sequence, opts: Optional[OracleOptions] = None, threads: int = 0,
-                normals: Optional[List[np.ndarray]] = None, inputs=None) -> List[Dict[str, object]]:
-    """Independent scenarios, OpenMP over scenarios (dynamic schedule)."""
+                normals: Optional[List[np.ndarray]] = None, inputs=None,
+                keep_zl: bool = False) -> List[Dict[str, object]]:
+    """Independent scenarios, OpenMP over scenarios (dynamic schedule).
+    keep_zl: also return the consensus copies z and duals lambda."""
     opts = opts or OracleOptions()
     prm = make_params(problem, opts)
-    hs = [_Holder(problem, sc, opts, None if normals is None else normals[k], False,
+    hs = [_Holder(problem, sc, opts, None if normals is None else normals[k], keep_zl,
                   None if inputs is None else inputs[k]) for k, sc in enumerate(scenarios)]
     S = len(hs)
     scs = (_Scenario * max(S, 1))(*[h.sc for h in hs])

@@ -61,7 +61,8 @@ class Batch(C.Structure):
 class Out(C.Structure):
     _fields_ = [("x", C.c_void_p), ("u", C.c_void_p), ("w", C.c_void_p), ("pair_active", C.c_void_p),
                 ("status", C.c_void_p), ("iters", C.c_void_p), ("r_norm", C.c_void_p), ("s_norm", C.c_void_p),
-                ("eps_pri", C.c_void_p), ("eps_dual", C.c_void_p), ("counters", C.c_void_p)]
+                ("eps_pri", C.c_void_p), ("eps_dual", C.c_void_p), ("counters", C.c_void_p),
+                ("hist", C.c_void_p)]
 
 
 _lib = None
@@ -214,11 +215,12 @@ class Solver:
         return int(nb.value)
 
     def prepare(self, n_agents, horizon, x0, xref, q_diag, r_diag, normals=None, agent_q=None, agent_r=None,
-                agent_lo=None, agent_hi=None, agent_A=None, agent_B=None):
+                agent_lo=None, agent_hi=None, agent_A=None, agent_B=None, history: bool = False):
         """Allocate device inputs, outputs and the workspace for a batch.
         agent_q [A][nx], agent_r [A][nu], agent_lo / agent_hi [A][nu],
         agent_A [A][nx*nx], agent_B [A][nx*nu]: heterogeneous agents (each
-        optional)."""
+        optional).  history: also record the residual norms of every
+        iteration (output "hist" [S][max_iter][2])."""
         torch = self.torch
         N = np.ascontiguousarray(n_agents, dtype=np.int32)
         T = np.ascontiguousarray(horizon, dtype=np.int32)
@@ -250,7 +252,8 @@ class Solver:
                  status=torch.zeros(S, dtype=torch.int32, device=dev), iters=torch.zeros(S, dtype=torch.int32, device=dev),
                  r_norm=torch.zeros(S, device=dev), s_norm=torch.zeros(S, device=dev),
                  eps_pri=torch.zeros(S, device=dev), eps_dual=torch.zeros(S, device=dev),
-                 counters=torch.zeros(S, 8, dtype=torch.int64, device=dev))
+                 counters=torch.zeros(S, 8, dtype=torch.int64, device=dev),
+                 hist=(torch.zeros(S, int(self.params.max_iter), 2, device=dev) if history else None))
         nbytes = self.workspace_bytes(N, T)
         ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
         return Prepared(self, b, o, ws, nbytes)
@@ -272,7 +275,7 @@ class Prepared:
                            _ptr(b["agent_q"]), _ptr(b["agent_r"]), _ptr(b["agent_lo"]), _ptr(b["agent_hi"]),
                            _ptr(b["agent_A"]), _ptr(b["agent_B"]))
         self.out = Out(*[_ptr(o[k]) for k in ("x", "u", "w", "pair_active", "status", "iters", "r_norm", "s_norm",
-                                              "eps_pri", "eps_dual", "counters")])
+                                              "eps_pri", "eps_dual", "counters", "hist")])
 
     def run(self, mode: int = MODE_BATCHED):
         s = self.solver
@@ -392,7 +395,7 @@ TurboADMMFunction = _Lazy()
 def split_outputs(res: Dict, n_agents: Sequence[int], horizon: Sequence[int], nx: int, nu: int):
     """Per-scenario numpy views of a result: list of dicts with x [N][T+1][nx],
     u [N][T][nu], w, pair_active [P][T], status, iters."""
-    host = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in res.items()}
+    host = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in res.items() if v is not None}
     out = []
     xo = uo = po = 0
     for s, (N, T) in enumerate(zip(n_agents, horizon)):
@@ -406,6 +409,8 @@ def split_outputs(res: Dict, n_agents: Sequence[int], horizon: Sequence[int], nx
                  r_norm=float(host["r_norm"][s]), s_norm=float(host["s_norm"][s]),
                  eps_pri=float(host["eps_pri"][s]), eps_dual=float(host["eps_dual"][s]),
                  counters=host["counters"][s])
+        if "hist" in host:
+            d["hist"] = host["hist"][s, :d["iters"]]
         out.append(d)
         xo += N * (T + 1)
         uo += N * T

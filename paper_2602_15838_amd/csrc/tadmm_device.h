@@ -87,6 +87,8 @@ struct WS {
   // per scenario [a_k, c_(k-1), beta, restart]
   float *mom;
   float *momst;
+  // optional output: [S][max_iter][2] residual norms of every stopping test
+  float *hist;
   // inputs (caller layouts)
   const float *x0, *xref, *qd, *rd, *normals;
   const float *aq, *ar, *alo, *ahi;  // heterogeneous agents (each NULL: the shared value)

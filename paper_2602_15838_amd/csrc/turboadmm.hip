@@ -984,8 +984,10 @@ __device__ void pair_agent_stage_impl(const Prob &pb, const WS &ws, const Scen &
   float *ob = REL ? ws.orx + 2LL * NU * sc.lo : nullptr;   // plane c at ob + c LS
   const float al = pb.alpha, bl = 1.0f - pb.alpha;
   // squared distance beyond which an inactive pair cannot become active
-  // (a margin of 0.1% over d_min covers the rounding of the normal)
-  const float far2 = (1.001f * pb.dmin) * (1.001f * pb.dmin);
+  // (a margin of 0.1% over d_min covers the rounding of the normal); never
+  // below the distance at which the normal falls back to the references
+  // (unit_normal), whose half-plane does not follow the positions
+  const float far2 = fmaxf((1.001f * pb.dmin) * (1.001f * pb.dmin), 1e-12f);
   for (int j0 = 0; j0 < np; j0 += kPB) {
     float gb[kPB], pjb[kPB][NU], qjb[kPB][NU];
     float Db[REL ? kPB : 1][NU], eb[REL ? kPB : 1][NU];
@@ -1379,6 +1381,11 @@ __device__ int scenario_test(const Prob &pb, const WS &ws, const Scen &sc, int k
     else if (k >= pb.max_iter) { done = 1; }
     if (!cap_hit) {
       sn_out[SN_R] = rn; sn_out[SN_S] = sn; sn_out[SN_EPRI] = epri; sn_out[SN_EDUAL] = edual;
+      if (ws.hist) {
+        float *h = ws.hist + 2 * ((long long)sc.s * pb.max_iter + (k - 1));
+        h[0] = rn;
+        h[1] = sn;
+      }
     }
     st[ST_NEAR] = (rn <= pb.refine_band * epri && sn <= pb.refine_band * edual) ? 1 : 0;
     // residual balancing (Boyd et al. 2011, Sec. 3.4.1): the next iteration's
@@ -2462,6 +2469,7 @@ WS make_ws(const Layout &L, char *ws, const tadmm_batch *b) {
   w.orx = L.o_orx ? (float *)(ws + L.o_orx) : nullptr;
   w.mom = L.o_mom ? (float *)(ws + L.o_mom) : nullptr;
   w.momst = L.o_momst ? (float *)(ws + L.o_momst) : nullptr;
+  w.hist = nullptr;
   return w;
 }
 
@@ -2671,7 +2679,8 @@ tadmm_status solve_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *o
   tadmm_status st = stage_tables(ctx, L, b->n_agents, b->horizon, w8);
   if (st != TADMM_OK) return st;
   const Prob pb = to_prob(ctx->prm);
-  const WS w = make_ws(L, w8, b);
+  WS w = make_ws(L, w8, b);
+  w.hist = out->hist;
   int *d_flags = (int *)(w8 + L.o_flags);
   if (ctx->prm.check_inputs) {
     st = run_checks<NX, NU>(ctx, pb, w, L.S, d_flags);
@@ -2721,7 +2730,8 @@ tadmm_status sqp_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *out
   if (st != TADMM_OK) return st;
   Prob pb = to_prob(ctx->prm);
   pb.normal_mode = TADMM_NORMAL_FROZEN;
-  const WS w = make_ws(L, w8, b);
+  WS w = make_ws(L, w8, b);
+  w.hist = out->hist;
   int *d_flags = (int *)(w8 + L.o_flags);
   if (ctx->prm.check_inputs) {
     st = run_checks<NX, NU>(ctx, pb, w, L.S, d_flags);

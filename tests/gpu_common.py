@@ -15,7 +15,7 @@ REL_TOL = 1e-4
 MARGIN = 1e-5
 
 
-def gpu_solve(problem, scs, mode=None, normals=None, solver_kw=None, return_prep=False):
+def gpu_solve(problem, scs, mode=None, normals=None, solver_kw=None, return_prep=False, history=False):
     import paper_2602_15838_amd as tadmm
     mode = tadmm.MODE_BATCHED if mode is None else mode
     pk = synth.pack(problem, scs)
@@ -23,7 +23,7 @@ def gpu_solve(problem, scs, mode=None, normals=None, solver_kw=None, return_prep
     nrm = None if normals is None else np.concatenate([np.asarray(n).reshape(-1, problem.nu) for n in normals])
     prep = solver.prepare(pk.n_agents, pk.horizon, pk.x0, pk.xref, pk.q_diag, pk.r_diag, nrm, agent_q=pk.agent_q,
                           agent_r=pk.agent_r, agent_lo=pk.agent_lo, agent_hi=pk.agent_hi, agent_A=pk.agent_A,
-                          agent_B=pk.agent_B)
+                          agent_B=pk.agent_B, history=history)
     prep.run(mode)
     res = tadmm.split_outputs(prep.result(), pk.n_agents, pk.horizon, problem.nx, problem.nu)
     if return_prep:
@@ -60,7 +60,7 @@ def oracle_same_instance(problem, scs, opts, threads=0, keep_zl=False, normals=N
         return [oracle.solve(P32, scs[0], opts, normals=None if normals is None else normals[0],
                              threads=max(threads, 1), keep_zl=keep_zl, inputs=fp32_inputs(scs[0]))]
     return oracle.solve_batch(P32, scs, opts, threads=threads, normals=normals,
-                              inputs=[fp32_inputs(sc) for sc in scs])
+                              inputs=[fp32_inputs(sc) for sc in scs], keep_zl=keep_zl)
 
 
 def self_sensitivity(problem, sc, opts, rel=1e-7, seed=0, threads=1) -> float:
@@ -116,17 +116,22 @@ def working_set_marginal(problem, o) -> np.ndarray:
     return ((w != 0) & (np.abs(mu) < MARGIN * scale)) | ((w == 0) & near)
 
 
-def pair_marginal(problem, sc, o, rho) -> np.ndarray:
+def pair_marginal(problem, sc, o, rho, normals=None) -> np.ndarray:
     """Half-planes whose violation v at the last consensus step is tiny:
-    active: v = 2|lambda_ij|/rho; inactive: v = d_min - n'(z_ij - z_ji)."""
+    active: v = 2|lambda_ij|/rho; inactive: v = d_min - n'(z_ij - z_ji), with
+    n the frozen normals [P][T][dp] when given, else those of the final
+    positions."""
     N, T = sc.N, sc.T
     x, z, lam = o["x"], o["z"], o["lam"]
     out = np.zeros((N * (N - 1) // 2, T), dtype=bool)
     p = 0
     for i in range(N):
         for j in range(i + 1, N):
-            d = x[i, 1:, :problem.dp] - x[j, 1:, :problem.dp]
-            n = d / np.maximum(np.linalg.norm(d, axis=1, keepdims=True), 1e-300)
+            if normals is not None:
+                n = normals[p]
+            else:
+                d = x[i, 1:, :problem.dp] - x[j, 1:, :problem.dp]
+                n = d / np.maximum(np.linalg.norm(d, axis=1, keepdims=True), 1e-300)
             act = o["pair_active"][p].astype(bool)
             v_act = 2.0 * np.linalg.norm(lam[i, j], axis=1) / rho
             v_in = problem.d_min - np.sum(n * (z[i, j] - z[j, i]), axis=1)
@@ -136,7 +141,7 @@ def pair_marginal(problem, sc, o, rho) -> np.ndarray:
     return out
 
 
-def compare(problem, sc, g, o, rho=None, check_sets=True, tol=REL_TOL):
+def compare(problem, sc, g, o, rho=None, check_sets=True, tol=REL_TOL, normals=None):
     """Assert parity of one scenario; returns a small report dict."""
     rho = problem.rho if rho is None else rho
     rel = rel_traj_err(g, o)
@@ -150,8 +155,31 @@ def compare(problem, sc, g, o, rho=None, check_sets=True, tol=REL_TOL):
         assert not diff.any(), f"N={sc.N} T={sc.T}: working sets differ at {np.argwhere(diff)[:5].tolist()}"
         rep["w_marginal"] = int(wm.sum())
         if "z" in o and sc.N > 1:
-            pm = pair_marginal(problem, sc, o, rho)
+            pm = pair_marginal(problem, sc, o, rho, normals)
             pdiff = (g["pair_active"] != o["pair_active"]) & ~pm
             assert not pdiff.any(), f"N={sc.N} T={sc.T}: active half-planes differ at {np.argwhere(pdiff)[:5].tolist()}"
             rep["pair_marginal"] = int(pm.sum())
     return rep
+
+
+def compare_history(g, o, frac_eps=0.05, rel=1e-3):
+    """Per-iteration residual norms of the stopping test (Sec. V-A), device
+    against oracle: |r_g - r_o| <= frac_eps * eps_pri + rel * r_o and the
+    same for s, at every iteration both sides ran.  The stopping decision
+    compares r with eps_pri, so an agreement to a small fraction of eps_pri
+    makes the two decisions the same except at a near tie; FP32 positions of
+    magnitude |p| carry an absolute rounding of about 6e-8 |p| per entry,
+    far below 5% of eps_pri >= 1e-4 sqrt(rows).  Returns the worst ratios."""
+    K = min(len(g["hist"]), len(o["hist"]))
+    assert K >= 1
+    hg = np.asarray(g["hist"][:K], dtype=np.float64)
+    ho = np.asarray(o["hist"][:K])
+    worst = [0.0, 0.0]
+    for q, eps_col in ((0, 2), (1, 3)):
+        bar = frac_eps * ho[:, eps_col] + rel * ho[:, q]
+        ratio = np.abs(hg[:, q] - ho[:, q]) / bar
+        worst[q] = float(ratio.max())
+        bad = np.nonzero(ratio > 1.0)[0]
+        assert bad.size == 0, (f"residual {'rs'[q]} differs at iteration {int(bad[0]) + 1}: "
+                               f"gpu {hg[bad[0], q]:.6e} oracle {ho[bad[0], q]:.6e} eps {ho[bad[0], eps_col]:.3e}")
+    return worst

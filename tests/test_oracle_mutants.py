@@ -51,6 +51,15 @@ MUTANTS = {
                                                 "memcpy(zh, z, zsz * sizeof(double));"),
     "relaxation_dual_update_unrelaxed": ("lam[ZI(i, j, t) + c] += rho * (xi[c] - a[c]);",
                                          "lam[ZI(i, j, t) + c] += rho * (pi[c] - a[c]);"),
+    "fallback_normal_rot90_sign": ("if (dp == 2) { c[0] = -v[1]; c[1] = v[0]; }",
+                                   "if (dp == 2) { c[0] = v[1]; c[1] = -v[0]; }"),
+    "fallback_normal_cross_axis_of_the_largest_component": (
+        "for (int k = 1; k < 3; ++k) if (fabs(v[k]) < fabs(v[kmin])) kmin = k;",
+        "for (int k = 1; k < 3; ++k) if (fabs(v[k]) > fabs(v[kmin])) kmin = k;"),
+    "fallback_normal_ties_to_the_highest_axis": (
+        "for (int k = 1; k < 3; ++k) if (fabs(v[k]) < fabs(v[kmin])) kmin = k;",
+        "for (int k = 1; k < 3; ++k) if (fabs(v[k]) <= fabs(v[kmin])) kmin = k;"),
+    "fallback_normal_e2_without_relative_motion": ("n[k] = (k == 0) ? 1.0 : 0.0;", "n[k] = (k == 1) ? 1.0 : 0.0;"),
     "relaxation_weights_swapped": ("prm->alpha * pi[c] + (1.0 - prm->alpha) * z[ZI(i, j, t) + c]",
                                    "(1.0 - prm->alpha) * pi[c] + prm->alpha * z[ZI(i, j, t) + c]"),
 }
@@ -83,7 +92,13 @@ PIN_FUNCS = [pins.test_agent_qp_unconstrained_matches_condensed_least_squares,
              pins.test_admm_relaxation_closed_form_far_apart,
              pins.test_admm_momentum_closed_form_far_apart,
              pins.test_admm_momentum_frozen_limit_is_the_same_kkt_point,
-             pins.test_admm_relaxation_frozen_limit_is_the_same_kkt_point]
+             pins.test_admm_relaxation_frozen_limit_is_the_same_kkt_point,
+             pins.test_fallback_normal_2d_turns_the_relative_velocity_counterclockwise,
+             pins.test_fallback_normal_3d_crosses_the_smallest_velocity_axis,
+             pins.test_fallback_normal_3d_ties_go_to_the_lowest_axis,
+             pins.test_fallback_normal_is_e1_without_relative_motion,
+             pins.test_fallback_normal_reference_position_first,
+             pins.test_frozen_reference_normals_of_an_exact_swap_use_the_velocity_rule]
 
 
 def _call_pin(fn):

@@ -422,6 +422,143 @@ def test_admm_frozen_limit_matches_slsqp():
     assert fun(res["u"].reshape(-1)) <= fun(sol.x) * (1 + 1e-9)
 
 
+# ---------------------------------------------------------------------------
+# The fallback normal of two coincident positions (Sec. III-A linearization;
+# the reading: the reference relative position, else the relative reference
+# velocity turned by 90 degrees (2-D) or crossed with the axis of its smallest
+# component (3-D, ties to the lowest axis), else e_1).  Each case fixes the
+# normal by geometric properties that determine it uniquely (unit length,
+# perpendicularity, orientation), not by the oracle's formula.
+# ---------------------------------------------------------------------------
+
+def _coincident_refs(rng, N, T, dp, vel):
+    """References of N agents whose positions all coincide at every step (so
+    the reference relative position is zero) with per-agent velocities vel
+    [N][dp]; the linearization point x is the references themselves."""
+    xr = np.zeros((N, T + 1, 2 * dp))
+    base = rng.normal(size=(T + 1, dp))
+    xr[:, :, :dp] = base[None]
+    xr[:, :, dp:] = vel[:, None, :]
+    return xr
+
+
+def _fallback_normals(dp, vel, T=3, seed=0):
+    p = synth.ProblemParams(dp=dp, u_max=2.0)
+    N = vel.shape[0]
+    xr = _coincident_refs(np.random.default_rng(seed), N, T, dp, vel)
+    sc = synth.Scenario(starts=xr[:, 0, :dp].copy(), goals=xr[:, -1, :dp].copy(), T=T)
+    x0 = xr[:, 0, :].copy()
+    return p, oracle.relinearize(p, sc, xr, inputs=(x0, xr))
+
+
+def test_fallback_normal_2d_turns_the_relative_velocity_counterclockwise():
+    """Coincident positions and coincident references, distinct reference
+    velocities: n is the unit vector perpendicular to dv = v_i - v_j with
+    det[dv, n] > 0 (dv turned counter-clockwise), the same at every step."""
+    rng = np.random.default_rng(21)
+    vel = rng.normal(size=(5, 2)) * 3.0
+    p, n = _fallback_normals(2, vel)
+    k = 0
+    for i in range(5):
+        for j in range(i + 1, 5):
+            dv = vel[i] - vel[j]
+            for t in range(n.shape[1]):
+                m = n[k, t]
+                assert np.linalg.norm(m) == pytest.approx(1.0, abs=1e-14)
+                assert abs(m @ dv) <= 1e-13 * np.linalg.norm(dv)
+                assert dv[0] * m[1] - dv[1] * m[0] > 0.5 * np.linalg.norm(dv)
+            k += 1
+
+
+def test_fallback_normal_3d_crosses_the_smallest_velocity_axis():
+    """3-D: n is perpendicular to dv and to e_k, k the axis of the smallest
+    |dv_k|, unit, with det[dv, e_k, n] > 0 (n along dv x e_k)."""
+    rng = np.random.default_rng(22)
+    vel = rng.normal(size=(6, 3)) * 2.0
+    p, n = _fallback_normals(3, vel)
+    k = 0
+    for i in range(6):
+        for j in range(i + 1, 6):
+            dv = vel[i] - vel[j]
+            kmin = int(np.argmin(np.abs(dv)))
+            assert np.sort(np.abs(dv))[1] > np.abs(dv)[kmin] * (1 + 1e-9)   # no tie here
+            e = np.eye(3)[kmin]
+            for t in range(n.shape[1]):
+                m = n[k, t]
+                assert np.linalg.norm(m) == pytest.approx(1.0, abs=1e-14)
+                assert abs(m @ dv) <= 1e-13 * np.linalg.norm(dv)
+                assert m[kmin] == 0.0
+                assert np.linalg.det(np.stack([dv, e, m])) > 0.0
+            k += 1
+
+
+def test_fallback_normal_3d_ties_go_to_the_lowest_axis():
+    """dv = (0, 0, c): axes 0 and 1 tie at |dv_k| = 0, axis 0 wins, so n is
+    perpendicular to e_0 and dv: n = sign(c) e_1 by the orientation rule;
+    dv = (a, a, b) with |b| > |a|: axis 0, n = sign(...) in the plane
+    perpendicular to e_0 and dv."""
+    vel = np.array([[0.0, 0.0, 1.5], [0.0, 0.0, 0.0], [0.7, 0.7, -2.0], [0.0, 0.0, 0.0]])
+    p, n = _fallback_normals(3, vel)
+    # pair (0, 1): dv = (0, 0, 1.5)
+    np.testing.assert_allclose(n[0, 0], [0.0, 1.0, 0.0], atol=1e-15)
+    # pair (2, 3) (index 5 of 6): dv = (0.7, 0.7, -2); axis 0 (tie with 1)
+    dv = vel[2] - vel[3]
+    m = n[5, 0]
+    assert m[0] == 0.0 and abs(m @ dv) <= 1e-14
+    assert np.linalg.det(np.stack([dv, np.eye(3)[0], m])) > 0.0
+
+
+@pytest.mark.parametrize("dp", [2, 3])
+def test_fallback_normal_is_e1_without_relative_motion(dp):
+    """Coincident positions, references and reference velocities: e_1."""
+    vel = np.tile(np.array([[0.3, -1.2, 0.8][:dp]]), (3, 1))
+    p, n = _fallback_normals(dp, vel)
+    e1 = np.eye(dp)[0]
+    for k in range(3):
+        np.testing.assert_array_equal(n[k], np.tile(e1, (n.shape[1], 1)))
+
+
+def test_fallback_normal_reference_position_first():
+    """References apart at a step, positions coincident: the normalized
+    reference relative position r_i - r_j (not the velocity rule)."""
+    rng = np.random.default_rng(23)
+    dp, N, T = 3, 4, 4
+    vel = rng.normal(size=(N, dp))
+    xr = _coincident_refs(rng, N, T, dp, vel)
+    xr[:, 2, :dp] += rng.normal(size=(N, dp))          # step 2: references apart
+    p = synth.ProblemParams(dp=dp, u_max=2.0)
+    sc = synth.Scenario(starts=xr[:, 0, :dp].copy(), goals=xr[:, -1, :dp].copy(), T=T)
+    x = xr.copy()
+    x[:, :, :dp] = 0.0                                     # every position coincident
+    n = oracle.relinearize(p, sc, x, inputs=(xr[:, 0, :].copy(), xr))
+    k = 0
+    for i in range(N):
+        for j in range(i + 1, N):
+            d = xr[i, 2, :dp] - xr[j, 2, :dp]
+            assert n[k, 1] @ d == pytest.approx(np.linalg.norm(d), rel=1e-13)
+            assert np.linalg.norm(n[k, 1]) == pytest.approx(1.0, abs=1e-14)
+            k += 1
+
+
+def test_frozen_reference_normals_of_an_exact_swap_use_the_velocity_rule():
+    """The unjittered two-agent swap (both references pass the origin at
+    t = T/2): a frozen solve with the oracle's own reference normals equals
+    one given the normals of the linearization at the references, and the
+    mid-horizon normal is perpendicular to the swap axis."""
+    p = synth.ProblemParams(dp=2, u_max=2.0)
+    sc = synth.circle_swap(2, 3.0, 20, 0.0, None)
+    xr = sc.xref()
+    assert np.all(xr[0, 10, :2] == xr[1, 10, :2])
+    n = oracle.relinearize(p, sc, xr)
+    dv = xr[0, 10, 2:] - xr[1, 10, 2:]
+    assert abs(n[0, 9] @ dv) <= 1e-12 and dv[0] * n[0, 9, 1] - dv[1] * n[0, 9, 0] > 0
+    o = oracle.OracleOptions(normal_mode=oracle.NORMAL_FROZEN, max_iter=80)
+    a = oracle.solve(p, sc, o)
+    b = oracle.solve(p, sc, o, normals=n)
+    np.testing.assert_array_equal(a["x"], b["x"])
+    np.testing.assert_array_equal(a["pair_active"], b["pair_active"])
+
+
 def test_admm_point_symmetry():
     """Point-symmetric data and normal e_y: the solution is point symmetric,
     p_1(t) = -p_0(t), which checks the pair indexing and the signs of the
