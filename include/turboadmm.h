@@ -258,6 +258,25 @@ tadmm_status tadmm_create(tadmm_ctx **ctx, const tadmm_params *params, void *str
 tadmm_status tadmm_solve(tadmm_ctx *ctx, const tadmm_batch *batch, const tadmm_out *out, void *workspace,
                          size_t workspace_bytes, int32_t mode);
 
+/* tadmm_solve() for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same solve, in TADMM_MODE_PLAIN or TADMM_MODE_BATCHED, with the
+ * workspace taken from a static device array of the library instead of the
+ * caller.  The array holds 64 MiB (TADMM_NOALLOC_WORKSPACE_BYTES) per device,
+ * from the library's load until the process ends; a batch whose
+ * tadmm_workspace_size() exceeds it returns TADMM_ERR_WORKSPACE.  The call
+ * makes no device or pinned-host allocation: the batched mode launches its
+ * kernels directly on the context's stream (no graph), the scenario tables
+ * are copied from ordinary host memory, and every region the solve reads is
+ * initialized by the solve itself.  Every call on a device shares that
+ * device's array, so calls that overlap in time on one device (two host
+ * threads, or two streams) race and corrupt each other's results; serialize
+ * them.  tadmm_polish() / tadmm_adjoint() do not follow this call
+ * (TADMM_ERR_STATE): they need the caller-owned workspace of tadmm_solve().
+ * Errors: as tadmm_solve(); TADMM_ERR_INVALID_ARG for TADMM_MODE_WIDE. */
+#define TADMM_NOALLOC_WORKSPACE_BYTES (64u << 20)
+tadmm_status tadmm_solve_noalloc(tadmm_ctx *ctx, const tadmm_batch *batch, const tadmm_out *out, int32_t mode);
+
 /* The derivative of a converged solve (an extension: the paper defines the
  * solve, not its derivative).  The solution of the last tadmm_solve() on this
  * context is read as the solution of the centralized QP (Sec. III-A, Eq. 1)

@@ -82,6 +82,8 @@ def lib():
         L.tadmm_create.argtypes = [C.POINTER(vp), C.POINTER(Params), vp]
         L.tadmm_solve.restype = C.c_int
         L.tadmm_solve.argtypes = [vp, C.POINTER(Batch), C.POINTER(Out), vp, C.c_size_t, C.c_int32]
+        L.tadmm_solve_noalloc.restype = C.c_int
+        L.tadmm_solve_noalloc.argtypes = [vp, C.POINTER(Batch), C.POINTER(Out), C.c_int32]
         L.tadmm_polish.restype = C.c_int
         L.tadmm_polish.argtypes = [vp, C.POINTER(Batch), C.POINTER(Out), vp, C.c_size_t, vp]
         L.tadmm_adjoint.restype = C.c_int
@@ -105,7 +107,8 @@ def lib():
     return _lib
 
 
-EXPORTED_SYMBOLS = ("tadmm_workspace_size", "tadmm_create", "tadmm_solve", "tadmm_sqp", "tadmm_polish",
+EXPORTED_SYMBOLS = ("tadmm_workspace_size", "tadmm_create", "tadmm_solve", "tadmm_solve_noalloc", "tadmm_sqp",
+                    "tadmm_polish",
                     "tadmm_adjoint", "tadmm_autotune",
                     "tadmm_last_kernel_ms", "tadmm_destroy", "tadmm_status_string", "tadmm_last_error",
                     "tadmm_version")
@@ -281,6 +284,14 @@ class Prepared:
         s = self.solver
         rc = lib().tadmm_solve(s._h, C.byref(self.batch), C.byref(self.out), C.c_void_p(self.ws.data_ptr()),
                                C.c_size_t(self.nbytes), int(mode))
+        s._check(rc)
+        return lib().tadmm_last_kernel_ms(s._h)
+
+    def run_noalloc(self, mode: int = MODE_BATCHED):
+        """The same solve through tadmm_solve_noalloc (the library's static
+        workspace instead of self.ws; nothing is allocated by the call)."""
+        s = self.solver
+        rc = lib().tadmm_solve_noalloc(s._h, C.byref(self.batch), C.byref(self.out), int(mode))
         s._check(rc)
         return lib().tadmm_last_kernel_ms(s._h)
 

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -2145,9 +2146,37 @@ __global__ void k_writeback(WS ws, int S, tadmm_out out) {
 // ===========================================================================
 // Host library
 // ===========================================================================
+
+// The workspace of tadmm_solve_noalloc(): a fixed device array, one per GPU
+// (each device that loads the library holds its own copy until the process
+// ends).  Host code never passes its name to a kernel: the name is a host-side
+// stand-in, and the device address comes from hipGetSymbolAddress, resolved
+// once per device when a context is created on it.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 namespace {
 
 using namespace tadmm;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device `dev` (the current device).
+hipError_t scratch_address(int dev, void **ptr) {
+  *ptr = nullptr;
+  if (dev < 0 || dev >= kMaxDevices) return hipSuccess;   // no static workspace on this device
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -2403,6 +2432,7 @@ struct tadmm_ctx {
   GraphKey wkey{};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   float last_ms = -1.f;
+  void *scratch = nullptr;           // device address of this device's static workspace
   // derivative bookkeeping: the last successful solve and its polish
   bool solved = false, polished = false;
   const void *solved_ws = nullptr;
@@ -2427,7 +2457,18 @@ tadmm_status fail(tadmm_ctx *ctx, tadmm_status s, const std::string &msg) {
   return s;
 }
 
-tadmm_status stage_tables(tadmm_ctx *ctx, const Layout &L, const int32_t *N, const int32_t *T, char *ws) {
+tadmm_status stage_tables(tadmm_ctx *ctx, const Layout &L, const int32_t *N, const int32_t *T, char *ws,
+                          bool noalloc = false) {
+  if (noalloc) {
+    // straight from the caller's and the layout's host arrays (no staging
+    // buffer); they outlive the solve, which synchronizes the stream
+    HIPCHK(hipMemcpyAsync(ws + L.o_N, N, sizeof(int) * L.S, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ws + L.o_T, T, sizeof(int) * L.S, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ws + L.o_tab, L.tab.data(), sizeof(long long) * L.S * TB_NCOL, hipMemcpyHostToDevice,
+                          ctx->stream));
+    HIPCHK(hipMemcpyAsync(ws + L.o_order, L.order.data(), sizeof(int) * L.S, hipMemcpyHostToDevice, ctx->stream));
+    return TADMM_OK;
+  }
   const size_t need = L.o_order + sizeof(int) * std::max(L.S, 1);
   if (ctx->h_stage_bytes < need) {
     if (ctx->h_stage) HIPCHK(hipHostFree(ctx->h_stage));
@@ -2518,7 +2559,7 @@ tadmm_status run_plain(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layout
 
 template <int NX, int NU, bool DI>
 tadmm_status run_batched(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layout &L, const tadmm_batch *b,
-                         const tadmm_out &out, void *ws, size_t bytes, int variant = 0) {
+                         const tadmm_out &out, void *ws, size_t bytes, int variant = 0, bool direct = false) {
   const int threads = ctx->prm.block_threads ? ctx->prm.block_threads : ctx->tuned_threads;
   // LDS for the positions of the largest scenario, up to 32 KB per workgroup
   // (larger scenarios read positions from global memory)
@@ -2538,15 +2579,9 @@ tadmm_status run_batched(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layo
   key.normals = w.normals; key.S = L.S; key.threads = threads; key.grid = grid; key.bytes = bytes; key.prm = ctx->prm;
   key.aq = w.aq; key.ar = w.ar; key.alo = w.alo; key.ahi = w.ahi; key.aA = w.aA; key.aB = w.aB;
   key.variant = variant;
-  if (!(ctx->gexec && key == ctx->key)) {
-    if (ctx->gexec) { (void)hipGraphExecDestroy(ctx->gexec); ctx->gexec = nullptr; }
-    if (ctx->graph) { (void)hipGraphDestroy(ctx->graph); ctx->graph = nullptr; }
-    // Captured on the context's private stream (the caller's stream may be the
-    // legacy default stream, which cannot be captured); launched on the
-    // caller's stream below.
-    hipStream_t cs = ctx->cap_stream;
-    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    // counters and the queue are cleared by fill kernels (no memset nodes)
+  // the launches of one solve: counters and the queue are cleared by fill
+  // kernels (no memset nodes), then the persistent kernel and the write-back
+  auto launch = [&](hipStream_t cs) -> hipError_t {
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, cs, w.queue, 1, 0);
     const long long nc = (long long)L.S * CT_NCOL;
     if (!pb.cont)   // a continuing SQP round keeps counting
@@ -2557,8 +2592,28 @@ tadmm_status run_batched(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layo
     void *args[] = {&kpb, &kw, &kS, &klds};
     const hipError_t lk = hipLaunchKernel(kfn, dim3(grid), dim3(threads), args, lds_bytes, cs);
     hipLaunchKernelGGL((k_writeback<NX, NU>), dim3(std::min(L.S, 4096)), dim3(256), 0, cs, w, L.S, out);
-    hipError_t le = hipGetLastError();
-    if (le == hipSuccess) le = lk;
+    const hipError_t le = hipGetLastError();
+    return le != hipSuccess ? le : lk;
+  };
+  if (direct) {
+    // no graph (its instantiation may allocate): the launches straight on the
+    // caller's stream
+    HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
+    HIPCHK(launch(ctx->stream));
+    HIPCHK(hipEventRecord(ctx->ev1, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipEventElapsedTime(&ctx->last_ms, ctx->ev0, ctx->ev1));
+    return TADMM_OK;
+  }
+  if (!(ctx->gexec && key == ctx->key)) {
+    if (ctx->gexec) { (void)hipGraphExecDestroy(ctx->gexec); ctx->gexec = nullptr; }
+    if (ctx->graph) { (void)hipGraphDestroy(ctx->graph); ctx->graph = nullptr; }
+    // Captured on the context's private stream (the caller's stream may be the
+    // legacy default stream, which cannot be captured); launched on the
+    // caller's stream below.
+    hipStream_t cs = ctx->cap_stream;
+    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    const hipError_t le = launch(cs);
     hipError_t ce = hipStreamEndCapture(cs, &ctx->graph);
     if (le != hipSuccess || ce != hipSuccess) {
       ctx->err = std::string("graph capture failed: ") + hipGetErrorString(le != hipSuccess ? le : ce);
@@ -2662,10 +2717,21 @@ tadmm_status run_wide(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layout 
   return TADMM_OK;
 }
 
+// noalloc: the workspace is the device's static array (ws, bytes), the
+// tables go straight from host arrays, the batched mode launches without a
+// graph and the wide mode (graphs) is not offered.
 template <int NX, int NU, bool DI>
-tadmm_status solve_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *out, void *ws, size_t bytes, int mode) {
+tadmm_status solve_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *out, void *ws, size_t bytes, int mode,
+                        bool noalloc = false) {
   Layout L;
   if (!make_layout(&ctx->prm, b->n_scen, b->n_agents, b->horizon, L, ctx->err)) return TADMM_ERR_SHAPE;
+  if (noalloc && mode != TADMM_MODE_PLAIN && mode != TADMM_MODE_BATCHED)
+    return fail(ctx, TADMM_ERR_INVALID_ARG, "tadmm_solve_noalloc takes TADMM_MODE_PLAIN or TADMM_MODE_BATCHED");
+  if (noalloc && !ws) return fail(ctx, TADMM_ERR_WORKSPACE, "no static workspace on this device");
+  if (noalloc && L.bytes > bytes)
+    return fail(ctx, TADMM_ERR_WORKSPACE, "batch needs " + std::to_string(L.bytes) +
+                                              " bytes of workspace; the static workspace of tadmm_solve_noalloc holds " +
+                                              std::to_string(bytes));
   if (!ws || bytes < L.bytes) return fail(ctx, TADMM_ERR_WORKSPACE, "workspace missing or smaller than tadmm_workspace_size()");
   if (((uintptr_t)ws) % kAlign) return fail(ctx, TADMM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   ctx->solved = false;
@@ -2676,7 +2742,7 @@ tadmm_status solve_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *o
   if (!b->agent_lo != !b->agent_hi) return fail(ctx, TADMM_ERR_INVALID_ARG, "agent_lo and agent_hi: both or neither");
   if (!b->agent_A != !b->agent_B) return fail(ctx, TADMM_ERR_INVALID_ARG, "agent_A and agent_B: both or neither");
   char *w8 = (char *)ws;
-  tadmm_status st = stage_tables(ctx, L, b->n_agents, b->horizon, w8);
+  tadmm_status st = stage_tables(ctx, L, b->n_agents, b->horizon, w8, noalloc);
   if (st != TADMM_OK) return st;
   const Prob pb = to_prob(ctx->prm);
   WS w = make_ws(L, w8, b);
@@ -2687,10 +2753,11 @@ tadmm_status solve_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *o
     if (st != TADMM_OK) return st;
   }
   if (mode == TADMM_MODE_PLAIN) st = run_plain<NX, NU, DI>(ctx, pb, w, L, b->n_agents, b->horizon, d_flags, *out);
-  else if (mode == TADMM_MODE_BATCHED) st = run_batched<NX, NU, DI>(ctx, pb, w, L, b, *out, ws, bytes);
+  else if (mode == TADMM_MODE_BATCHED) st = run_batched<NX, NU, DI>(ctx, pb, w, L, b, *out, ws, bytes, 0, noalloc);
   else if (mode == TADMM_MODE_WIDE) st = run_wide<NX, NU, DI>(ctx, pb, w, L, b, *out, ws, bytes);
   else return fail(ctx, TADMM_ERR_INVALID_ARG, "unknown mode");
   if (st != TADMM_OK) return st;
+  if (noalloc) return TADMM_OK;   // the derivative needs a caller-owned workspace
   ctx->solved = true;
   ctx->solved_ws = ws;
   ctx->solved_bytes = bytes;
@@ -2902,8 +2969,9 @@ tadmm_status tadmm_create(tadmm_ctx **pctx, const tadmm_params *params, void *st
   if (e == hipSuccess) e = hipEventCreate(&ctx->ev0);
   if (e == hipSuccess) e = hipEventCreate(&ctx->ev1);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = scratch_address(ctx->device, &ctx->scratch);
   if (e != hipSuccess) {
-    delete ctx;
+    (void)tadmm_destroy(ctx);
     return TADMM_ERR_HIP;
   }
   *pctx = ctx;
@@ -2938,6 +3006,22 @@ tadmm_status tadmm_solve(tadmm_ctx *ctx, const tadmm_batch *batch, const tadmm_o
               : solve_impl<4, 2, false>(ctx, batch, out, workspace, workspace_bytes, mode);
   return di ? solve_impl<6, 3, true>(ctx, batch, out, workspace, workspace_bytes, mode)
             : solve_impl<6, 3, false>(ctx, batch, out, workspace, workspace_bytes, mode);
+}
+
+tadmm_status tadmm_solve_noalloc(tadmm_ctx *ctx, const tadmm_batch *batch, const tadmm_out *out, int32_t mode) {
+  if (!ctx) return TADMM_ERR_INVALID_ARG;
+  if (!batch || !out) return fail(ctx, TADMM_ERR_INVALID_ARG, "batch / out is NULL");
+  ctx->err.clear();
+  ctx->solved = false;
+  ctx->polished = false;
+  const bool di = is_double_integrator(ctx->prm, batch);
+  void *ws = ctx->scratch;
+  const size_t bytes = kStaticScratchBytes;
+  if (ctx->prm.nx == 4)
+    return di ? solve_impl<4, 2, true>(ctx, batch, out, ws, bytes, mode, true)
+              : solve_impl<4, 2, false>(ctx, batch, out, ws, bytes, mode, true);
+  return di ? solve_impl<6, 3, true>(ctx, batch, out, ws, bytes, mode, true)
+            : solve_impl<6, 3, false>(ctx, batch, out, ws, bytes, mode, true);
 }
 
 tadmm_status tadmm_sqp(tadmm_ctx *ctx, const tadmm_batch *batch, const tadmm_out *out, void *workspace,
