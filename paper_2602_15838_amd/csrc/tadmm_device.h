@@ -51,7 +51,7 @@ struct Prob {
 };
 
 // Per-scenario table columns (int64).
-enum { TB_F = 0, TB_B, TB_L, TB_A, TB_XO, TB_UO, TB_PO, TB_LB, TB_D, TB_NCOL };
+enum { TB_F = 0, TB_B, TB_L, TB_A, TB_XO, TB_UO, TB_PO, TB_D, TB_NCOL };
 // Per-scenario int32 state columns.
 // ST_COLD: a continuing SQP round restarts the duals (the previous round did
 // not converge); written by the round's bookkeeping, read by the setup.
@@ -73,7 +73,7 @@ struct WS {
   int8_t *wr;                        // working-set regions  [NU][N(T+1)] per scenario
   int *adirty;                       // [agents][nu] highest stale factor stage of each local QP (-1: none)
   float *gam;                        // [T][N][N] per scenario: gamma of ordered copy (i, j) at [t][j][i]
-  uint8_t *pact;                     // [T][N][N] per scenario
+                                     // (> 0 exactly where the half-plane was violated)
   int *sst;                          // [S][ST_NCOL]
   float *snorm;                      // [S][SN_NCOL]
   unsigned long long *cnt;           // [S][CT_NCOL]
@@ -169,7 +169,7 @@ __device__ __forceinline__ float wave_sum(float v) {
 
 struct Scen {
   int s, N, T, GS;
-  long long fo, bo, lo, ao, xo, uo, po, lb, dof;
+  long long fo, bo, lo, ao, xo, uo, po, dof;
 };
 
 // Scenario descriptors are wave-uniform; readfirstlane tells the compiler so
@@ -190,7 +190,7 @@ __device__ __forceinline__ Scen load_scen(const WS &ws, int s) {
   sc.GS = sc.N * (sc.T + 1);
   const long long *tb = ws.tab + (long long)sc.s * TB_NCOL;
   sc.fo = uni64(tb[TB_F]); sc.bo = uni64(tb[TB_B]); sc.lo = uni64(tb[TB_L]); sc.ao = uni64(tb[TB_A]);
-  sc.xo = uni64(tb[TB_XO]); sc.uo = uni64(tb[TB_UO]); sc.po = uni64(tb[TB_PO]); sc.lb = uni64(tb[TB_LB]);
+  sc.xo = uni64(tb[TB_XO]); sc.uo = uni64(tb[TB_UO]); sc.po = uni64(tb[TB_PO]);
   sc.dof = uni64(tb[TB_D]);
   return sc;
 }

@@ -346,7 +346,6 @@ __device__ void eqp_freeze(const Prob &pb, const WS &ws, const EWS &ew, const Sc
   int2 *cl = ew.clist + sc.po;
   double *nu = ew.cg + 6 * sc.po;
   const float *gm = ws.gam + sc.lo;
-  const uint8_t *pa = ws.pact + sc.lb;
   const int per = (TP + nth - 1) / nth;
   const int q0 = min(TP, tid * per), q1 = min(TP, q0 + per);
   int cnt = 0;
@@ -363,7 +362,7 @@ __device__ void eqp_freeze(const Prob &pb, const WS &ws, const EWS &ew, const Sc
         pcur = p;
       }
       const int e = (t - 1) * N * N + j * N + i;   // ordered copy (i, j), i first
-      const bool act = pa[e] != 0;
+      const bool act = gm[e] > 0.f;   // violated at the last consensus step
       if (pass == 0) {
         float n[NU];
         if (pb.normal_mode == NORMAL_FROZEN) {

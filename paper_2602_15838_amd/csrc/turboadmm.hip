@@ -92,7 +92,8 @@ struct AgentView {
   __device__ __forceinline__ AgentView(const Prob &pb, const WS &ws, const Scen &sc, int i_)
       : R(ws.fr + sc.fo), Wb(ws.wr + sc.bo), D(ws.dr + sc.dof), dirty(ws.adirty + (sc.ao + i_) * NU_),
         qd(ws.aq ? ws.aq + (sc.ao + i_) * NX : ws.qd + (long long)sc.s * NX), GS((unsigned)sc.GS),
-        N((unsigned)sc.N), i((unsigned)i_), rho(ws.rhos[2 * sc.s]), rho_prev(ws.rhos[2 * sc.s + 1]),
+        N((unsigned)sc.N), i((unsigned)i_), rho(pb.adapt ? ws.rhos[2 * sc.s] : pb.rho),
+        rho_prev(pb.adapt ? ws.rhos[2 * sc.s + 1] : pb.rho),
         Ad(ws.aA ? ws.aA + (sc.ao + i_) * (NX * NX) : nullptr),
         Bd(ws.aB ? ws.aB + (sc.ao + i_) * (NX * NU) : nullptr) {
     const float *rd = ws.ar ? ws.ar + (sc.ao + i_) * NU : ws.rd + (long long)sc.s * NU;
@@ -125,7 +126,11 @@ struct AgentView {
   __device__ __forceinline__ DynSel dyn(const Prob &pb) const { return DynSel{pb, Ad, Bd}; }
 };
 
-template <int NXF, int NUF>
+// LA: the affine feedforward k_t and the equality-QP input of the axis
+// problem live in LDS ([t][2][nl] over the scenario's nl axis problems, this
+// one at column l) instead of the axis-stage region: both are written and
+// read only within one x-update, so they need not reach HBM.
+template <int NXF, int NUF, bool LA = false>
 struct AxisView {
   static constexpr int NX = 2, NU = 1, NS = 1, NP = 3;
   static constexpr bool DI = true;
@@ -139,10 +144,13 @@ struct AxisView {
   unsigned GS, N, i, c;
   float qd[2], lo[1], hi[1], hu[1];
   float rho, rho_prev;        // penalty of this iteration, of the last one
+  float *la = nullptr;        // LA: the LDS slots, [t][2][nl]
+  unsigned nl = 0, l = 0;
   __device__ __forceinline__ AxisView(const Prob &pb, const WS &ws, const Scen &sc, int i_, int c_)
       : R(ws.fr + sc.fo), AX(ws.fr + sc.fo + (long long)Fld<NXF, NUF>::NF * sc.GS), Wb(ws.wr + sc.bo),
         D(ws.dr + sc.dof), dirty(ws.adirty + (sc.ao + i_) * NUF + c_), GS((unsigned)sc.GS), N((unsigned)sc.N),
-        i((unsigned)i_), c((unsigned)c_), rho(ws.rhos[2 * sc.s]), rho_prev(ws.rhos[2 * sc.s + 1]) {
+        i((unsigned)i_), c((unsigned)c_), rho(pb.adapt ? ws.rhos[2 * sc.s] : pb.rho),
+        rho_prev(pb.adapt ? ws.rhos[2 * sc.s + 1] : pb.rho) {
     const float *q = ws.aq ? ws.aq + (sc.ao + i_) * NXF : ws.qd + (long long)sc.s * NXF;
     const float *rd = ws.ar ? ws.ar + (sc.ao + i_) * NUF : ws.rd + (long long)sc.s * NUF;
     qd[0] = q[c];
@@ -173,8 +181,14 @@ struct AxisView {
   __device__ __forceinline__ float &KC(int, int t) const { return ax<AXA_FAC, 4>(3, t); }
   __device__ __forceinline__ float &CC(int r, int t) const { return ax<AXA_C, 2>(r, t); }
   __device__ __forceinline__ float &PV(int r, int t) const { return ax<AXA_PV, 2>(r, t); }
-  __device__ __forceinline__ float &KV(int, int t) const { return ax<AXA_AFF, 2>(0, t); }
-  __device__ __forceinline__ float &UE(int, int t) const { return ax<AXA_AFF, 2>(1, t); }
+  __device__ __forceinline__ float &KV(int, int t) const {
+    if constexpr (LA) return la[(unsigned)t * 2u * nl + l];
+    else return ax<AXA_AFF, 2>(0, t);
+  }
+  __device__ __forceinline__ float &UE(int, int t) const {
+    if constexpr (LA) return la[((unsigned)t * 2u + 1u) * nl + l];
+    else return ax<AXA_AFF, 2>(1, t);
+  }
   __device__ __forceinline__ float &PU(int k, int t) const { return ax<AXA_P, 4>(k, t); }
   __device__ __forceinline__ float &Q(int r, int t) const {
     return fref(R, GS, g(t), r ? F::Q + NUF + (int)c : F::QZ + (int)c);
@@ -868,11 +882,18 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, const
 template <int NX, int NU, bool DI>
 __host__ __device__ constexpr int xupdate_lanes(int N) { return DI ? N * NU : N; }
 
-template <int NX, int NU, bool DI>
+// LA (with DI): the axis problems' k and EQP-input slots in LDS at la,
+// 2 T N NU floats.
+template <int NX, int NU, bool DI, bool LA = false>
 __device__ __forceinline__ int local_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int l, int k,
-                                             long long cnt[CT_NCOL]) {
+                                             long long cnt[CT_NCOL], float *la = nullptr) {
   if constexpr (DI) {
-    const AxisView<NX, NU> m(pb, ws, sc, l / NU, l % NU);
+    AxisView<NX, NU, LA> m(pb, ws, sc, l / NU, l % NU);
+    if constexpr (LA) {
+      m.la = la;
+      m.nl = (unsigned)(sc.N * NU);
+      m.l = (unsigned)l;
+    }
     return agent_xupdate(pb, ws, sc, m, k, cnt);
   } else {
     const AgentView<NX, NU, false> m(pb, ws, sc, l);
@@ -950,8 +971,8 @@ __device__ void pair_agent_stage_impl(const Prob &pb, const WS &ws, const Scen &
 #pragma unroll
   for (int c = 0; c < NX; ++c) bad |= !isfinite(Ri(F::X + c));
   float *gm = ws.gam + sc.lo;
-  uint8_t *pa = ws.pact + sc.lb;
-  const float rho = ws.rhos[2 * sc.s], irho = 1.0f / rho;
+  // (the per-scenario penalty equals pb.rho unless it adapts)
+  const float rho = pb.adapt ? ws.rhos[2 * sc.s] : pb.rho, irho = 1.0f / rho;
   const bool frozen = pb.normal_mode == NORMAL_FROZEN;
   float es[NU], zd[NU], ls[NU];   // sum (lam_old - 2 lam_new), sum (z - C x), sum lam_new
 #pragma unroll
@@ -1023,9 +1044,7 @@ __device__ void pair_agent_stage_impl(const Prob &pb, const WS &ws, const Scen &
           if (d2 > far2) {
 #pragma unroll
             for (int c = 0; c < NU; ++c) z2 = fmaf(pi[c], pi[c], z2);
-            const int li = gbase + j * N;
-            gm[li] = 0.f;
-            if (i < j) pa[li] = 0;
+            gm[gbase + j * N] = 0.f;
             continue;
           }
         }
@@ -1087,9 +1106,7 @@ __device__ void pair_agent_stage_impl(const Prob &pb, const WS &ws, const Scen &
           z2 = fmaf(zo, zo, z2);
         }
       }
-      const bool first = i < j;
-      gm[li] = gam;
-      if (first) pa[li] = (uint8_t)(v > 0.f);
+      gm[li] = gam;   // (the half-plane is active at this step iff gam > 0)
     }
   }
   float s2 = 0.f, ax2 = 0.f, aty2 = 0.f;
@@ -1179,7 +1196,6 @@ __device__ void pair_agent_stage_mom(const Prob &pb, const WS &ws, const Scen &s
 #pragma unroll
   for (int c = 0; c < NX; ++c) bad |= !isfinite(Ri(F::X + c));
   float *gm = ws.gam + sc.lo;
-  uint8_t *pa = ws.pact + sc.lb;
   const long long LS = (long long)sc.T * N * N;
   float *mp = ws.mom + (long long)MP_N * NU * sc.lo;
   auto plane = [&](int which, int c) { return mp + (long long)(which * NU + c) * LS; };
@@ -1242,7 +1258,6 @@ __device__ void pair_agent_stage_mom(const Prob &pb, const WS &ws, const Scen &s
       ls[c] += lo;
     }
     gm[li] = gam;
-    if (i < j) pa[li] = (uint8_t)(v > 0.f);
    }
   }
   float s2 = 0.f, ax2 = 0.f, aty2 = 0.f;
@@ -1465,11 +1480,7 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
         }
       }
       float *gm = ws.gam + sc.lo;
-      uint8_t *pa = ws.pact + sc.lb;
-      for (int idx = tid; idx < T * N * N; idx += nthreads) {
-        gm[idx] = 0.f;
-        pa[idx] = 0;
-      }
+      for (int idx = tid; idx < T * N * N; idx += nthreads) gm[idx] = 0.f;
       if (pb.relax) {
         // the copies restart at z = C x: D = C x_i - C x_j, e = 0
         const long long LS = (long long)T * N * N;
@@ -1561,11 +1572,7 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
   }
   const int LS = T * N * N;
   float *gm = ws.gam + sc.lo;
-  uint8_t *pa = ws.pact + sc.lb;
-  for (int idx = tid; idx < LS; idx += nthreads) {
-    gm[idx] = 0.f;
-    pa[idx] = 0;
-  }
+  for (int idx = tid; idx < LS; idx += nthreads) gm[idx] = 0.f;
   if constexpr (MOM) {
     // momentum: zh = z_0 = z_(-1) = C r, lh = lambda_0 = lambda_(-1) = 0;
     // alpha_1 = 1, c_0 = inf
@@ -1687,9 +1694,21 @@ __global__ __launch_bounds__(256) void k_extrap(Prob pb, WS ws, int s) {
 // scenario's own stopping test passes; the three phases are separated by
 // workgroup barriers.  Every wave reaches the queue read, so the grid drains
 // once the counter passes S.
-// VAR: 0 plain ADMM, 1 over-relaxed, 2 momentum (each a kernel of its own).
+// VAR: 0 plain ADMM, 1 over-relaxed, 2 momentum (each a kernel of its own);
+// 3 plain ADMM without the options (normals of the iterates, shared weights
+// and boxes, fixed penalty, no state boxes, not a continuing SQP round): the
+// option flags and pointers are constants here, so their code and registers
+// drop out of the kernel, and with double-integrator dynamics the x-update
+// keeps its per-pass slots (k, EQP input) in the LDS that the consensus step
+// uses for the positions (the host sizes it for both, 2 T N NU floats).
 template <int NX, int NU, bool DI, int VAR>
 __device__ __forceinline__ void persistent_body(Prob pb, WS ws, int S, int lds_floats) {
+  if constexpr (VAR == 3) {
+    pb.sbox = 0; pb.pbox = 0; pb.adapt = 0; pb.relax = 0; pb.mom = 0; pb.cont = 0;
+    pb.normal_mode = NORMAL_PER_ITER;
+    ws.aq = nullptr; ws.ar = nullptr; ws.alo = nullptr; ws.ahi = nullptr; ws.aA = nullptr; ws.aB = nullptr;
+    ws.normals = nullptr; ws.orx = nullptr; ws.mom = nullptr; ws.momst = nullptr;
+  }
   extern __shared__ float lds_pos[];  // positions of the scenario and the previous ones, [t][i][c] each
   __shared__ int s_item;
   __shared__ int s_cap;
@@ -1711,7 +1730,7 @@ __device__ __forceinline__ void persistent_body(Prob pb, WS ws, int S, int lds_f
     for (int k = 1; k <= pb.max_iter; ++k) {
       const unsigned long long c0 = wall_clock64();
       for (int l = tid; l < xupdate_lanes<NX, NU, DI>(sc.N); l += nt)
-        if (local_xupdate<NX, NU, DI>(pb, ws, sc, l, k, cnt)) atomicOr(&s_cap, 1);
+        if (local_xupdate<NX, NU, DI, VAR == 3 && DI>(pb, ws, sc, l, k, cnt, lds_pos)) atomicOr(&s_cap, 1);
       __syncthreads();
       const unsigned long long c1 = wall_clock64();
       const int cap = s_cap;
@@ -1797,12 +1816,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 
 template <int NX, int NU, bool DI>
 const void *persistent_kernel(bool lean, int var) {
-  if (lean) return var == 2 ? (const void *)k_admm_persistent_lean<NX, NU, DI, 2>
+  if (lean) return var == 3 ? (const void *)k_admm_persistent_lean<NX, NU, DI, 3>
+                 : var == 2 ? (const void *)k_admm_persistent_lean<NX, NU, DI, 2>
                  : var == 1 ? (const void *)k_admm_persistent_lean<NX, NU, DI, 1>
                             : (const void *)k_admm_persistent_lean<NX, NU, DI, 0>;
-  return var == 2 ? (const void *)k_admm_persistent<NX, NU, DI, 2>
+  return var == 3 ? (const void *)k_admm_persistent<NX, NU, DI, 3>
+         : var == 2 ? (const void *)k_admm_persistent<NX, NU, DI, 2>
          : var == 1 ? (const void *)k_admm_persistent<NX, NU, DI, 1>
                     : (const void *)k_admm_persistent<NX, NU, DI, 0>;
+}
+
+// The persistent kernel variant of a solve (VAR of persistent_body).
+int persistent_variant(const Prob &pb, const WS &w) {
+  if (pb.mom) return 2;
+  if (pb.relax) return 1;
+  const bool plain = !pb.sbox && !pb.pbox && !pb.adapt && !pb.cont && pb.normal_mode == NORMAL_PER_ITER &&
+                     !w.aq && !w.ar && !w.alo && !w.ahi && !w.aA && !w.aB;
+  return plain ? 3 : 0;
 }
 
 __global__ void k_fill_i32(int *p, int n, int v) {
@@ -2124,7 +2154,7 @@ __global__ void k_writeback(WS ws, int S, tadmm_out out) {
         const int i = e % N, j = (e / N) % N, t = e / (N * N) + 1;
         if (j <= i) continue;
         const int p = i * N - i * (i + 1) / 2 + (j - i - 1);
-        out.pair_active[sc.po + (long long)p * T + (t - 1)] = ws.pact[sc.lb + e];
+        out.pair_active[sc.po + (long long)p * T + (t - 1)] = (uint8_t)(ws.gam[sc.lo + e] > 0.f);
       }
     if (threadIdx.x == 0) {
       const int *st = ws.sst + (long long)s * ST_NCOL;
@@ -2185,7 +2215,7 @@ struct Layout {
   int S = 0, nx = 0, nu = 0, NF = 0;
   long long A = 0, sumGS = 0, sumL = 0;
   size_t o_N = 0, o_T = 0, o_tab = 0, o_order = 0, o_queue = 0, o_sst = 0, o_snorm = 0, o_cnt = 0, o_flags = 0;
-  size_t o_adirty = 0, o_fr = 0, o_dr = 0, o_wr = 0, o_gam = 0, o_pact = 0, bytes = 0;
+  size_t o_adirty = 0, o_fr = 0, o_dr = 0, o_wr = 0, o_gam = 0, bytes = 0;
   size_t o_er = 0, o_nrm = 0, o_cidx = 0, o_clist = 0, o_cg = 0, o_m = 0;
   size_t o_wide = 0;   // wide mode: iteration number, scenario index
   size_t o_sqpj = 0, o_sqpi = 0, o_sqpf = 0;   // SQP: objective [S] (FP64); skip, rounds [2][S]; min distance [S]
@@ -2263,7 +2293,7 @@ bool make_layout(const tadmm_params *p, int S, const int32_t *N, const int32_t *
   L = Layout();
   L.S = S; L.nx = p->nx; L.nu = p->nu; L.NF = fields_per_stage(p->nx, p->nu);
   L.tab.assign((size_t)S * TB_NCOL, 0);
-  long long fo = 0, bo = 0, lo = 0, ao = 0, xo = 0, uo = 0, po = 0, lb = 0, dof = 0;
+  long long fo = 0, bo = 0, lo = 0, ao = 0, xo = 0, uo = 0, po = 0, dof = 0;
   for (int s = 0; s < S; ++s) {
     const long long n = N[s], t = T[s];
     if (n < 1 || t < 1) { err = "every scenario needs N >= 1 and T >= 1"; return false; }
@@ -2275,19 +2305,18 @@ bool make_layout(const tadmm_params *p, int S, const int32_t *N, const int32_t *
       err = "scenario too large for 32-bit in-scenario offsets"; return false;
     }
     long long *tb = &L.tab[(size_t)s * TB_NCOL];
-    tb[TB_F] = fo; tb[TB_B] = bo; tb[TB_L] = lo; tb[TB_A] = ao; tb[TB_XO] = xo; tb[TB_UO] = uo; tb[TB_PO] = po; tb[TB_LB] = lb;
+    tb[TB_F] = fo; tb[TB_B] = bo; tb[TB_L] = lo; tb[TB_A] = ao; tb[TB_XO] = xo; tb[TB_UO] = uo; tb[TB_PO] = po;
     tb[TB_D] = dof;
     fo += (long long)L.NF * GS + axis_region_floats(GS, p->nu) + input_region_floats(GS, p->nu);
     dof += (long long)p->nx * GS;
     bo += 4ll * GS;
     lo += t * n * n;
-    lb += t * n * n;
     ao += n;
     xo += GS;
     uo += n * t;
     po += n * (n - 1) / 2 * t;
   }
-  L.A = ao; L.sumGS = xo; L.sumL = lb;
+  L.A = ao; L.sumGS = xo; L.sumL = lo;
   size_t off = 0;
   auto take = [&](size_t bytes) { const size_t o = off; off = align_up(off + std::max<size_t>(bytes, 1)); return o; };
   L.o_N = take(sizeof(int) * S);
@@ -2304,7 +2333,6 @@ bool make_layout(const tadmm_params *p, int S, const int32_t *N, const int32_t *
   L.o_dr = take(sizeof(double) * (size_t)dof);
   L.o_wr = take((size_t)bo);
   L.o_gam = take(sizeof(float) * (size_t)lo);
-  L.o_pact = take((size_t)lb);
   // equality-QP solves of the derivative (sized for FP64)
   L.sumPT = po;
   L.o_er = take(sizeof(double) * (size_t)eqp_fields_per_stage(p->nx) * (size_t)xo);
@@ -2497,7 +2525,6 @@ WS make_ws(const Layout &L, char *ws, const tadmm_batch *b) {
   w.wr = (int8_t *)(ws + L.o_wr);
   w.adirty = (int *)(ws + L.o_adirty);
   w.gam = (float *)(ws + L.o_gam);
-  w.pact = (uint8_t *)(ws + L.o_pact);
   w.sst = (int *)(ws + L.o_sst);
   w.snorm = (float *)(ws + L.o_snorm);
   w.cnt = (unsigned long long *)(ws + L.o_cnt);
@@ -2563,12 +2590,20 @@ tadmm_status run_batched(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layo
   const int threads = ctx->prm.block_threads ? ctx->prm.block_threads : ctx->tuned_threads;
   // LDS for the positions of the largest scenario, up to 32 KB per workgroup
   // (larger scenarios read positions from global memory)
-  long long max_gs = 0;
-  for (int s = 0; s < L.S; ++s) max_gs = std::max<long long>(max_gs, (long long)b->n_agents[s] * (b->horizon[s] + 1));
+  long long max_gs = 0, max_tn = 0;
+  for (int s = 0; s < L.S; ++s) {
+    max_gs = std::max<long long>(max_gs, (long long)b->n_agents[s] * (b->horizon[s] + 1));
+    max_tn = std::max<long long>(max_tn, (long long)b->n_agents[s] * b->horizon[s]);
+  }
   const bool lean = (threads == 64);
-  const int lds_floats = (int)std::min<long long>(2 * max_gs * NU, lean ? 4096 : 8192);
+  const long long cap_floats = lean ? 4096 : 8192;
+  int var = persistent_variant(pb, w);
+  // variant 3 keeps the x-update's slots of every scenario in LDS
+  if (var == 3 && DI && 2 * max_tn * NU > cap_floats) var = 0;
+  const long long want = std::max<long long>(2 * max_gs * NU, (var == 3 && DI) ? 2 * max_tn * NU : 0);
+  const int lds_floats = (int)std::min<long long>(want, cap_floats);
   const size_t lds_bytes = sizeof(float) * (size_t)lds_floats;
-  const void *kfn = persistent_kernel<NX, NU, DI>(lean, pb.mom ? 2 : (pb.relax ? 1 : 0));
+  const void *kfn = persistent_kernel<NX, NU, DI>(lean, var);
   int per_cu = 0;
   HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, threads, lds_bytes));
   if (per_cu < 1) return fail(ctx, TADMM_ERR_HIP, "persistent kernel does not fit on a compute unit");
