@@ -956,7 +956,13 @@ __device__ __forceinline__ void pair_normal(const Prob &pb, const WS &ws, const 
 // gamma) and e = z_ij - C x_i (offsets stay small).  The duals keep their
 // collapsed form lambda_ij = -gamma n, since the projection still moves the
 // pair symmetrically about its midpoint.
-template <int NX, int NU, bool REL>
+// MASK (N <= 64): the agent-stage keeps a bit mask of its partners j whose
+// gamma (ordered copy (i, j)) is nonzero, in the residual slots RED+5 (j <
+// 32) and RED+6; gamma is read only where the bit is set and written only
+// where it was or becomes nonzero.  The stored gammas stay exact (zero where
+// the bit is clear), so every other reader sees the same values, while an
+// inactive pair, most of them, costs no memory access.
+template <int NX, int NU, bool REL, bool MASK = false>
 __device__ void pair_agent_stage_impl(const Prob &pb, const WS &ws, const Scen &sc, int i, int t,
                                       const float *__restrict__ lpos, const float *__restrict__ lprev, int lofs) {
   using F = Fld<NX, NU>;
@@ -1010,13 +1016,19 @@ __device__ void pair_agent_stage_impl(const Prob &pb, const WS &ws, const Scen &
   // below the distance at which the normal falls back to the references
   // (unit_normal), whose half-plane does not follow the positions
   const float far2 = fmaxf((1.001f * pb.dmin) * (1.001f * pb.dmin), 1e-12f);
+  unsigned mw0 = 0u, mw1 = 0u, nm0 = 0u, nm1 = 0u;   // MASK: partners with gamma != 0, before / after
+  if constexpr (MASK) {
+    mw0 = __float_as_uint(Ri(F::RED + 5));
+    if (N > 32) mw1 = __float_as_uint(Ri(F::RED + 6));
+  }
+  auto was_on = [&](int j) -> bool { return (((j < 32) ? (mw0 >> j) : (mw1 >> (j - 32))) & 1u) != 0u; };
   for (int j0 = 0; j0 < np; j0 += kPB) {
     float gb[kPB], pjb[kPB][NU], qjb[kPB][NU];
     float Db[REL ? kPB : 1][NU], eb[REL ? kPB : 1][NU];
 #pragma unroll
     for (int q = 0; q < kPB; ++q)
       if (j0 + q < np) {
-        gb[q] = gm[gbase + jof(j0 + q) * N];
+        gb[q] = (!MASK || was_on(jof(j0 + q))) ? gm[gbase + jof(j0 + q) * N] : 0.f;
         partner(jof(j0 + q), pjb[q], qjb[q]);
         if constexpr (REL) {
 #pragma unroll
@@ -1044,7 +1056,7 @@ __device__ void pair_agent_stage_impl(const Prob &pb, const WS &ws, const Scen &
           if (d2 > far2) {
 #pragma unroll
             for (int c = 0; c < NU; ++c) z2 = fmaf(pi[c], pi[c], z2);
-            gm[gbase + j * N] = 0.f;
+            if constexpr (!MASK) gm[gbase + j * N] = 0.f;   // (with the mask: zero already)
             continue;
           }
         }
@@ -1106,8 +1118,22 @@ __device__ void pair_agent_stage_impl(const Prob &pb, const WS &ws, const Scen &
           z2 = fmaf(zo, zo, z2);
         }
       }
-      gm[li] = gam;   // (the half-plane is active at this step iff gam > 0)
+      // (the half-plane is active at this step iff gam > 0)
+      if constexpr (MASK) {
+        const bool on = gam > 0.f;
+        if (on || gold != 0.f) gm[li] = gam;
+        if (on) {
+          if (j < 32) nm0 |= 1u << j;
+          else nm1 |= 1u << (j - 32);
+        }
+      } else {
+        gm[li] = gam;
+      }
     }
+  }
+  if constexpr (MASK) {
+    Ri(F::RED + 5) = __uint_as_float(nm0);
+    if (N > 32) Ri(F::RED + 6) = __uint_as_float(nm1);
   }
   float s2 = 0.f, ax2 = 0.f, aty2 = 0.f;
   const float nn = (float)(N - 1);
@@ -1545,6 +1571,8 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) Wb[(unsigned)idx * 4u + c] = 0;
+    Rg(F::RED + 5) = 0.f;   // no partner with a nonzero gamma (the consensus step's mask)
+    Rg(F::RED + 6) = 0.f;
     if (t == 0) {
       const float *x0 = ws.x0 + (sc.ao + i) * NX;
 #pragma unroll
@@ -1754,7 +1782,7 @@ __device__ __forceinline__ void persistent_body(Prob pb, WS ws, int S, int lds_f
           if constexpr (VAR == 2)
             pair_agent_stage_mom<NX, NU>(pb, ws, sc, idx % sc.N, idx / sc.N + 1, staged ? lds_pos : nullptr);
           else
-            pair_agent_stage_impl<NX, NU, VAR == 1>(pb, ws, sc, idx % sc.N, idx / sc.N + 1,
+            pair_agent_stage_impl<NX, NU, VAR == 1, VAR == 3>(pb, ws, sc, idx % sc.N, idx / sc.N + 1,
                                                     staged ? lds_pos : nullptr, staged ? lds_prev : nullptr, 0);
         }
         if (tid == 0) cnt[CT_PAIRS] += (long long)sc.N * (sc.N - 1) / 2 * sc.T;
@@ -2598,8 +2626,11 @@ tadmm_status run_batched(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layo
   const bool lean = (threads == 64);
   const long long cap_floats = lean ? 4096 : 8192;
   int var = persistent_variant(pb, w);
-  // variant 3 keeps the x-update's slots of every scenario in LDS
-  if (var == 3 && DI && 2 * max_tn * NU > cap_floats) var = 0;
+  // variant 3 keeps the x-update's slots of every scenario in LDS and a
+  // 64-bit partner mask per agent-stage
+  long long max_n = 0;
+  for (int s = 0; s < L.S; ++s) max_n = std::max<long long>(max_n, b->n_agents[s]);
+  if (var == 3 && ((DI && 2 * max_tn * NU > cap_floats) || max_n > 64)) var = 0;
   const long long want = std::max<long long>(2 * max_gs * NU, (var == 3 && DI) ? 2 * max_tn * NU : 0);
   const int lds_floats = (int)std::min<long long>(want, cap_floats);
   const size_t lds_bytes = sizeof(float) * (size_t)lds_floats;
