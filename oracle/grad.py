@@ -15,11 +15,11 @@ implicit function theorem the gradient of a loss L(w) is
 
     dL/dtheta = -[wbar; ybar]' dF/dtheta,   K [wbar; ybar] = [dL/dw; 0],
 
-with K the (symmetric) KKT matrix.  Here K is assembled densely, the partial
-derivatives dF/dtheta are taken by central differences of the KKT map itself
-(F is smooth in theta and only H, c and e depend on it; no re-solve), and
-everything is FP64.  A second, independent reference re-solves the EQP at
-theta +- h (central finite differences of the whole solve).
+with K the (symmetric) KKT matrix.  Here K is assembled densely and the
+partial derivatives dF/dtheta are written out in closed form (only H, c and
+e depend on theta; see implicit_gradient), everything in FP64.  A second,
+independent reference re-solves the EQP at theta +- h (central finite
+differences of the whole solve).
 
 Parameters theta: the log of the diagonal of Q (nx), the log of the diagonal
 of R (nu), the initial states x0 [N][nx] and the references xref [N][T+1][nx].
@@ -198,35 +198,46 @@ def pack_dw(ins: EqpInstance, gx, gu):
     return np.concatenate([np.concatenate([gu[i].ravel(), gx[i, 1:].ravel()]) for i in range(ins.N)])
 
 
-def implicit_gradient(ins: EqpInstance, gx, gu, fd_step: float = 1e-6) -> Dict[str, np.ndarray]:
+def implicit_gradient(ins: EqpInstance, gx, gu) -> Dict[str, np.ndarray]:
     """dL/dtheta by the implicit function theorem on the dense KKT system.
 
     gx [N][T+1][nx], gu [N][T][nu]: dL/dx and dL/du at the EQP solution.  The
     t = 0 entry of gx is the direct dependence of L on x_0 = x0 and is added to
-    dL/dx0.  dF/dtheta is taken by central differences of the KKT map."""
+    dL/dx0.  The partial derivatives of F = [H w + c + E'y ; E w - e] in
+    closed form, with w_t = qT_scale at t = T and 1 before:
+      log q_k:  d(H w + c)/d log q_k = 2 w_t q_k (x_t,k - r_t,k) on x_t,k, t >= 1
+      log r_a:  d(H w)/d log r_a = 2 r_a u_t,a on u_t,a
+      x0_i:     d(E w - e)/d x0_i = -A on the t = 0 dynamics rows of agent i
+      r_i,t,k:  dc/d r_i,t,k = -2 w_t q_k on x_t,k of agent i (t >= 1)
+    and dL/dtheta = -(wbar' dF_top/dtheta + ybar' dF_bot/dtheta)."""
     E, tags = constraints(ins)
     w, y = solve(ins, E=E, tags=tags)
     H, c = objective(ins)
     K = kkt_matrix(H, E)
     adj = np.linalg.solve(K, np.concatenate([pack_dw(ins, gx, gu), np.zeros(E.shape[0])]))
     wbar, ybar = adj[:H.size], adj[H.size:]
-    base = ins.theta()
+    N, T, nx, nu = ins.N, ins.T, ins.nx, ins.nu
+    q, r = np.exp(ins.logq), np.exp(ins.logr)
+    x, u = trajectories(ins, w)
+    xb, ub = trajectories(ins, wbar)                 # the adjoint in the layout of (x, u); xb[:, 0] unused
+    wt = np.ones(T + 1)
+    wt[T] = ins.qT_scale
+    wt[0] = 0.0                                      # x_0 is data, not a variable
     out = {}
-    for name in PARAMS:
-        arr = base[name]
-        grad = np.zeros_like(arr)
-        for k in range(arr.size):
-            th = {kk: vv.copy() for kk, vv in base.items()}
-            vals = []
-            for sgn in (1.0, -1.0):
-                th[name].reshape(-1)[k] = arr.reshape(-1)[k] + sgn * fd_step
-                Hs, cs = objective(ins, th)
-                vals.append((Hs * w + cs, rhs(ins, tags, th)))
-            dF_top = (vals[0][0] - vals[1][0]) / (2.0 * fd_step)
-            dF_bot = -(vals[0][1] - vals[1][1]) / (2.0 * fd_step)
-            grad.reshape(-1)[k] = -(wbar @ dF_top + ybar @ dF_bot)
-        out[name] = grad
-    out["x0"] = out["x0"] + gx[:, 0, :]
+    # log q: -sum_{i,t} wbar_x[i,t,k] * 2 w_t q_k (x - r)[i,t,k]
+    out["logq"] = -np.einsum("itk,t,k,itk->k", xb, wt * 2.0, q, x - ins.xref)
+    # log r: -sum_{i,t} wbar_u[i,t,a] * 2 r_a u[i,t,a]
+    out["logr"] = -np.einsum("ita,a,ita->a", ub, 2.0 * r, u)
+    # references: -wbar_x[i,t,k] * (-2 w_t q_k), t >= 1 (zero at t = 0)
+    out["xref"] = np.einsum("itk,t,k->itk", xb, wt * 2.0, q)
+    # x0: the t = 0 dynamics rows x_1 - B u_0 = A x0; dF_bot/dx0 = -A, so the
+    # gradient is ybar_rows' A, plus the direct term
+    g0 = np.zeros((N, nx))
+    for k, tg in enumerate(tags):
+        if tg[0] == "dyn" and tg[2] == 0:
+            _, i, _, row = tg
+            g0[i] += ybar[k] * ins.A[row]
+    out["x0"] = g0 + gx[:, 0, :]
     return out
 
 

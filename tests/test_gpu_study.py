@@ -49,3 +49,39 @@ def test_sweep_small():
         assert r["status"] in (0, 1) and r["plain_ms_per_solve"] > 0 and r["wide_ms_per_solve"] > 0
     fit = recs[-1]
     assert fit["study"] == "sweep_fit" and np.isfinite(fit["plain_time_exponent"])
+
+
+@pytest.mark.parametrize("variant", ["base", "hotstart", "turbo"])
+def test_ablation_variant_lockstep_with_oracle(variant):
+    """Each ablation variant (the start strategies of Sec. V-B: Base,
+    Hotstart, Turbo) against the oracle run with the same strategy (start of
+    every local QP, hotstart, factor reuse): 25 iterations in lockstep on
+    three 6-agent crossings of the study, trajectories, working sets,
+    active half-planes and every iteration's residual norms.  The work
+    counts of both sides are printed; each side's Base needs the most
+    active-set passes."""
+    from tests import gpu_common as gc
+    flags = study.VARIANTS[variant]
+    p, scs = study.ablation_scenarios(6, 3)
+    K = 25
+    kw = dict(flags, eps_abs=0.0, eps_rel=0.0, max_iter=K)
+    _say(f"ablation variant {variant} lockstep K={K}")
+    g = gc.gpu_solve(p, scs, solver_kw=kw, history=True)
+    opts = gc.oracle_opts(kw, lockstep=K)
+    opts.lu_reuse = bool(flags["cache_factors"])
+    o = gc.oracle_same_instance(p, scs, opts, keep_zl=True)
+    worst = 0.0
+    for sc, gr, orr in zip(scs, g, o):
+        assert gr["iters"] == K and orr["iters"] == K
+        rep = gc.compare(p, sc, gr, orr)
+        gc.compare_history(gr, orr)
+        worst = max(worst, rep["rel"])
+    gp = [int(gr["counters"][0]) for gr in g]
+    op = [int(orr["as_passes"]) for orr in o]
+    _say(f"  worst rel {worst:.2e}; active-set passes device (axis problems) {gp}, oracle (agent QPs) {op}")
+    if variant == "base":
+        base = study.VARIANTS["turbo"]
+        t = gc.gpu_solve(p, scs, solver_kw=dict(base, eps_abs=0.0, eps_rel=0.0, max_iter=K))
+        to = gc.oracle_same_instance(p, scs, gc.oracle_opts(dict(base, max_iter=K), lockstep=K))
+        assert sum(gp) > sum(int(x["counters"][0]) for x in t)
+        assert sum(op) > sum(int(x["as_passes"]) for x in to)
