@@ -2244,7 +2244,7 @@ struct Layout {
   long long A = 0, sumGS = 0, sumL = 0;
   size_t o_N = 0, o_T = 0, o_tab = 0, o_order = 0, o_queue = 0, o_sst = 0, o_snorm = 0, o_cnt = 0, o_flags = 0;
   size_t o_adirty = 0, o_fr = 0, o_dr = 0, o_wr = 0, o_gam = 0, bytes = 0;
-  size_t o_er = 0, o_nrm = 0, o_cidx = 0, o_clist = 0, o_cg = 0, o_m = 0;
+  size_t o_er = 0, o_nrm = 0, o_cidx = 0, o_clist = 0, o_cg = 0, o_m = 0, o_coff = 0, o_cent = 0;
   size_t o_wide = 0;   // wide mode: iteration number, scenario index
   size_t o_sqpj = 0, o_sqpi = 0, o_sqpf = 0;   // SQP: objective [S] (FP64); skip, rounds [2][S]; min distance [S]
   size_t o_rho = 0;    // [S][2] penalty of the next / last iteration
@@ -2367,6 +2367,8 @@ bool make_layout(const tadmm_params *p, int S, const int32_t *N, const int32_t *
   L.o_nrm = take(sizeof(float) * (size_t)p->nu * (size_t)po);
   L.o_cidx = take(sizeof(int) * (size_t)po);
   L.o_clist = take(sizeof(int2) * (size_t)po);
+  L.o_coff = take(sizeof(int) * (size_t)xo);
+  L.o_cent = take(sizeof(int2) * 2 * (size_t)po);
   L.o_cg = take(sizeof(double) * 6 * (size_t)po);
   L.o_m = take(sizeof(int) * S);
   L.o_wide = take(sizeof(int) * 64);
@@ -2932,6 +2934,8 @@ EWS make_ews(const Layout &L, char *ws) {
   e.nrm = (float *)(ws + L.o_nrm);
   e.cidx = (int *)(ws + L.o_cidx);
   e.clist = (int2 *)(ws + L.o_clist);
+  e.coff = (int *)(ws + L.o_coff);
+  e.cent = (int2 *)(ws + L.o_cent);
   e.cg = (double *)(ws + L.o_cg);
   e.m = (int *)(ws + L.o_m);
   return e;

@@ -195,9 +195,9 @@ def _rejection_points(rng: np.random.Generator, n: int, lo: float, hi: float, mi
 
 
 def random_box(rng: np.random.Generator, N: int, T: int, half: float = 5.0, min_sep: float = 1.0,
-               dt: float = DT) -> Scenario:
-    starts = _rejection_points(rng, N, -half, half, min_sep)
-    goals = _rejection_points(rng, N, -half, half, min_sep)
+               dt: float = DT, dp: int = 2) -> Scenario:
+    starts = _rejection_points(rng, N, -half, half, min_sep, dp)
+    goals = _rejection_points(rng, N, -half, half, min_sep, dp)
     return Scenario(starts=starts, goals=goals, T=T, dt=dt)
 
 

@@ -162,21 +162,27 @@ def compare(problem, sc, g, o, rho=None, check_sets=True, tol=REL_TOL, normals=N
     return rep
 
 
-def compare_history(g, o, frac_eps=0.05, rel=1e-3):
+def compare_history(g, o, sc, dp, frac_eps=0.05, rel=1e-3, eps_abs=1e-4):
     """Per-iteration residual norms of the stopping test (Sec. V-A), device
     against oracle: |r_g - r_o| <= frac_eps * eps_pri + rel * r_o and the
-    same for s, at every iteration both sides ran.  The stopping decision
-    compares r with eps_pri, so an agreement to a small fraction of eps_pri
-    makes the two decisions the same except at a near tie; FP32 positions of
-    magnitude |p| carry an absolute rounding of about 6e-8 |p| per entry,
-    far below 5% of eps_pri >= 1e-4 sqrt(rows).  Returns the worst ratios."""
+    same for s, at every iteration both sides ran.  eps_pri is the run's own
+    tolerance, and at least the absolute part of the workload's
+    (sqrt(2 P T dp) eps_abs with eps_abs = 1e-4; sqrt(N T dp) eps_abs for s),
+    so that a lockstep run with its tolerances set to zero keeps the same
+    bar.  The stopping decision compares r with eps_pri, so an agreement to a
+    small fraction of eps_pri makes the two decisions the same except at a
+    near tie; FP32 positions of magnitude |p| carry an absolute rounding of
+    about 6e-8 |p| per entry, far below 5% of eps_pri.  Returns the worst
+    ratios."""
     K = min(len(g["hist"]), len(o["hist"]))
     assert K >= 1
     hg = np.asarray(g["hist"][:K], dtype=np.float64)
     ho = np.asarray(o["hist"][:K])
+    P = sc.N * (sc.N - 1) / 2
+    floor = {0: np.sqrt(2.0 * P * sc.T * dp) * eps_abs, 1: np.sqrt(float(sc.N) * sc.T * dp) * eps_abs}
     worst = [0.0, 0.0]
     for q, eps_col in ((0, 2), (1, 3)):
-        bar = frac_eps * ho[:, eps_col] + rel * ho[:, q]
+        bar = frac_eps * np.maximum(ho[:, eps_col], floor[q]) + rel * ho[:, q]
         ratio = np.abs(hg[:, q] - ho[:, q]) / bar
         worst[q] = float(ratio.max())
         bad = np.nonzero(ratio > 1.0)[0]

@@ -425,3 +425,71 @@ def test_three_d_scale_polish_and_adjoint_run():
     assert st[0] > 0 and sa[0] == st[0]
     assert all(np.all(np.isfinite(a)) and np.abs(a).max() < 1e8 for a in g)
     assert st[2] < 1.0 and sa[2] < 1.0   # MINRES never increases the residual
+
+
+# ---------------------------------------------------------------------------
+# 3-D: a small certified case family against the oracle's dense KKT gradient
+# ---------------------------------------------------------------------------
+
+IDS_3D = [3, 9, 19, 24]   # the first certified seeds (5 agents, 3-D, T = 20) of seed stream 6
+
+
+@functools.lru_cache(maxsize=1)
+def _cases_3d():
+    p = synth.ProblemParams(dp=3, u_max=3.0)
+    scs = [synth.random_box(synth.rng_for(6, s), 5, 20, half=2.0, dp=3) for s in IDS_3D]
+    cases = GC.build_cases(p, scs, IDS_3D, want=len(IDS_3D), threads=0)
+    assert [c.sid for c in cases] == IDS_3D
+    return p, cases
+
+
+def test_three_d_gradient_matches_dense_kkt_and_finite_differences():
+    """3-D double integrator (state 6, input 3), 5 agents crossing in a small
+    box, frozen normals of the oracle's converged solve: the device identifies
+    the oracle's active sets, polishes to the equality-QP solution, and its
+    adjoint (FP64 sweeps) meets the dense-KKT implicit gradient and central
+    finite differences of the oracle's equality QP at 1e-5 per block."""
+    import torch
+    import paper_2602_15838_amd as tadmm
+    p, cases = _cases_3d()
+    pk, nrm = _pack(p, cases)
+    solver = tadmm.Solver(tadmm.make_params(p, eqp_fp64=True, **FROZEN_KW))
+    prep = solver.prepare(pk.n_agents, pk.horizon, pk.x0, pk.xref, pk.q_diag, pk.r_diag, nrm)
+    prep.run(tadmm.MODE_BATCHED)
+    pre = tadmm.split_outputs(prep.result(), pk.n_agents, pk.horizon, p.nx, p.nu)
+    assert _matching(pre, cases) == list(range(len(cases)))
+    prep.polish()
+    post = tadmm.split_outputs(prep.result(), pk.n_agents, pk.horizon, p.nx, p.nu)
+    per, want, worst_fd = [], [], {n: 0.0 for n in G.PARAMS}
+    for k, c in enumerate(cases):
+        w, _ = G.solve(c.ins)
+        x, u = G.trajectories(c.ins, w)
+        rel = GC.rel_err(np.concatenate([post[k]["x"].ravel(), post[k]["u"].ravel()]),
+                         np.concatenate([x.ravel(), u.ravel()]))
+        assert rel <= POLISH_TOL[True], (c.sid, rel)
+        _, gx, gu = _tracking(c, x, u)
+        per.append((gx, gu))
+        want.append(G.implicit_gradient(c.ins, gx, gu))
+    gx, gu = _flat_upstream(pk, per, p.nx, p.nu)
+    outs = prep.adjoint(torch.tensor(gx, dtype=torch.float32), torch.tensor(gu, dtype=torch.float32))
+    gg = _split_grads(pk, outs, p.nx, p.nu)
+    worst = {n: 0.0 for n in G.PARAMS}
+    rng = np.random.default_rng(8)
+    for k, c in enumerate(cases):
+        for n in G.PARAMS:
+            rel = GC.rel_err(gg[k][n], want[k][n])
+            worst[n] = max(worst[n], rel)
+            assert rel <= GRAD_TOL, (c.sid, n, rel)
+        ins = c.ins
+        pref = ins.xref[:, :, :ins.nu].copy()
+        loss = lambda x, u, th: float(np.sum((x[:, :, :ins.nu] - pref) ** 2))
+        ent = dict(x0=rng.choice(ins.x0.size, 8, replace=False), xref=rng.choice(ins.xref.size, 16, replace=False))
+        fd = G.fd_gradient(ins, loss, entries=ent)
+        for n in G.PARAMS:
+            idx = np.arange(fd[n].size) if n not in ent else np.asarray(ent[n])
+            a, b = gg[k][n].reshape(-1)[idx], fd[n].reshape(-1)[idx]
+            rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-12)
+            worst_fd[n] = max(worst_fd[n], rel)
+            assert rel <= GRAD_TOL, (c.sid, n, rel)
+    print(f"3-D: worst relative gradient error vs dense KKT {worst}, vs central FD {worst_fd}")
+    solver.close()

@@ -91,7 +91,7 @@ def test_lockstep_config1(K):
     o = gc.oracle_same_instance(p, scs, gc.oracle_opts(lockstep=K), keep_zl=True, threads=4)[0]
     assert _lockstep_ok(g, K) and o["iters"] == K
     rep = gc.compare(p, scs[0], g, o)
-    rep["hist_worst"] = gc.compare_history(g, o)
+    rep["hist_worst"] = gc.compare_history(g, o, scs[0], p.dp)
     _say(f"  {rep}")
 
 
@@ -109,7 +109,7 @@ def test_lockstep_config2_sample():
         assert _lockstep_ok(gr, K), (sc.N, sc.T, gr["status"], gr["iters"])
         rep = gc.compare(p, sc, gr, orr)
         worst = max(worst, rep["rel"])
-        h = gc.compare_history(gr, orr)
+        h = gc.compare_history(gr, orr, sc, p.dp)
         worst_h = [max(a, b) for a, b in zip(worst_h, h)]
     _say(f"  worst rel {worst:.2e}; worst residual-history ratio (r, s) {worst_h}")
 
@@ -213,7 +213,7 @@ def test_exact_swap_frozen_reference_normals(mode):
     assert o["pair_active"][0, 9] == 1          # the mid-horizon half-plane binds
     rep = gc.compare(p, sc, g, o, normals=oracle.relinearize(gc.Fp32Problem(p), sc, gc.fp32_inputs(sc)[1],
                                                              inputs=gc.fp32_inputs(sc)))
-    rep["hist_worst"] = gc.compare_history(g, o)
+    rep["hist_worst"] = gc.compare_history(g, o, sc, p.dp)
     _say(f"  {rep}")
 
 
@@ -228,7 +228,7 @@ def test_exact_swap_per_iteration_normals():
     assert o["status"] == oracle.CONVERGED
     assert g["status"] == tadmm.SCEN_CONVERGED and abs(g["iters"] - o["iters"]) <= 2, (g["iters"], o["iters"])
     rep = gc.compare(p, sc, g, o)
-    rep["hist_worst"] = gc.compare_history(g, o)
+    rep["hist_worst"] = gc.compare_history(g, o, sc, p.dp)
     _say(f"  {rep}")
 
 
@@ -247,7 +247,7 @@ def test_coincident_positions_per_iteration_fallback():
     o = gc.oracle_same_instance(p, [sc], gc.oracle_opts(lockstep=K), keep_zl=True)[0]
     assert _lockstep_ok(g, K) and o["iters"] == K
     rep = gc.compare(p, sc, g, o)
-    rep["hist_worst"] = gc.compare_history(g, o)
+    rep["hist_worst"] = gc.compare_history(g, o, sc, p.dp)
     assert np.all(np.abs(g["x"][0, 1:, 0] - g["x"][1, 1:, 0]) > 0.0)   # pushed apart along e_1
     _say(f"  {rep}")
 

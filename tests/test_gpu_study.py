@@ -74,7 +74,7 @@ def test_ablation_variant_lockstep_with_oracle(variant):
     for sc, gr, orr in zip(scs, g, o):
         assert gr["iters"] == K and orr["iters"] == K
         rep = gc.compare(p, sc, gr, orr)
-        gc.compare_history(gr, orr)
+        gc.compare_history(gr, orr, sc, p.dp)
         worst = max(worst, rep["rel"])
     gp = [int(gr["counters"][0]) for gr in g]
     op = [int(orr["as_passes"]) for orr in o]
