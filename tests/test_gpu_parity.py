@@ -485,3 +485,26 @@ def test_poisoned_scenario_is_isolated():
         np.testing.assert_array_equal(pois[s]["x"], clean[s]["x"])
         assert pois[s]["iters"] == clean[s]["iters"]
     solver.close()
+
+
+def test_autotuned_configuration_meets_the_parity_bar():
+    """tadmm_autotune on a sample of the ragged batch picks a workgroup size
+    among its candidates; the solve in that configuration equals the oracle
+    to the parity bar (statuses, iterations within 2, trajectories, sets) and
+    is bitwise the default configuration's (the arithmetic of a scenario
+    does not depend on the launch shape)."""
+    p, scs = synth.config2(S=16)
+    _say("autotuned configuration vs the oracle")
+    g0, prep, solver = gc.gpu_solve(p, scs, return_prep=True)
+    best = prep.autotune()
+    assert best in (64, 128, 192, 256)
+    prep.run(tadmm.MODE_BATCHED)
+    g = tadmm.split_outputs(prep.result(), [s.N for s in scs], [s.T for s in scs], p.nx, p.nu)
+    o = gc.oracle_same_instance(p, scs, gc.oracle_opts(), keep_zl=True)
+    for sc, ga, gr, orr in zip(scs, g0, g, o):
+        np.testing.assert_array_equal(ga["x"], gr["x"])
+        assert gr["status"] == orr["status"] and abs(gr["iters"] - orr["iters"]) <= 2
+        tol, _ = _full_tol(p, sc, orr)
+        gc.compare(p, sc, gr, orr, tol=tol)
+    _say(f"  tuned workgroup size {best}")
+    solver.close()
