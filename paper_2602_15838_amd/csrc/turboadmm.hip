@@ -1001,6 +1001,15 @@ __device__ void pair_agent_stage_impl(const Prob &pb, const WS &ws, const Scen &
       }
     }
   };
+  auto partner_pos = [&](int j, float pj[NU]) {
+    if (lpos) {
+#pragma unroll
+      for (int c = 0; c < NU; ++c) pj[c] = lpos[(t * N + j - lofs) * NU + c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < NU; ++c) pj[c] = R[fidx(GS, (unsigned)(t * N + j), F::X + c)];
+    }
+  };
   const int gbase = (t - 1) * N * N + i;        // + j * N: this lane's ordered copy (i, j)
   // The partner loop skips j == i and runs in batches of kPB partners: the
   // duals and positions of a batch are all read before the first is used
@@ -1022,112 +1031,160 @@ __device__ void pair_agent_stage_impl(const Prob &pb, const WS &ws, const Scen &
     if (N > 32) mw1 = __float_as_uint(Ri(F::RED + 6));
   }
   auto was_on = [&](int j) -> bool { return (((j < 32) ? (mw0 >> j) : (mw1 >> (j - 32))) & 1u) != 0u; };
-  for (int j0 = 0; j0 < np; j0 += kPB) {
-    float gb[kPB], pjb[kPB][NU], qjb[kPB][NU];
-    float Db[REL ? kPB : 1][NU], eb[REL ? kPB : 1][NU];
+  // The full consensus step of partner j: gold is its dual before the step,
+  // pj and qj its positions of this step and of the previous one, Dq and eq
+  // its relaxed planes (REL).
+  auto full = [&](int j, float gold, const float *pj, const float *qj, const float *Dq, const float *eq) {
+    float n[NU];
+    pair_normal<NX, NU>(pb, ws, sc, i, j, t, pi, pj, n);
+    // lambda_ij of the previous step, -gamma_prev n_prev
+    float lown[NU];
+    {
+      float np_[NU];
+      if (frozen) {
 #pragma unroll
-    for (int q = 0; q < kPB; ++q)
-      if (j0 + q < np) {
-        gb[q] = (!MASK || was_on(jof(j0 + q))) ? gm[gbase + jof(j0 + q) * N] : 0.f;
-        partner(jof(j0 + q), pjb[q], qjb[q]);
-        if constexpr (REL) {
+        for (int c = 0; c < NU; ++c) np_[c] = n[c];
+      } else if (gold != 0.f) {
+        pair_normal<NX, NU>(pb, ws, sc, i, j, t, qi, qj, np_);
+      } else {
+        // an inactive pair's dual is zero whatever its normal
 #pragma unroll
-          for (int c = 0; c < NU; ++c) {
-            Db[q][c] = ob[c * LS + gbase + jof(j0 + q) * N];
-            eb[q][c] = ob[(NU + c) * LS + gbase + jof(j0 + q) * N];
-          }
-        }
+        for (int c = 0; c < NU; ++c) np_[c] = 0.f;
       }
 #pragma unroll
-    for (int q = 0; q < kPB; ++q) {
-      if (j0 + q >= np) break;
-      const int j = jof(j0 + q);
-      const float gold = gb[q];
-      const float *pj = pjb[q], *qj = qjb[q];
-      if constexpr (!REL) {
-        // A pair that was inactive and is now clearly apart (the half-plane
-        // about the separation direction holds with room to spare) stays
-        // inactive: z_ij = C x_i and every dual term is zero, so only the
-        // copies' norm and the zero dual are recorded.
-        if (!frozen && gold == 0.f) {
+      for (int c = 0; c < NU; ++c) lown[c] = -gold * np_[c];
+    }
+    const int li = gbase + j * N;  // this lane's ordered copy (i, j)
+    float g = 0.f;
+    float abv[NU];
+#pragma unroll
+    for (int c = 0; c < NU; ++c) {
+      // a - b; relaxed: xh_i - xh_j = alpha (p_i - p_j) + (1 - alpha) D
+      float dx;
+      if constexpr (REL) dx = fmaf(al, pi[c] - pj[c], bl * Dq[c]);
+      else dx = pi[c] - pj[c];
+      abv[c] = dx + 2.0f * irho * lown[c];
+      g = fmaf(n[c], abv[c], g);
+    }
+    const float v = pb.dmin - g;
+    const float gam = 0.5f * rho * fmaxf(v, 0.f);
+#pragma unroll
+    for (int c = 0; c < NU; ++c) {
+      const float lo = -gam * n[c];                  // lambda_ij after Eq. 5
+      const float dl = (lown[c] - lo) * irho;        // z_ij - xh_i
+      if constexpr (REL) {
+        // e' = z_ij - C x_i = (1 - alpha)(z^k_ij - C x_i) + dl, z^k_ij = C x^k_i + e
+        const float en = fmaf(bl, (qi[c] + eq[c]) - pi[c], dl);
+        const float zo = pi[c] + en;
+        ob[c * LS + li] = fmaf(fmaxf(v, 0.f), n[c], abv[c]);   // z_ij - z_ji after the projection
+        ob[(NU + c) * LS + li] = en;
+        es[c] += fmaf(rho, en, -lo);                 // rho (z_ij - C x_i) - lam_new
+        zd[c] += en;
+        ls[c] += lo;
+        r2 = fmaf(en, en, r2);
+        z2 = fmaf(zo, zo, z2);
+      } else {
+        const float zo = pi[c] + dl;
+        es[c] += lown[c] - 2.0f * lo;                // rho z_ij - lam_new - rho C x_i
+        zd[c] += dl;
+        ls[c] += lo;
+        r2 = fmaf(dl, dl, r2);
+        z2 = fmaf(zo, zo, z2);
+      }
+    }
+    // (the half-plane is active at this step iff gam > 0)
+    if constexpr (MASK) {
+      const bool on = gam > 0.f;
+      if (on || gold != 0.f) gm[li] = gam;
+      if (on) {
+        if (j < 32) nm0 |= 1u << j;
+        else nm1 |= 1u << (j - 32);
+      }
+    } else {
+      gm[li] = gam;
+    }
+  };
+  if (REL || frozen) {
+    // every partner takes the full step, in batches of kPB
+    for (int j0 = 0; j0 < np; j0 += kPB) {
+      float gb[kPB], pjb[kPB][NU], qjb[kPB][NU];
+      float Db[REL ? kPB : 1][NU], eb[REL ? kPB : 1][NU];
+#pragma unroll
+      for (int q = 0; q < kPB; ++q)
+        if (j0 + q < np) {
+          gb[q] = (!MASK || was_on(jof(j0 + q))) ? gm[gbase + jof(j0 + q) * N] : 0.f;
+          partner(jof(j0 + q), pjb[q], qjb[q]);
+          if constexpr (REL) {
+#pragma unroll
+            for (int c = 0; c < NU; ++c) {
+              Db[q][c] = ob[c * LS + gbase + jof(j0 + q) * N];
+              eb[q][c] = ob[(NU + c) * LS + gbase + jof(j0 + q) * N];
+            }
+          }
+        }
+#pragma unroll
+      for (int q = 0; q < kPB; ++q) {
+        if (j0 + q >= np) break;
+        full(jof(j0 + q), gb[q], pjb[q], qjb[q], Db[REL ? q : 0], eb[REL ? q : 0]);
+      }
+    }
+  } else {
+    // Normals of the iterates, partners in chunks of 32.  A scan finds the
+    // partners that need the full step: a nonzero dual before the step, or
+    // a squared distance of at most far2.  The others were inactive and are
+    // clearly apart, so the half-plane about their separation direction
+    // holds with room to spare and they stay inactive: z_ij = C x_i and
+    // every dual term is zero, and the scan records only the copy's norm
+    // (and, without the mask, the zero dual).  The partners found then take
+    // the full step in increasing order, up to four per lane at a time.  A
+    // wave's lanes thus run the full step together: in a crossing, most
+    // partner slots of a wave hold a near partner of some lane, while each
+    // lane has few.
+    for (int c0 = 0; c0 < np; c0 += 32) {
+      const int cn = min(32, np - c0);
+      unsigned need = 0u;
+      for (int q0 = 0; q0 < cn; q0 += kPB) {
+        float gb[kPB], pjb[kPB][NU];
+#pragma unroll
+        for (int q = 0; q < kPB; ++q)
+          if (q0 + q < cn) {
+            const int j = jof(c0 + q0 + q);
+            if constexpr (MASK) gb[q] = was_on(j) ? 1.f : 0.f;
+            else gb[q] = gm[gbase + j * N];
+            partner_pos(j, pjb[q]);
+          }
+#pragma unroll
+        for (int q = 0; q < kPB; ++q) {
+          if (q0 + q >= cn) break;
           float d2 = 0.f;
 #pragma unroll
-          for (int c = 0; c < NU; ++c) d2 = fmaf(pi[c] - pj[c], pi[c] - pj[c], d2);
-          if (d2 > far2) {
+          for (int c = 0; c < NU; ++c) d2 = fmaf(pi[c] - pjb[q][c], pi[c] - pjb[q][c], d2);
+          if (gb[q] == 0.f && d2 > far2) {
 #pragma unroll
             for (int c = 0; c < NU; ++c) z2 = fmaf(pi[c], pi[c], z2);
-            if constexpr (!MASK) gm[gbase + j * N] = 0.f;   // (with the mask: zero already)
-            continue;
+            if constexpr (!MASK) gm[gbase + jof(c0 + q0 + q) * N] = 0.f;   // (with the mask: zero already)
+          } else {
+            need |= 1u << (q0 + q);
           }
         }
       }
-      float n[NU];
-      pair_normal<NX, NU>(pb, ws, sc, i, j, t, pi, pj, n);
-      // lambda_ij of the previous step, -gamma_prev n_prev
-      float lown[NU];
-      {
-        float np_[NU];
-        if (frozen) {
+      while (need) {
+        int jb[4];
+        float gb[4], pjb[4][NU], qjb[4][NU];
 #pragma unroll
-          for (int c = 0; c < NU; ++c) np_[c] = n[c];
-        } else if (gold != 0.f) {
-          pair_normal<NX, NU>(pb, ws, sc, i, j, t, qi, qj, np_);
-        } else {
-          // an inactive pair's dual is zero whatever its normal
-#pragma unroll
-          for (int c = 0; c < NU; ++c) np_[c] = 0.f;
+        for (int b = 0; b < 4; ++b) {
+          jb[b] = -1;
+          if (need) {
+            const int j = jof(c0 + __builtin_ctz(need));
+            need &= need - 1u;
+            jb[b] = j;
+            gb[b] = (!MASK || was_on(j)) ? gm[gbase + j * N] : 0.f;
+            partner(j, pjb[b], qjb[b]);
+          }
         }
 #pragma unroll
-        for (int c = 0; c < NU; ++c) lown[c] = -gold * np_[c];
-      }
-      const int li = gbase + j * N;  // this lane's ordered copy (i, j)
-      float g = 0.f;
-      float abv[NU];
-#pragma unroll
-      for (int c = 0; c < NU; ++c) {
-        // a - b; relaxed: xh_i - xh_j = alpha (p_i - p_j) + (1 - alpha) D
-        float dx;
-        if constexpr (REL) dx = fmaf(al, pi[c] - pj[c], bl * Db[q][c]);
-        else dx = pi[c] - pj[c];
-        abv[c] = dx + 2.0f * irho * lown[c];
-        g = fmaf(n[c], abv[c], g);
-      }
-      const float v = pb.dmin - g;
-      const float gam = 0.5f * rho * fmaxf(v, 0.f);
-#pragma unroll
-      for (int c = 0; c < NU; ++c) {
-        const float lo = -gam * n[c];                  // lambda_ij after Eq. 5
-        const float dl = (lown[c] - lo) * irho;        // z_ij - xh_i
-        if constexpr (REL) {
-          // e' = z_ij - C x_i = (1 - alpha)(z^k_ij - C x_i) + dl, z^k_ij = C x^k_i + e
-          const float en = fmaf(bl, (qi[c] + eb[q][c]) - pi[c], dl);
-          const float zo = pi[c] + en;
-          ob[c * LS + li] = fmaf(fmaxf(v, 0.f), n[c], abv[c]);   // z_ij - z_ji after the projection
-          ob[(NU + c) * LS + li] = en;
-          es[c] += fmaf(rho, en, -lo);                 // rho (z_ij - C x_i) - lam_new
-          zd[c] += en;
-          ls[c] += lo;
-          r2 = fmaf(en, en, r2);
-          z2 = fmaf(zo, zo, z2);
-        } else {
-          const float zo = pi[c] + dl;
-          es[c] += lown[c] - 2.0f * lo;                // rho z_ij - lam_new - rho C x_i
-          zd[c] += dl;
-          ls[c] += lo;
-          r2 = fmaf(dl, dl, r2);
-          z2 = fmaf(zo, zo, z2);
-        }
-      }
-      // (the half-plane is active at this step iff gam > 0)
-      if constexpr (MASK) {
-        const bool on = gam > 0.f;
-        if (on || gold != 0.f) gm[li] = gam;
-        if (on) {
-          if (j < 32) nm0 |= 1u << j;
-          else nm1 |= 1u << (j - 32);
-        }
-      } else {
-        gm[li] = gam;
+        for (int b = 0; b < 4; ++b)
+          if (jb[b] >= 0) full(jb[b], gb[b], pjb[b], qjb[b], nullptr, nullptr);
       }
     }
   }
