@@ -58,10 +58,12 @@ enum { TB_F = 0, TB_B, TB_L, TB_A, TB_XO, TB_UO, TB_PO, TB_D, TB_NCOL };
 enum { ST_STATUS = 0, ST_ITERS, ST_CAP, ST_DONE, ST_NEAR, ST_COLD, ST_NCOL = 8 };
 // Per-scenario float state columns.
 enum { SN_R = 0, SN_S, SN_EPRI, SN_EDUAL, SN_NCOL = 4 };
-// Per-scenario counters (int64).
 // Per-scenario counters (int64): work units, and in the batched kernel the
 // time spent in each phase (ticks of the 100 MHz device real-time clock).
 enum { CT_PASSES = 0, CT_REFACTOR, CT_AFFINE, CT_PAIRS, CT_T_X, CT_T_PAIR, CT_T_TEST, CT_RESERVED, CT_NCOL = 8 };
+// the first CT_NXU columns are the x-update's own (passes, refactored and
+// affine stages), counted per lane
+constexpr int CT_NXU = 3;
 
 struct WS {
   const int *N, *T;                  // [S]

@@ -723,7 +723,7 @@ __device__ void refine_solution(const Prob &pb, const V &m, int T, int n_nbr, bo
 // view's stages: agent-stages or axis-stages).
 template <class V>
 __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, const V &m, int k,
-                             long long cnt[CT_NCOL]) {
+                             unsigned cnt[CT_NXU]) {
   constexpr int NX = V::NX, NU = V::NU;
   using D = Dyn<NX, NU, V::DI>;
   const int T = sc.T;
@@ -886,7 +886,7 @@ __host__ __device__ constexpr int xupdate_lanes(int N) { return DI ? N * NU : N;
 // 2 T N NU floats.
 template <int NX, int NU, bool DI, bool LA = false>
 __device__ __forceinline__ int local_xupdate(const Prob &pb, const WS &ws, const Scen &sc, int l, int k,
-                                             long long cnt[CT_NCOL], float *la = nullptr) {
+                                             unsigned cnt[CT_NXU], float *la = nullptr) {
   if constexpr (DI) {
     AxisView<NX, NU, LA> m(pb, ws, sc, l / NU, l % NU);
     if constexpr (LA) {
@@ -956,12 +956,15 @@ __device__ __forceinline__ void pair_normal(const Prob &pb, const WS &ws, const 
 // gamma) and e = z_ij - C x_i (offsets stay small).  The duals keep their
 // collapsed form lambda_ij = -gamma n, since the projection still moves the
 // pair symmetrically about its midpoint.
-// MASK (N <= 64): the agent-stage keeps a bit mask of its partners j whose
-// gamma (ordered copy (i, j)) is nonzero, in the residual slots RED+5 (j <
-// 32) and RED+6; gamma is read only where the bit is set and written only
-// where it was or becomes nonzero.  The stored gammas stay exact (zero where
-// the bit is clear), so every other reader sees the same values, while an
-// inactive pair, most of them, costs no memory access.
+// Partner masks (every scenario of at most 64 agents; MASK: known to hold
+// for the whole launch): the agent-stage keeps a bit mask of its partners j
+// whose gamma (ordered copy (i, j)) is nonzero, in the residual slots RED+5
+// (j < 32) and RED+6; gamma is read only where the bit is set and written
+// only where it was or becomes nonzero.  The stored gammas stay exact (zero
+// where the bit is clear), so every other reader sees the same values, and
+// every mode computes the same iterates, while an inactive pair, most of
+// them, costs no memory access.  A set bit whose gamma was cleared by other
+// code only costs a read of that zero.
 template <int NX, int NU, bool REL, bool MASK = false>
 __device__ void pair_agent_stage_impl(const Prob &pb, const WS &ws, const Scen &sc, int i, int t,
                                       const float *__restrict__ lpos, const float *__restrict__ lprev, int lofs) {
@@ -1025,8 +1028,9 @@ __device__ void pair_agent_stage_impl(const Prob &pb, const WS &ws, const Scen &
   // below the distance at which the normal falls back to the references
   // (unit_normal), whose half-plane does not follow the positions
   const float far2 = fmaxf((1.001f * pb.dmin) * (1.001f * pb.dmin), 1e-12f);
-  unsigned mw0 = 0u, mw1 = 0u, nm0 = 0u, nm1 = 0u;   // MASK: partners with gamma != 0, before / after
-  if constexpr (MASK) {
+  const bool msk = MASK || N <= 64;
+  unsigned mw0 = 0u, mw1 = 0u, nm0 = 0u, nm1 = 0u;   // msk: partners with gamma != 0, before / after
+  if (msk) {
     mw0 = __float_as_uint(Ri(F::RED + 5));
     if (N > 32) mw1 = __float_as_uint(Ri(F::RED + 6));
   }
@@ -1093,7 +1097,7 @@ __device__ void pair_agent_stage_impl(const Prob &pb, const WS &ws, const Scen &
       }
     }
     // (the half-plane is active at this step iff gam > 0)
-    if constexpr (MASK) {
+    if (msk) {
       const bool on = gam > 0.f;
       if (on || gold != 0.f) gm[li] = gam;
       if (on) {
@@ -1112,7 +1116,7 @@ __device__ void pair_agent_stage_impl(const Prob &pb, const WS &ws, const Scen &
 #pragma unroll
       for (int q = 0; q < kPB; ++q)
         if (j0 + q < np) {
-          gb[q] = (!MASK || was_on(jof(j0 + q))) ? gm[gbase + jof(j0 + q) * N] : 0.f;
+          gb[q] = (!msk || was_on(jof(j0 + q))) ? gm[gbase + jof(j0 + q) * N] : 0.f;
           partner(jof(j0 + q), pjb[q], qjb[q]);
           if constexpr (REL) {
 #pragma unroll
@@ -1149,8 +1153,7 @@ __device__ void pair_agent_stage_impl(const Prob &pb, const WS &ws, const Scen &
         for (int q = 0; q < kPB; ++q)
           if (q0 + q < cn) {
             const int j = jof(c0 + q0 + q);
-            if constexpr (MASK) gb[q] = was_on(j) ? 1.f : 0.f;
-            else gb[q] = gm[gbase + j * N];
+            gb[q] = msk ? (was_on(j) ? 1.f : 0.f) : gm[gbase + j * N];
             partner_pos(j, pjb[q]);
           }
 #pragma unroll
@@ -1162,7 +1165,7 @@ __device__ void pair_agent_stage_impl(const Prob &pb, const WS &ws, const Scen &
           if (gb[q] == 0.f && d2 > far2) {
 #pragma unroll
             for (int c = 0; c < NU; ++c) z2 = fmaf(pi[c], pi[c], z2);
-            if constexpr (!MASK) gm[gbase + jof(c0 + q0 + q) * N] = 0.f;   // (with the mask: zero already)
+            if (!msk) gm[gbase + jof(c0 + q0 + q) * N] = 0.f;   // (with the mask: zero already)
           } else {
             need |= 1u << (q0 + q);
           }
@@ -1178,7 +1181,7 @@ __device__ void pair_agent_stage_impl(const Prob &pb, const WS &ws, const Scen &
             const int j = jof(c0 + __builtin_ctz(need));
             need &= need - 1u;
             jb[b] = j;
-            gb[b] = (!MASK || was_on(j)) ? gm[gbase + j * N] : 0.f;
+            gb[b] = (!msk || was_on(j)) ? gm[gbase + j * N] : 0.f;
             partner(j, pjb[b], qjb[b]);
           }
         }
@@ -1188,7 +1191,7 @@ __device__ void pair_agent_stage_impl(const Prob &pb, const WS &ws, const Scen &
       }
     }
   }
-  if constexpr (MASK) {
+  if (msk) {
     Ri(F::RED + 5) = __uint_as_float(nm0);
     if (N > 32) Ri(F::RED + 6) = __uint_as_float(nm1);
   }
@@ -1716,6 +1719,13 @@ __device__ __forceinline__ void add_counters(const WS &ws, int s, const long lon
     if (c[q]) atomicAdd(ws.cnt + (long long)s * CT_NCOL + q, (unsigned long long)c[q]);
 }
 
+// the x-update's own counters of one lane (the first CT_NXU columns)
+__device__ __forceinline__ void add_counters(const WS &ws, int s, const unsigned c[CT_NXU]) {
+#pragma unroll
+  for (int q = 0; q < CT_NXU; ++q)
+    if (c[q]) atomicAdd(ws.cnt + (long long)s * CT_NCOL + q, (unsigned long long)c[q]);
+}
+
 // ===========================================================================
 // Kernels: plain path (one scenario, host loop)
 // ===========================================================================
@@ -1732,7 +1742,7 @@ __global__ __launch_bounds__(64) void k_xupdate(Prob pb, WS ws, int s, int k) {
   const Scen sc = load_scen(ws, s);
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= xupdate_lanes<NX, NU, DI>(sc.N)) return;
-  long long cnt[CT_NCOL] = {};
+  unsigned cnt[CT_NXU] = {};
   const int capped = local_xupdate<NX, NU, DI>(pb, ws, sc, l, k, cnt);
   if (capped) atomicOr(ws.sst + (long long)s * ST_NCOL + ST_CAP, 1);
   add_counters(ws, s, cnt);
@@ -1798,6 +1808,7 @@ __device__ __forceinline__ void persistent_body(Prob pb, WS ws, int S, int lds_f
   __shared__ int s_item;
   __shared__ int s_cap;
   __shared__ int s_done;
+  __shared__ long long s_tc[CT_NCOL];
   const int tid = threadIdx.x, nt = blockDim.x;
   for (;;) {
     if (tid == 0) s_item = atomicAdd(ws.queue, 1);
@@ -1810,7 +1821,12 @@ __device__ __forceinline__ void persistent_body(Prob pb, WS ws, int S, int lds_f
     const Scen sc = load_scen(ws, s);
     scenario_setup<NX, NU, VAR == 2>(pb, ws, sc, tid, nt);
     if (tid == 0) { s_cap = 0; s_done = 0; }
-    long long cnt[CT_NCOL] = {};
+    // each lane's x-update counters in registers (32 bits: one scenario's
+    // counts fit), the workgroup's pair count and phase times in LDS, kept by
+    // thread 0
+    unsigned cnt[CT_NXU] = {};
+    if (tid == 0)
+      for (int q = 0; q < CT_NCOL; ++q) s_tc[q] = 0;
     __syncthreads();
     for (int k = 1; k <= pb.max_iter; ++k) {
       const unsigned long long c0 = wall_clock64();
@@ -1842,7 +1858,7 @@ __device__ __forceinline__ void persistent_body(Prob pb, WS ws, int S, int lds_f
             pair_agent_stage_impl<NX, NU, VAR == 1, VAR == 3>(pb, ws, sc, idx % sc.N, idx / sc.N + 1,
                                                     staged ? lds_pos : nullptr, staged ? lds_prev : nullptr, 0);
         }
-        if (tid == 0) cnt[CT_PAIRS] += (long long)sc.N * (sc.N - 1) / 2 * sc.T;
+        if (tid == 0) s_tc[CT_PAIRS] += (long long)sc.N * (sc.N - 1) / 2 * sc.T;
         __syncthreads();
         if (staged) {
           // the positions of this step are in LDS already
@@ -1871,13 +1887,18 @@ __device__ __forceinline__ void persistent_body(Prob pb, WS ws, int S, int lds_f
         }
       }
       if (tid == 0) {
-        cnt[CT_T_X] += (long long)(c1 - c0);
-        cnt[CT_T_PAIR] += (long long)(c2 - c1);
-        cnt[CT_T_TEST] += (long long)(wall_clock64() - c2);
+        s_tc[CT_T_X] += (long long)(c1 - c0);
+        s_tc[CT_T_PAIR] += (long long)(c2 - c1);
+        s_tc[CT_T_TEST] += (long long)(wall_clock64() - c2);
       }
       if (s_done) break;
     }
     add_counters(ws, s, cnt);
+    if (tid == 0) {
+      long long c[CT_NCOL];
+      for (int q = 0; q < CT_NCOL; ++q) c[q] = s_tc[q];
+      add_counters(ws, s, c);
+    }
     __syncthreads();
   }
 }
@@ -1955,7 +1976,7 @@ __global__ __launch_bounds__(64) void k_wide_x(Prob pb, WS ws, const int *wide) 
   const Scen sc = load_scen(ws, s);
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= xupdate_lanes<NX, NU, DI>(sc.N)) return;
-  long long cnt[CT_NCOL] = {};
+  unsigned cnt[CT_NXU] = {};
   if (local_xupdate<NX, NU, DI>(pb, ws, sc, l, uni(wide[0]), cnt)) atomicOr(st + ST_CAP, 1);
   add_counters(ws, s, cnt);
 }
