@@ -91,6 +91,7 @@ struct WS {
   float *momst;
   // optional output: [S][max_iter][2] residual norms of every stopping test
   float *hist;
+  float *tpart;                      // many-workgroup mode: block sums of the stopping test [blocks][5][64]
   // inputs (caller layouts)
   const float *x0, *xref, *qd, *rd, *normals;
   const float *aq, *ar, *alo, *ahi;  // heterogeneous agents (each NULL: the shared value)

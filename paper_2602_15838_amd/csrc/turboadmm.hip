@@ -1425,35 +1425,61 @@ __device__ __forceinline__ void commit_positions(const WS &ws, const Scen &sc, i
     for (int c = 0; c < NU; ++c) fref(R, GS, (unsigned)idx, F::XP + c) = fref(R, GS, (unsigned)idx, F::X + c);
 }
 
+// The stopping test's sums over agent-stages run in blocks of kTestBlock
+// consecutive agent-stages (t >= 1, agent fastest): in block b, lane l adds
+// the block's stages l, l + 64, ... in that order, starting from zero; the
+// lane then adds the block sums in block order, and a fixed butterfly adds
+// the lanes.  Every mode keeps this order (the many-workgroup mode forms the
+// blocks in parallel), so every mode computes the same residuals.
+constexpr int kTestBlock = 512;
+
+template <int NX, int NU>
+__device__ __forceinline__ void test_block(const WS &ws, const Scen &sc, int b0, int lane, float p[5]) {
+  using F = Fld<NX, NU>;
+  const float *R = ws.fr + sc.fo;
+  const int NT = sc.N * sc.T;
+  constexpr int U = kTestBlock / 64;
+  float v[U][5];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int idx = b0 + lane + 64 * u;
+    if (idx < NT) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) v[u][q] = R[fidx((unsigned)sc.GS, (unsigned)(sc.N + idx), F::RED + q)];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 5; ++q) p[q] = 0.f;
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (b0 + lane + 64 * u < NT) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) p[q] += v[u][q];
+    }
+}
+
 // Residual norms and the stopping test of Sec. V-A (Boyd et al. 2011, Sec.
 // 3.3.1): p = 2 P T dp consensus rows, n = N T dp position variables.
-// Executed by one full wavefront; the sum over agent-stages has a fixed order
-// (lane l takes stages l, l+64, ...; then a fixed butterfly).
+// Executed by one full wavefront, summing in the block order above; `part`:
+// the block sums already formed ([b][5][64]), else formed here.
 // MOM: the momentum variant's combined residual and extrapolation decision.
 template <int NX, int NU, bool MOM = false>
-__device__ int scenario_test(const Prob &pb, const WS &ws, const Scen &sc, int k, int lane, int cap_hit) {
+__device__ int scenario_test(const Prob &pb, const WS &ws, const Scen &sc, int k, int lane, int cap_hit,
+                             const float *part = nullptr) {
   using F = Fld<NX, NU>;
   const float *R = ws.fr + sc.fo;
   const int NT = sc.N * sc.T;
   float a[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-  // lane l adds stages l, l + 64, ... in that order; the loads of two of
-  // them are issued before the first is added
-  for (int idx0 = lane; idx0 < NT; idx0 += 2 * 64) {
-    float v[2][5];
+  for (int b0 = 0, b = 0; b0 < NT; b0 += kTestBlock, ++b) {
+    float p[5];
+    if (part) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int idx = idx0 + 64 * u;
-      if (idx < NT) {
-#pragma unroll
-        for (int q = 0; q < 5; ++q) v[u][q] = R[fidx((unsigned)sc.GS, (unsigned)(sc.N + idx), F::RED + q)];
-      }
+      for (int q = 0; q < 5; ++q) p[q] = part[(b * 5 + q) * 64 + lane];
+    } else {
+      test_block<NX, NU>(ws, sc, b0, lane, p);
     }
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
-      if (idx0 + 64 * u < NT) {
-#pragma unroll
-        for (int q = 0; q < 5; ++q) a[q] += v[u][q];
-      }
+    for (int q = 0; q < 5; ++q) a[q] += p[q];
   }
 #pragma unroll
   for (int q = 0; q < 5; ++q) a[q] = wave_sum(a[q]);
@@ -2021,6 +2047,45 @@ __global__ __launch_bounds__(256) void k_wide_pair(Prob pb, WS ws, const int *wi
   }
 }
 
+// one wave per block of the stopping test's sums (kTestBlock agent-stages):
+// the block's sums into ws.tpart, and the positions of the block's
+// agent-stages committed as the previous ones
+template <int NX, int NU>
+__global__ __launch_bounds__(64) void k_wide_tpart(Prob pb, WS ws, const int *wide) {
+  const int s = uni(wide[1]);
+  const int *st = ws.sst + (long long)s * ST_NCOL;
+  if (uni(st[ST_DONE])) return;
+  const Scen sc = load_scen(ws, s);
+  const int b = blockIdx.x, b0 = b * kTestBlock, lane = threadIdx.x;
+  if (b0 >= sc.N * sc.T) return;
+  float p[5];
+  test_block<NX, NU>(ws, sc, b0, lane, p);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) ws.tpart[(b * 5 + q) * 64 + lane] = p[q];
+  if (!uni(st[ST_CAP])) {
+    using F = Fld<NX, NU>;
+    float *R = ws.fr + sc.fo;
+    const unsigned GS = (unsigned)sc.GS;
+    const int e = min(sc.N * sc.T, b0 + kTestBlock);
+    constexpr int U = kTestBlock / 64;
+    float xv[U][NU];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = b0 + lane + 64 * u;
+      if (idx < e)
+#pragma unroll
+        for (int c = 0; c < NU; ++c) xv[u][c] = fref(R, GS, (unsigned)(sc.N + idx), F::X + c);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = b0 + lane + 64 * u;
+      if (idx < e)
+#pragma unroll
+        for (int c = 0; c < NU; ++c) fref(R, GS, (unsigned)(sc.N + idx), F::XP + c) = xv[u][c];
+    }
+  }
+}
+
 template <int NX, int NU>
 __global__ __launch_bounds__(64) void k_wide_test(Prob pb, WS ws, const int *wide) {
   const int s = uni(wide[1]);
@@ -2028,9 +2093,8 @@ __global__ __launch_bounds__(64) void k_wide_test(Prob pb, WS ws, const int *wid
   if (uni(st[ST_DONE])) return;
   const Scen sc = load_scen(ws, s);
   const int cap = uni(st[ST_CAP]);
-  if (pb.mom) (void)scenario_test<NX, NU, true>(pb, ws, sc, uni(wide[0]), threadIdx.x, cap);
-  else (void)scenario_test<NX, NU>(pb, ws, sc, uni(wide[0]), threadIdx.x, cap);
-  if (!cap) commit_positions<NX, NU>(ws, sc, threadIdx.x, blockDim.x);
+  if (pb.mom) (void)scenario_test<NX, NU, true>(pb, ws, sc, uni(wide[0]), threadIdx.x, cap, ws.tpart);
+  else (void)scenario_test<NX, NU>(pb, ws, sc, uni(wide[0]), threadIdx.x, cap, ws.tpart);
 }
 
 // Momentum in the many-workgroup mode: the extrapolation after the test.
@@ -2324,6 +2388,7 @@ struct Layout {
   size_t o_adirty = 0, o_fr = 0, o_dr = 0, o_wr = 0, o_gam = 0, bytes = 0;
   size_t o_er = 0, o_nrm = 0, o_cidx = 0, o_clist = 0, o_cg = 0, o_m = 0, o_coff = 0, o_cent = 0;
   size_t o_wide = 0;   // wide mode: iteration number, scenario index
+  size_t o_tpart = 0;  // wide mode: block sums of the stopping test, [blocks][5][64]
   size_t o_sqpj = 0, o_sqpi = 0, o_sqpf = 0;   // SQP: objective [S] (FP64); skip, rounds [2][S]; min distance [S]
   size_t o_rho = 0;    // [S][2] penalty of the next / last iteration
   size_t o_orx = 0;    // over-relaxation: [2 nu] planes shaped like the gamma region
@@ -2399,9 +2464,10 @@ bool make_layout(const tadmm_params *p, int S, const int32_t *N, const int32_t *
   L = Layout();
   L.S = S; L.nx = p->nx; L.nu = p->nu; L.NF = fields_per_stage(p->nx, p->nu);
   L.tab.assign((size_t)S * TB_NCOL, 0);
-  long long fo = 0, bo = 0, lo = 0, ao = 0, xo = 0, uo = 0, po = 0, dof = 0;
+  long long fo = 0, bo = 0, lo = 0, ao = 0, xo = 0, uo = 0, po = 0, dof = 0, max_nt = 1;
   for (int s = 0; s < S; ++s) {
     const long long n = N[s], t = T[s];
+    max_nt = std::max(max_nt, n * t);
     if (n < 1 || t < 1) { err = "every scenario needs N >= 1 and T >= 1"; return false; }
     if (n > 4096 || t > 65536) { err = "scenario too large (N <= 4096, T <= 65536)"; return false; }
     const long long GS = n * (t + 1);
@@ -2450,6 +2516,7 @@ bool make_layout(const tadmm_params *p, int S, const int32_t *N, const int32_t *
   L.o_cg = take(sizeof(double) * 6 * (size_t)po);
   L.o_m = take(sizeof(int) * S);
   L.o_wide = take(sizeof(int) * 64);
+  L.o_tpart = take(sizeof(float) * 5 * 64 * (size_t)((max_nt + kTestBlock - 1) / kTestBlock));
   L.o_sqpj = take(sizeof(double) * S);
   L.o_sqpi = take(sizeof(int) * 2 * S);
   L.o_sqpf = take(sizeof(float) * S);
@@ -2646,6 +2713,7 @@ WS make_ws(const Layout &L, char *ws, const tadmm_batch *b) {
   w.mom = L.o_mom ? (float *)(ws + L.o_mom) : nullptr;
   w.momst = L.o_momst ? (float *)(ws + L.o_momst) : nullptr;
   w.hist = nullptr;
+  w.tpart = (float *)(ws + L.o_tpart);
   return w;
 }
 
@@ -2795,6 +2863,7 @@ tadmm_status run_wide(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layout 
     max_work = std::max(max_work, std::max(n * (t + 1), t * n * n));
   }
   const int gx = (int)((xupdate_lanes<NX, NU, DI>((int)max_n) + 63) / 64), gp = (int)((max_nt + 255) / 256);
+  const int gt = (int)((max_nt + kTestBlock - 1) / kTestBlock);   // blocks of the stopping test's sums
   const int gsetup = (int)std::min<long long>((max_work + 255) / 256, 4096);
   // LDS of a pair block: the stages of 256 agent-stages, current and previous positions
   long long max_ng = 0;
@@ -2825,6 +2894,7 @@ tadmm_status run_wide(tadmm_ctx *ctx, const Prob &pb, const WS &w, const Layout 
           hipLaunchKernelGGL((k_wide_x<NX, NU, DI>), dim3(gx), dim3(64), 0, cs, pb, w, (const int *)d_wide);
           hipLaunchKernelGGL((k_wide_pair<NX, NU>), dim3(gp), dim3(256), lds_bytes, cs, pb, w, (const int *)d_wide,
                              lds_floats);
+          hipLaunchKernelGGL((k_wide_tpart<NX, NU>), dim3(gt), dim3(64), 0, cs, pb, w, (const int *)d_wide);
           hipLaunchKernelGGL((k_wide_test<NX, NU>), dim3(1), dim3(64), 0, cs, pb, w, (const int *)d_wide);
           if (pb.mom)
             hipLaunchKernelGGL((k_wide_extrap<NX, NU>), dim3(gp), dim3(256), 0, cs, pb, w, (const int *)d_wide);
