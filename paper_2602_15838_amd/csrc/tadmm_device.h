@@ -138,12 +138,12 @@ struct Fld {
   static constexpr int U = KV + pad4(NU);       // current iterate u_t            [NU]
   static constexpr int X = U + pad4(NU);        // current iterate x_t            [NX]
   static constexpr int UE = X + pad4(NX);       // equality-QP solution u_t       [NU]
-  static constexpr int XP = UE + pad4(NU);      // C x^k (previous positions)     [DP]
+  // (the previous positions C x^k are a dense array after the inputs)
   // written together by every consensus step: the position part of q,
   //   GQP - rho n_nbr C x^k_t - sum_j (lambda_ij^(k-1) - 2 lambda_ij^k)
   // (from the small dual part: no long sums of position-sized terms in
   // FP32), then ZD = sum_j z_ij - n_nbr C x^k                      [2 DP]
-  static constexpr int QZ = XP + pad4(DP);
+  static constexpr int QZ = UE + pad4(NU);
   static constexpr int GQP = QZ + pad4(2 * DP);  // -2 Q_t r_t, positions          [DP]
   // state box on the non-position states: the copy y and its dual mu
   // [2 DP], and the constant velocity tracking term -2 Q_t r_t     [DP]

@@ -64,6 +64,13 @@ template <int NX, int NU>
 __device__ __forceinline__ float &uref(float *R, unsigned GS, unsigned g, int c) {
   return R[(size_t)Fld<NX, NU>::NF * GS + (size_t)axis_region_floats(GS, NU) + (size_t)g * NU + c];
 }
+// The previous positions C x^k are a dense [GS][NU] array after the inputs
+// (the consensus step commits every agent-stage's positions: whole spans).
+template <int NX, int NU>
+__device__ __forceinline__ float &xpref(float *R, unsigned GS, unsigned g, int c) {
+  return R[(size_t)Fld<NX, NU>::NF * GS + (size_t)axis_region_floats(GS, NU) + (size_t)input_region_floats(GS, NU) +
+           (size_t)g * NU + c];
+}
 
 // An agent's dynamics for the dynamics products: its own matrices when the
 // batch gives them, else the shared ones of the kernel arguments.
@@ -976,7 +983,7 @@ __device__ void pair_agent_stage_impl(const Prob &pb, const WS &ws, const Scen &
   float pi[NU], qi[NU];   // positions of this step and of the previous one
   bool bad = false;
 #pragma unroll
-  for (int c = 0; c < NU; ++c) { pi[c] = Ri(F::X + c); qi[c] = Ri(F::XP + c); }
+  for (int c = 0; c < NU; ++c) { pi[c] = Ri(F::X + c); qi[c] = xpref<NX, NU>(R, GS, gi, c); }
 #pragma unroll
   for (int c = 0; c < NX; ++c) bad |= !isfinite(Ri(F::X + c));
   float *gm = ws.gam + sc.lo;
@@ -1000,7 +1007,7 @@ __device__ void pair_agent_stage_impl(const Prob &pb, const WS &ws, const Scen &
 #pragma unroll
       for (int c = 0; c < NU; ++c) {
         pj[c] = R[fidx(GS, (unsigned)(t * N + j), F::X + c)];
-        qj[c] = R[fidx(GS, (unsigned)(t * N + j), F::XP + c)];
+        qj[c] = xpref<NX, NU>(R, GS, (unsigned)(t * N + j), c);
       }
     }
   };
@@ -1422,7 +1429,7 @@ __device__ __forceinline__ void commit_positions(const WS &ws, const Scen &sc, i
   const unsigned GS = (unsigned)sc.GS;
   for (int idx = sc.N + tid; idx < sc.GS; idx += nthreads)
 #pragma unroll
-    for (int c = 0; c < NU; ++c) fref(R, GS, (unsigned)idx, F::XP + c) = fref(R, GS, (unsigned)idx, F::X + c);
+    for (int c = 0; c < NU; ++c) xpref<NX, NU>(R, GS, (unsigned)idx, c) = fref(R, GS, (unsigned)idx, F::X + c);
 }
 
 // The stopping test's sums over agent-stages run in blocks of kTestBlock
@@ -1651,7 +1658,7 @@ __device__ void scenario_setup(const Prob &pb, const WS &ws, const Scen &sc, int
       Rg(F::YP + NU + c) = 0.f;
       if (pb.pbox && t >= 1) qz -= pb.sigma * y0;
       Rg(F::QZ + c) = qz;
-      Rg(F::XP + c) = r[c];
+      xpref<NX, NU>(R, (unsigned)GS, (unsigned)idx, c) = r[c];
       Rg(F::QZ + NU + c) = 0.f;
       uref<NX, NU>(R, (unsigned)GS, (unsigned)idx, c) = 0.f;
     }
@@ -1873,7 +1880,7 @@ __device__ __forceinline__ void persistent_body(Prob pb, WS ws, int S, int lds_f
 #pragma unroll
             for (int c = 0; c < NU; ++c) {
               lds_pos[idx * NU + c] = fref(R, GS, (unsigned)idx, Fld<NX, NU>::X + c);
-              lds_prev[idx * NU + c] = fref(R, GS, (unsigned)idx, Fld<NX, NU>::XP + c);
+              lds_prev[idx * NU + c] = xpref<NX, NU>(R, GS, (unsigned)idx, c);
             }
           __syncthreads();
         }
@@ -1892,7 +1899,7 @@ __device__ __forceinline__ void persistent_body(Prob pb, WS ws, int S, int lds_f
           const unsigned GS = (unsigned)sc.GS;
           for (int idx = sc.N + tid; idx < sc.GS; idx += nt)
 #pragma unroll
-            for (int c = 0; c < NU; ++c) fref(R, GS, (unsigned)idx, Fld<NX, NU>::XP + c) = lds_pos[idx * NU + c];
+            for (int c = 0; c < NU; ++c) xpref<NX, NU>(R, GS, (unsigned)idx, c) = lds_pos[idx * NU + c];
         } else {
           commit_positions<NX, NU>(ws, sc, tid, nt);
         }
@@ -2032,7 +2039,7 @@ __global__ __launch_bounds__(256) void k_wide_pair(Prob pb, WS ws, const int *wi
 #pragma unroll
       for (int c = 0; c < NU; ++c) {
         lds_pos[e * NU + c] = fref(R, GS, (unsigned)(g0 + e), Fld<NX, NU>::X + c);
-        lds_prev[e * NU + c] = fref(R, GS, (unsigned)(g0 + e), Fld<NX, NU>::XP + c);
+        lds_prev[e * NU + c] = xpref<NX, NU>(R, GS, (unsigned)(g0 + e), c);
       }
     __syncthreads();
   }
@@ -2081,7 +2088,7 @@ __global__ __launch_bounds__(64) void k_wide_tpart(Prob pb, WS ws, const int *wi
       const int idx = b0 + lane + 64 * u;
       if (idx < e)
 #pragma unroll
-        for (int c = 0; c < NU; ++c) fref(R, GS, (unsigned)(sc.N + idx), F::XP + c) = xv[u][c];
+        for (int c = 0; c < NU; ++c) xpref<NX, NU>(R, GS, (unsigned)(sc.N + idx), c) = xv[u][c];
     }
   }
 }
@@ -2471,7 +2478,7 @@ bool make_layout(const tadmm_params *p, int S, const int32_t *N, const int32_t *
     if (n < 1 || t < 1) { err = "every scenario needs N >= 1 and T >= 1"; return false; }
     if (n > 4096 || t > 65536) { err = "scenario too large (N <= 4096, T <= 65536)"; return false; }
     const long long GS = n * (t + 1);
-    if ((long long)L.NF * GS + axis_region_floats(GS, p->nu) + input_region_floats(GS, p->nu) >= (1ll << 31) ||
+    if ((long long)L.NF * GS + axis_region_floats(GS, p->nu) + 2 * input_region_floats(GS, p->nu) >= (1ll << 31) ||
         (long long)p->nu * t * n * n >= (1ll << 31) ||
         (long long)p->nx * GS >= (1ll << 31)) {
       err = "scenario too large for 32-bit in-scenario offsets"; return false;
@@ -2479,7 +2486,7 @@ bool make_layout(const tadmm_params *p, int S, const int32_t *N, const int32_t *
     long long *tb = &L.tab[(size_t)s * TB_NCOL];
     tb[TB_F] = fo; tb[TB_B] = bo; tb[TB_L] = lo; tb[TB_A] = ao; tb[TB_XO] = xo; tb[TB_UO] = uo; tb[TB_PO] = po;
     tb[TB_D] = dof;
-    fo += (long long)L.NF * GS + axis_region_floats(GS, p->nu) + input_region_floats(GS, p->nu);
+    fo += (long long)L.NF * GS + axis_region_floats(GS, p->nu) + 2 * input_region_floats(GS, p->nu);
     dof += (long long)p->nx * GS;
     bo += 4ll * GS;
     lo += t * n * n;
