@@ -866,11 +866,14 @@ __device__ void eqp_scenario(const Prob &pb, const WS &ws, const EWS &ew, const 
   __syncthreads();
 }
 
-template <int NX, int NU, bool DI, class R>
-__global__ __launch_bounds__(256) void k_eqp(Prob pb, WS ws, EWS ew, EqpIO io, int S, int mode, int max_cg,
-                                             double tol) {
-  __shared__ double red[4];
-  __shared__ int scan[257];
+// BT threads per workgroup: 256, or 512 where a scenario has more axis
+// problems than 256 (every sweep of a MINRES iteration then runs all of them
+// at once)
+template <int NX, int NU, bool DI, class R, int BT = 256>
+__global__ __launch_bounds__(BT) void k_eqp(Prob pb, WS ws, EWS ew, EqpIO io, int S, int mode, int max_cg,
+                                            double tol) {
+  __shared__ double red[BT / 64];
+  __shared__ int scan[BT + 1];
   for (int s = blockIdx.x; s < S; s += gridDim.x)
     eqp_scenario<NX, NU, DI, R>(pb, ws, ew, io, s, mode, max_cg, tol, red, scan);
 }

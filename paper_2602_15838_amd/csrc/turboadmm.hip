@@ -3127,8 +3127,13 @@ tadmm_status eqp_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *out
   const EWS ew = make_ews(L, w8);
   const int grid = std::min(L.S, 65535);
   const int max_cg = 4000;
+  int max_lanes = 0;
+  for (int s = 0; s < L.S; ++s) max_lanes = std::max(max_lanes, xupdate_lanes<NX, NU, DI>(b->n_agents[s]));
   HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
-  if (ctx->prm.eqp_fp64)
+  if (ctx->prm.eqp_fp64 && max_lanes > 256)
+    hipLaunchKernelGGL((k_eqp<NX, NU, DI, double, 512>), dim3(grid), dim3(512), 0, ctx->stream, pb, w, ew, io, L.S,
+                       mode, max_cg, 1e-12);
+  else if (ctx->prm.eqp_fp64)
     hipLaunchKernelGGL((k_eqp<NX, NU, DI, double>), dim3(grid), dim3(256), 0, ctx->stream, pb, w, ew, io, L.S, mode,
                        max_cg, 1e-12);
   else
