@@ -97,8 +97,8 @@ def step_stats(v):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--scenarios", type=int, default=4096)
     ap.add_argument("--plain-sample", type=int, default=-1, help="scenarios of the plain path (-1: the whole batch)")
     ap.add_argument("--cpu-sample", type=int, default=640)
