@@ -292,7 +292,7 @@ tadmm_status tadmm_solve_noalloc(tadmm_ctx *ctx, const tadmm_batch *batch, const
  * Schur system D H^-1 D' nu = d - D w(0) by MINRES (warm start: the duals of
  * the last consensus step; when the held rows cannot all hold, which a solve
  * stopped at max_iter can leave, MINRES stops at a least-squares solution,
- * once ||S r|| <= 1e-6 ||S|| ||r|| (3e-4 with eqp_fp64 = 0), or after 4000
+ * once ||S r|| <= 1e-4 ||S|| ||r|| (3e-4 with eqp_fp64 = 0), or after 4000
  * iterations).  It overwrites out->x and out->u
  * (required, DEVICE, layouts of tadmm_out) with the polished solution and
  * keeps it in the workspace.  Call it once per solve; TADMM_ERR_STATE without

@@ -755,7 +755,7 @@ __device__ void eqp_scenario(const Prob &pb, const WS &ws, const EWS &ew, const 
   const double beta1 = sqrt(block_sum(acc, red));
   const double ref = (mode == EQ_POLISH) ? fmax((double)pb.dmin * sqrt((double)m), beta1) : beta1;
   const int cap = min(max_cg, 2 * m + 20);
-  const double ls_tol = sqrt(tol);
+  const double ls_tol = fmax(sqrt(tol), 1e-4);
   double beta = beta1, oldb = 0.0, dbar = 0.0, epsln = 0.0, phibar = beta1, cs = -1.0, sn = 0.0, gmax = 0.0;
   double anorm2 = 0.0;   // Frobenius norm of the Lanczos tridiagonal so far, an estimate of ||S||^2
   int it = 0;

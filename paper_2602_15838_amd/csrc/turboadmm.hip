@@ -3136,6 +3136,9 @@ tadmm_status eqp_impl(tadmm_ctx *ctx, const tadmm_batch *b, const tadmm_out *out
   else if (ctx->prm.eqp_fp64)
     hipLaunchKernelGGL((k_eqp<NX, NU, DI, double>), dim3(grid), dim3(256), 0, ctx->stream, pb, w, ew, io, L.S, mode,
                        max_cg, 1e-12);
+  else if (max_lanes > 256)
+    hipLaunchKernelGGL((k_eqp<NX, NU, DI, float, 512>), dim3(grid), dim3(512), 0, ctx->stream, pb, w, ew, io, L.S,
+                       mode, max_cg, 1e-7);
   else
     hipLaunchKernelGGL((k_eqp<NX, NU, DI, float>), dim3(grid), dim3(256), 0, ctx->stream, pb, w, ew, io, L.S, mode,
                        max_cg, 1e-7);
