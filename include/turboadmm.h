@@ -230,7 +230,12 @@ typedef struct {
                                 agent-stages, affine agent-stage passes, pair-
                                 step updates; batched mode also the time spent
                                 in the x-update, pair and test phases (ticks of
-                                the 100 MHz device clock, one workgroup), 0     */
+                                the 100 MHz device clock, one workgroup), 0.
+                                Diagnostics only: batched mode tallies each
+                                lane's share of the first three over a whole
+                                scenario in 32 bits, so they wrap once one
+                                lane's share passes 2^32 (max_iter x T x
+                                passes per iteration beyond about 4e9)        */
   float *hist;               /* [S][max_iter][2] or NULL: for every iteration k
                                 = 1..iters the primal and dual residual norms
                                 ||r||, ||s|| of its stopping test (Sec. V-A) at
