@@ -298,14 +298,26 @@ struct SweepStage {
   }
 };
 
+// Later passes of one x-update change neither q nor the factors above the
+// highest stage ts whose working set changed (the refactor starts there), so
+// p_t above ts is what the previous sweep computed: the sweep stores p at
+// every stage that is a multiple of kSweepMark, and a sweep given ts < T - 1
+// restarts from the first such stage above ts (ts < 0 or >= T - 1: from T).
+constexpr int kSweepMark = 8;
 template <class V>
-__device__ __forceinline__ void affine_sweep(const Prob &pb, const V &m, int T) {
+__device__ __forceinline__ int affine_sweep(const Prob &pb, const V &m, int T, int ts = -1) {
   constexpr int NX = V::NX, NU = V::NU, B = V::kSweepBatch;
   using D = Dyn<NX, NU, V::DI>;
+  const int top = (ts >= 0 && ts < T - 1) ? min(T, (ts + kSweepMark) / kSweepMark * kSweepMark) : T;
   float p[NX];
+  if (top == T) {
 #pragma unroll
-  for (int r = 0; r < NX; ++r) p[r] = m.Q(r, T);
-  for (int t0 = T - 1; t0 >= 0; t0 -= B) {
+    for (int r = 0; r < NX; ++r) p[r] = m.Q(r, T);
+  } else {
+#pragma unroll
+    for (int r = 0; r < NX; ++r) p[r] = m.PV(r, top);
+  }
+  for (int t0 = top - 1; t0 >= 0; t0 -= B) {
     SweepStage<V> st[B];
 #pragma unroll
     for (int q = 0; q < B; ++q)
@@ -318,8 +330,9 @@ __device__ __forceinline__ void affine_sweep(const Prob &pb, const V &m, int T) 
       bool fixed = false;
 #pragma unroll
       for (int a = 0; a < NU; ++a) fixed |= (cur.wt[a] != 0);
-      // p_{t+1} is read back only for the costates of a stage with a fixed input
-      if (fixed) {
+      // p_{t+1} is read back for the costates of a stage with a fixed input,
+      // and by a restarted sweep at the marked stages
+      if (fixed || (t + 1) % kSweepMark == 0) {
 #pragma unroll
         for (int r = 0; r < NX; ++r) m.PV(r, t + 1) = p[r];
       }
@@ -347,6 +360,7 @@ __device__ __forceinline__ void affine_sweep(const Prob &pb, const V &m, int T) 
       }
     }
   }
+  return top;
 }
 
 // relative FP32 rounding allowance of a multiplier (about 64 ulps)
@@ -815,9 +829,12 @@ __device__ int agent_xupdate(const Prob &pb, const WS &ws, const Scen &sc, const
   PendingStep pd{false, 0.f, -1, 0, 0.f};
   for (int it = 0; it < cap; ++it) {
     if (!pb.cache) td = T - 1;
+    // the first pass sweeps every stage (q changed with the consensus step);
+    // a later one from the highest stage whose working set changed
+    const int ts = it == 0 ? -1 : td;
     if (td >= 0) { refactor(pb, m, T, n_nbr, td); cnt[CT_REFACTOR] += td + 1; td = -1; }
-    affine_sweep(pb, m, T);
-    cnt[CT_AFFINE] += T;
+    const int swept = affine_sweep(pb, m, T, ts);
+    cnt[CT_AFFINE] += (T + swept) / 2;   // (rollout stages + sweep stages) / 2
     const StepInfo si = forward_rollout(pb, m, T, refine, pd);
     pd.on = false;
     cnt[CT_PASSES] += 1;
