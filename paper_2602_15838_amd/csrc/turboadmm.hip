@@ -303,7 +303,7 @@ struct SweepStage {
 // p_t above ts is what the previous sweep computed: the sweep stores p at
 // every stage that is a multiple of kSweepMark, and a sweep given ts < T - 1
 // restarts from the first such stage above ts (ts < 0 or >= T - 1: from T).
-constexpr int kSweepMark = 8;
+constexpr int kSweepMark = 4;
 template <class V>
 __device__ __forceinline__ int affine_sweep(const Prob &pb, const V &m, int T, int ts = -1) {
   constexpr int NX = V::NX, NU = V::NU, B = V::kSweepBatch;
@@ -597,26 +597,34 @@ __device__ void refine_solution(const Prob &pb, const V &m, int T, int n_nbr, bo
   constexpr int NX = V::NX, NU = V::NU, NS = V::NS;
   using D = Dyn<NX, NU, V::DI>;
   auto uin = [&](int a, int t) -> float { return FROM_UE ? m.UE(a, t) : m.U(a, t); };
+  // every loop below reads the data of V::kBatch stages before it computes
+  // the first of them (one memory round trip per batch)
+  constexpr int B = V::kBatch;
   double x[NX];
   if (!states_ready) {
 #pragma unroll
     for (int r = 0; r < NX; ++r) { x[r] = (double)m.X(r, 0); m.d(r, 0) = x[r]; }
     // (1) exact rollout of the stored inputs
-    float un[NU];
+    for (int t0 = 0; t0 < T; t0 += B) {
+      float ub[B][NU];
 #pragma unroll
-    for (int a = 0; a < NU; ++a) un[a] = uin(a, 0);
-    for (int t = 0; t < T; ++t) {
-      double u[NU], xn[NX];
+      for (int q = 0; q < B; ++q)
+        if (t0 + q < T) {
 #pragma unroll
-      for (int a = 0; a < NU; ++a) u[a] = (double)un[a];
-      if (t + 1 < T) {
+          for (int a = 0; a < NU; ++a) ub[q][a] = uin(a, t0 + q);
+        }
 #pragma unroll
-        for (int a = 0; a < NU; ++a) un[a] = uin(a, t + 1);
+      for (int q = 0; q < B; ++q) {
+        const int t = t0 + q;
+        if (t >= T) break;
+        double u[NU], xn[NX];
+#pragma unroll
+        for (int a = 0; a < NU; ++a) u[a] = (double)ub[q][a];
+        D::ax(m.dyn(pb), x, xn);
+        D::add_bu(m.dyn(pb), u, xn);
+#pragma unroll
+        for (int r = 0; r < NX; ++r) { x[r] = xn[r]; m.d(r, t + 1) = xn[r]; }
       }
-      D::ax(m.dyn(pb), x, xn);
-      D::add_bu(m.dyn(pb), u, xn);
-#pragma unroll
-      for (int r = 0; r < NX; ++r) { x[r] = xn[r]; m.d(r, t + 1) = xn[r]; }
     }
   }
   // (2) backward: FP64 adjoint (reduced gradient) and the FP32 correction sweep
@@ -651,11 +659,16 @@ __device__ void refine_solution(const Prob &pb, const V &m, int T, int n_nbr, bo
       st.xd[c] = m.d(c, t);
     }
   };
-  BStage nxt;
-  bload(nxt, T - 1);
-  for (int t = T - 1; t >= 0; --t) {
-    const BStage cur = nxt;
-    if (t >= 1) bload(nxt, t - 1);
+  for (int t0 = T - 1; t0 >= 0; t0 -= B) {
+   BStage bst[B];
+#pragma unroll
+   for (int q = 0; q < B; ++q)
+     if (t0 - q >= 0) bload(bst[q], t0 - q);
+#pragma unroll
+   for (int q = 0; q < B; ++q) {
+    const int t = t0 - q;
+    if (t < 0) break;
+    const BStage &cur = bst[q];
     double bnu[NU];
     float bpc[NU], sg[NU];
     D::btx(m.dyn(pb), nu, bnu);
@@ -688,6 +701,7 @@ __device__ void refine_solution(const Prob &pb, const V &m, int T, int n_nbr, bo
         nu[c] = nn[c] + fma((double)hx[c], cur.xd[c], (double)cur.q[c]);
       }
     }
+   }
   }
   // (3) correction rollout, update in FP64, round back to FP32
   float dx[NX];
@@ -705,11 +719,16 @@ __device__ void refine_solution(const Prob &pb, const V &m, int T, int n_nbr, bo
       for (int c = 0; c < NX; ++c) st.K[a][c] = m.K(a, c, t);
     }
   };
-  FStage fn;
-  fload(fn, 0);
-  for (int t = 0; t < T; ++t) {
-    const FStage cur = fn;
-    if (t + 1 < T) fload(fn, t + 1);
+  for (int t0 = 0; t0 < T; t0 += B) {
+   FStage fst[B];
+#pragma unroll
+   for (int q = 0; q < B; ++q)
+     if (t0 + q < T) fload(fst[q], t0 + q);
+#pragma unroll
+   for (int q = 0; q < B; ++q) {
+    const int t = t0 + q;
+    if (t >= T) break;
+    const FStage &cur = fst[q];
     float du[NU], uf[NU];
     double ud[NU];
 #pragma unroll
@@ -736,6 +755,7 @@ __device__ void refine_solution(const Prob &pb, const V &m, int T, int n_nbr, bo
       x[r] = xn[r];
       m.X(r, t + 1) = (float)xn[r];
     }
+   }
   }
 }
 
