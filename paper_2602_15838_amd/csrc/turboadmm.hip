@@ -85,7 +85,7 @@ template <int NX_, int NU_, bool DI_>
 struct AgentView {
   static constexpr int NX = NX_, NU = NU_, NS = NU_ * (NU_ + 1) / 2, NP = NX_ * (NX_ + 1) / 2;
   static constexpr bool DI = DI_;
-  static constexpr int kBatch = 2, kSweepBatch = 2;
+  static constexpr int kBatch = 2, kSweepBatch = 2, kRefineBatch = 1;
   using F = Fld<NX, NU>;
   float *__restrict__ R;
   int8_t *__restrict__ Wb;
@@ -142,6 +142,10 @@ struct AxisView {
   static constexpr int NX = 2, NU = 1, NS = 1, NP = 3;
   static constexpr bool DI = true;
   static constexpr int kBatch = 4, kSweepBatch = 4;
+  // the refinement's stages per batch: 4 in the plain-option kernel, whose
+  // LDS slots leave the registers for it, one elsewhere (the option paths'
+  // registers would spill in the x-update)
+  static constexpr int kRefineBatch = LA ? 4 : 1;
   using F = Fld<NXF, NUF>;
   float *__restrict__ R;      // agent-stage region
   float *__restrict__ AX;     // axis-stage region
@@ -597,9 +601,9 @@ __device__ void refine_solution(const Prob &pb, const V &m, int T, int n_nbr, bo
   constexpr int NX = V::NX, NU = V::NU, NS = V::NS;
   using D = Dyn<NX, NU, V::DI>;
   auto uin = [&](int a, int t) -> float { return FROM_UE ? m.UE(a, t) : m.U(a, t); };
-  // every loop below reads the data of V::kBatch stages before it computes
-  // the first of them (one memory round trip per batch)
-  constexpr int B = V::kBatch;
+  // every loop below reads the data of V::kRefineBatch stages before it
+  // computes the first of them (one memory round trip per batch)
+  constexpr int B = V::kRefineBatch;
   double x[NX];
   if (!states_ready) {
 #pragma unroll
