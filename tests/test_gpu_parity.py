@@ -401,6 +401,28 @@ def test_ablation_flags_same_iterates(flag):
         assert cb[0] >= ca[0]         # at least as many active-set passes
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_cached_factors_and_restarted_sweeps_are_exact(mode):
+    """With cached factors, a later active-set pass refactors only the stages
+    at and below its working-set change and restarts the affine sweep from a
+    kept stage above it (Eqs. 7-8 with the other stages' factors and costates
+    unchanged).  Without caching every pass refactors and sweeps every stage:
+    the same arithmetic on the same inputs, so the iterates, iteration counts
+    and statuses must be bitwise equal, with fewer refactored stages and
+    fewer swept stages in the cached run."""
+    p, scs = synth.config2(S=12)
+    _say(f"cached factors vs full refactors, mode={mode}")
+    a = gc.gpu_solve(p, scs, mode=mode)
+    b = gc.gpu_solve(p, scs, mode=mode, solver_kw=dict(cache_factors=False))
+    for ga, gb in zip(a, b):
+        assert np.array_equal(ga["x"], gb["x"]) and np.array_equal(ga["u"], gb["u"])
+        assert ga["iters"] == gb["iters"] and ga["status"] == gb["status"]
+        assert np.array_equal(ga["counters"][0], gb["counters"][0])   # the same active-set passes
+    ca = sum(g["counters"] for g in a)
+    cb = sum(g["counters"] for g in b)
+    assert ca[1] < cb[1] and ca[2] < cb[2], (ca, cb)
+
+
 # ---------------------------------------------------------------------------
 # edge cases and failure paths
 # ---------------------------------------------------------------------------
