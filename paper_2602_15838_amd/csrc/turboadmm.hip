@@ -1211,9 +1211,10 @@ __device__ void pair_agent_stage_impl(const Prob &pb, const WS &ws, const Scen &
 #pragma unroll
           for (int c = 0; c < NU; ++c) d2 = fmaf(pi[c] - pjb[q][c], pi[c] - pjb[q][c], d2);
           if (gb[q] == 0.f && d2 > far2) {
+            // (its dual stays zero: the word already holds +0, the only zero
+            // any step writes)
 #pragma unroll
             for (int c = 0; c < NU; ++c) z2 = fmaf(pi[c], pi[c], z2);
-            if (!msk) gm[gbase + jof(c0 + q0 + q) * N] = 0.f;   // (with the mask: zero already)
           } else {
             need |= 1u << (q0 + q);
           }
