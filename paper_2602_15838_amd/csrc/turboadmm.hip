@@ -1027,6 +1027,11 @@ __device__ void pair_agent_stage_impl(const Prob &pb, const WS &ws, const Scen &
   for (int c = 0; c < NU; ++c) { pi[c] = Ri(F::X + c); qi[c] = xpref<NX, NU>(R, GS, gi, c); }
 #pragma unroll
   for (int c = 0; c < NX; ++c) bad |= !isfinite(Ri(F::X + c));
+  // the last step's ZD and this stage's tracking term, read with the
+  // positions (one memory round trip rather than another after the partners)
+  float zdo[NU], gqp[NU];
+#pragma unroll
+  for (int c = 0; c < NU; ++c) { zdo[c] = Ri(F::QZ + NU + c); gqp[c] = Ri(F::GQP + c); }
   float *gm = ws.gam + sc.lo;
   // (the per-scenario penalty equals pb.rho unless it adapts)
   const float rho = pb.adapt ? ws.rhos[2 * sc.s] : pb.rho, irho = 1.0f / rho;
@@ -1249,11 +1254,11 @@ __device__ void pair_agent_stage_impl(const Prob &pb, const WS &ws, const Scen &
 #pragma unroll
   for (int c = 0; c < NU; ++c) {
     // rho sum_j (z_ij^(k+1) - z_ij^k) = rho (n_nbr (C x^(k+1) - C x^k) + ZD^(k+1) - ZD^k)
-    const float ds = rho * fmaf(nn, pi[c] - qi[c], zd[c] - Ri(F::QZ + NU + c));
+    const float ds = rho * fmaf(nn, pi[c] - qi[c], zd[c] - zdo[c]);
     s2 = fmaf(ds, ds, s2);
     ax2 = fmaf(pi[c], pi[c], ax2);
     aty2 = fmaf(ls[c], ls[c], aty2);
-    Ri(F::QZ + c) = fmaf(-rho * nn, pi[c], Ri(F::GQP + c)) - es[c];
+    Ri(F::QZ + c) = fmaf(-rho * nn, pi[c], gqp[c]) - es[c];
     Ri(F::QZ + NU + c) = zd[c];
   }
   ax2 *= nn;
